@@ -1,0 +1,230 @@
+/*
+ * hkgeneo.h -- C ABI of the MI355X two-level overlapping Schwarz preconditioner with the
+ * H_k-GenEO coarse space, and of the flexible GMRES solver built on it.
+ *
+ * Problem (paper Sec. 1, eq. (1.1); Sec. 2.1, eqs. (2.11)-(2.12)):
+ *     -div(A grad u) - k^2 u = f in Omega,  u = 0 on the boundary,
+ * discretised by conforming P1 / Q1 finite elements: B = A - k^2 S with A the stiffness and S
+ * the consistent mass matrix.  The preconditioner (eq. (2.23)) is
+ *     M^{-1} = Z B_0^{-1} Z^T + sum_D E_D W_D B_D^{-1} R_D,     B_D = R_D B E_D,  B_0 = Z^T B Z,
+ * where the subdomains D are the blocks of an element partition extended by element layers
+ * (Def. 2.8), R_D restricts to the internal dofs of D (Def. 2.12), W_D is the identity
+ * (additive Schwarz, eq. (2.22)) or the partition-of-unity weights 1/mu (Def. 2.13), and the
+ * columns of Z are E_i Xi_i p_l for the eigenvectors p_l of the local indefinite generalised
+ * eigenproblem b_{D_i}(p, v) = lambda (Xi_i p, Xi_i v)_{1,k,D_i} (Def. 2.14) with the smallest
+ * eigenvalues, chosen as in Def. 2.15.
+ *
+ * Conventions
+ *   - All entry points return an int32 status: 0 = HKG_OK, < 0 an error, > 0 a warning.
+ *   - Arrays passed to hkgeneo_setup are HOST arrays; they are copied and not retained.
+ *   - Vectors passed to hkgeneo_apply / hkgeneo_gmres_solve are DEVICE arrays (HIP device
+ *     pointers on the current device) of float64, column-major n_dof x nrhs with leading
+ *     dimension ld >= n_dof, owned by the caller.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *   - A context is not thread safe: calls on one context must not overlap.
+ *   - Dense device matrices are column-major.
+ */
+#ifndef HKGENEO_H
+#define HKGENEO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define HKG_OK 0
+#define HKG_EINVAL (-1)            /* bad sizes or ids; overlap leaving a dof with mu = 0; k < 0     */
+#define HKG_ENOMEM (-2)            /* device allocation failed                                       */
+#define HKG_EHIP (-3)              /* HIP runtime error (also surfaces errors of earlier async calls) */
+#define HKG_ESINGULAR_LOCAL (-4)   /* zero pivot in a local Dirichlet matrix B_D (subdomain named by
+                                      hkgeneo_last_error)                                            */
+#define HKG_EEIG (-5)              /* local eigenproblem failed: B~_GG singular, C_II not SPD, or more
+                                      eigenvectors needed than max_eig_per_sub (hkgeneo_last_error)  */
+#define HKG_ESINGULAR_COARSE (-6)  /* zero pivot in the coarse matrix B_0                             */
+#define HKG_ENOTCONV 1             /* solve returned without reaching rtol; see hkgeneo_rhs_info      */
+
+/* element types */
+#define HKG_P1 1                   /* linear simplices (triangles in 2D)       */
+#define HKG_Q1 2                   /* bilinear / trilinear tensor-product cells */
+
+/* eigenvector selection (Def. 2.15) */
+#define HKG_EIG_THRESHOLD 0        /* keep lambda < tau                                             */
+#define HKG_EIG_FIXED 1            /* keep nev per subdomain                                        */
+
+/* local prolongation weights */
+#define HKG_PROLONG_AS 0           /* W_D = I, additive Schwarz of eq. (2.22)                       */
+#define HKG_PROLONG_POU 1          /* W_D = diag(1/mu) on dof(D) (Def. 2.13)                        */
+
+typedef struct hkgeneo_ctx hkgeneo_ctx;
+
+/*
+ * The discrete problem.  Every pointer is a host pointer; all are read during hkgeneo_setup only.
+ *   elem_vert [n_elem*npe]   vertex ids of each element (npe = 3 for 2D P1, 4 for 2D Q1, 8 for 3D Q1;
+ *                            Q1 local node a = ax + 2 ay (+ 4 az))
+ *   vert_dof  [n_vert]       dof id of each vertex, -1 on the Dirichlet boundary
+ *   elem_K, elem_M [n_elem*npe*npe]  row-major element stiffness (coefficient folded in) and mass
+ *   row_ptr [n_dof+1], col_idx [nnz]  CSR pattern shared by A and S, column ids sorted per row
+ *   A_val, S_val [nnz]       stiffness and consistent mass values on that pattern
+ *   elem_part [n_elem]       non-overlapping partition, ids in [0, n_sub)
+ *   overlap [n_sub]          element layers added to each block (>= 1)
+ *   k                        wavenumber (>= 0)
+ */
+typedef struct {
+    int32_t dim;
+    int32_t elem_type;
+    int32_t n_vert;
+    int32_t n_elem;
+    int32_t n_dof;
+    int32_t nnz;
+    const int32_t *elem_vert;
+    const int32_t *vert_dof;
+    const double *elem_K;
+    const double *elem_M;
+    const int32_t *row_ptr;
+    const int32_t *col_idx;
+    const double *A_val;
+    const double *S_val;
+    const int32_t *elem_part;
+    int32_t n_sub;
+    const int32_t *overlap;
+    double k;
+} hkgeneo_problem;
+
+/*
+ * Method options.  hkgeneo_default_options fills the defaults listed here.
+ *   eig_mode, tau, nev   selection of Def. 2.15 (default HKG_EIG_FIXED, tau 0, nev 10); the count
+ *                        is raised to include every lambda <= 0 and to close a cluster
+ *                        (lambda_{m+1} - lambda_m <= cluster_rtol max(1, |lambda_m|)).
+ *   cluster_rtol         default 1e-8
+ *   max_eig_per_sub      hard cap on m_i (default 64); exceeding it is HKG_EEIG
+ *   local_prec           64: local factors and local solves in float64; 32: in float32 with float32
+ *                        accumulation (coarse space, Arnoldi and residuals stay float64)
+ *   prolong              HKG_PROLONG_AS (default) or HKG_PROLONG_POU
+ *   two_level            1 (default): add the coarse correction; 0: one-level only
+ *   restart, max_iter, rtol   FGMRES(restart) stopping at ||f - B u|| <= rtol ||f||
+ *                        (defaults 50, 1000, 1e-8)
+ */
+typedef struct {
+    int32_t eig_mode;
+    double tau;
+    int32_t nev;
+    double cluster_rtol;
+    int32_t max_eig_per_sub;
+    int32_t local_prec;
+    int32_t prolong;
+    int32_t two_level;
+    int32_t restart;
+    int32_t max_iter;
+    double rtol;
+} hkgeneo_options;
+
+/* per right-hand side outcome of hkgeneo_gmres_solve (host array of nrhs entries) */
+typedef struct {
+    int32_t iters;          /* preconditioner applications                         */
+    int32_t converged;      /* 1 if ||f - B u|| <= rtol ||f|| (checked in float64)  */
+    double relres_est;      /* Arnoldi recurrence estimate |g_{j+1}| / ||f||         */
+    double relres_true;     /* ||f - B u|| / ||f|| recomputed at the end             */
+} hkgeneo_rhs_info;
+
+/* summary of a context (host struct) */
+typedef struct {
+    int32_t n_dof;
+    int32_t n_sub;
+    int32_t lambda_overlap;   /* Lambda: max number of subdomains containing one element       */
+    int32_t m0;               /* coarse dimension sum_i m_i                                    */
+    int32_t sum_nI;           /* sum of |dof(D_i)|                                             */
+    int32_t max_nI;
+    int32_t max_nG;           /* max |ovdof(D_i) \ dof(D_i)|                                   */
+    int32_t bad_sub;          /* -1 for a context that was set up (failures return no context)  */
+    int64_t device_bytes;     /* device memory held by the context                             */
+    double setup_ms;          /* wall time of hkgeneo_setup                                    */
+} hkgeneo_stats;
+
+/* Fill `opt` with the defaults documented above. */
+void hkgeneo_default_options(hkgeneo_options *opt);
+
+/*
+ * Build the preconditioner (Sec. 2.3-2.4): overlap extension, index sets and multiplicities on the
+ * host; local Dirichlet factors, local eigenproblems, coarse basis and coarse factor on the device.
+ * Synchronous: returns after the device work is done, so its status is final.
+ * On success *out owns every device buffer; release it with hkgeneo_destroy.  On failure *out is NULL.
+ */
+int32_t hkgeneo_setup(const hkgeneo_problem *prob, const hkgeneo_options *opt, void *stream,
+                      hkgeneo_ctx **out);
+
+/*
+ * z = M^{-1} r (eq. (2.23)) for nrhs columns.  r and z are device arrays n_dof x nrhs (ld >= n_dof),
+ * must not alias.  Asynchronous on `stream`; HIP errors surface on the next synchronous call.
+ * Errors: HKG_EINVAL for a NULL pointer, nrhs < 1 or ld < n_dof.
+ */
+int32_t hkgeneo_apply(hkgeneo_ctx *ctx, const double *r, double *z, int32_t nrhs, int32_t ld,
+                      void *stream);
+
+/*
+ * Solve B u = f with right-preconditioned flexible GMRES(restart) and M^{-1} as preconditioner,
+ * starting from u = 0, independently for each of the nrhs columns.  f, u are device arrays
+ * n_dof x nrhs (ld >= n_dof); `info` is a host array of nrhs entries (may be NULL).  Synchronous.
+ * Returns HKG_OK if every column converged, HKG_ENOTCONV otherwise (u holds the last iterate).
+ */
+int32_t hkgeneo_gmres_solve(hkgeneo_ctx *ctx, const double *f, double *u, int32_t nrhs, int32_t ld,
+                            hkgeneo_rhs_info *info, void *stream);
+
+/* w = B x for nrhs columns (device arrays, ld >= n_dof).  Asynchronous. */
+int32_t hkgeneo_matvec(hkgeneo_ctx *ctx, const double *x, double *w, int32_t nrhs, int32_t ld,
+                       void *stream);
+
+/* Scalar summary of a context. */
+int32_t hkgeneo_query(const hkgeneo_ctx *ctx, hkgeneo_stats *out);
+
+/*
+ * Per-subdomain sizes into host arrays of n_sub entries (any may be NULL):
+ * nI = |dof(D_i)|, nG = |Gamma_i|, m = selected eigenvectors m_i.
+ */
+int32_t hkgeneo_query_subdomains(const hkgeneo_ctx *ctx, int32_t *nI, int32_t *nG, int32_t *m);
+
+/*
+ * Index sets of subdomain `sub` into host arrays: dof ids of dof(D) ascending (nI entries) and of
+ * Gamma ascending (nG entries); either may be NULL.  mu (host, n_dof entries, may be NULL) receives
+ * the multiplicities of Def. 2.13 when sub == 0.
+ */
+int32_t hkgeneo_query_index_sets(const hkgeneo_ctx *ctx, int32_t sub, int32_t *dof, int32_t *gamma,
+                                 int32_t *mu);
+
+/*
+ * Eigen data of subdomain `sub` (host arrays): the count smallest eigenvalues of Def. 2.14
+ * ascending (count <= m_i + 1 when m_i < nI, else m_i), and the coarse basis block Z_i = X_I P_i
+ * (nI x m_i column-major), either may be NULL.
+ */
+int32_t hkgeneo_query_eigen(const hkgeneo_ctx *ctx, int32_t sub, double *lambda, int32_t count,
+                            double *Z);
+
+/* The coarse matrix B_0 = Z^T B Z (m0 x m0 column-major, host array). */
+int32_t hkgeneo_query_coarse_matrix(const hkgeneo_ctx *ctx, double *B0);
+
+/*
+ * Host-only overlapping decomposition (no device work): Def. 2.8 applied overlap[i] times to each
+ * block of elem_part, then dof(D_i) and Gamma_i = ovdof(D_i) \ dof(D_i) (Def. 2.12), the
+ * multiplicities mu (Def. 2.13) and Lambda.  Only the element, vertex and partition fields of `prob`
+ * are read.  Outputs are host arrays, each optional (NULL): nI, nG [n_sub]; dof, gamma the
+ * concatenated ascending index sets (sum nI, sum nG entries; call once without them to size them);
+ * mu [n_dof]; lambda_overlap one int.  Errors: HKG_EINVAL for bad ids or a dof internal to no
+ * subdomain (overlap too small).
+ */
+int32_t hkgeneo_partition(const hkgeneo_problem *prob, int32_t *nI, int32_t *nG, int32_t *dof, int32_t *gamma,
+                          int32_t *mu, int32_t *lambda_overlap);
+
+/* Release every device buffer of the context (NULL is ignored). */
+void hkgeneo_destroy(hkgeneo_ctx *ctx);
+
+/* Static description of a status code. */
+const char *hkgeneo_strerror(int32_t status);
+
+/* Detail of the last failure on the calling thread (empty if none); valid until the next call. */
+const char *hkgeneo_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HKGENEO_H */

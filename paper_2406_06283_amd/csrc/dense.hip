@@ -1,0 +1,464 @@
+// Batched dense linear algebra for uneven matrix sizes: tiled GEMM, blocked LU with partial
+// pivoting, blocked triangular solves with many right-hand sides, and the inverse built from them.
+//
+// Every batched kernel takes one descriptor per matrix (offset, size, leading dimension) and uses
+// blockIdx.y as the batch index, so a launch covers matrices of different sizes; work past a
+// matrix's own size returns early.  Matrices are column-major.  T is double or float; the float
+// instantiations accumulate in float (the mixed-precision local factors).
+#include "internal.hpp"
+#include "kernels.hpp"
+
+namespace hkg {
+
+constexpr int GT = 64;       // GEMM tile (GT x GT outputs per 256-thread block, 4 x 4 per thread)
+constexpr int GK = 16;       // GEMM k-step staged through LDS
+constexpr int LU_NB = 32;    // LU / triangular-solve block size
+
+// ------------------------------------------------------------------------------------------------
+// GEMM tile: C[tm*GT.., tn*GT..] = beta C + alpha op(A) op(B) with op(A) M x K, op(B) K x N.
+// ------------------------------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void gemm_tile(int M, int N, int K, const T *__restrict__ A, int lda, bool ta,
+                                          const T *__restrict__ B, int ldb, bool tb, T *__restrict__ C,
+                                          int ldc, T alpha, T beta, int tm, int tn) {
+    __shared__ T sA[GK][GT + 1];
+    __shared__ T sB[GK][GT + 1];
+    const int tid = threadIdx.x;
+    const int tx = tid & 15, ty = tid >> 4;
+    const int i0 = tm * GT, j0 = tn * GT;
+    T acc[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[r][c] = T(0);
+
+    for (int k0 = 0; k0 < K; k0 += GK) {
+        // stage op(A)(i0 + ii, k0 + kk) into sA[kk][ii]
+        for (int e = tid; e < GK * GT; e += 256) {
+            int ii, kk;
+            if (!ta) { ii = e % GT; kk = e / GT; } else { kk = e % GK; ii = e / GK; }
+            int gi = i0 + ii, gk = k0 + kk;
+            T v = T(0);
+            if (gi < M && gk < K) v = ta ? A[gk + (int64_t)gi * lda] : A[gi + (int64_t)gk * lda];
+            sA[kk][ii] = v;
+        }
+        // stage op(B)(k0 + kk, j0 + jj) into sB[kk][jj]
+        for (int e = tid; e < GK * GT; e += 256) {
+            int jj, kk;
+            if (!tb) { kk = e % GK; jj = e / GK; } else { jj = e % GT; kk = e / GT; }
+            int gj = j0 + jj, gk = k0 + kk;
+            T v = T(0);
+            if (gj < N && gk < K) v = tb ? B[gj + (int64_t)gk * ldb] : B[gk + (int64_t)gj * ldb];
+            sB[kk][jj] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < GK; ++kk) {
+            T a[4], b[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) a[r] = sA[kk][tx + 16 * r];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) b[c] = sB[kk][ty + 16 * c];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[r][c] = fma(a[r], b[c], acc[r][c]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        int gj = j0 + ty + 16 * c;
+        if (gj >= N) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            int gi = i0 + tx + 16 * r;
+            if (gi >= M) continue;
+            T *p = C + gi + (int64_t)gj * ldc;
+            *p = (beta == T(0) ? T(0) : beta * *p) + alpha * acc[r][c];
+        }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_gemm_batched(const GemmJob *__restrict__ jobs, const T *__restrict__ Ab,
+                                                      const T *__restrict__ Bb, T *__restrict__ Cb, T alpha, T beta,
+                                                      int ta, int tb, int tiles_m_max) {
+    const GemmJob J = jobs[blockIdx.y];
+    const int tm = blockIdx.x % tiles_m_max, tn = blockIdx.x / tiles_m_max;
+    if (tm * GT >= J.M || tn * GT >= J.N) return;
+    gemm_tile<T>(J.M, J.N, J.K, Ab + J.offA, J.lda, ta, Bb + J.offB, J.ldb, tb, Cb + J.offC, J.ldc, alpha, beta, tm,
+                 tn);
+}
+
+template <typename T>
+int32_t gemm_batched(const GemmJob *d_jobs, int nbatch, int maxM, int maxN, const T *A, const T *B, T *C, T alpha,
+                     T beta, bool ta, bool tb, hipStream_t s) {
+    if (nbatch == 0 || maxM == 0 || maxN == 0) return HKG_OK;
+    int tmm = (maxM + GT - 1) / GT, tnm = (maxN + GT - 1) / GT;
+    dim3 grid(tmm * tnm, nbatch);
+    hipLaunchKernelGGL(k_gemm_batched<T>, grid, dim3(256), 0, s, d_jobs, A, B, C, alpha, beta, (int)ta, (int)tb, tmm);
+    HKG_HIP(hipGetLastError());
+    return HKG_OK;
+}
+template int32_t gemm_batched<double>(const GemmJob *, int, int, int, const double *, const double *, double *, double,
+                                      double, bool, bool, hipStream_t);
+template int32_t gemm_batched<float>(const GemmJob *, int, int, int, const float *, const float *, float *, float,
+                                     float, bool, bool, hipStream_t);
+
+// ------------------------------------------------------------------------------------------------
+// LU with partial pivoting, right-looking blocked (panel, row swaps, U12 solve, trailing GEMM).
+// Pivots are absolute row indices (0-based) stored at piv[m.off_piv + j]; info[b] = first zero
+// pivot column + 1 (0 if none).  With pivot == false the factorisation is LU without row exchanges
+// (used for symmetric positive definite matrices).
+// ------------------------------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_lu_panel(const DMat *__restrict__ mats, const int64_t *__restrict__ poff,
+                                                  T *__restrict__ Ab, int32_t *__restrict__ piv, int32_t *__restrict__ info,
+                                                  int j0, int pivot) {
+    const DMat m = mats[blockIdx.x];
+    const int n = m.n;
+    if (j0 >= n) return;
+    T *A = Ab + m.off;
+    const int ld = m.ld;
+    const int jend = min(j0 + LU_NB, n);
+    __shared__ T sval[256];
+    __shared__ int sidx[256];
+    __shared__ int s_p;
+    const int tid = threadIdx.x;
+    for (int j = j0; j < jend; ++j) {
+        int p = j;
+        if (pivot) {
+            // argmax |A[i, j]|, i >= j; ties resolved to the smallest row index
+            T best = T(-1);
+            int bi = n;
+            for (int i = j + tid; i < n; i += 256) {
+                T v = fabs(A[i + (int64_t)j * ld]);
+                if (v > best) { best = v; bi = i; }
+            }
+            sval[tid] = best;
+            sidx[tid] = bi;
+            __syncthreads();
+            for (int w = 128; w > 0; w >>= 1) {
+                if (tid < w) {
+                    T a = sval[tid], b = sval[tid + w];
+                    int ia = sidx[tid], ib = sidx[tid + w];
+                    if (b > a || (b == a && ib < ia)) { sval[tid] = b; sidx[tid] = ib; }
+                }
+                __syncthreads();
+            }
+            if (tid == 0) s_p = sidx[0] < n ? sidx[0] : j;
+            __syncthreads();
+            p = s_p;
+        }
+        if (tid == 0) piv[poff[blockIdx.x] + j] = p;
+        // swap rows j and p inside the panel columns
+        if (p != j) {
+            for (int c = j0 + tid; c < jend; c += 256) {
+                T t = A[j + (int64_t)c * ld];
+                A[j + (int64_t)c * ld] = A[p + (int64_t)c * ld];
+                A[p + (int64_t)c * ld] = t;
+            }
+        }
+        __syncthreads();
+        const T d = A[j + (int64_t)j * ld];
+        if (d == T(0) || !isfinite(d)) {
+            if (tid == 0 && info[blockIdx.x] == 0) info[blockIdx.x] = j + 1;
+            __syncthreads();
+            continue;
+        }
+        const T rd = T(1) / d;
+        for (int i = j + 1 + tid; i < n; i += 256) A[i + (int64_t)j * ld] *= rd;
+        __syncthreads();
+        // rank-1 update of the rest of the panel
+        const int w = jend - j - 1;
+        if (w > 0) {
+            const int rows = n - j - 1;
+            for (int e = tid; e < rows * w; e += 256) {
+                int i = j + 1 + e % rows, c = j + 1 + e / rows;
+                A[i + (int64_t)c * ld] -= A[i + (int64_t)j * ld] * A[j + (int64_t)c * ld];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// apply the row exchanges of panel [j0, j0+NB) to the columns outside the panel
+template <typename T>
+__global__ __launch_bounds__(256) void k_lu_laswp(const DMat *__restrict__ mats, const int64_t *__restrict__ poff,
+                                                  T *__restrict__ Ab, const int32_t *__restrict__ piv, int j0) {
+    const DMat m = mats[blockIdx.y];
+    const int n = m.n;
+    if (j0 >= n) return;
+    const int jend = min(j0 + LU_NB, n);
+    const int outside = n - (jend - j0);
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= outside) return;
+    const int c = t < j0 ? t : t + (jend - j0);
+    T *A = Ab + m.off + (int64_t)c * m.ld;
+    const int32_t *pv = piv + poff[blockIdx.y];
+    for (int j = j0; j < jend; ++j) {
+        int p = pv[j];
+        if (p != j) {
+            T x = A[j];
+            A[j] = A[p];
+            A[p] = x;
+        }
+    }
+}
+
+// U12 = L11^{-1} A12 for the panel rows, one thread per column
+template <typename T>
+__global__ __launch_bounds__(256) void k_lu_trsm_row(const DMat *__restrict__ mats, T *__restrict__ Ab, int j0) {
+    const DMat m = mats[blockIdx.y];
+    const int n = m.n;
+    const int jend = min(j0 + LU_NB, n);
+    if (jend >= n) return;
+    __shared__ T L[LU_NB][LU_NB + 1];
+    T *A = Ab + m.off;
+    const int ld = m.ld, nb = jend - j0;
+    for (int e = threadIdx.x; e < nb * nb; e += 256) {
+        int r = e % nb, c = e / nb;
+        L[r][c] = A[j0 + r + (int64_t)(j0 + c) * ld];
+    }
+    __syncthreads();
+    const int c = jend + blockIdx.x * 256 + threadIdx.x;
+    if (c >= n) return;
+    T x[LU_NB];
+    for (int r = 0; r < nb; ++r) {
+        T v = A[j0 + r + (int64_t)c * ld];
+        for (int k = 0; k < r; ++k) v -= L[r][k] * x[k];
+        x[r] = v;
+    }
+    for (int r = 0; r < nb; ++r) A[j0 + r + (int64_t)c * ld] = x[r];
+}
+
+// A22 -= L21 U12
+template <typename T>
+__global__ __launch_bounds__(256) void k_lu_update(const DMat *__restrict__ mats, T *__restrict__ Ab, int j0,
+                                                   int tiles_m_max) {
+    const DMat m = mats[blockIdx.y];
+    const int n = m.n;
+    const int jend = min(j0 + LU_NB, n);
+    const int rem = n - jend;
+    if (rem <= 0) return;
+    const int tm = blockIdx.x % tiles_m_max, tn = blockIdx.x / tiles_m_max;
+    if (tm * GT >= rem || tn * GT >= rem) return;
+    T *A = Ab + m.off;
+    const int ld = m.ld;
+    gemm_tile<T>(rem, rem, jend - j0, A + jend + (int64_t)j0 * ld, ld, false, A + j0 + (int64_t)jend * ld, ld, false,
+                 A + jend + (int64_t)jend * ld, ld, T(-1), T(1), tm, tn);
+}
+
+template <typename T>
+int32_t lu_batched(const DMat *d_mats, const int64_t *d_poff, int nbatch, int maxn, T *A, int32_t *piv,
+                   int32_t *info, bool pivot, hipStream_t s) {
+    if (nbatch == 0) return HKG_OK;
+    HKG_HIP(hipMemsetAsync(info, 0, sizeof(int32_t) * nbatch, s));
+    if (maxn == 0) return HKG_OK;
+    for (int j0 = 0; j0 < maxn; j0 += LU_NB) {
+        hipLaunchKernelGGL(k_lu_panel<T>, dim3(nbatch), dim3(256), 0, s, d_mats, d_poff, A, piv, info, j0, (int)pivot);
+        if (pivot) {
+            int outside = maxn;
+            hipLaunchKernelGGL(k_lu_laswp<T>, dim3((outside + 255) / 256, nbatch), dim3(256), 0, s, d_mats, d_poff, A,
+                               piv, j0);
+        }
+        int rem = maxn - j0 - LU_NB;
+        if (rem > 0) {
+            hipLaunchKernelGGL(k_lu_trsm_row<T>, dim3((rem + 255) / 256, nbatch), dim3(256), 0, s, d_mats, A, j0);
+            int tiles = (rem + GT - 1) / GT;
+            hipLaunchKernelGGL(k_lu_update<T>, dim3(tiles * tiles, nbatch), dim3(256), 0, s, d_mats, A, j0, tiles);
+        }
+    }
+    HKG_HIP(hipGetLastError());
+    return HKG_OK;
+}
+template int32_t lu_batched<double>(const DMat *, const int64_t *, int, int, double *, int32_t *, int32_t *, bool,
+                                    hipStream_t);
+template int32_t lu_batched<float>(const DMat *, const int64_t *, int, int, float *, int32_t *, int32_t *, bool,
+                                   hipStream_t);
+
+// ------------------------------------------------------------------------------------------------
+// Blocked triangular solves op(T) X = X with many right-hand sides (T n x n, X n x ncol):
+//   TRI_LOWER_UNIT        T unit lower (the L of an LU)
+//   TRI_UPPER             T upper, non-unit (the U of an LU)
+//   TRI_LOWER_UNIT_TRANS  T^T with T unit lower (i.e. unit upper read from the lower triangle)
+// Diagonal blocks are solved one thread per column; off-diagonal blocks are GEMM updates.
+// ------------------------------------------------------------------------------------------------
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void k_tri_diag(const TriJob *__restrict__ jobs, const T *__restrict__ Tb,
+                                                  T *__restrict__ Xb, int k0) {
+    const TriJob J = jobs[blockIdx.y];
+    if (k0 >= J.n) return;
+    const int nb = min(LU_NB, J.n - k0);
+    __shared__ T Ls[LU_NB][LU_NB + 1];
+    const T *Tm = Tb + J.offT;
+    for (int e = threadIdx.x; e < nb * nb; e += 256) {
+        int r = e % nb, c = e / nb;
+        // Ls[r][c] = op(T)[k0 + r, k0 + c]
+        Ls[r][c] = (MODE == TRI_LOWER_UNIT_TRANS) ? Tm[k0 + c + (int64_t)(k0 + r) * J.ldT]
+                                                  : Tm[k0 + r + (int64_t)(k0 + c) * J.ldT];
+    }
+    __syncthreads();
+    const int col = blockIdx.x * 256 + threadIdx.x;
+    if (col >= J.ncol) return;
+    T *X = Xb + J.offX + (int64_t)col * J.ldX + k0;
+    T x[LU_NB];
+    if (MODE == TRI_LOWER_UNIT) {
+        for (int r = 0; r < nb; ++r) {
+            T v = X[r];
+            for (int k = 0; k < r; ++k) v -= Ls[r][k] * x[k];
+            x[r] = v;
+        }
+    } else {
+        for (int r = nb - 1; r >= 0; --r) {
+            T v = X[r];
+            for (int k = r + 1; k < nb; ++k) v -= Ls[r][k] * x[k];
+            x[r] = (MODE == TRI_UPPER) ? v / Ls[r][r] : v;
+        }
+    }
+    for (int r = 0; r < nb; ++r) X[r] = x[r];
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void k_tri_update(const TriJob *__restrict__ jobs, const T *__restrict__ Tb,
+                                                    T *__restrict__ Xb, int k0, int tiles_m_max) {
+    const TriJob J = jobs[blockIdx.y];
+    if (k0 >= J.n) return;
+    const int k1 = min(k0 + LU_NB, J.n);
+    const T *Tm = Tb + J.offT;
+    T *X = Xb + J.offX;
+    const int tm = blockIdx.x % tiles_m_max, tn = blockIdx.x / tiles_m_max;
+    if (MODE == TRI_LOWER_UNIT) {
+        // rows below: X[k1:, :] -= T[k1:, k0:k1] X[k0:k1, :]
+        int M = J.n - k1;
+        if (M <= 0 || tm * GT >= M || tn * GT >= J.ncol) return;
+        gemm_tile<T>(M, J.ncol, k1 - k0, Tm + k1 + (int64_t)k0 * J.ldT, J.ldT, false, X + k0, J.ldX, false, X + k1,
+                     J.ldX, T(-1), T(1), tm, tn);
+    } else if (MODE == TRI_UPPER) {
+        // rows above: X[:k0, :] -= T[:k0, k0:k1] X[k0:k1, :]
+        int M = k0;
+        if (M <= 0 || tm * GT >= M || tn * GT >= J.ncol) return;
+        gemm_tile<T>(M, J.ncol, k1 - k0, Tm + (int64_t)k0 * J.ldT, J.ldT, false, X + k0, J.ldX, false, X, J.ldX, T(-1),
+                     T(1), tm, tn);
+    } else {
+        // rows above: X[:k0, :] -= (T[k0:k1, :k0])^T X[k0:k1, :]
+        int M = k0;
+        if (M <= 0 || tm * GT >= M || tn * GT >= J.ncol) return;
+        gemm_tile<T>(M, J.ncol, k1 - k0, Tm + k0, J.ldT, true, X + k0, J.ldX, false, X, J.ldX, T(-1), T(1), tm, tn);
+    }
+}
+
+template <typename T>
+int32_t tri_solve_batched(const TriJob *d_jobs, int nbatch, int maxn, int maxcol, const T *Tm, T *X, int mode,
+                          hipStream_t s) {
+    if (nbatch == 0 || maxn == 0 || maxcol == 0) return HKG_OK;
+    const int nblk = (maxn + LU_NB - 1) / LU_NB;
+    const int tiles_m = (maxn + GT - 1) / GT, tiles_n = (maxcol + GT - 1) / GT;
+    const dim3 gd((maxcol + 255) / 256, nbatch), gu(tiles_m * tiles_n, nbatch);
+    for (int b = 0; b < nblk; ++b) {
+        // block boundaries sit at multiples of LU_NB in every matrix, so one k0 serves the whole
+        // batch: ascending for the lower solve, descending for the upper ones (blocks past a
+        // matrix's own size return at once).
+        if (mode == TRI_LOWER_UNIT) {
+            int k0 = b * LU_NB;
+            hipLaunchKernelGGL((k_tri_diag<T, TRI_LOWER_UNIT>), gd, dim3(256), 0, s, d_jobs, Tm, X, k0);
+            hipLaunchKernelGGL((k_tri_update<T, TRI_LOWER_UNIT>), gu, dim3(256), 0, s, d_jobs, Tm, X, k0, tiles_m);
+        } else {
+            int k0 = (nblk - 1 - b) * LU_NB;
+            if (mode == TRI_UPPER) {
+                hipLaunchKernelGGL((k_tri_diag<T, TRI_UPPER>), gd, dim3(256), 0, s, d_jobs, Tm, X, k0);
+                hipLaunchKernelGGL((k_tri_update<T, TRI_UPPER>), gu, dim3(256), 0, s, d_jobs, Tm, X, k0, tiles_m);
+            } else {
+                hipLaunchKernelGGL((k_tri_diag<T, TRI_LOWER_UNIT_TRANS>), gd, dim3(256), 0, s, d_jobs, Tm, X, k0);
+                hipLaunchKernelGGL((k_tri_update<T, TRI_LOWER_UNIT_TRANS>), gu, dim3(256), 0, s, d_jobs, Tm, X, k0,
+                                   tiles_m);
+            }
+        }
+    }
+    HKG_HIP(hipGetLastError());
+    return HKG_OK;
+}
+template int32_t tri_solve_batched<double>(const TriJob *, int, int, int, const double *, double *, int, hipStream_t);
+template int32_t tri_solve_batched<float>(const TriJob *, int, int, int, const float *, float *, int, hipStream_t);
+
+// ------------------------------------------------------------------------------------------------
+// helpers: X = P * I (row exchanges of an LU applied to the identity), transposes, copies
+// ------------------------------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_perm_identity(const DMat *__restrict__ mats, const int64_t *__restrict__ poff,
+                                                       const int32_t *__restrict__ piv, T *__restrict__ Xb) {
+    const DMat m = mats[blockIdx.y];
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    if (c >= m.n) return;
+    T *X = Xb + m.off + (int64_t)c * m.ld;
+    for (int i = 0; i < m.n; ++i) X[i] = T(0);
+    // column c of P: follow the exchanges applied in order to row c's unit entry
+    int r = c;
+    const int32_t *pv = piv + poff[blockIdx.y];
+    for (int j = 0; j < m.n; ++j) {
+        int p = pv[j];
+        if (r == j) r = p;
+        else if (r == p) r = j;
+    }
+    X[r] = T(1);
+}
+
+template <typename T>
+int32_t perm_identity_batched(const DMat *d_mats, const int64_t *d_poff, int nbatch, int maxn, const int32_t *piv,
+                              T *X, hipStream_t s) {
+    if (nbatch == 0 || maxn == 0) return HKG_OK;
+    hipLaunchKernelGGL(k_perm_identity<T>, dim3((maxn + 255) / 256, nbatch), dim3(256), 0, s, d_mats, d_poff, piv, X);
+    HKG_HIP(hipGetLastError());
+    return HKG_OK;
+}
+template int32_t perm_identity_batched<double>(const DMat *, const int64_t *, int, int, const int32_t *, double *,
+                                               hipStream_t);
+template int32_t perm_identity_batched<float>(const DMat *, const int64_t *, int, int, const int32_t *, float *,
+                                              hipStream_t);
+
+// out = in^T for square matrices with the same descriptors (separate buffers)
+template <typename T>
+__global__ __launch_bounds__(256) void k_transpose(const DMat *__restrict__ mats, const T *__restrict__ in,
+                                                   T *__restrict__ out, int tiles_max) {
+    const DMat m = mats[blockIdx.y];
+    __shared__ T tile[32][33];
+    const int ti = blockIdx.x % tiles_max, tj = blockIdx.x / tiles_max;
+    if (ti * 32 >= m.n || tj * 32 >= m.n) return;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+    for (int r = ty; r < 32; r += 8) {
+        int i = ti * 32 + tx, j = tj * 32 + r;
+        if (i < m.n && j < m.n) tile[r][tx] = in[m.off + i + (int64_t)j * m.ld];
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        int i = tj * 32 + tx, j = ti * 32 + r;   // out[i, j] = in[j, i]
+        if (i < m.n && j < m.n) out[m.off + i + (int64_t)j * m.ld] = tile[tx][r];
+    }
+}
+
+template <typename T>
+int32_t transpose_batched(const DMat *d_mats, int nbatch, int maxn, const T *in, T *out, hipStream_t s) {
+    if (nbatch == 0 || maxn == 0) return HKG_OK;
+    int tiles = (maxn + 31) / 32;
+    hipLaunchKernelGGL(k_transpose<T>, dim3(tiles * tiles, nbatch), dim3(256), 0, s, d_mats, in, out, tiles);
+    HKG_HIP(hipGetLastError());
+    return HKG_OK;
+}
+template int32_t transpose_batched<double>(const DMat *, int, int, const double *, double *, hipStream_t);
+
+// FP64 -> FP32 copy of a flat buffer
+__global__ void k_cast_f64_f32(const double *__restrict__ in, float *__restrict__ out, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = (float)in[i];
+}
+
+int32_t cast_f64_f32(const double *in, float *out, int64_t n, hipStream_t s) {
+    if (n == 0) return HKG_OK;
+    int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_cast_f64_f32, dim3(blocks), dim3(256), 0, s, in, out, n);
+    HKG_HIP(hipGetLastError());
+    return HKG_OK;
+}
+
+}  // namespace hkg

@@ -1,0 +1,446 @@
+// Local H_k-GenEO eigenproblems (Def. 2.14) on the GPU, batched over subdomains.
+//
+// The pencil (B~, X D~ X) on ovdof(D) has |Gamma| infinite eigenvalues (its right-hand side vanishes
+// on Gamma); the finite ones are those of the symmetric-definite pencil S p = lambda C_II p with
+// S = B_II - B_IG B~_GG^{-1} B_GI (Lemma 2.6 gives real eigenvalues and C-orthonormal vectors).  The
+// host driver forms S and the factor C_II = L L^T; the kernels here take the standard symmetric
+// matrix L^{-1} S L^{-T} through:
+//   1. Householder reduction to tridiagonal form T = Q^T (L^{-1} S L^{-T}) Q,
+//   2. Sturm-sequence counts on T: the number of eigenvalues below tau / below 0 and bisection for
+//      the smallest ones, with the selection of Def. 2.15 (lambda_{m+1} > 0, clusters kept whole),
+//   3. inverse iteration on T for the selected eigenvalues (re-orthogonalised inside clusters),
+//   4. back-transformation by Q (and by L^{-T} on the host side), the sign convention (largest
+//      entry positive), and the partition-of-unity scaling X that gives the coarse basis
+//      Z_i = X_I P_i (Def. 2.15),
+// and finally the blocks of the coarse matrix B_0 = Z^T B Z (eq. (2.23)).
+#include "internal.hpp"
+#include "kernels.hpp"
+
+namespace hkg {
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// block-wide sum; every thread gets the result. red must hold one double per wave.
+__device__ __forceinline__ double block_sum(double v, double *red) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    v = wave_sum(v);
+    __syncthreads();
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int i = 0; i < nw; ++i) t += red[i];
+    return t;
+}
+
+// ------------------------------------------------------------------------------------------------
+// 1. Householder tridiagonalisation of the full symmetric nI x nI matrix at offSq (both triangles
+//    kept up to date).  Reflector j is stored in column j below the diagonal (its first entry, 1,
+//    explicitly), with tau[j]; d and e receive the diagonal and sub-diagonal of T.
+// ------------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_sytrd(const SubDev *__restrict__ subs, double *__restrict__ Sq,
+                                                double *__restrict__ dout, double *__restrict__ eout,
+                                                double *__restrict__ tout) {
+    extern __shared__ double sh[];
+    const SubDev sd = subs[blockIdx.x];
+    const int n = sd.nI;
+    double *A = Sq + sd.offSq;
+    const int ld = n;
+    double *v = sh;           // n
+    double *p = sh + n;       // n
+    double *red = sh + 2 * n; // 16
+    double *d = dout + sd.offI, *e = eout + sd.offI, *tau = tout + sd.offI;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
+
+    for (int j = 0; j + 1 < n; ++j) {
+        const int L = n - j - 1;
+        double *x = A + (j + 1) + (int64_t)j * ld;        // A[j+1:, j]
+        for (int i = tid; i < L; i += blockDim.x) v[i] = x[i];
+        __syncthreads();
+        const double alpha = v[0];
+        double part = 0.0;
+        for (int i = 1 + tid; i < L; i += blockDim.x) part += v[i] * v[i];
+        const double xn2 = block_sum(part, red);
+        if (tid == 0) d[j] = A[j + (int64_t)j * ld];
+        if (xn2 == 0.0) {
+            if (tid == 0) { e[j] = alpha; tau[j] = 0.0; }
+            __syncthreads();
+            continue;
+        }
+        const double beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+        const double t = (beta - alpha) / beta;
+        const double scal = 1.0 / (alpha - beta);
+        __syncthreads();
+        for (int i = tid; i < L; i += blockDim.x) {
+            double vi = (i == 0) ? 1.0 : v[i] * scal;
+            v[i] = vi;
+            x[i] = vi;
+        }
+        if (tid == 0) { e[j] = beta; tau[j] = t; }
+        __syncthreads();
+        // p = tau A22 v, one wave per column of the symmetric A22 (column c dotted with v)
+        double *A22 = A + (j + 1) + (int64_t)(j + 1) * ld;
+        for (int c = wv; c < L; c += nw) {
+            const double *col = A22 + (int64_t)c * ld;
+            double s = 0.0;
+            for (int i = lane; i < L; i += 64) s += col[i] * v[i];
+            s = wave_sum(s);
+            if (lane == 0) p[c] = t * s;
+        }
+        __syncthreads();
+        part = 0.0;
+        for (int i = tid; i < L; i += blockDim.x) part += p[i] * v[i];
+        const double K = 0.5 * t * block_sum(part, red);
+        for (int i = tid; i < L; i += blockDim.x) p[i] -= K * v[i];     // p becomes w
+        __syncthreads();
+        // A22 -= v w^T + w v^T
+        const int64_t LL = (int64_t)L * L;
+        for (int64_t q = tid; q < LL; q += blockDim.x) {
+            int r = (int)(q % L), c = (int)(q / L);
+            A22[r + (int64_t)c * ld] -= v[r] * p[c] + p[r] * v[c];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) d[n - 1] = A[(n - 1) + (int64_t)(n - 1) * ld];
+}
+
+int32_t tridiagonalize_n(const SubDev *d_sub, int nsub, int maxnI, double *Sq, double *d, double *e, double *tau,
+                         hipStream_t s) {
+    size_t shm = (size_t)(2 * maxnI + 16) * sizeof(double);
+    hipLaunchKernelGGL(k_sytrd, dim3(nsub), dim3(1024), shm, s, d_sub, Sq, d, e, tau);
+    HKG_HIP(hipGetLastError());
+    return HKG_OK;
+}
+
+// ------------------------------------------------------------------------------------------------
+// 2. Sturm counts and selection.
+// ------------------------------------------------------------------------------------------------
+// number of eigenvalues of T (diagonal d, off-diagonal e) strictly below sigma
+__device__ int sturm_count(const double *__restrict__ d, const double *__restrict__ e, int n, double sigma,
+                           double pivmin) {
+    int cnt = 0;
+    double q = d[0] - sigma;
+    if (fabs(q) < pivmin) q = -pivmin;
+    cnt += (q < 0.0);
+    for (int i = 1; i < n; ++i) {
+        q = d[i] - sigma - e[i - 1] * e[i - 1] / q;
+        if (fabs(q) < pivmin) q = -pivmin;
+        cnt += (q < 0.0);
+    }
+    return cnt;
+}
+
+// k-th smallest eigenvalue (0-based) by bisection in (lo, hi]
+__device__ double bisect_kth(const double *d, const double *e, int n, int k, double lo, double hi, double pivmin) {
+    for (int it = 0; it < 200; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        if (sturm_count(d, e, n, mid, pivmin) <= k) lo = mid;
+        else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+// one wave per subdomain
+__global__ __launch_bounds__(64) void k_select(const SubDev *__restrict__ subs, const double *__restrict__ dbuf,
+                                               const double *__restrict__ ebuf, int mode, double tau, int nev,
+                                               double rtol, int mmax, int32_t *__restrict__ m_out,
+                                               double *__restrict__ lam_out, int32_t *__restrict__ flag) {
+    const SubDev sd = subs[blockIdx.x];
+    const int n = sd.nI;
+    const double *d = dbuf + sd.offI, *e = ebuf + sd.offI;
+    const int lane = threadIdx.x;
+    // Gershgorin interval and the pivot floor of the Sturm recurrence
+    double lo = 1e300, hi = -1e300, emax2 = 0.0;
+    for (int i = lane; i < n; i += 64) {
+        double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < n ? fabs(e[i]) : 0.0);
+        lo = fmin(lo, d[i] - r);
+        hi = fmax(hi, d[i] + r);
+        if (i + 1 < n) emax2 = fmax(emax2, e[i] * e[i]);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        lo = fmin(lo, __shfl_xor(lo, o, 64));
+        hi = fmax(hi, __shfl_xor(hi, o, 64));
+        emax2 = fmax(emax2, __shfl_xor(emax2, o, 64));
+    }
+    const double tnorm = fmax(fabs(lo), fabs(hi));
+    const double pivmin = fmax(2.2250738585072014e-308, 2.2204460492503131e-16 * 2.2204460492503131e-16 * emax2);
+    lo -= 2.2204460492503131e-16 * tnorm * n + pivmin;
+    hi += 2.2204460492503131e-16 * tnorm * n + pivmin;
+    int m = (mode == HKG_EIG_THRESHOLD) ? sturm_count(d, e, n, tau, pivmin) : nev;
+    m = max(m, sturm_count(d, e, n, 0.0, pivmin));   // every lambda <= 0 (Def. 2.15: lambda_{m+1} > 0)
+    m = min(m, n);
+    double *lam = lam_out + (int64_t)blockIdx.x * (mmax + 2);
+    if (m > mmax) {
+        if (lane == 0) { flag[blockIdx.x] = 1; m_out[blockIdx.x] = m; }
+        return;
+    }
+    const int need = min(n, m + 1);
+    for (int k = lane; k < need; k += 64) lam[k] = bisect_kth(d, e, n, k, lo, hi, pivmin);
+    __syncthreads();
+    if (lane == 0) {
+        // close a cluster at the cut: lambda_{m+1} - lambda_m <= rtol max(1, |lambda_m|)
+        while (m > 0 && m < n && lam[m] - lam[m - 1] <= rtol * fmax(1.0, fabs(lam[m - 1]))) {
+            ++m;
+            if (m > mmax) break;
+            if (m < n) lam[m] = bisect_kth(d, e, n, m, lo, hi, pivmin);
+        }
+        flag[blockIdx.x] = (m > mmax) ? 1 : 0;
+        m_out[blockIdx.x] = m;
+    }
+}
+
+int32_t select_eigs(const SubDev *d_sub, int nsub, const double *d, const double *e, int mode, double tau, int nev,
+                    double rtol, int mmax, int32_t *m_out, double *lam_out, int32_t *flag, hipStream_t s) {
+    hipLaunchKernelGGL(k_select, dim3(nsub), dim3(64), 0, s, d_sub, d, e, mode, tau, nev, rtol, mmax, m_out, lam_out,
+                       flag);
+    HKG_HIP(hipGetLastError());
+    return HKG_OK;
+}
+
+// ------------------------------------------------------------------------------------------------
+// 3. inverse iteration on T for each selected eigenvalue: (T - lambda I) y = b by Gaussian
+//    elimination with partial pivoting on the tridiagonal (one thread; it is a serial recurrence),
+//    then Gram-Schmidt against the vectors already computed for eigenvalues within 1e-3 ||T|| and
+//    normalisation (whole block).  Three sweeps from a fixed pseudo-random start vector.
+// ------------------------------------------------------------------------------------------------
+__device__ __forceinline__ double start_value(int i, int k) {
+    uint32_t h = (uint32_t)i * 2654435761u ^ ((uint32_t)k * 40503u + 0x9e3779b9u);
+    h ^= h >> 15; h *= 2246822519u; h ^= h >> 13; h *= 3266489917u; h ^= h >> 16;
+    return ((double)(h & 0xffffff) / 16777216.0) * 2.0 - 1.0;
+}
+
+__global__ __launch_bounds__(256) void k_inverse_iteration(const SubDev *__restrict__ subs, const double *__restrict__ dbuf,
+                                                           const double *__restrict__ ebuf, const double *__restrict__ lam_all,
+                                                           int mmax, double *__restrict__ Zb) {
+    extern __shared__ double sh[];
+    const SubDev sd = subs[blockIdx.x];
+    const int n = sd.nI, m = sd.m;
+    if (m == 0) return;
+    const double *d = dbuf + sd.offI, *e = ebuf + sd.offI;
+    const double *lam = lam_all + (int64_t)blockIdx.x * (mmax + 2);
+    double *dd = sh, *du = sh + n, *du2 = sh + 2 * n, *fac = sh + 3 * n, *b = sh + 4 * n, *red = sh + 5 * n;
+    unsigned char *swp = (unsigned char *)(red + 8);
+    double *Z = Zb + sd.offZ;
+    const int tid = threadIdx.x;
+    __shared__ double s_tnorm;
+    if (tid == 0) {
+        double t = 0.0;
+        for (int i = 0; i < n; ++i)
+            t = fmax(t, fabs(d[i]) + (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < n ? fabs(e[i]) : 0.0));
+        s_tnorm = t;
+    }
+    __syncthreads();
+    const double tnorm = s_tnorm;
+    const double pert = 2.2204460492503131e-16 * fmax(tnorm, 1e-300);
+    const double orth_tol = 1e-3 * tnorm;
+    for (int k = 0; k < m; ++k) {
+        const double lk = lam[k];
+        if (tid == 0) {
+            // factor T - lk I = P L U (U has two super-diagonals)
+            for (int i = 0; i < n; ++i) dd[i] = d[i] - lk;
+            for (int i = 0; i + 1 < n; ++i) { du[i] = e[i]; fac[i] = e[i]; }   // fac holds the sub-diagonal
+            for (int i = 0; i + 1 < n; ++i) {
+                const double sub = fac[i];
+                if (fabs(dd[i]) >= fabs(sub)) {
+                    swp[i] = 0;
+                    if (dd[i] == 0.0) dd[i] = pert;
+                    const double f = sub / dd[i];
+                    fac[i] = f;
+                    dd[i + 1] -= f * du[i];
+                    if (i + 2 < n) du2[i] = 0.0;
+                } else {
+                    swp[i] = 1;
+                    const double f = dd[i] / sub;
+                    fac[i] = f;
+                    dd[i] = sub;
+                    const double tmp = dd[i + 1];
+                    dd[i + 1] = du[i] - f * tmp;
+                    if (i + 2 < n) {
+                        du2[i] = du[i + 1];
+                        du[i + 1] = -f * du2[i];
+                    }
+                    du[i] = tmp;
+                }
+            }
+            if (dd[n - 1] == 0.0) dd[n - 1] = pert;
+        }
+        for (int i = tid; i < n; i += 256) b[i] = start_value(i, k);
+        __syncthreads();
+        for (int sweep = 0; sweep < 3; ++sweep) {
+            if (tid == 0) {
+                for (int i = 0; i + 1 < n; ++i) {
+                    if (!swp[i]) {
+                        b[i + 1] -= fac[i] * b[i];
+                    } else {
+                        const double t = b[i];
+                        b[i] = b[i + 1];
+                        b[i + 1] = t - fac[i] * b[i + 1];
+                    }
+                }
+                b[n - 1] /= dd[n - 1];
+                if (n >= 2) b[n - 2] = (b[n - 2] - du[n - 2] * b[n - 1]) / dd[n - 2];
+                for (int i = n - 3; i >= 0; --i) b[i] = (b[i] - du[i] * b[i + 1] - du2[i] * b[i + 2]) / dd[i];
+                // rescale to keep the iterate finite
+                double mx = 0.0;
+                for (int i = 0; i < n; ++i) mx = fmax(mx, fabs(b[i]));
+                const double inv = mx > 0.0 ? 1.0 / mx : 1.0;
+                for (int i = 0; i < n; ++i) b[i] *= inv;
+            }
+            __syncthreads();
+            // modified Gram-Schmidt against earlier vectors of the same cluster
+            for (int q = 0; q < k; ++q) {
+                if (fabs(lam[q] - lk) > orth_tol) continue;
+                const double *zq = Z + (int64_t)q * n;
+                double part = 0.0;
+                for (int i = tid; i < n; i += 256) part += zq[i] * b[i];
+                const double dot = block_sum(part, red);
+                for (int i = tid; i < n; i += 256) b[i] -= dot * zq[i];
+                __syncthreads();
+            }
+            double part = 0.0;
+            for (int i = tid; i < n; i += 256) part += b[i] * b[i];
+            const double nrm = sqrt(block_sum(part, red));
+            const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+            for (int i = tid; i < n; i += 256) b[i] *= inv;
+            __syncthreads();
+        }
+        for (int i = tid; i < n; i += 256) Z[(int64_t)k * n + i] = b[i];
+        __syncthreads();
+    }
+}
+
+int32_t tridiag_vectors_n(const SubDev *d_sub, int nsub, int maxnI, const double *d, const double *e, const double *lam,
+                          int mmax, double *Z, hipStream_t s) {
+    size_t shm = (size_t)(5 * maxnI + 8) * sizeof(double) + (size_t)maxnI + 16;
+    hipLaunchKernelGGL(k_inverse_iteration, dim3(nsub), dim3(256), shm, s, d_sub, d, e, lam, mmax, Z);
+    HKG_HIP(hipGetLastError());
+    return HKG_OK;
+}
+
+// ------------------------------------------------------------------------------------------------
+// 4. back-transformation y <- Q y with Q = H_0 H_1 ... H_{n-2} (reflectors applied last-first)
+// ------------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_back_transform(const SubDev *__restrict__ subs, const double *__restrict__ Sq,
+                                                        const double *__restrict__ taub, double *__restrict__ Zb) {
+    extern __shared__ double sh[];
+    const SubDev sd = subs[blockIdx.x];
+    const int n = sd.nI, m = sd.m;
+    if (m == 0) return;
+    const double *A = Sq + sd.offSq;
+    const double *tau = taub + sd.offI;
+    double *Z = Zb + sd.offZ;
+    double *dots = sh;          // m
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    for (int j = n - 2; j >= 0; --j) {
+        const double t = tau[j];
+        if (t == 0.0) continue;
+        const int L = n - j - 1;
+        const double *v = A + (j + 1) + (int64_t)j * n;
+        for (int c = wv; c < m; c += 4) {
+            const double *z = Z + (int64_t)c * n + j + 1;
+            double s = 0.0;
+            for (int i = lane; i < L; i += 64) s += v[i] * z[i];
+            s = wave_sum(s);
+            if (lane == 0) dots[c] = t * s;
+        }
+        __syncthreads();
+        for (int64_t q = tid; q < (int64_t)L * m; q += 256) {
+            int i = (int)(q % L), c = (int)(q / L);
+            Z[(int64_t)c * n + j + 1 + i] -= dots[c] * v[i];
+        }
+        __syncthreads();
+    }
+}
+
+int32_t back_transform_n(const SubDev *d_sub, int nsub, int mmax, const double *Sq, const double *tau, double *Z,
+                         hipStream_t s) {
+    size_t shm = (size_t)(mmax + 2) * sizeof(double);
+    hipLaunchKernelGGL(k_back_transform, dim3(nsub), dim3(256), shm, s, d_sub, Sq, tau, Z);
+    HKG_HIP(hipGetLastError());
+    return HKG_OK;
+}
+
+// Z[i, :] /= sqrt(U_ii) with U the upper factor of C_II = L U (no row exchanges)
+__global__ __launch_bounds__(256) void k_scale_rows(const SubDev *__restrict__ subs, const double *__restrict__ C,
+                                                    double *__restrict__ Zb) {
+    const SubDev sd = subs[blockIdx.x];
+    const int n = sd.nI;
+    for (int64_t q = threadIdx.x; q < (int64_t)n * sd.m; q += 256) {
+        int i = (int)(q % n);
+        Zb[sd.offZ + q] /= sqrt(C[sd.offSq + i + (int64_t)i * n]);
+    }
+}
+
+int32_t scale_rows_invsqrt_diag(const SubDev *d_sub, int nsub, const double *C, double *Z, hipStream_t s) {
+    hipLaunchKernelGGL(k_scale_rows, dim3(nsub), dim3(256), 0, s, d_sub, C, Z);
+    HKG_HIP(hipGetLastError());
+    return HKG_OK;
+}
+
+// sign convention (entry of largest magnitude positive, first on ties) then Z = X_I P
+__global__ __launch_bounds__(256) void k_finish_basis(const SubDev *__restrict__ subs, const int32_t *__restrict__ I_idx,
+                                                      const double *__restrict__ winv, double *__restrict__ Zb) {
+    const SubDev sd = subs[blockIdx.x];
+    const int n = sd.nI, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int c = wv; c < sd.m; c += 4) {
+        double *z = Zb + sd.offZ + (int64_t)c * n;
+        double best = -1.0;
+        int bi = n;
+        for (int i = lane; i < n; i += 64) {
+            double a = fabs(z[i]);
+            if (a > best) { best = a; bi = i; }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            double ob = __shfl_xor(best, o, 64);
+            int oi = __shfl_xor(bi, o, 64);
+            if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+        }
+        const double sgn = (bi < n && z[bi] < 0.0) ? -1.0 : 1.0;
+        for (int i = lane; i < n; i += 64) z[i] = sgn * z[i] * winv[I_idx[sd.offI + i]];
+    }
+}
+
+int32_t finish_basis(const SubDev *d_sub, int nsub, const int32_t *I_idx, const double *winv, double *Z,
+                     hipStream_t s) {
+    hipLaunchKernelGGL(k_finish_basis, dim3(nsub), dim3(256), 0, s, d_sub, I_idx, winv, Z);
+    HKG_HIP(hipGetLastError());
+    return HKG_OK;
+}
+
+// ------------------------------------------------------------------------------------------------
+// coarse matrix blocks: B_0[(j, b), (i, a)] = sum over q in ovdof(D_i) and dof(D_j) of
+//   Z_j[q, b] (B Z_i)[q, a],  with (B Z_i)[q, a] = Y_i[a, q] and Y_i = Z_i^T [B_II | B_IG]  (B symmetric)
+// ------------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_coarse_pairs(const int32_t *__restrict__ pi, const int32_t *__restrict__ pj,
+                                                      const int32_t *__restrict__ ptr, const int32_t *__restrict__ qi,
+                                                      const int32_t *__restrict__ qj, const SubDev *__restrict__ subs,
+                                                      const double *__restrict__ Y, const double *__restrict__ Zb,
+                                                      double *__restrict__ B0, int m0) {
+    const int t = blockIdx.x;
+    const SubDev si = subs[pi[t]], sj = subs[pj[t]];
+    const int mi = si.m, mj = sj.m;
+    if (mi == 0 || mj == 0) return;
+    const int beg = ptr[t], end = ptr[t + 1];
+    for (int q = threadIdx.x; q < mi * mj; q += 256) {
+        const int b = q % mj, a = q / mj;
+        double s = 0.0;
+        for (int u = beg; u < end; ++u)
+            s += Zb[sj.offZ + qj[u] + (int64_t)b * sj.nI] * Y[si.offY + a + (int64_t)qi[u] * mi];
+        B0[(int64_t)(sj.offm + b) + (int64_t)(si.offm + a) * m0] = s;
+    }
+}
+
+int32_t coarse_pairs(int npairs, const int32_t *pi, const int32_t *pj, const int32_t *ptr, const int32_t *qi,
+                     const int32_t *qj, const SubDev *d_sub, const double *Y, const double *Z, double *B0, int m0,
+                     hipStream_t s) {
+    if (npairs == 0) return HKG_OK;
+    hipLaunchKernelGGL(k_coarse_pairs, dim3(npairs), dim3(256), 0, s, pi, pj, ptr, qi, qj, d_sub, Y, Z, B0, m0);
+    HKG_HIP(hipGetLastError());
+    return HKG_OK;
+}
+
+}  // namespace hkg

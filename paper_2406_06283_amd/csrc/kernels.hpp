@@ -1,0 +1,109 @@
+// Host-callable launch wrappers of the HIP kernels (all asynchronous on the given stream).
+#pragma once
+
+#include "internal.hpp"
+
+namespace hkg {
+
+enum { TRI_LOWER_UNIT = 0, TRI_UPPER = 1, TRI_LOWER_UNIT_TRANS = 2 };
+
+// ---- dense.hip --------------------------------------------------------------------------------
+template <typename T>
+int32_t gemm_batched(const GemmJob *d_jobs, int nbatch, int maxM, int maxN, const T *A, const T *B, T *C, T alpha,
+                     T beta, bool ta, bool tb, hipStream_t s);
+template <typename T>
+int32_t lu_batched(const DMat *d_mats, const int64_t *d_poff, int nbatch, int maxn, T *A, int32_t *piv,
+                   int32_t *info, bool pivot, hipStream_t s);
+template <typename T>
+int32_t tri_solve_batched(const TriJob *d_jobs, int nbatch, int maxn, int maxcol, const T *Tm, T *X, int mode,
+                          hipStream_t s);
+template <typename T>
+int32_t perm_identity_batched(const DMat *d_mats, const int64_t *d_poff, int nbatch, int maxn, const int32_t *piv,
+                              T *X, hipStream_t s);
+template <typename T>
+int32_t transpose_batched(const DMat *d_mats, int nbatch, int maxn, const T *in, T *out, hipStream_t s);
+int32_t cast_f64_f32(const double *in, float *out, int64_t n, hipStream_t s);
+
+// ---- setup.hip: local blocks of every subdomain ---------------------------------------------------
+struct SubDev {             // per-subdomain device descriptors
+    int32_t nI, nG;
+    int64_t offI, offG;     // into I_idx / G_idx and the concatenated local vectors
+    int64_t offBIO;         // [B_II | B_IG], nI x (nI + nG), ld nI
+    int64_t offSq;          // nI x nI work matrices (Schur, C_II, ...), ld nI
+    int64_t offGG;          // nG x nG, ld nG
+    int64_t offGI;          // nG x nI, ld nG
+    int64_t offPiv;         // pivots (max(nI, nG))
+    int32_t bandBeg, bandEnd;
+    int64_t offZ;           // nI x m, ld nI
+    int64_t offY;           // m x (nI + nG), ld m
+    int32_t m, offm;        // eigenvectors kept, coarse offset
+};
+
+int32_t form_operator(const double *A, const double *S, double k2, double *B, double *Dk, int64_t nnz, hipStream_t s);
+int32_t extract_blocks(const SubDev *d_sub, int nsub, int maxnI, const int32_t *rowptr, const int32_t *colidx,
+                       const double *Bval, const double *Dval, const int32_t *I_idx, const int32_t *G_idx,
+                       const double *winv, double *BIO, double *CII, hipStream_t s);
+int32_t assemble_gamma(const SubDev *d_sub, int nsub, int npe, const int32_t *band_elem, const int32_t *band_loc,
+                       const double *elemK, const double *elemM, double k2, double *BGG, hipStream_t s);
+int32_t gather_gamma_rows(const SubDev *d_sub, int nsub, int maxnI, const double *BIO, double *GI, hipStream_t s);
+template <typename T>
+int32_t apply_pivots_rows(const SubDev *d_sub, int nsub, int maxcol, const int32_t *piv, T *X, int which, hipStream_t s);
+int32_t copy_bii(const SubDev *d_sub, int nsub, int maxnI, const double *BIO, double *out, hipStream_t s);
+int32_t copy_bii_f32(const SubDev *d_sub, int nsub, int maxnI, const double *BIO, float *out, hipStream_t s);
+int32_t check_spd_pivots(const SubDev *d_sub, int nsub, const double *C, int32_t *flag, hipStream_t s);
+int32_t scale_sym(const SubDev *d_sub, int nsub, int maxnI, const double *C, double *S, hipStream_t s);
+
+// ---- eigen.hip: tridiagonalisation, selection, eigenvectors --------------------------------------
+int32_t tridiagonalize_n(const SubDev *d_sub, int nsub, int maxnI, double *Sq, double *d, double *e, double *tau,
+                         hipStream_t s);
+int32_t select_eigs(const SubDev *d_sub, int nsub, const double *d, const double *e, int mode, double tau, int nev,
+                    double rtol, int mmax, int32_t *m_out, double *lam_out, int32_t *flag, hipStream_t s);
+int32_t tridiag_vectors_n(const SubDev *d_sub, int nsub, int maxnI, const double *d, const double *e, const double *lam,
+                          int mmax, double *Z, hipStream_t s);
+int32_t back_transform_n(const SubDev *d_sub, int nsub, int mmax, const double *Sq, const double *tau, double *Z,
+                         hipStream_t s);
+int32_t scale_rows_invsqrt_diag(const SubDev *d_sub, int nsub, const double *C, double *Z, hipStream_t s);
+int32_t finish_basis(const SubDev *d_sub, int nsub, const int32_t *I_idx, const double *winv, double *Z,
+                     hipStream_t s);
+int32_t coarse_pairs(int npairs, const int32_t *pi, const int32_t *pj, const int32_t *ptr, const int32_t *qi,
+                     const int32_t *qj, const SubDev *d_sub, const double *Y, const double *Z, double *B0, int m0,
+                     hipStream_t s);
+
+// ---- apply.hip: one application of the two-level preconditioner ----------------------------------
+struct ApplyPlan {
+    int nsub, maxnI, nrhs, m0, two_level, local_f32, n_dof, max_m;
+    const SubDev *d_sub;
+    const int32_t *I_idx;
+    const double *winv_loc;     // local prolongation weights per concatenated position (1 or 1/mu)
+    const void *Minv;           // local inverses (float or double), nI x nI at offSq
+    const double *Z;
+    const double *B0inv;
+    const int32_t *tp_ptr, *tp_pos;
+    double *u;                  // sum nI x nrhs
+    double *c, *y;              // m0 x nrhs
+    int64_t sum_nI;
+};
+int32_t apply_two_level(const ApplyPlan &p, const double *r, int ldr, double *z, int ldz, hipStream_t s);
+
+// ---- krylov.hip ------------------------------------------------------------------------------------
+int32_t spmv(int n, int nrhs, const int32_t *rowptr, const int32_t *colidx, const double *val, const double *x,
+             int ldx, double *y, int ldy, const double *f, int ldf, hipStream_t s);
+
+struct GmresDev {
+    int n, nrhs, restart, nblk;
+    double *V;          // n x (restart+1) per rhs, column stride n, rhs stride n*(restart+1)
+    double *Zk;         // n x restart per rhs
+    double *H;          // (restart+1) x restart per rhs, column-major
+    double *cs, *sn;    // restart per rhs
+    double *g;          // restart+1 per rhs
+    double *part;       // nblk x (restart+2) partial sums per rhs
+    double *hcol;       // restart+2 per rhs: current column before rotations
+    double *scal;       // 8 per rhs: [beta0, fnorm, |g_{j+1}|, breakdown, ...]
+    int32_t *active;    // per rhs
+};
+int32_t gmres_norm_init(const GmresDev &G, const double *r, int ldr, hipStream_t s);
+int32_t gmres_arnoldi_step(const GmresDev &G, int j, hipStream_t s);
+int32_t gmres_finish_cycle(const GmresDev &G, const int32_t *jd, double *x, int ldx, hipStream_t s);
+int32_t vec_norms(int n, int nrhs, const double *x, int ldx, double *out, double *part, int nblk, hipStream_t s);
+
+}  // namespace hkg

@@ -214,14 +214,17 @@ def coef_cells(centroids: np.ndarray, n_cells: int, seed: int, log10_range=(0.0,
 
 def coef_lognormal(centroids: np.ndarray, seed: int, sigma: float = 1.0, corr_len: float = 0.1,
                    n_features: int = 1024) -> np.ndarray:
-    """a = exp(sigma g), g a unit-variance Gaussian field with covariance exp(-|x-y|^2 / (2 l^2)),
-    approximated by n_features random Fourier features (Rahimi-Recht), evaluated at centroids."""
+    """a = exp(sigma g) / min(exp(sigma g)), g a unit-variance Gaussian field with covariance
+    exp(-|x-y|^2 / (2 l^2)) approximated by n_features random Fourier features (Rahimi-Recht) and
+    evaluated at the element centroids.  Dividing by the minimum over the mesh gives a_min = 1, the
+    normalisation of Assumption 2.1(ii), so that kh keeps its meaning where a is small."""
     rng = np.random.Generator(np.random.PCG64(seed))
     d = centroids.shape[1]
     omega = rng.standard_normal((n_features, d)) / corr_len
     phase = rng.uniform(0.0, 2.0 * np.pi, size=n_features)
     g = np.sqrt(2.0 / n_features) * np.cos(centroids @ omega.T + phase[None, :]).sum(axis=1)
-    return np.exp(sigma * g)
+    a = np.exp(sigma * g)
+    return a / a.min()
 
 
 # ----------------------------------------------------------------------------

@@ -1,0 +1,163 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle on the same seeded inputs.
+
+Tolerances.  The oracle and the library apply the same operator in FP64 with different summation
+orders (and the library applies B_D^{-1}, B_0^{-1} as products with inverses formed from the LU
+factors), so one preconditioner application agrees to a few hundred ulps of cond(B_D) eps; the
+element-wise bar is 1e-10 relative to max|z|.  Eigenvalues agree to 1e-10 relative to the spectral
+radius of the reduced pencil.  Solutions of FP64 FGMRES agree to 1e-8 relative (the Krylov iterates
+are the same up to rounding), iteration counts within 2.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_2406_06283_amd import hkgeneo as H  # noqa: E402
+from paper_2406_06283_amd import problems as pb  # noqa: E402
+from paper_2406_06283_amd.configs import H32_K10, H128_K40  # noqa: E402
+from oracle import fgmres, local, schwarz  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _oracle(p, **kw):
+    return schwarz.TwoLevelSchwarz(p, schwarz.Options(**kw))
+
+
+def _gpu_apply(S, vecs):
+    r = torch.from_numpy(np.ascontiguousarray(vecs)).to(DEV)
+    z = S.apply(r)
+    torch.cuda.synchronize()
+    return z.cpu().numpy()
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+CASES = [
+    ("p1_n16_s4_ov1_k6", dict(N=16, k=6.0, s=4, overlap=1, coef="cells", seed=3, n_cells=4), dict(nev=3)),
+    ("p1_n24_s3_ov2_k9_lognormal", dict(N=24, k=9.0, s=3, overlap=2, coef="lognormal", seed=2), dict(nev=5)),
+    ("p1_n20_s3_uneven", dict(N=20, k=7.0, s=3, overlap=[1, 2, 3, 1, 2, 3, 2, 1, 1], coef="cells", seed=5,
+                              n_cells=5), dict(nev=4)),
+    ("q1_3d_n6_s2", dict(N=6, dim=3, elem_type=pb.Q1, k=4.0, s=2, overlap=1, coef="cells", seed=1, n_cells=3),
+     dict(nev=3)),
+]
+
+
+@pytest.mark.parametrize("name,pkw,okw", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("two_level", [0, 1])
+def test_apply_matches_oracle(name, pkw, okw, two_level):
+    _say(f"[apply] {name} two_level={two_level}")
+    pkw = dict(pkw)
+    N = pkw.pop("N")
+    p = pb.make_problem(N, **pkw)
+    M = _oracle(p, eig_mode=local.EIG_FIXED, two_level=bool(two_level), **okw)
+    rng = np.random.default_rng(11)
+    R = rng.standard_normal((3, p.n_dof))
+    with H.Solver(p, H.default_options(eig_mode=H.HKG_EIG_FIXED, two_level=two_level, **okw)) as S:
+        if two_level:
+            assert S.stats()["m0"] == M.m0
+            assert list(S.subdomains()[2]) == M.m
+        Zg = _gpu_apply(S, R)
+    Zo = np.stack([M.apply(r) for r in R])
+    scale = np.abs(Zo).max()
+    assert np.abs(Zg - Zo).max() <= 1e-10 * scale, np.abs(Zg - Zo).max() / scale
+
+
+@pytest.mark.parametrize("name,pkw,okw", CASES[:3], ids=[c[0] for c in CASES[:3]])
+def test_eigenvalues_and_coarse_space_match_oracle(name, pkw, okw):
+    _say(f"[eigen] {name}")
+    pkw = dict(pkw)
+    N = pkw.pop("N")
+    p = pb.make_problem(N, **pkw)
+    M = _oracle(p, eig_mode=local.EIG_FIXED, **okw)
+    with H.Solver(p, H.default_options(eig_mode=H.HKG_EIG_FIXED, **okw)) as S:
+        nI, nG, m = S.subdomains()
+        for i, s in enumerate(M.subs):
+            assert nI[i] == s.dof.size and nG[i] == s.gamma.size and m[i] == M.m[i]
+            lam, Zi = S.eigen(i)
+            lo = M.eigvals[i][:lam.size]
+            rad = np.abs(M.eigvals[i]).max()
+            assert np.abs(lam - lo).max() <= 1e-10 * rad
+            # the span of the selected vectors is what the method uses: compare X P P^T X projectors
+            Zo = M.Z_local[i]
+            Pg, Po = Zi @ Zi.T, Zo @ Zo.T
+            assert np.abs(Pg - Po).max() <= 1e-8 * np.abs(Po).max()
+        B0 = S.coarse_matrix()
+    # B_0 itself depends on each eigenvector's sign, fixed by the same convention on both sides
+    np.testing.assert_allclose(B0, M.B0, atol=1e-9 * np.abs(M.B0).max())
+
+
+def test_fgmres_h32_k10_matches_oracle():
+    _say("[fgmres] h=1/32 k=10 4x4 nev=10")
+    p = H32_K10.problem()
+    M = _oracle(p, eig_mode=local.EIG_FIXED, nev=10)
+    x, oinfo = fgmres.solve(p, M)
+    with H.Solver(p, H.options_for(H32_K10)) as S:
+        f = torch.from_numpy(p.f).to(DEV)
+        u, info, st = S.solve(f)
+        torch.cuda.synchronize()
+        u = u.cpu().numpy()[0]
+    assert st == H.HKG_OK and info[0]["converged"]
+    assert abs(info[0]["iters"] - oinfo["iters"]) <= 2, (info[0]["iters"], oinfo["iters"])
+    B = M.B
+    assert np.linalg.norm(p.f[0] - B @ u) / np.linalg.norm(p.f[0]) <= 1e-8
+    assert np.linalg.norm(u - x) / np.linalg.norm(x) <= 1e-8
+
+
+def test_fgmres_multi_rhs_equals_single():
+    _say("[fgmres] multi-rhs")
+    p = pb.make_problem(24, k=8.0, s=3, overlap=2, coef="cells", seed=4, n_cells=4, rhs="normal", nrhs=3)
+    opts = H.default_options(eig_mode=H.HKG_EIG_FIXED, nev=4)
+    with H.Solver(p, opts) as S:
+        f = torch.from_numpy(p.f).to(DEV)
+        U, info, _ = S.solve(f)
+        singles = [S.solve(f[r:r + 1].clone())[0] for r in range(3)]
+        torch.cuda.synchronize()
+    for r in range(3):
+        assert info[r]["converged"]
+        np.testing.assert_array_equal(U[r].cpu().numpy(), singles[r][0].cpu().numpy())
+
+
+def test_zero_rhs_and_single_subdomain():
+    _say("[fgmres] zero rhs / one subdomain")
+    p = pb.make_problem(12, k=9.0, s=1, overlap=1, rhs="zero")
+    with H.Solver(p, H.default_options(eig_mode=H.HKG_EIG_FIXED, nev=3)) as S:
+        u, info, st = S.solve(torch.zeros((1, p.n_dof), dtype=torch.float64, device=DEV))
+        assert info[0]["iters"] == 0 and float(u.abs().max()) == 0.0
+        f = torch.from_numpy(pb.make_problem(12, k=9.0, s=1, overlap=1).f).to(DEV)
+        u, info, st = S.solve(f)
+        assert info[0]["iters"] == 2 and info[0]["converged"]     # M^{-1} B has eigenvalues {1, 2}
+
+
+def test_mixed_precision_reaches_fp64_residual():
+    _say("[fgmres] fp32 local solves, h=1/32")
+    p = H32_K10.problem()
+    with H.Solver(p, H.options_for(H32_K10)) as S64, H.Solver(p, H.options_for(H32_K10, local_prec=32)) as S32:
+        f = torch.from_numpy(p.f).to(DEV)
+        u64, i64, _ = S64.solve(f)
+        u32, i32, st = S32.solve(f)
+        torch.cuda.synchronize()
+    assert st == H.HKG_OK and i32[0]["converged"] and i32[0]["relres_true"] <= 1e-8
+    assert abs(i32[0]["iters"] - i64[0]["iters"]) <= 2
+
+
+@pytest.mark.slow
+def test_fgmres_h128_k40_matches_oracle():
+    _say("[fgmres] h=1/128 k=40 8x8 tau")
+    p = H128_K40.problem()
+    M = _oracle(p, eig_mode=local.EIG_THRESHOLD, tau=H128_K40.tau)
+    x, oinfo = fgmres.solve(p, M)
+    with H.Solver(p, H.options_for(H128_K40)) as S:
+        assert list(S.subdomains()[2]) == M.m and S.stats()["m0"] == M.m0
+        f = torch.from_numpy(p.f).to(DEV)
+        u, info, st = S.solve(f)
+        torch.cuda.synchronize()
+        u = u.cpu().numpy()[0]
+    assert st == H.HKG_OK
+    assert abs(info[0]["iters"] - oinfo["iters"]) <= 2, (info[0]["iters"], oinfo["iters"])
+    assert np.linalg.norm(p.f[0] - M.B @ u) / np.linalg.norm(p.f[0]) <= 1e-8
+    assert np.linalg.norm(u - x) / np.linalg.norm(x) <= 1e-8

@@ -105,6 +105,9 @@ typedef struct {
  *   two_level            1 (default): add the coarse correction; 0: one-level only
  *   restart, max_iter, rtol   FGMRES(restart) stopping at ||f - B u|| <= rtol ||f||
  *                        (defaults 50, 1000, 1e-8)
+ *   keep_workspace       0 (default): free the factorisation workspace (dense local blocks, Schur
+ *                        complements, eigen work arrays) when setup/factor returns; 1: keep it for
+ *                        the next hkgeneo_factor (no allocation on refactorisation)
  */
 typedef struct {
     int32_t eig_mode;
@@ -118,6 +121,7 @@ typedef struct {
     int32_t restart;
     int32_t max_iter;
     double rtol;
+    int32_t keep_workspace;
 } hkgeneo_options;
 
 /* per right-hand side outcome of hkgeneo_gmres_solve (host array of nrhs entries) */
@@ -155,6 +159,15 @@ int32_t hkgeneo_setup(const hkgeneo_problem *prob, const hkgeneo_options *opt, v
                       hkgeneo_ctx **out);
 
 /*
+ * Recompute every numeric part of the preconditioner (the local blocks, local eigenproblems, coarse
+ * space, coarse and local factors) on the device from the inputs that hkgeneo_setup made resident;
+ * the host partition and the index sets are reused.  Synchronous; statuses as for hkgeneo_setup.
+ * Separates the numeric factorisation from the host analysis, so that it can be timed and repeated
+ * with its inputs in device memory.
+ */
+int32_t hkgeneo_factor(hkgeneo_ctx *ctx, void *stream);
+
+/*
  * z = M^{-1} r (eq. (2.23)) for nrhs columns.  r and z are device arrays n_dof x nrhs (ld >= n_dof),
  * must not alias.  Asynchronous on `stream`; HIP errors surface on the next synchronous call.
  * Errors: HKG_EINVAL for a NULL pointer, nrhs < 1 or ld < n_dof.
@@ -174,6 +187,17 @@ int32_t hkgeneo_gmres_solve(hkgeneo_ctx *ctx, const double *f, double *u, int32_
 /* w = B x for nrhs columns (device arrays, ld >= n_dof).  Asynchronous. */
 int32_t hkgeneo_matvec(hkgeneo_ctx *ctx, const double *x, double *w, int32_t nrhs, int32_t ld,
                        void *stream);
+
+/*
+ * Measurement hook.  enable = 1 starts recording HIP events around every launch of the local-solve
+ * kernel (gather + product with the local inverses, the kernel that dominates one application) on
+ * the stream it is launched on, and clears earlier records; 0 stops recording.
+ */
+int32_t hkgeneo_profile(hkgeneo_ctx *ctx, int32_t enable);
+
+/* Sum of the recorded local-solve kernel durations (ms) and the number of launches recorded;
+ * waits for the recorded events. */
+int32_t hkgeneo_profile_read(hkgeneo_ctx *ctx, double *total_ms, int64_t *launches);
 
 /* Scalar summary of a context. */
 int32_t hkgeneo_query(const hkgeneo_ctx *ctx, hkgeneo_stats *out);

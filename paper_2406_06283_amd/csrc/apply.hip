@@ -151,6 +151,7 @@ __global__ __launch_bounds__(256) void k_sum_local(int n, const int32_t *__restr
 int32_t apply_two_level(const ApplyPlan &p, const double *r, int ldr, double *z, int ldz, hipStream_t s) {
     const int tiles = (p.maxnI + LS_ROWS - 1) / LS_ROWS;
     const int64_t ldu = p.sum_nI;
+    if (p.ev0) HKG_HIP(hipEventRecord(p.ev0, s));
     if (p.local_f32) {
         size_t shm = ((p.maxnI * sizeof(float) + 7) / 8) * 8 + LS_ROWS * LS_WAVES * sizeof(double);
         hipLaunchKernelGGL(k_local_solve<float>, dim3(tiles, p.nsub, p.nrhs), dim3(LS_ROWS * LS_WAVES), shm, s, p.d_sub,
@@ -161,6 +162,7 @@ int32_t apply_two_level(const ApplyPlan &p, const double *r, int ldr, double *z,
                            p.d_sub, p.I_idx, p.winv_loc, (const double *)p.Minv, r, ldr, p.u, ldu);
     }
     HKG_HIP(hipGetLastError());
+    if (p.ev1) HKG_HIP(hipEventRecord(p.ev1, s));
     if (p.two_level && p.m0 > 0) {
         hipLaunchKernelGGL(k_restrict, dim3(p.nsub, p.nrhs), dim3(256), (size_t)p.maxnI * sizeof(double), s, p.d_sub,
                            p.I_idx, p.Z, r, ldr, p.c, p.m0);

@@ -1,0 +1,68 @@
+// The context behind the opaque hkgeneo_ctx handle, and device-buffer helpers of the host driver.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+#include "kernels.hpp"
+
+struct hkgeneo_ctx {
+    hkgeneo_options opt{};
+    int n_dof = 0, nnz = 0, n_sub = 0, m0 = 0, max_nI = 0, max_nG = 0, max_m = 0, npe = 0, dim = 2;
+    int64_t sum_nI = 0, nBIO = 0, nSq = 0, nGG = 0, nGI = 0, nPiv = 0;
+    double k = 0.0;
+    hkg::Partition P;
+    hkg::CoarsePairs CP;
+    std::vector<hkg::SubDev> subs;        // host copy of the per-subdomain descriptors
+    std::vector<int32_t> m_host;
+    std::vector<double> lam_host;         // n_sub x (max_eig_per_sub + 2)
+    std::vector<double> B0_host;          // kept for queries when m0 is small
+    int64_t device_bytes = 0;
+
+    // resident inputs and static descriptors (analysis phase)
+    hkg::DevBuf rowptr, colidx, Aval, Sval, I_idx, G_idx, winv, wloc, tp_ptr, tp_pos, subs_d;
+    hkg::DevBuf bandK, bandM, bandLoc, pairs;
+    hkg::DevBuf matsGG, matsSq, poffSub, jobsGI, jobsSq, gjobsSchur, matsLoc, poffLoc, jobsLoc;
+    // numeric results (factorisation phase)
+    hkg::DevBuf Bval, Minv, Z, B0inv;
+    // factorisation workspace (kept between calls when opt.keep_workspace, freed otherwise)
+    hkg::DevBuf wDk, wBIO, wCII, wGG, wGI, wS, wW, wPiv, wInfo, wFlag, wD, wE, wTau, wM, wLam, wY, wB0, wLU, wPivL,
+        wJobsZ, wGjobsY, wMisc, wPiv0;
+    // apply workspace
+    hkg::DevBuf u, c, y;
+    int ws_nrhs = 0;
+    // gmres workspace
+    hkg::DevBuf V, Zk, H, cs, sn, g, part, hcol, scal, active, want, rnorm, npart, fnorm;
+    int gm_nrhs = 0;
+    // measurement hook: events around the local-solve kernel
+    bool prof = false;
+    std::vector<hipEvent_t> ev;
+    size_t ev_used = 0;
+    hkgeneo_stats stats{};
+};
+
+namespace hkg {
+
+int32_t dalloc(hkgeneo_ctx *c, DevBuf *b, size_t bytes);           // fresh allocation
+int32_t walloc(hkgeneo_ctx *c, DevBuf *b, size_t bytes);           // reuse if large enough
+void drelease(hkgeneo_ctx *c, DevBuf *b);
+int32_t upload_bytes(hkgeneo_ctx *c, DevBuf *b, const void *host, size_t bytes, hipStream_t s, bool reuse);
+
+template <typename T>
+int32_t upload(hkgeneo_ctx *c, DevBuf *b, const T *host, size_t count, hipStream_t s, bool reuse = false) {
+    return upload_bytes(c, b, host, count * sizeof(T), s, reuse);
+}
+
+template <typename T>
+T *dp(const DevBuf &b) {
+    return reinterpret_cast<T *>(b.p);
+}
+
+int32_t analyze(hkgeneo_ctx *c, const hkgeneo_problem *p, hipStream_t s, int32_t *bad);
+int32_t factor(hkgeneo_ctx *c, hipStream_t s);
+void free_workspace(hkgeneo_ctx *c);
+
+}  // namespace hkg

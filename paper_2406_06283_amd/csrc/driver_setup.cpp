@@ -1,0 +1,409 @@
+// Host driver of the setup: analysis (host partition and resident inputs) and factorisation (every
+// numeric step, on the device, from the resident inputs).
+//
+// Factorisation, per subdomain D_i (batched over subdomains with uneven sizes):
+//   B = A - k^2 S, D_k = A + k^2 S on the CSR pattern                               (Sec. 2.1)
+//   [B_II | B_IG] and C_II = X D_k[I,I] X from the CSR rows of dof(D_i)        (eq. 2.22, Def. 2.14)
+//   B~_GG from the elements of D_i carrying Gamma dofs                               (eq. 2.18)
+//   S = B_II - B_IG B~_GG^{-1} B_GI,  C_II = L U (no exchanges),  S^ = L^-1 S L^-T    (Lemma 2.6)
+//   tridiagonalise S^, select m_i (Def. 2.15), eigenvectors, back-transform, Z_i = X_I P_i
+//   B_0 = Z^T B Z over neighbouring pairs, B_0 = P L U, B_0^{-1}                     (eq. 2.23)
+//   B_D = P L U and B_D^{-1} in float64 or float32                                     (eq. 2.22)
+#include <algorithm>
+#include <cstring>
+
+#include "ctx.hpp"
+
+namespace hkg {
+
+int32_t dalloc(hkgeneo_ctx *c, DevBuf *b, size_t bytes) {
+    drelease(c, b);
+    if (bytes == 0) bytes = 8;
+    hipError_t e = hipMalloc(&b->p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        b->p = nullptr;
+        set_last_error("hipMalloc of " + std::to_string(bytes) + " bytes failed");
+        return HKG_ENOMEM;
+    }
+    b->bytes = bytes;
+    c->device_bytes += (int64_t)bytes;
+    return HKG_OK;
+}
+
+int32_t walloc(hkgeneo_ctx *c, DevBuf *b, size_t bytes) {
+    if (b->p && b->bytes >= bytes && bytes > 0) return HKG_OK;
+    return dalloc(c, b, bytes);
+}
+
+void drelease(hkgeneo_ctx *c, DevBuf *b) {
+    if (b->p) {
+        (void)hipFree(b->p);
+        c->device_bytes -= (int64_t)b->bytes;
+    }
+    b->p = nullptr;
+    b->bytes = 0;
+}
+
+// host -> device copy that has completed when it returns (the host source may be a temporary)
+int32_t upload_bytes(hkgeneo_ctx *c, DevBuf *b, const void *host, size_t bytes, hipStream_t s, bool reuse) {
+    HKG_TRY(reuse ? walloc(c, b, bytes) : dalloc(c, b, bytes));
+    if (bytes) {
+        HKG_HIP(hipMemcpyAsync(b->p, host, bytes, hipMemcpyHostToDevice, s));
+        HKG_HIP(hipStreamSynchronize(s));
+    }
+    return HKG_OK;
+}
+
+void free_workspace(hkgeneo_ctx *c) {
+    DevBuf *w[] = {&c->wDk, &c->wBIO, &c->wCII, &c->wGG, &c->wGI, &c->wS, &c->wW, &c->wPiv, &c->wInfo,
+                   &c->wFlag, &c->wD, &c->wE, &c->wTau, &c->wM, &c->wLam, &c->wY, &c->wB0, &c->wLU,
+                   &c->wPivL, &c->wJobsZ, &c->wGjobsY, &c->wMisc, &c->wPiv0};
+    for (DevBuf *b : w) drelease(c, b);
+}
+
+// ------------------------------------------------------------------------------------------------
+// analysis: partition, layout, resident inputs, descriptors that depend on the partition only
+// ------------------------------------------------------------------------------------------------
+int32_t analyze(hkgeneo_ctx *c, const hkgeneo_problem *p, hipStream_t s, int32_t *bad) {
+    HKG_TRY(build_partition(p, &c->P, bad));
+    c->npe = c->P.npe;
+    const Partition &P = c->P;
+    const int ns = c->n_sub;
+    c->subs.resize(ns);
+    int64_t oBIO = 0, oSq = 0, oGG = 0, oGI = 0, oPiv = 0;
+    for (int i = 0; i < ns; ++i) {
+        SubDev &sd = c->subs[i];
+        sd = SubDev{};
+        sd.nI = P.nI[i];
+        sd.nG = P.nG[i];
+        sd.offI = P.offI[i];
+        sd.offG = P.offG[i];
+        sd.offBIO = oBIO;
+        sd.offSq = oSq;
+        sd.offGG = oGG;
+        sd.offGI = oGI;
+        sd.offPiv = oPiv;
+        sd.bandBeg = P.band_ptr[i];
+        sd.bandEnd = P.band_ptr[i + 1];
+        oBIO += (int64_t)sd.nI * (sd.nI + sd.nG);
+        oSq += (int64_t)sd.nI * sd.nI;
+        oGG += (int64_t)sd.nG * sd.nG;
+        oGI += (int64_t)sd.nG * sd.nI;
+        oPiv += std::max(sd.nI, sd.nG);
+        c->max_nI = std::max(c->max_nI, sd.nI);
+        c->max_nG = std::max(c->max_nG, sd.nG);
+    }
+    c->nBIO = oBIO;
+    c->nSq = oSq;
+    c->nGG = oGG;
+    c->nGI = oGI;
+    c->nPiv = oPiv;
+    c->sum_nI = P.offI[ns];
+    // 1/mu from the multiplicities; local prolongation weights (1, or 1/mu for the weighted variant)
+    std::vector<double> winv(c->n_dof), wloc(c->sum_nI);
+    for (int d = 0; d < c->n_dof; ++d) winv[d] = 1.0 / (double)P.mu[d];
+    for (int64_t t = 0; t < c->sum_nI; ++t) wloc[t] = (c->opt.prolong == HKG_PROLONG_POU) ? winv[P.I_idx[t]] : 1.0;
+    HKG_TRY(upload(c, &c->rowptr, p->row_ptr, c->n_dof + 1, s));
+    HKG_TRY(upload(c, &c->colidx, p->col_idx, c->nnz, s));
+    HKG_TRY(upload(c, &c->Aval, p->A_val, c->nnz, s));
+    HKG_TRY(upload(c, &c->Sval, p->S_val, c->nnz, s));
+    HKG_TRY(upload(c, &c->I_idx, P.I_idx.data(), P.I_idx.size(), s));
+    if (P.G_idx.empty()) HKG_TRY(dalloc(c, &c->G_idx, sizeof(int32_t)));
+    else HKG_TRY(upload(c, &c->G_idx, P.G_idx.data(), P.G_idx.size(), s));
+    HKG_TRY(upload(c, &c->winv, winv.data(), winv.size(), s));
+    HKG_TRY(upload(c, &c->wloc, wloc.data(), wloc.size(), s));
+    HKG_TRY(upload(c, &c->tp_ptr, P.tp_ptr.data(), P.tp_ptr.size(), s));
+    HKG_TRY(upload(c, &c->tp_pos, P.tp_pos.data(), P.tp_pos.size(), s));
+    HKG_TRY(upload(c, &c->subs_d, c->subs.data(), ns, s));
+
+    // element matrices of the band elements (the elements of each D_i carrying Gamma dofs)
+    const int npe2 = c->npe * c->npe;
+    const size_t nb = P.band_elem.size();
+    {
+        std::vector<double> hk(std::max<size_t>(nb * npe2, 1)), hm(std::max<size_t>(nb * npe2, 1));
+        for (size_t b = 0; b < nb; ++b) {
+            std::memcpy(&hk[b * npe2], p->elem_K + (size_t)P.band_elem[b] * npe2, npe2 * sizeof(double));
+            std::memcpy(&hm[b * npe2], p->elem_M + (size_t)P.band_elem[b] * npe2, npe2 * sizeof(double));
+        }
+        HKG_TRY(upload(c, &c->bandK, hk.data(), hk.size(), s));
+        HKG_TRY(upload(c, &c->bandM, hm.data(), hm.size(), s));
+        std::vector<int32_t> bl(P.band_loc);
+        if (bl.empty()) bl.push_back(-1);
+        HKG_TRY(upload(c, &c->bandLoc, bl.data(), bl.size(), s));
+    }
+
+    // descriptors for the batched dense kernels
+    std::vector<DMat> hGG(ns), hSq(ns);
+    std::vector<int64_t> hpo(ns), hpl(ns);
+    std::vector<TriJob> jGI(ns), jSq(ns);
+    std::vector<GemmJob> gS(ns);
+    int64_t pl = 0;
+    for (int i = 0; i < ns; ++i) {
+        const SubDev &sd = c->subs[i];
+        const int ldG = std::max(sd.nG, 1);
+        hGG[i] = {sd.offGG, sd.nG, ldG};
+        hSq[i] = {sd.offSq, sd.nI, sd.nI};
+        hpo[i] = sd.offPiv;
+        hpl[i] = pl;
+        pl += sd.nI;
+        jGI[i] = {sd.offGG, sd.offGI, sd.nG, ldG, sd.nI, ldG};
+        jSq[i] = {sd.offSq, sd.offSq, sd.nI, sd.nI, sd.nI, sd.nI};
+        gS[i] = {sd.offBIO + (int64_t)sd.nI * sd.nI, sd.offGI, sd.offSq, sd.nI, sd.nI, sd.nG, sd.nI, ldG, sd.nI};
+    }
+    HKG_TRY(upload(c, &c->matsGG, hGG.data(), ns, s));
+    HKG_TRY(upload(c, &c->matsSq, hSq.data(), ns, s));
+    HKG_TRY(upload(c, &c->poffSub, hpo.data(), ns, s));
+    HKG_TRY(upload(c, &c->poffLoc, hpl.data(), ns, s));
+    HKG_TRY(upload(c, &c->jobsGI, jGI.data(), ns, s));
+    HKG_TRY(upload(c, &c->jobsSq, jSq.data(), ns, s));
+    HKG_TRY(upload(c, &c->gjobsSchur, gS.data(), ns, s));
+
+    // neighbouring pairs of the coarse matrix
+    build_coarse_pairs(P, &c->CP);
+    {
+        const CoarsePairs &CP = c->CP;
+        std::vector<int32_t> packed;
+        packed.insert(packed.end(), CP.pi.begin(), CP.pi.end());
+        packed.insert(packed.end(), CP.pj.begin(), CP.pj.end());
+        packed.insert(packed.end(), CP.ptr.begin(), CP.ptr.end());
+        packed.insert(packed.end(), CP.qi.begin(), CP.qi.end());
+        packed.insert(packed.end(), CP.qj.begin(), CP.qj.end());
+        HKG_TRY(upload(c, &c->pairs, packed.data(), packed.size(), s));
+    }
+    return HKG_OK;
+}
+
+// ------------------------------------------------------------------------------------------------
+// factorisation
+// ------------------------------------------------------------------------------------------------
+namespace {
+
+int32_t read_flags(hkgeneo_ctx *c, const DevBuf &buf, int n, std::vector<int32_t> *out, hipStream_t s) {
+    out->assign(n, 0);
+    HKG_HIP(hipMemcpyAsync(out->data(), buf.p, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HKG_HIP(hipStreamSynchronize(s));
+    (void)c;
+    return HKG_OK;
+}
+
+template <typename T>
+int32_t local_inverses(hkgeneo_ctx *c, hipStream_t s) {
+    const int ns = c->n_sub;
+    const SubDev *dsub = dp<SubDev>(c->subs_d);
+    HKG_TRY(walloc(c, &c->wLU, c->nSq * sizeof(T)));
+    if (c->Minv.bytes != (size_t)c->nSq * sizeof(T)) HKG_TRY(dalloc(c, &c->Minv, c->nSq * sizeof(T)));
+    HKG_TRY(walloc(c, &c->wPivL, c->sum_nI * sizeof(int32_t)));
+    HKG_TRY(walloc(c, &c->wInfo, ns * sizeof(int32_t)));
+    if (sizeof(T) == 8) HKG_TRY(copy_bii(dsub, ns, c->max_nI, dp<double>(c->wBIO), (double *)c->wLU.p, s));
+    else HKG_TRY(copy_bii_f32(dsub, ns, c->max_nI, dp<double>(c->wBIO), (float *)c->wLU.p, s));
+    HKG_TRY(lu_batched<T>(dp<DMat>(c->matsSq), dp<int64_t>(c->poffLoc), ns, c->max_nI, dp<T>(c->wLU),
+                          dp<int32_t>(c->wPivL), dp<int32_t>(c->wInfo), true, s));
+    std::vector<int32_t> info;
+    HKG_TRY(read_flags(c, c->wInfo, ns, &info, s));
+    for (int i = 0; i < ns; ++i)
+        if (info[i]) {
+            set_last_error("zero pivot in the local Dirichlet matrix of subdomain " + std::to_string(i));
+            return HKG_ESINGULAR_LOCAL;
+        }
+    // B_D^{-1} = U^{-1} L^{-1} P
+    HKG_TRY(perm_identity_batched<T>(dp<DMat>(c->matsSq), dp<int64_t>(c->poffLoc), ns, c->max_nI,
+                                     dp<int32_t>(c->wPivL), dp<T>(c->Minv), s));
+    HKG_TRY(tri_solve_batched<T>(dp<TriJob>(c->jobsSq), ns, c->max_nI, c->max_nI, dp<T>(c->wLU), dp<T>(c->Minv),
+                                 TRI_LOWER_UNIT, s));
+    HKG_TRY(tri_solve_batched<T>(dp<TriJob>(c->jobsSq), ns, c->max_nI, c->max_nI, dp<T>(c->wLU), dp<T>(c->Minv),
+                                 TRI_UPPER, s));
+    return HKG_OK;
+}
+
+int32_t coarse_space(hkgeneo_ctx *c, hipStream_t s) {
+    const int ns = c->n_sub;
+    const hkgeneo_options &o = c->opt;
+    const int mmax = o.max_eig_per_sub;
+    const SubDev *dsub = dp<SubDev>(c->subs_d);
+    const double k2 = c->k * c->k;
+    HKG_TRY(walloc(c, &c->wGG, std::max<int64_t>(c->nGG, 1) * sizeof(double)));
+    HKG_TRY(walloc(c, &c->wGI, std::max<int64_t>(c->nGI, 1) * sizeof(double)));
+    HKG_TRY(walloc(c, &c->wS, c->nSq * sizeof(double)));
+    HKG_TRY(walloc(c, &c->wW, c->nSq * sizeof(double)));
+    HKG_TRY(walloc(c, &c->wPiv, c->nPiv * sizeof(int32_t)));
+    HKG_TRY(walloc(c, &c->wInfo, ns * sizeof(int32_t)));
+    HKG_TRY(walloc(c, &c->wFlag, ns * sizeof(int32_t)));
+    // B~_GG and its LU
+    HKG_HIP(hipMemsetAsync(c->wGG.p, 0, c->wGG.bytes, s));
+    HKG_TRY(assemble_gamma(dsub, ns, c->npe, nullptr, dp<int32_t>(c->bandLoc), dp<double>(c->bandK),
+                           dp<double>(c->bandM), k2, dp<double>(c->wGG), s));
+    HKG_TRY(lu_batched<double>(dp<DMat>(c->matsGG), dp<int64_t>(c->poffSub), ns, c->max_nG, dp<double>(c->wGG),
+                               dp<int32_t>(c->wPiv), dp<int32_t>(c->wInfo), true, s));
+    std::vector<int32_t> flags;
+    HKG_TRY(read_flags(c, c->wInfo, ns, &flags, s));
+    for (int i = 0; i < ns; ++i)
+        if (flags[i]) {
+            set_last_error("the Gamma block of the local Neumann matrix is singular in subdomain " + std::to_string(i));
+            return HKG_EEIG;
+        }
+    // X = B~_GG^{-1} B_GI ; S = B_II - B_IG X
+    HKG_TRY(gather_gamma_rows(dsub, ns, c->max_nI, dp<double>(c->wBIO), dp<double>(c->wGI), s));
+    HKG_TRY(apply_pivots_rows<double>(dsub, ns, c->max_nI, dp<int32_t>(c->wPiv), dp<double>(c->wGI), 0, s));
+    HKG_TRY(tri_solve_batched<double>(dp<TriJob>(c->jobsGI), ns, c->max_nG, c->max_nI, dp<double>(c->wGG),
+                                      dp<double>(c->wGI), TRI_LOWER_UNIT, s));
+    HKG_TRY(tri_solve_batched<double>(dp<TriJob>(c->jobsGI), ns, c->max_nG, c->max_nI, dp<double>(c->wGG),
+                                      dp<double>(c->wGI), TRI_UPPER, s));
+    HKG_TRY(copy_bii(dsub, ns, c->max_nI, dp<double>(c->wBIO), dp<double>(c->wS), s));
+    HKG_TRY(gemm_batched<double>(dp<GemmJob>(c->gjobsSchur), ns, c->max_nI, c->max_nI, dp<double>(c->wBIO),
+                                 dp<double>(c->wGI), dp<double>(c->wS), -1.0, 1.0, false, false, s));
+    // C_II = L U without exchanges (positive pivots <=> SPD); S^ = D^{-1/2} L^{-1} S L^{-T} D^{-1/2}
+    HKG_TRY(lu_batched<double>(dp<DMat>(c->matsSq), dp<int64_t>(c->poffSub), ns, c->max_nI, dp<double>(c->wCII),
+                               dp<int32_t>(c->wPiv), dp<int32_t>(c->wInfo), false, s));
+    HKG_TRY(check_spd_pivots(dsub, ns, dp<double>(c->wCII), dp<int32_t>(c->wFlag), s));
+    HKG_TRY(read_flags(c, c->wFlag, ns, &flags, s));
+    for (int i = 0; i < ns; ++i)
+        if (flags[i]) {
+            set_last_error("C_II is not positive definite in subdomain " + std::to_string(i));
+            return HKG_EEIG;
+        }
+    HKG_TRY(tri_solve_batched<double>(dp<TriJob>(c->jobsSq), ns, c->max_nI, c->max_nI, dp<double>(c->wCII),
+                                      dp<double>(c->wS), TRI_LOWER_UNIT, s));
+    HKG_TRY(transpose_batched<double>(dp<DMat>(c->matsSq), ns, c->max_nI, dp<double>(c->wS), dp<double>(c->wW), s));
+    HKG_TRY(tri_solve_batched<double>(dp<TriJob>(c->jobsSq), ns, c->max_nI, c->max_nI, dp<double>(c->wCII),
+                                      dp<double>(c->wW), TRI_LOWER_UNIT, s));
+    HKG_TRY(scale_sym(dsub, ns, c->max_nI, dp<double>(c->wCII), dp<double>(c->wW), s));
+    // tridiagonal form and selection
+    HKG_TRY(walloc(c, &c->wD, c->sum_nI * sizeof(double)));
+    HKG_TRY(walloc(c, &c->wE, c->sum_nI * sizeof(double)));
+    HKG_TRY(walloc(c, &c->wTau, c->sum_nI * sizeof(double)));
+    HKG_TRY(tridiagonalize_n(dsub, ns, c->max_nI, dp<double>(c->wW), dp<double>(c->wD), dp<double>(c->wE),
+                             dp<double>(c->wTau), s));
+    HKG_TRY(walloc(c, &c->wM, ns * sizeof(int32_t)));
+    HKG_TRY(walloc(c, &c->wLam, (size_t)ns * (mmax + 2) * sizeof(double)));
+    HKG_TRY(select_eigs(dsub, ns, dp<double>(c->wD), dp<double>(c->wE), o.eig_mode, o.tau, o.nev, o.cluster_rtol, mmax,
+                        dp<int32_t>(c->wM), dp<double>(c->wLam), dp<int32_t>(c->wFlag), s));
+    c->m_host.assign(ns, 0);
+    c->lam_host.assign((size_t)ns * (mmax + 2), 0.0);
+    HKG_HIP(hipMemcpyAsync(c->m_host.data(), c->wM.p, ns * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HKG_HIP(hipMemcpyAsync(c->lam_host.data(), c->wLam.p, c->lam_host.size() * sizeof(double), hipMemcpyDeviceToHost,
+                           s));
+    HKG_TRY(read_flags(c, c->wFlag, ns, &flags, s));
+    for (int i = 0; i < ns; ++i)
+        if (flags[i]) {
+            set_last_error("subdomain " + std::to_string(i) + " needs " + std::to_string(c->m_host[i]) +
+                           " eigenvectors, more than max_eig_per_sub");
+            return HKG_EEIG;
+        }
+    // coarse layout
+    int64_t offZ = 0, offY = 0;
+    int offm = 0;
+    c->max_m = 0;
+    for (int i = 0; i < ns; ++i) {
+        SubDev &sd = c->subs[i];
+        sd.m = c->m_host[i];
+        sd.offm = offm;
+        sd.offZ = offZ;
+        sd.offY = offY;
+        offm += sd.m;
+        offZ += (int64_t)sd.nI * sd.m;
+        offY += (int64_t)sd.m * (sd.nI + sd.nG);
+        c->max_m = std::max(c->max_m, sd.m);
+    }
+    c->m0 = offm;
+    if (c->m0 > 7000) {
+        set_last_error("coarse dimension " + std::to_string(c->m0) + " exceeds the supported 7000");
+        return HKG_EINVAL;
+    }
+    HKG_HIP(hipMemcpyAsync(c->subs_d.p, c->subs.data(), ns * sizeof(SubDev), hipMemcpyHostToDevice, s));
+    HKG_HIP(hipStreamSynchronize(s));
+    if (c->m0 == 0) return HKG_OK;
+    // eigenvectors -> coarse basis Z_i = X_I P_i
+    if (c->Z.bytes != (size_t)offZ * sizeof(double)) HKG_TRY(dalloc(c, &c->Z, offZ * sizeof(double)));
+    HKG_TRY(tridiag_vectors_n(dsub, ns, c->max_nI, dp<double>(c->wD), dp<double>(c->wE), dp<double>(c->wLam), mmax,
+                              dp<double>(c->Z), s));
+    HKG_TRY(back_transform_n(dsub, ns, mmax, dp<double>(c->wW), dp<double>(c->wTau), dp<double>(c->Z), s));
+    HKG_TRY(scale_rows_invsqrt_diag(dsub, ns, dp<double>(c->wCII), dp<double>(c->Z), s));
+    {
+        std::vector<TriJob> hj(ns);
+        std::vector<GemmJob> hg(ns);
+        int maxN = 0;
+        for (int i = 0; i < ns; ++i) {
+            const SubDev &sd = c->subs[i];
+            hj[i] = {sd.offSq, sd.offZ, sd.nI, sd.nI, sd.m, sd.nI};
+            hg[i] = {sd.offZ, sd.offBIO, sd.offY, sd.m, sd.nI + sd.nG, sd.nI, sd.nI, sd.nI, std::max(sd.m, 1)};
+            maxN = std::max(maxN, sd.nI + sd.nG);
+        }
+        HKG_TRY(upload(c, &c->wJobsZ, hj.data(), ns, s, true));
+        HKG_TRY(upload(c, &c->wGjobsY, hg.data(), ns, s, true));
+        HKG_TRY(tri_solve_batched<double>(dp<TriJob>(c->wJobsZ), ns, c->max_nI, c->max_m, dp<double>(c->wCII),
+                                          dp<double>(c->Z), TRI_LOWER_UNIT_TRANS, s));
+        HKG_TRY(finish_basis(dsub, ns, dp<int32_t>(c->I_idx), dp<double>(c->winv), dp<double>(c->Z), s));
+        // Y_i = Z_i^T [B_II | B_IG]
+        HKG_TRY(walloc(c, &c->wY, std::max<int64_t>(offY, 1) * sizeof(double)));
+        HKG_TRY(gemm_batched<double>(dp<GemmJob>(c->wGjobsY), ns, c->max_m, maxN, dp<double>(c->Z), dp<double>(c->wBIO),
+                                     dp<double>(c->wY), 1.0, 0.0, true, false, s));
+    }
+    // B_0 blocks over neighbouring pairs
+    const CoarsePairs &CP = c->CP;
+    const int npairs = (int)CP.pi.size();
+    const int32_t *pp = dp<int32_t>(c->pairs);
+    const int m0 = c->m0;
+    HKG_TRY(walloc(c, &c->wB0, (size_t)m0 * m0 * sizeof(double)));
+    HKG_HIP(hipMemsetAsync(c->wB0.p, 0, (size_t)m0 * m0 * sizeof(double), s));
+    HKG_TRY(coarse_pairs(npairs, pp, pp + npairs, pp + 2 * npairs, pp + 3 * npairs + 1,
+                         pp + 3 * npairs + 1 + CP.qi.size(), dsub, dp<double>(c->wY), dp<double>(c->Z),
+                         dp<double>(c->wB0), m0, s));
+    if ((int64_t)m0 * m0 <= (int64_t)2048 * 2048) {
+        c->B0_host.resize((size_t)m0 * m0);
+        HKG_HIP(hipMemcpyAsync(c->B0_host.data(), c->wB0.p, c->B0_host.size() * sizeof(double), hipMemcpyDeviceToHost,
+                               s));
+    } else {
+        c->B0_host.clear();
+    }
+    // B_0 = P L U and B_0^{-1}
+    DMat hm{0, m0, m0};
+    int64_t hp0 = 0;
+    TriJob tj{0, 0, m0, m0, m0, m0};
+    uint8_t blob[sizeof(DMat) + sizeof(int64_t) + sizeof(TriJob)];
+    std::memcpy(blob, &hm, sizeof(DMat));
+    std::memcpy(blob + sizeof(DMat), &hp0, sizeof(int64_t));
+    std::memcpy(blob + sizeof(DMat) + sizeof(int64_t), &tj, sizeof(TriJob));
+    HKG_TRY(upload_bytes(c, &c->wMisc, blob, sizeof(blob), s, true));
+    const DMat *dm = reinterpret_cast<const DMat *>(c->wMisc.p);
+    const int64_t *dpo = reinterpret_cast<const int64_t *>((uint8_t *)c->wMisc.p + sizeof(DMat));
+    const TriJob *dj = reinterpret_cast<const TriJob *>((uint8_t *)c->wMisc.p + sizeof(DMat) + sizeof(int64_t));
+    HKG_TRY(walloc(c, &c->wPiv0, m0 * sizeof(int32_t)));
+    HKG_TRY(lu_batched<double>(dm, dpo, 1, m0, dp<double>(c->wB0), dp<int32_t>(c->wPiv0), dp<int32_t>(c->wInfo), true,
+                               s));
+    HKG_TRY(read_flags(c, c->wInfo, 1, &flags, s));
+    if (flags[0]) {
+        set_last_error("zero pivot in the coarse matrix B_0");
+        return HKG_ESINGULAR_COARSE;
+    }
+    if (c->B0inv.bytes != (size_t)m0 * m0 * sizeof(double)) HKG_TRY(dalloc(c, &c->B0inv, (size_t)m0 * m0 * sizeof(double)));
+    HKG_TRY(perm_identity_batched<double>(dm, dpo, 1, m0, dp<int32_t>(c->wPiv0), dp<double>(c->B0inv), s));
+    HKG_TRY(tri_solve_batched<double>(dj, 1, m0, m0, dp<double>(c->wB0), dp<double>(c->B0inv), TRI_LOWER_UNIT, s));
+    HKG_TRY(tri_solve_batched<double>(dj, 1, m0, m0, dp<double>(c->wB0), dp<double>(c->B0inv), TRI_UPPER, s));
+    return HKG_OK;
+}
+
+}  // namespace
+
+int32_t factor(hkgeneo_ctx *c, hipStream_t s) {
+    const int ns = c->n_sub;
+    const SubDev *dsub = dp<SubDev>(c->subs_d);
+    HKG_TRY(walloc(c, &c->wDk, c->nnz * sizeof(double)));
+    if (c->Bval.bytes != (size_t)c->nnz * sizeof(double)) HKG_TRY(dalloc(c, &c->Bval, c->nnz * sizeof(double)));
+    HKG_TRY(form_operator(dp<double>(c->Aval), dp<double>(c->Sval), c->k * c->k, dp<double>(c->Bval), dp<double>(c->wDk),
+                          c->nnz, s));
+    HKG_TRY(walloc(c, &c->wBIO, c->nBIO * sizeof(double)));
+    HKG_TRY(walloc(c, &c->wCII, c->nSq * sizeof(double)));
+    HKG_HIP(hipMemsetAsync(c->wBIO.p, 0, c->nBIO * sizeof(double), s));
+    HKG_HIP(hipMemsetAsync(c->wCII.p, 0, c->nSq * sizeof(double), s));
+    HKG_TRY(extract_blocks(dsub, ns, c->max_nI, dp<int32_t>(c->rowptr), dp<int32_t>(c->colidx), dp<double>(c->Bval),
+                           dp<double>(c->wDk), dp<int32_t>(c->I_idx), dp<int32_t>(c->G_idx), dp<double>(c->winv),
+                           dp<double>(c->wBIO), dp<double>(c->wCII), s));
+    if (c->opt.two_level) HKG_TRY(coarse_space(c, s));
+    if (c->opt.local_prec == 32) HKG_TRY(local_inverses<float>(c, s));
+    else HKG_TRY(local_inverses<double>(c, s));
+    HKG_HIP(hipStreamSynchronize(s));
+    return HKG_OK;
+}
+
+}  // namespace hkg

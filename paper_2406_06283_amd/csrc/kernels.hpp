@@ -82,6 +82,7 @@ struct ApplyPlan {
     double *u;                  // sum nI x nrhs
     double *c, *y;              // m0 x nrhs
     int64_t sum_nI;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;   // optional: recorded around the local-solve kernel
 };
 int32_t apply_two_level(const ApplyPlan &p, const double *r, int ldr, double *z, int ldz, hipStream_t s);
 

@@ -47,7 +47,8 @@ class hkgeneo_problem(ctypes.Structure):
 class hkgeneo_options(ctypes.Structure):
     _fields_ = [("eig_mode", c_int32), ("tau", c_double), ("nev", c_int32), ("cluster_rtol", c_double),
                 ("max_eig_per_sub", c_int32), ("local_prec", c_int32), ("prolong", c_int32),
-                ("two_level", c_int32), ("restart", c_int32), ("max_iter", c_int32), ("rtol", c_double)]
+                ("two_level", c_int32), ("restart", c_int32), ("max_iter", c_int32), ("rtol", c_double),
+                ("keep_workspace", c_int32)]
 
 
 class hkgeneo_rhs_info(ctypes.Structure):
@@ -64,6 +65,9 @@ class hkgeneo_stats(ctypes.Structure):
 SIGNATURES = {
     "hkgeneo_default_options": (None, [POINTER(hkgeneo_options)]),
     "hkgeneo_setup": (c_int32, [POINTER(hkgeneo_problem), POINTER(hkgeneo_options), c_void_p, POINTER(c_void_p)]),
+    "hkgeneo_factor": (c_int32, [c_void_p, c_void_p]),
+    "hkgeneo_profile": (c_int32, [c_void_p, c_int32]),
+    "hkgeneo_profile_read": (c_int32, [c_void_p, POINTER(c_double), POINTER(c_int64)]),
     "hkgeneo_apply": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_void_p]),
     "hkgeneo_gmres_solve": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_int32, POINTER(hkgeneo_rhs_info),
                                       c_void_p]),
@@ -201,6 +205,19 @@ class Solver:
         _check(self.lib.hkgeneo_setup(ctypes.byref(self._pv.c), ctypes.byref(self.options), _stream_handle(stream),
                                       ctypes.byref(h)), "hkgeneo_setup")
         self.handle = h
+
+    def factor(self, stream=None):
+        """Redo the numeric setup on the device from the resident inputs."""
+        _check(self.lib.hkgeneo_factor(self.handle, _stream_handle(stream)), "hkgeneo_factor")
+
+    def profile(self, enable: bool):
+        _check(self.lib.hkgeneo_profile(self.handle, int(enable)), "hkgeneo_profile")
+
+    def profile_read(self):
+        t = c_double()
+        n = c_int64()
+        _check(self.lib.hkgeneo_profile_read(self.handle, ctypes.byref(t), ctypes.byref(n)), "hkgeneo_profile_read")
+        return t.value, n.value
 
     # --- raw-pointer style (same names as the C ABI) ---
     def _as_block(self, t):

@@ -161,3 +161,18 @@ def test_fgmres_h128_k40_matches_oracle():
     assert abs(info[0]["iters"] - oinfo["iters"]) <= 2, (info[0]["iters"], oinfo["iters"])
     assert np.linalg.norm(p.f[0] - M.B @ u) / np.linalg.norm(p.f[0]) <= 1e-8
     assert np.linalg.norm(u - x) / np.linalg.norm(x) <= 1e-8
+
+
+def test_refactor_reproduces_setup_bitwise():
+    _say("[factor] refactorisation from resident inputs")
+    p = pb.make_problem(24, k=9.0, s=3, overlap=2, coef="lognormal", seed=2)
+    R = torch.from_numpy(np.random.default_rng(5).standard_normal((2, p.n_dof))).to(DEV)
+    for keep in (0, 1):
+        with H.Solver(p, H.default_options(eig_mode=H.HKG_EIG_FIXED, nev=5, keep_workspace=keep)) as S:
+            z1 = S.apply(R).clone()
+            S.factor()
+            z2 = S.apply(R).clone()
+            S.factor()
+            z3 = S.apply(R)
+            torch.cuda.synchronize()
+            assert torch.equal(z1, z2) and torch.equal(z2, z3)

@@ -27,11 +27,14 @@ METRIC = "Helmholtz solves/s to rel.res 1e-8 (mixed vs FP64); p50/p99 solve late
 HBM_PEAK_GBS = 8000.0
 
 
-def local_solve_bytes(nI: np.ndarray, word: int) -> int:
+def local_solve_bytes(nI: np.ndarray, m: np.ndarray, word: int) -> int:
     """Algorithmic bytes of one local-solve launch (one right-hand side): the local inverses
-    (sum n_D^2 words), the gathered residual entries with their indices, the weights, the output."""
+    (sum n_D^2 words), the gathered residual entries with their indices, the weights and the output,
+    and the coarse restriction fused into the same kernel (Z_i^T: sum n_D m_i doubles, m0 outputs)."""
     s = int(nI.sum())
-    return int(word * int((nI.astype(np.int64) ** 2).sum()) + s * (8 + 4) + s * 8 + s * 8)
+    nI64 = nI.astype(np.int64)
+    return int(word * int((nI64 ** 2).sum()) + s * (8 + 4) + s * 8 + s * 8
+               + 8 * int((nI64 * m.astype(np.int64)).sum()) + 8 * int(m.sum()))
 
 
 def run_gpu(args, w, p):
@@ -128,7 +131,7 @@ def main():
     ok32 = all(x <= 1e-8 for x in r32["relres"])
     # roofline of the local-solve kernel (fp64 path): algorithmic bytes per launch / mean duration
     word = 8
-    bpl = local_solve_bytes(r64["nI"], word)
+    bpl = local_solve_bytes(r64["nI"], r64["m"], word)
     avg_s = r64["local_ms"] / max(r64["launches"], 1) / 1e3
     achieved = bpl / avg_s / 1e9
     line = {

@@ -99,8 +99,11 @@ typedef struct {
  *                        (lambda_{m+1} - lambda_m <= cluster_rtol max(1, |lambda_m|)).
  *   cluster_rtol         default 1e-8
  *   max_eig_per_sub      hard cap on m_i (default 64); exceeding it is HKG_EEIG
- *   local_prec           64: local factors and local solves in float64; 32: in float32 with float32
- *                        accumulation (coarse space, Arnoldi and residuals stay float64)
+ *   local_prec           64: local inverses stored and applied in float64; 32: stored and applied in
+ *                        float32 with float32 accumulation (coarse space, Arnoldi, residuals and the
+ *                        outer FGMRES stay float64)
+ *   local_factor_prec    with local_prec 32: 64 (default) forms B_D = P L U and B_D^{-1} in float64 and
+ *                        rounds the inverse to float32 storage; 32 runs the LU and the inverse in float32
  *   prolong              HKG_PROLONG_AS (default) or HKG_PROLONG_POU
  *   two_level            1 (default): add the coarse correction; 0: one-level only
  *   restart, max_iter, rtol   FGMRES(restart) stopping at ||f - B u|| <= rtol ||f||
@@ -122,6 +125,7 @@ typedef struct {
     int32_t max_iter;
     double rtol;
     int32_t keep_workspace;
+    int32_t local_factor_prec;
 } hkgeneo_options;
 
 /* per right-hand side outcome of hkgeneo_gmres_solve (host array of nrhs entries) */

@@ -23,19 +23,19 @@ struct hkgeneo_ctx {
     int64_t device_bytes = 0;
 
     // resident inputs and static descriptors (analysis phase)
-    hkg::DevBuf rowptr, colidx, Aval, Sval, I_idx, G_idx, winv, wloc, tp_ptr, tp_pos, subs_d;
+    hkg::DevBuf rowptr, colidx, Aval, Sval, I_idx, G_idx, winv, wloc, tp_ptr, tp_pos, tp_sub, subs_d;
     hkg::DevBuf bandK, bandM, bandLoc, pairs;
     hkg::DevBuf matsGG, matsSq, poffSub, jobsGI, jobsSq, gjobsSchur, matsLoc, poffLoc, jobsLoc;
     // numeric results (factorisation phase)
-    hkg::DevBuf Bval, Minv, Z, B0inv;
+    hkg::DevBuf Bval, Minv, Z, Zr, B0inv;
     // factorisation workspace (kept between calls when opt.keep_workspace, freed otherwise)
     hkg::DevBuf wDk, wBIO, wCII, wGG, wGI, wS, wW, wPiv, wInfo, wFlag, wD, wE, wTau, wM, wLam, wY, wB0, wLU, wPivL,
-        wJobsZ, wGjobsY, wMisc, wPiv0;
+        wJobsZ, wGjobsY, wMisc, wPiv0, wInv;
     // apply workspace
-    hkg::DevBuf u, c, y;
+    hkg::DevBuf u, c, y, ypart;
     int ws_nrhs = 0;
     // gmres workspace
-    hkg::DevBuf V, Zk, H, cs, sn, g, part, hcol, scal, active, want, rnorm, npart, fnorm;
+    hkg::DevBuf V, Zk, H, cs, sn, g, part, hcol, scal, active, want, rnorm, npart, fnorm, itersd;
     int gm_nrhs = 0;
     // measurement hook: events around the local-solve kernel
     bool prof = false;

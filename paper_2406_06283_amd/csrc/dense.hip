@@ -207,30 +207,49 @@ __global__ __launch_bounds__(256) void k_lu_laswp(const DMat *__restrict__ mats,
     }
 }
 
-// U12 = L11^{-1} A12 for the panel rows, one thread per column
+// Triangular solve of one LU_NB block against a tile of TRI_COLS columns held in LDS: each thread
+// solves its own column (x[r] in xs[r][tid]); T is the padded LU_NB x LU_NB triangle in LDS.
+constexpr int TRI_COLS = 128;
+
+template <typename T, int MODE>
+__device__ __forceinline__ void solve_block_lds(T (*Ls)[LU_NB + 1], T (*xs)[TRI_COLS + 1], int tid) {
+    if (MODE == TRI_LOWER_UNIT) {
+        for (int r = 1; r < LU_NB; ++r) {
+            T v = xs[r][tid];
+            for (int k = 0; k < r; ++k) v -= Ls[r][k] * xs[k][tid];
+            xs[r][tid] = v;
+        }
+    } else {
+        for (int r = LU_NB - 1; r >= 0; --r) {
+            T v = xs[r][tid];
+            for (int k = r + 1; k < LU_NB; ++k) v -= Ls[r][k] * xs[k][tid];
+            xs[r][tid] = (MODE == TRI_UPPER) ? v / Ls[r][r] : v;
+        }
+    }
+}
+
+// U12 = L11^{-1} A12 for the panel rows (the block is padded to LU_NB with the identity)
 template <typename T>
-__global__ __launch_bounds__(256) void k_lu_trsm_row(const DMat *__restrict__ mats, T *__restrict__ Ab, int j0) {
+__global__ __launch_bounds__(TRI_COLS) void k_lu_trsm_row(const DMat *__restrict__ mats, T *__restrict__ Ab, int j0) {
     const DMat m = mats[blockIdx.y];
     const int n = m.n;
     const int jend = min(j0 + LU_NB, n);
     if (jend >= n) return;
     __shared__ T L[LU_NB][LU_NB + 1];
+    __shared__ T xs[LU_NB][TRI_COLS + 1];
     T *A = Ab + m.off;
     const int ld = m.ld, nb = jend - j0;
-    for (int e = threadIdx.x; e < nb * nb; e += 256) {
-        int r = e % nb, c = e / nb;
-        L[r][c] = A[j0 + r + (int64_t)(j0 + c) * ld];
+    for (int e = threadIdx.x; e < LU_NB * LU_NB; e += TRI_COLS) {
+        int r = e % LU_NB, c = e / LU_NB;
+        L[r][c] = (r < nb && c < nb) ? A[j0 + r + (int64_t)(j0 + c) * ld] : T(r == c ? 1 : 0);
     }
+    const int c = jend + blockIdx.x * TRI_COLS + threadIdx.x;
+    const bool valid = c < n;
+    for (int r = 0; r < LU_NB; ++r) xs[r][threadIdx.x] = (valid && r < nb) ? A[j0 + r + (int64_t)c * ld] : T(0);
     __syncthreads();
-    const int c = jend + blockIdx.x * 256 + threadIdx.x;
-    if (c >= n) return;
-    T x[LU_NB];
-    for (int r = 0; r < nb; ++r) {
-        T v = A[j0 + r + (int64_t)c * ld];
-        for (int k = 0; k < r; ++k) v -= L[r][k] * x[k];
-        x[r] = v;
-    }
-    for (int r = 0; r < nb; ++r) A[j0 + r + (int64_t)c * ld] = x[r];
+    solve_block_lds<T, TRI_LOWER_UNIT>(L, xs, threadIdx.x);
+    if (valid)
+        for (int r = 0; r < nb; ++r) A[j0 + r + (int64_t)c * ld] = xs[r][threadIdx.x];
 }
 
 // A22 -= L21 U12
@@ -265,7 +284,8 @@ int32_t lu_batched(const DMat *d_mats, const int64_t *d_poff, int nbatch, int ma
         }
         int rem = maxn - j0 - LU_NB;
         if (rem > 0) {
-            hipLaunchKernelGGL(k_lu_trsm_row<T>, dim3((rem + 255) / 256, nbatch), dim3(256), 0, s, d_mats, A, j0);
+            hipLaunchKernelGGL(k_lu_trsm_row<T>, dim3((rem + TRI_COLS - 1) / TRI_COLS, nbatch), dim3(TRI_COLS), 0, s,
+                               d_mats, A, j0);
             int tiles = (rem + GT - 1) / GT;
             hipLaunchKernelGGL(k_lu_update<T>, dim3(tiles * tiles, nbatch), dim3(256), 0, s, d_mats, A, j0, tiles);
         }
@@ -286,38 +306,31 @@ template int32_t lu_batched<float>(const DMat *, const int64_t *, int, int, floa
 // Diagonal blocks are solved one thread per column; off-diagonal blocks are GEMM updates.
 // ------------------------------------------------------------------------------------------------
 template <typename T, int MODE>
-__global__ __launch_bounds__(256) void k_tri_diag(const TriJob *__restrict__ jobs, const T *__restrict__ Tb,
-                                                  T *__restrict__ Xb, int k0) {
+__global__ __launch_bounds__(TRI_COLS) void k_tri_diag(const TriJob *__restrict__ jobs, const T *__restrict__ Tb,
+                                                       T *__restrict__ Xb, int k0) {
     const TriJob J = jobs[blockIdx.y];
-    if (k0 >= J.n) return;
+    if (k0 >= J.n || (int)blockIdx.x * TRI_COLS >= J.ncol) return;
     const int nb = min(LU_NB, J.n - k0);
     __shared__ T Ls[LU_NB][LU_NB + 1];
+    __shared__ T xs[LU_NB][TRI_COLS + 1];
     const T *Tm = Tb + J.offT;
-    for (int e = threadIdx.x; e < nb * nb; e += 256) {
-        int r = e % nb, c = e / nb;
-        // Ls[r][c] = op(T)[k0 + r, k0 + c]
-        Ls[r][c] = (MODE == TRI_LOWER_UNIT_TRANS) ? Tm[k0 + c + (int64_t)(k0 + r) * J.ldT]
-                                                  : Tm[k0 + r + (int64_t)(k0 + c) * J.ldT];
+    // Ls = op(T)[k0:k0+nb, k0:k0+nb] padded with the identity to LU_NB x LU_NB
+    for (int e = threadIdx.x; e < LU_NB * LU_NB; e += TRI_COLS) {
+        int r = e % LU_NB, c = e / LU_NB;
+        T v = T(r == c ? 1 : 0);
+        if (r < nb && c < nb)
+            v = (MODE == TRI_LOWER_UNIT_TRANS) ? Tm[k0 + c + (int64_t)(k0 + r) * J.ldT]
+                                               : Tm[k0 + r + (int64_t)(k0 + c) * J.ldT];
+        Ls[r][c] = v;
     }
-    __syncthreads();
-    const int col = blockIdx.x * 256 + threadIdx.x;
-    if (col >= J.ncol) return;
+    const int col = blockIdx.x * TRI_COLS + threadIdx.x;
+    const bool valid = col < J.ncol;
     T *X = Xb + J.offX + (int64_t)col * J.ldX + k0;
-    T x[LU_NB];
-    if (MODE == TRI_LOWER_UNIT) {
-        for (int r = 0; r < nb; ++r) {
-            T v = X[r];
-            for (int k = 0; k < r; ++k) v -= Ls[r][k] * x[k];
-            x[r] = v;
-        }
-    } else {
-        for (int r = nb - 1; r >= 0; --r) {
-            T v = X[r];
-            for (int k = r + 1; k < nb; ++k) v -= Ls[r][k] * x[k];
-            x[r] = (MODE == TRI_UPPER) ? v / Ls[r][r] : v;
-        }
-    }
-    for (int r = 0; r < nb; ++r) X[r] = x[r];
+    for (int r = 0; r < LU_NB; ++r) xs[r][threadIdx.x] = (valid && r < nb) ? X[r] : T(0);
+    __syncthreads();
+    solve_block_lds<T, MODE>(Ls, xs, threadIdx.x);
+    if (valid)
+        for (int r = 0; r < nb; ++r) X[r] = xs[r][threadIdx.x];
 }
 
 template <typename T, int MODE>
@@ -355,22 +368,22 @@ int32_t tri_solve_batched(const TriJob *d_jobs, int nbatch, int maxn, int maxcol
     if (nbatch == 0 || maxn == 0 || maxcol == 0) return HKG_OK;
     const int nblk = (maxn + LU_NB - 1) / LU_NB;
     const int tiles_m = (maxn + GT - 1) / GT, tiles_n = (maxcol + GT - 1) / GT;
-    const dim3 gd((maxcol + 255) / 256, nbatch), gu(tiles_m * tiles_n, nbatch);
+    const dim3 gd((maxcol + TRI_COLS - 1) / TRI_COLS, nbatch), gu(tiles_m * tiles_n, nbatch);
     for (int b = 0; b < nblk; ++b) {
         // block boundaries sit at multiples of LU_NB in every matrix, so one k0 serves the whole
         // batch: ascending for the lower solve, descending for the upper ones (blocks past a
         // matrix's own size return at once).
         if (mode == TRI_LOWER_UNIT) {
             int k0 = b * LU_NB;
-            hipLaunchKernelGGL((k_tri_diag<T, TRI_LOWER_UNIT>), gd, dim3(256), 0, s, d_jobs, Tm, X, k0);
+            hipLaunchKernelGGL((k_tri_diag<T, TRI_LOWER_UNIT>), gd, dim3(TRI_COLS), 0, s, d_jobs, Tm, X, k0);
             hipLaunchKernelGGL((k_tri_update<T, TRI_LOWER_UNIT>), gu, dim3(256), 0, s, d_jobs, Tm, X, k0, tiles_m);
         } else {
             int k0 = (nblk - 1 - b) * LU_NB;
             if (mode == TRI_UPPER) {
-                hipLaunchKernelGGL((k_tri_diag<T, TRI_UPPER>), gd, dim3(256), 0, s, d_jobs, Tm, X, k0);
+                hipLaunchKernelGGL((k_tri_diag<T, TRI_UPPER>), gd, dim3(TRI_COLS), 0, s, d_jobs, Tm, X, k0);
                 hipLaunchKernelGGL((k_tri_update<T, TRI_UPPER>), gu, dim3(256), 0, s, d_jobs, Tm, X, k0, tiles_m);
             } else {
-                hipLaunchKernelGGL((k_tri_diag<T, TRI_LOWER_UNIT_TRANS>), gd, dim3(256), 0, s, d_jobs, Tm, X, k0);
+                hipLaunchKernelGGL((k_tri_diag<T, TRI_LOWER_UNIT_TRANS>), gd, dim3(TRI_COLS), 0, s, d_jobs, Tm, X, k0);
                 hipLaunchKernelGGL((k_tri_update<T, TRI_LOWER_UNIT_TRANS>), gu, dim3(256), 0, s, d_jobs, Tm, X, k0,
                                    tiles_m);
             }

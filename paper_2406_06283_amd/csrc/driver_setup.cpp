@@ -58,7 +58,7 @@ int32_t upload_bytes(hkgeneo_ctx *c, DevBuf *b, const void *host, size_t bytes, 
 void free_workspace(hkgeneo_ctx *c) {
     DevBuf *w[] = {&c->wDk, &c->wBIO, &c->wCII, &c->wGG, &c->wGI, &c->wS, &c->wW, &c->wPiv, &c->wInfo,
                    &c->wFlag, &c->wD, &c->wE, &c->wTau, &c->wM, &c->wLam, &c->wY, &c->wB0, &c->wLU,
-                   &c->wPivL, &c->wJobsZ, &c->wGjobsY, &c->wMisc, &c->wPiv0};
+                   &c->wPivL, &c->wJobsZ, &c->wGjobsY, &c->wMisc, &c->wPiv0, &c->wInv};
     for (DevBuf *b : w) drelease(c, b);
 }
 
@@ -115,6 +115,13 @@ int32_t analyze(hkgeneo_ctx *c, const hkgeneo_problem *p, hipStream_t s, int32_t
     HKG_TRY(upload(c, &c->wloc, wloc.data(), wloc.size(), s));
     HKG_TRY(upload(c, &c->tp_ptr, P.tp_ptr.data(), P.tp_ptr.size(), s));
     HKG_TRY(upload(c, &c->tp_pos, P.tp_pos.data(), P.tp_pos.size(), s));
+    {
+        std::vector<int32_t> owner(c->sum_nI), tsub(P.tp_pos.size());
+        for (int i = 0; i < ns; ++i)
+            for (int64_t t = P.offI[i]; t < P.offI[i + 1]; ++t) owner[t] = i;
+        for (size_t t = 0; t < P.tp_pos.size(); ++t) tsub[t] = owner[P.tp_pos[t]];
+        HKG_TRY(upload(c, &c->tp_sub, tsub.data(), tsub.size(), s));
+    }
     HKG_TRY(upload(c, &c->subs_d, c->subs.data(), ns, s));
 
     // element matrices of the band elements (the elements of each D_i carrying Gamma dofs)
@@ -187,12 +194,12 @@ int32_t read_flags(hkgeneo_ctx *c, const DevBuf &buf, int n, std::vector<int32_t
     return HKG_OK;
 }
 
+// B_D = P L U and B_D^{-1} = U^{-1} L^{-1} P, computed in precision T into `out` (nSq entries)
 template <typename T>
-int32_t local_inverses(hkgeneo_ctx *c, hipStream_t s) {
+int32_t local_inverses(hkgeneo_ctx *c, T *out, hipStream_t s) {
     const int ns = c->n_sub;
     const SubDev *dsub = dp<SubDev>(c->subs_d);
     HKG_TRY(walloc(c, &c->wLU, c->nSq * sizeof(T)));
-    if (c->Minv.bytes != (size_t)c->nSq * sizeof(T)) HKG_TRY(dalloc(c, &c->Minv, c->nSq * sizeof(T)));
     HKG_TRY(walloc(c, &c->wPivL, c->sum_nI * sizeof(int32_t)));
     HKG_TRY(walloc(c, &c->wInfo, ns * sizeof(int32_t)));
     if (sizeof(T) == 8) HKG_TRY(copy_bii(dsub, ns, c->max_nI, dp<double>(c->wBIO), (double *)c->wLU.p, s));
@@ -206,14 +213,25 @@ int32_t local_inverses(hkgeneo_ctx *c, hipStream_t s) {
             set_last_error("zero pivot in the local Dirichlet matrix of subdomain " + std::to_string(i));
             return HKG_ESINGULAR_LOCAL;
         }
-    // B_D^{-1} = U^{-1} L^{-1} P
     HKG_TRY(perm_identity_batched<T>(dp<DMat>(c->matsSq), dp<int64_t>(c->poffLoc), ns, c->max_nI,
-                                     dp<int32_t>(c->wPivL), dp<T>(c->Minv), s));
-    HKG_TRY(tri_solve_batched<T>(dp<TriJob>(c->jobsSq), ns, c->max_nI, c->max_nI, dp<T>(c->wLU), dp<T>(c->Minv),
-                                 TRI_LOWER_UNIT, s));
-    HKG_TRY(tri_solve_batched<T>(dp<TriJob>(c->jobsSq), ns, c->max_nI, c->max_nI, dp<T>(c->wLU), dp<T>(c->Minv),
-                                 TRI_UPPER, s));
+                                     dp<int32_t>(c->wPivL), out, s));
+    HKG_TRY(tri_solve_batched<T>(dp<TriJob>(c->jobsSq), ns, c->max_nI, c->max_nI, dp<T>(c->wLU), out, TRI_LOWER_UNIT,
+                                 s));
+    HKG_TRY(tri_solve_batched<T>(dp<TriJob>(c->jobsSq), ns, c->max_nI, c->max_nI, dp<T>(c->wLU), out, TRI_UPPER, s));
     return HKG_OK;
+}
+
+// the resident local operators in the storage precision of opt.local_prec, factorised in
+// opt.local_factor_prec (a float64 inverse rounded to float32 storage, or all in float32)
+int32_t local_operators(hkgeneo_ctx *c, hipStream_t s) {
+    const bool store32 = c->opt.local_prec == 32;
+    const size_t bytes = (size_t)c->nSq * (store32 ? sizeof(float) : sizeof(double));
+    if (c->Minv.bytes != bytes) HKG_TRY(dalloc(c, &c->Minv, bytes));
+    if (!store32) return local_inverses<double>(c, dp<double>(c->Minv), s);
+    if (c->opt.local_factor_prec == 32) return local_inverses<float>(c, dp<float>(c->Minv), s);
+    HKG_TRY(walloc(c, &c->wS, c->nSq * sizeof(double)));
+    HKG_TRY(local_inverses<double>(c, dp<double>(c->wS), s));
+    return cast_f64_f32(dp<double>(c->wS), dp<float>(c->Minv), c->nSq, s);
 }
 
 int32_t coarse_space(hkgeneo_ctx *c, hipStream_t s) {
@@ -276,8 +294,8 @@ int32_t coarse_space(hkgeneo_ctx *c, hipStream_t s) {
                              dp<double>(c->wTau), s));
     HKG_TRY(walloc(c, &c->wM, ns * sizeof(int32_t)));
     HKG_TRY(walloc(c, &c->wLam, (size_t)ns * (mmax + 2) * sizeof(double)));
-    HKG_TRY(select_eigs(dsub, ns, dp<double>(c->wD), dp<double>(c->wE), o.eig_mode, o.tau, o.nev, o.cluster_rtol, mmax,
-                        dp<int32_t>(c->wM), dp<double>(c->wLam), dp<int32_t>(c->wFlag), s));
+    HKG_TRY(select_eigs(dsub, ns, c->max_nI, dp<double>(c->wD), dp<double>(c->wE), o.eig_mode, o.tau, o.nev,
+                        o.cluster_rtol, mmax, dp<int32_t>(c->wM), dp<double>(c->wLam), dp<int32_t>(c->wFlag), s));
     c->m_host.assign(ns, 0);
     c->lam_host.assign((size_t)ns * (mmax + 2), 0.0);
     HKG_HIP(hipMemcpyAsync(c->m_host.data(), c->wM.p, ns * sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -315,9 +333,12 @@ int32_t coarse_space(hkgeneo_ctx *c, hipStream_t s) {
     if (c->m0 == 0) return HKG_OK;
     // eigenvectors -> coarse basis Z_i = X_I P_i
     if (c->Z.bytes != (size_t)offZ * sizeof(double)) HKG_TRY(dalloc(c, &c->Z, offZ * sizeof(double)));
+    HKG_TRY(walloc(c, &c->wInv, (size_t)offZ * (5 * sizeof(double) + 1)));
     HKG_TRY(tridiag_vectors_n(dsub, ns, c->max_nI, dp<double>(c->wD), dp<double>(c->wE), dp<double>(c->wLam), mmax,
-                              dp<double>(c->Z), s));
-    HKG_TRY(back_transform_n(dsub, ns, mmax, dp<double>(c->wW), dp<double>(c->wTau), dp<double>(c->Z), s));
+                              dp<double>(c->Z), dp<double>(c->wInv),
+                              reinterpret_cast<unsigned char *>(dp<double>(c->wInv) + 5 * offZ), s));
+    HKG_TRY(back_transform_n(dsub, ns, c->max_nI, c->max_m, dp<double>(c->wW), dp<double>(c->wTau), dp<double>(c->Z),
+                             s));
     HKG_TRY(scale_rows_invsqrt_diag(dsub, ns, dp<double>(c->wCII), dp<double>(c->Z), s));
     {
         std::vector<TriJob> hj(ns);
@@ -334,6 +355,8 @@ int32_t coarse_space(hkgeneo_ctx *c, hipStream_t s) {
         HKG_TRY(tri_solve_batched<double>(dp<TriJob>(c->wJobsZ), ns, c->max_nI, c->max_m, dp<double>(c->wCII),
                                           dp<double>(c->Z), TRI_LOWER_UNIT_TRANS, s));
         HKG_TRY(finish_basis(dsub, ns, dp<int32_t>(c->I_idx), dp<double>(c->winv), dp<double>(c->Z), s));
+        if (c->Zr.bytes != (size_t)offZ * sizeof(double)) HKG_TRY(dalloc(c, &c->Zr, offZ * sizeof(double)));
+        HKG_TRY(transpose_basis(dsub, ns, dp<double>(c->Z), dp<double>(c->Zr), s));
         // Y_i = Z_i^T [B_II | B_IG]
         HKG_TRY(walloc(c, &c->wY, std::max<int64_t>(offY, 1) * sizeof(double)));
         HKG_TRY(gemm_batched<double>(dp<GemmJob>(c->wGjobsY), ns, c->max_m, maxN, dp<double>(c->Z), dp<double>(c->wBIO),
@@ -400,8 +423,7 @@ int32_t factor(hkgeneo_ctx *c, hipStream_t s) {
                            dp<double>(c->wDk), dp<int32_t>(c->I_idx), dp<int32_t>(c->G_idx), dp<double>(c->winv),
                            dp<double>(c->wBIO), dp<double>(c->wCII), s));
     if (c->opt.two_level) HKG_TRY(coarse_space(c, s));
-    if (c->opt.local_prec == 32) HKG_TRY(local_inverses<float>(c, s));
-    else HKG_TRY(local_inverses<double>(c, s));
+    HKG_TRY(local_operators(c, s));
     HKG_HIP(hipStreamSynchronize(s));
     return HKG_OK;
 }

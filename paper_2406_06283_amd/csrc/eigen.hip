@@ -118,15 +118,15 @@ int32_t tridiagonalize_n(const SubDev *d_sub, int nsub, int maxnI, double *Sq, d
 // ------------------------------------------------------------------------------------------------
 // 2. Sturm counts and selection.
 // ------------------------------------------------------------------------------------------------
-// number of eigenvalues of T (diagonal d, off-diagonal e) strictly below sigma
-__device__ int sturm_count(const double *__restrict__ d, const double *__restrict__ e, int n, double sigma,
+// number of eigenvalues of T (diagonal d, squared off-diagonal e2) strictly below sigma
+__device__ int sturm_count(const double *__restrict__ d, const double *__restrict__ e2, int n, double sigma,
                            double pivmin) {
     int cnt = 0;
     double q = d[0] - sigma;
     if (fabs(q) < pivmin) q = -pivmin;
     cnt += (q < 0.0);
     for (int i = 1; i < n; ++i) {
-        q = d[i] - sigma - e[i - 1] * e[i - 1] / q;
+        q = d[i] - sigma - e2[i - 1] / q;
         if (fabs(q) < pivmin) q = -pivmin;
         cnt += (q < 0.0);
     }
@@ -134,44 +134,51 @@ __device__ int sturm_count(const double *__restrict__ d, const double *__restric
 }
 
 // k-th smallest eigenvalue (0-based) by bisection in (lo, hi]
-__device__ double bisect_kth(const double *d, const double *e, int n, int k, double lo, double hi, double pivmin) {
+__device__ double bisect_kth(const double *d, const double *e2, int n, int k, double lo, double hi, double pivmin) {
     for (int it = 0; it < 200; ++it) {
         double mid = 0.5 * (lo + hi);
         if (mid <= lo || mid >= hi) break;
-        if (sturm_count(d, e, n, mid, pivmin) <= k) lo = mid;
+        if (sturm_count(d, e2, n, mid, pivmin) <= k) lo = mid;
         else hi = mid;
     }
     return 0.5 * (lo + hi);
 }
 
-// one wave per subdomain
+// one wave per subdomain; T staged in LDS as (d, e^2)
 __global__ __launch_bounds__(64) void k_select(const SubDev *__restrict__ subs, const double *__restrict__ dbuf,
                                                const double *__restrict__ ebuf, int mode, double tau, int nev,
                                                double rtol, int mmax, int32_t *__restrict__ m_out,
                                                double *__restrict__ lam_out, int32_t *__restrict__ flag) {
+    extern __shared__ double sh[];
     const SubDev sd = subs[blockIdx.x];
     const int n = sd.nI;
-    const double *d = dbuf + sd.offI, *e = ebuf + sd.offI;
+    const double *dg = dbuf + sd.offI, *eg = ebuf + sd.offI;
+    double *d = sh, *e2 = sh + n;
     const int lane = threadIdx.x;
     // Gershgorin interval and the pivot floor of the Sturm recurrence
     double lo = 1e300, hi = -1e300, emax2 = 0.0;
     for (int i = lane; i < n; i += 64) {
-        double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < n ? fabs(e[i]) : 0.0);
-        lo = fmin(lo, d[i] - r);
-        hi = fmax(hi, d[i] + r);
-        if (i + 1 < n) emax2 = fmax(emax2, e[i] * e[i]);
+        double r = (i > 0 ? fabs(eg[i - 1]) : 0.0) + (i + 1 < n ? fabs(eg[i]) : 0.0);
+        lo = fmin(lo, dg[i] - r);
+        hi = fmax(hi, dg[i] + r);
+        d[i] = dg[i];
+        if (i + 1 < n) {
+            e2[i] = eg[i] * eg[i];
+            emax2 = fmax(emax2, e2[i]);
+        }
     }
     for (int o = 32; o > 0; o >>= 1) {
         lo = fmin(lo, __shfl_xor(lo, o, 64));
         hi = fmax(hi, __shfl_xor(hi, o, 64));
         emax2 = fmax(emax2, __shfl_xor(emax2, o, 64));
     }
+    __syncthreads();
     const double tnorm = fmax(fabs(lo), fabs(hi));
     const double pivmin = fmax(2.2250738585072014e-308, 2.2204460492503131e-16 * 2.2204460492503131e-16 * emax2);
     lo -= 2.2204460492503131e-16 * tnorm * n + pivmin;
     hi += 2.2204460492503131e-16 * tnorm * n + pivmin;
-    int m = (mode == HKG_EIG_THRESHOLD) ? sturm_count(d, e, n, tau, pivmin) : nev;
-    m = max(m, sturm_count(d, e, n, 0.0, pivmin));   // every lambda <= 0 (Def. 2.15: lambda_{m+1} > 0)
+    int m = (mode == HKG_EIG_THRESHOLD) ? sturm_count(d, e2, n, tau, pivmin) : nev;
+    m = max(m, sturm_count(d, e2, n, 0.0, pivmin));   // every lambda <= 0 (Def. 2.15: lambda_{m+1} > 0)
     m = min(m, n);
     double *lam = lam_out + (int64_t)blockIdx.x * (mmax + 2);
     if (m > mmax) {
@@ -179,33 +186,35 @@ __global__ __launch_bounds__(64) void k_select(const SubDev *__restrict__ subs, 
         return;
     }
     const int need = min(n, m + 1);
-    for (int k = lane; k < need; k += 64) lam[k] = bisect_kth(d, e, n, k, lo, hi, pivmin);
+    for (int k = lane; k < need; k += 64) lam[k] = bisect_kth(d, e2, n, k, lo, hi, pivmin);
     __syncthreads();
     if (lane == 0) {
         // close a cluster at the cut: lambda_{m+1} - lambda_m <= rtol max(1, |lambda_m|)
         while (m > 0 && m < n && lam[m] - lam[m - 1] <= rtol * fmax(1.0, fabs(lam[m - 1]))) {
             ++m;
             if (m > mmax) break;
-            if (m < n) lam[m] = bisect_kth(d, e, n, m, lo, hi, pivmin);
+            if (m < n) lam[m] = bisect_kth(d, e2, n, m, lo, hi, pivmin);
         }
         flag[blockIdx.x] = (m > mmax) ? 1 : 0;
         m_out[blockIdx.x] = m;
     }
 }
 
-int32_t select_eigs(const SubDev *d_sub, int nsub, const double *d, const double *e, int mode, double tau, int nev,
-                    double rtol, int mmax, int32_t *m_out, double *lam_out, int32_t *flag, hipStream_t s) {
-    hipLaunchKernelGGL(k_select, dim3(nsub), dim3(64), 0, s, d_sub, d, e, mode, tau, nev, rtol, mmax, m_out, lam_out,
-                       flag);
+int32_t select_eigs(const SubDev *d_sub, int nsub, int maxnI, const double *d, const double *e, int mode, double tau,
+                    int nev, double rtol, int mmax, int32_t *m_out, double *lam_out, int32_t *flag, hipStream_t s) {
+    hipLaunchKernelGGL(k_select, dim3(nsub), dim3(64), (size_t)2 * maxnI * sizeof(double), s, d_sub, d, e, mode, tau, nev,
+                       rtol, mmax, m_out, lam_out, flag);
     HKG_HIP(hipGetLastError());
     return HKG_OK;
 }
 
 // ------------------------------------------------------------------------------------------------
-// 3. inverse iteration on T for each selected eigenvalue: (T - lambda I) y = b by Gaussian
-//    elimination with partial pivoting on the tridiagonal (one thread; it is a serial recurrence),
-//    then Gram-Schmidt against the vectors already computed for eigenvalues within 1e-3 ||T|| and
-//    normalisation (whole block).  Three sweeps from a fixed pseudo-random start vector.
+// 3. inverse iteration on T for each selected eigenvalue, one lane per eigenvalue: (T - lambda I) y = b
+//    by Gaussian elimination with partial pivoting on the tridiagonal (a serial recurrence per lane),
+//    then, by the whole wave, Gram-Schmidt against the earlier vectors whose eigenvalues lie within
+//    1e-3 ||T|| and normalisation.  Three sweeps from a fixed pseudo-random start vector.
+//    Per-lane work arrays live in a global scratch area, interleaved (entry i of lane k at i m + k)
+//    so that the lanes' accesses coalesce.
 // ------------------------------------------------------------------------------------------------
 __device__ __forceinline__ double start_value(int i, int k) {
     uint32_t h = (uint32_t)i * 2654435761u ^ ((uint32_t)k * 40503u + 0x9e3779b9u);
@@ -213,153 +222,155 @@ __device__ __forceinline__ double start_value(int i, int k) {
     return ((double)(h & 0xffffff) / 16777216.0) * 2.0 - 1.0;
 }
 
-__global__ __launch_bounds__(256) void k_inverse_iteration(const SubDev *__restrict__ subs, const double *__restrict__ dbuf,
-                                                           const double *__restrict__ ebuf, const double *__restrict__ lam_all,
-                                                           int mmax, double *__restrict__ Zb) {
-    extern __shared__ double sh[];
+__global__ __launch_bounds__(64) void k_inverse_iteration(const SubDev *__restrict__ subs, const double *__restrict__ dbuf,
+                                                          const double *__restrict__ ebuf, const double *__restrict__ lam_all,
+                                                          int mmax, double *__restrict__ Zb, double *__restrict__ scratch,
+                                                          unsigned char *__restrict__ swp_all) {
     const SubDev sd = subs[blockIdx.x];
     const int n = sd.nI, m = sd.m;
     if (m == 0) return;
     const double *d = dbuf + sd.offI, *e = ebuf + sd.offI;
     const double *lam = lam_all + (int64_t)blockIdx.x * (mmax + 2);
-    double *dd = sh, *du = sh + n, *du2 = sh + 2 * n, *fac = sh + 3 * n, *b = sh + 4 * n, *red = sh + 5 * n;
-    unsigned char *swp = (unsigned char *)(red + 8);
+    const int64_t nm = (int64_t)n * m;
+    double *dd = scratch + 5 * sd.offZ, *du = dd + nm, *du2 = du + nm, *fac = du2 + nm, *b = fac + nm;
+    unsigned char *swp = swp_all + sd.offZ;
     double *Z = Zb + sd.offZ;
-    const int tid = threadIdx.x;
-    __shared__ double s_tnorm;
-    if (tid == 0) {
-        double t = 0.0;
-        for (int i = 0; i < n; ++i)
-            t = fmax(t, fabs(d[i]) + (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < n ? fabs(e[i]) : 0.0));
-        s_tnorm = t;
-    }
-    __syncthreads();
-    const double tnorm = s_tnorm;
+    const int lane = threadIdx.x;
+    double tnorm = 0.0;
+    for (int i = lane; i < n; i += 64)
+        tnorm = fmax(tnorm, fabs(d[i]) + (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < n ? fabs(e[i]) : 0.0));
+    for (int o = 32; o > 0; o >>= 1) tnorm = fmax(tnorm, __shfl_xor(tnorm, o, 64));
     const double pert = 2.2204460492503131e-16 * fmax(tnorm, 1e-300);
     const double orth_tol = 1e-3 * tnorm;
-    for (int k = 0; k < m; ++k) {
+    // factor T - lambda_k I = P L U for every selected k (lane k), U with two super-diagonals
+    for (int k = lane; k < m; k += 64) {
         const double lk = lam[k];
-        if (tid == 0) {
-            // factor T - lk I = P L U (U has two super-diagonals)
-            for (int i = 0; i < n; ++i) dd[i] = d[i] - lk;
-            for (int i = 0; i + 1 < n; ++i) { du[i] = e[i]; fac[i] = e[i]; }   // fac holds the sub-diagonal
-            for (int i = 0; i + 1 < n; ++i) {
-                const double sub = fac[i];
-                if (fabs(dd[i]) >= fabs(sub)) {
-                    swp[i] = 0;
-                    if (dd[i] == 0.0) dd[i] = pert;
-                    const double f = sub / dd[i];
-                    fac[i] = f;
-                    dd[i + 1] -= f * du[i];
-                    if (i + 2 < n) du2[i] = 0.0;
-                } else {
-                    swp[i] = 1;
-                    const double f = dd[i] / sub;
-                    fac[i] = f;
-                    dd[i] = sub;
-                    const double tmp = dd[i + 1];
-                    dd[i + 1] = du[i] - f * tmp;
-                    if (i + 2 < n) {
-                        du2[i] = du[i + 1];
-                        du[i + 1] = -f * du2[i];
-                    }
-                    du[i] = tmp;
-                }
+        double ddi = d[0] - lk;                       // running diagonal entry of row i
+        double dui = n > 1 ? e[0] : 0.0;              // running entry (i, i+1)
+        for (int i = 0; i + 1 < n; ++i) {
+            const double sub = e[i];
+            const double dnext = d[i + 1] - lk;
+            const double unext = (i + 2 < n) ? e[i + 1] : 0.0;
+            const int64_t q = (int64_t)i * m + k;
+            if (fabs(ddi) >= fabs(sub)) {
+                if (ddi == 0.0) ddi = pert;
+                const double f = sub / ddi;
+                swp[q] = 0;
+                fac[q] = f;
+                dd[q] = ddi;
+                du[q] = dui;
+                du2[q] = 0.0;
+                ddi = dnext - f * dui;
+                dui = unext;
+            } else {
+                const double f = ddi / sub;
+                swp[q] = 1;
+                fac[q] = f;
+                dd[q] = sub;
+                du[q] = dnext;
+                du2[q] = unext;
+                ddi = dui - f * dnext;
+                dui = -f * unext;
             }
-            if (dd[n - 1] == 0.0) dd[n - 1] = pert;
         }
-        for (int i = tid; i < n; i += 256) b[i] = start_value(i, k);
-        __syncthreads();
-        for (int sweep = 0; sweep < 3; ++sweep) {
-            if (tid == 0) {
-                for (int i = 0; i + 1 < n; ++i) {
-                    if (!swp[i]) {
-                        b[i + 1] -= fac[i] * b[i];
-                    } else {
-                        const double t = b[i];
-                        b[i] = b[i + 1];
-                        b[i + 1] = t - fac[i] * b[i + 1];
-                    }
+        if (ddi == 0.0) ddi = pert;
+        dd[(int64_t)(n - 1) * m + k] = ddi;
+        for (int i = 0; i < n; ++i) b[(int64_t)i * m + k] = start_value(i, k);
+    }
+    __syncthreads();
+    for (int sweep = 0; sweep < 3; ++sweep) {
+        for (int k = lane; k < m; k += 64) {
+            for (int i = 0; i + 1 < n; ++i) {
+                const int64_t q = (int64_t)i * m + k;
+                const double bi = b[q], bn = b[q + m];
+                if (!swp[q]) {
+                    b[q + m] = bn - fac[q] * bi;
+                } else {
+                    b[q] = bn;
+                    b[q + m] = bi - fac[q] * bn;
                 }
-                b[n - 1] /= dd[n - 1];
-                if (n >= 2) b[n - 2] = (b[n - 2] - du[n - 2] * b[n - 1]) / dd[n - 2];
-                for (int i = n - 3; i >= 0; --i) b[i] = (b[i] - du[i] * b[i + 1] - du2[i] * b[i + 2]) / dd[i];
-                // rescale to keep the iterate finite
-                double mx = 0.0;
-                for (int i = 0; i < n; ++i) mx = fmax(mx, fabs(b[i]));
-                const double inv = mx > 0.0 ? 1.0 / mx : 1.0;
-                for (int i = 0; i < n; ++i) b[i] *= inv;
             }
-            __syncthreads();
-            // modified Gram-Schmidt against earlier vectors of the same cluster
+            double x2 = 0.0, x1 = 0.0, mx = 0.0;     // x_{i+2}, x_{i+1}
+            for (int i = n - 1; i >= 0; --i) {
+                const int64_t q = (int64_t)i * m + k;
+                double v = b[q];
+                if (i + 1 < n) v -= du[q] * x1;
+                if (i + 2 < n) v -= du2[q] * x2;
+                v /= dd[q];
+                b[q] = v;
+                x2 = x1;
+                x1 = v;
+                mx = fmax(mx, fabs(v));
+            }
+            const double inv = mx > 0.0 ? 1.0 / mx : 1.0;
+            for (int i = 0; i < n; ++i) b[(int64_t)i * m + k] *= inv;
+        }
+        __syncthreads();
+        // modified Gram-Schmidt inside clusters, then normalisation (the whole wave per vector)
+        for (int k = 0; k < m; ++k) {
             for (int q = 0; q < k; ++q) {
-                if (fabs(lam[q] - lk) > orth_tol) continue;
-                const double *zq = Z + (int64_t)q * n;
-                double part = 0.0;
-                for (int i = tid; i < n; i += 256) part += zq[i] * b[i];
-                const double dot = block_sum(part, red);
-                for (int i = tid; i < n; i += 256) b[i] -= dot * zq[i];
+                if (fabs(lam[q] - lam[k]) > orth_tol) continue;
+                double s = 0.0;
+                for (int i = lane; i < n; i += 64) s += b[(int64_t)i * m + q] * b[(int64_t)i * m + k];
+                s = wave_sum(s);
+                for (int i = lane; i < n; i += 64) b[(int64_t)i * m + k] -= s * b[(int64_t)i * m + q];
                 __syncthreads();
             }
-            double part = 0.0;
-            for (int i = tid; i < n; i += 256) part += b[i] * b[i];
-            const double nrm = sqrt(block_sum(part, red));
-            const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
-            for (int i = tid; i < n; i += 256) b[i] *= inv;
+            double s = 0.0;
+            for (int i = lane; i < n; i += 64) s += b[(int64_t)i * m + k] * b[(int64_t)i * m + k];
+            s = wave_sum(s);
+            const double inv = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+            for (int i = lane; i < n; i += 64) b[(int64_t)i * m + k] *= inv;
             __syncthreads();
         }
-        for (int i = tid; i < n; i += 256) Z[(int64_t)k * n + i] = b[i];
-        __syncthreads();
     }
+    for (int k = 0; k < m; ++k)
+        for (int i = lane; i < n; i += 64) Z[(int64_t)k * n + i] = b[(int64_t)i * m + k];
 }
 
 int32_t tridiag_vectors_n(const SubDev *d_sub, int nsub, int maxnI, const double *d, const double *e, const double *lam,
-                          int mmax, double *Z, hipStream_t s) {
-    size_t shm = (size_t)(5 * maxnI + 8) * sizeof(double) + (size_t)maxnI + 16;
-    hipLaunchKernelGGL(k_inverse_iteration, dim3(nsub), dim3(256), shm, s, d_sub, d, e, lam, mmax, Z);
+                          int mmax, double *Z, double *scratch, unsigned char *swp, hipStream_t s) {
+    (void)maxnI;
+    hipLaunchKernelGGL(k_inverse_iteration, dim3(nsub), dim3(64), 0, s, d_sub, d, e, lam, mmax, Z, scratch, swp);
     HKG_HIP(hipGetLastError());
     return HKG_OK;
 }
 
 // ------------------------------------------------------------------------------------------------
-// 4. back-transformation y <- Q y with Q = H_0 H_1 ... H_{n-2} (reflectors applied last-first)
+// 4. back-transformation y <- Q y with Q = H_0 H_1 ... H_{n-2} (reflectors applied last-first), one
+//    wave per eigenvector with the vector staged in LDS
 // ------------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_back_transform(const SubDev *__restrict__ subs, const double *__restrict__ Sq,
-                                                        const double *__restrict__ taub, double *__restrict__ Zb) {
-    extern __shared__ double sh[];
+__global__ __launch_bounds__(64) void k_back_transform(const SubDev *__restrict__ subs, const double *__restrict__ Sq,
+                                                       const double *__restrict__ taub, double *__restrict__ Zb) {
+    extern __shared__ double zs[];
     const SubDev sd = subs[blockIdx.x];
-    const int n = sd.nI, m = sd.m;
-    if (m == 0) return;
+    const int c = blockIdx.y;
+    if (c >= sd.m) return;
+    const int n = sd.nI, lane = threadIdx.x;
     const double *A = Sq + sd.offSq;
     const double *tau = taub + sd.offI;
-    double *Z = Zb + sd.offZ;
-    double *dots = sh;          // m
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    double *z = Zb + sd.offZ + (int64_t)c * n;
+    for (int i = lane; i < n; i += 64) zs[i] = z[i];
+    __syncthreads();
     for (int j = n - 2; j >= 0; --j) {
         const double t = tau[j];
         if (t == 0.0) continue;
         const int L = n - j - 1;
         const double *v = A + (j + 1) + (int64_t)j * n;
-        for (int c = wv; c < m; c += 4) {
-            const double *z = Z + (int64_t)c * n + j + 1;
-            double s = 0.0;
-            for (int i = lane; i < L; i += 64) s += v[i] * z[i];
-            s = wave_sum(s);
-            if (lane == 0) dots[c] = t * s;
-        }
-        __syncthreads();
-        for (int64_t q = tid; q < (int64_t)L * m; q += 256) {
-            int i = (int)(q % L), c = (int)(q / L);
-            Z[(int64_t)c * n + j + 1 + i] -= dots[c] * v[i];
-        }
+        double s = 0.0;
+        for (int i = lane; i < L; i += 64) s += v[i] * zs[j + 1 + i];
+        s = t * wave_sum(s);
+        for (int i = lane; i < L; i += 64) zs[j + 1 + i] -= s * v[i];
         __syncthreads();
     }
+    for (int i = lane; i < n; i += 64) z[i] = zs[i];
 }
 
-int32_t back_transform_n(const SubDev *d_sub, int nsub, int mmax, const double *Sq, const double *tau, double *Z,
-                         hipStream_t s) {
-    size_t shm = (size_t)(mmax + 2) * sizeof(double);
-    hipLaunchKernelGGL(k_back_transform, dim3(nsub), dim3(256), shm, s, d_sub, Sq, tau, Z);
+int32_t back_transform_n(const SubDev *d_sub, int nsub, int maxnI, int max_m, const double *Sq, const double *tau,
+                         double *Z, hipStream_t s) {
+    if (max_m == 0) return HKG_OK;
+    hipLaunchKernelGGL(k_back_transform, dim3(nsub, max_m), dim3(64), (size_t)maxnI * sizeof(double), s, d_sub, Sq, tau,
+                       Z);
     HKG_HIP(hipGetLastError());
     return HKG_OK;
 }

@@ -56,12 +56,12 @@ int32_t scale_sym(const SubDev *d_sub, int nsub, int maxnI, const double *C, dou
 // ---- eigen.hip: tridiagonalisation, selection, eigenvectors --------------------------------------
 int32_t tridiagonalize_n(const SubDev *d_sub, int nsub, int maxnI, double *Sq, double *d, double *e, double *tau,
                          hipStream_t s);
-int32_t select_eigs(const SubDev *d_sub, int nsub, const double *d, const double *e, int mode, double tau, int nev,
-                    double rtol, int mmax, int32_t *m_out, double *lam_out, int32_t *flag, hipStream_t s);
+int32_t select_eigs(const SubDev *d_sub, int nsub, int maxnI, const double *d, const double *e, int mode, double tau,
+                    int nev, double rtol, int mmax, int32_t *m_out, double *lam_out, int32_t *flag, hipStream_t s);
 int32_t tridiag_vectors_n(const SubDev *d_sub, int nsub, int maxnI, const double *d, const double *e, const double *lam,
-                          int mmax, double *Z, hipStream_t s);
-int32_t back_transform_n(const SubDev *d_sub, int nsub, int mmax, const double *Sq, const double *tau, double *Z,
-                         hipStream_t s);
+                          int mmax, double *Z, double *scratch, unsigned char *swp, hipStream_t s);
+int32_t back_transform_n(const SubDev *d_sub, int nsub, int maxnI, int max_m, const double *Sq, const double *tau,
+                         double *Z, hipStream_t s);
 int32_t scale_rows_invsqrt_diag(const SubDev *d_sub, int nsub, const double *C, double *Z, hipStream_t s);
 int32_t finish_basis(const SubDev *d_sub, int nsub, const int32_t *I_idx, const double *winv, double *Z,
                      hipStream_t s);
@@ -76,19 +76,23 @@ struct ApplyPlan {
     const int32_t *I_idx;
     const double *winv_loc;     // local prolongation weights per concatenated position (1 or 1/mu)
     const void *Minv;           // local inverses (float or double), nI x nI at offSq
-    const double *Z;
+    const double *Zr;           // Z_i row-major (n_I x m_i) at offZ
     const double *B0inv;
-    const int32_t *tp_ptr, *tp_pos;
+    const int32_t *tp_ptr, *tp_pos, *tp_sub;
     double *u;                  // sum nI x nrhs
     double *c, *y;              // m0 x nrhs
+    double *ypart;              // chunks x m0 x nrhs
     int64_t sum_nI;
+    const int32_t *active = nullptr;           // optional per-rhs flags (FGMRES): skip inactive columns
     hipEvent_t ev0 = nullptr, ev1 = nullptr;   // optional: recorded around the local-solve kernel
 };
 int32_t apply_two_level(const ApplyPlan &p, const double *r, int ldr, double *z, int ldz, hipStream_t s);
+int apply_ypart_chunks(int m0);
+int32_t transpose_basis(const SubDev *d_sub, int nsub, const double *Z, double *Zr, hipStream_t s);
 
 // ---- krylov.hip ------------------------------------------------------------------------------------
 int32_t spmv(int n, int nrhs, const int32_t *rowptr, const int32_t *colidx, const double *val, const double *x,
-             int ldx, double *y, int ldy, const double *f, int ldf, hipStream_t s);
+             int ldx, double *y, int ldy, const double *f, int ldf, hipStream_t s, const int32_t *active = nullptr);
 
 struct GmresDev {
     int n, nrhs, restart, nblk;
@@ -101,6 +105,8 @@ struct GmresDev {
     double *hcol;       // restart+2 per rhs: current column before rotations
     double *scal;       // 8 per rhs: [beta0, fnorm, |g_{j+1}|, breakdown, ...]
     int32_t *active;    // per rhs
+    int32_t *iters;     // per rhs: preconditioner applications so far
+    int max_iter;
 };
 int32_t gmres_norm_init(const GmresDev &G, const double *r, int ldr, hipStream_t s);
 int32_t gmres_arnoldi_step(const GmresDev &G, int j, hipStream_t s);

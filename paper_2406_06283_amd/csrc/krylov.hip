@@ -11,16 +11,18 @@
 namespace hkg {
 
 constexpr int KB = 256;          // threads per block
-constexpr int KR = 4;            // rows per thread
+constexpr int KR = 1;            // rows per thread
 constexpr int ROWS_PER_BLOCK = KB * KR;
 
 // y = B x  (f == nullptr)   or   y = f - B x ; CSR, one thread per row
 __global__ __launch_bounds__(256) void k_spmv(int n, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
                                               const double *__restrict__ val, const double *__restrict__ x, int ldx,
-                                              double *__restrict__ y, int ldy, const double *__restrict__ f, int ldf) {
+                                              double *__restrict__ y, int ldy, const double *__restrict__ f, int ldf,
+                                              const int32_t *__restrict__ active) {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
     const int rhs = blockIdx.y;
+    if (active && !active[rhs]) return;
     const double *xx = x + (int64_t)rhs * ldx;
     double s = 0.0;
     for (int t = rowptr[i]; t < rowptr[i + 1]; ++t) s = fma(val[t], xx[colidx[t]], s);
@@ -29,9 +31,9 @@ __global__ __launch_bounds__(256) void k_spmv(int n, const int32_t *__restrict__
 }
 
 int32_t spmv(int n, int nrhs, const int32_t *rowptr, const int32_t *colidx, const double *val, const double *x,
-             int ldx, double *y, int ldy, const double *f, int ldf, hipStream_t s) {
+             int ldx, double *y, int ldy, const double *f, int ldf, hipStream_t s, const int32_t *active) {
     hipLaunchKernelGGL(k_spmv, dim3((n + 255) / 256, nrhs), dim3(256), 0, s, n, rowptr, colidx, val, x, ldx, y, ldy, f,
-                       ldf);
+                       ldf, active);
     HKG_HIP(hipGetLastError());
     return HKG_OK;
 }
@@ -179,7 +181,8 @@ __global__ __launch_bounds__(KB) void k_arnoldi_finish(GmresDev G, int j, double
         const int conv = fabs(g[j + 1]) <= tol_abs_scale * sc[1];
         const int brk = hn <= 1e-14 * hc[m + 1];
         const int sing = d == 0.0;
-        if (conv || brk || sing || j + 1 == m) {
+        const int it = ++G.iters[rhs];
+        if (conv || brk || sing || j + 1 == m || it >= G.max_iter) {
             G.active[rhs] = 0;
             sc[3] = (double)(j + 1);       // columns used in this cycle
             sc[4] = conv ? 1.0 : 0.0;

@@ -48,7 +48,7 @@ class hkgeneo_options(ctypes.Structure):
     _fields_ = [("eig_mode", c_int32), ("tau", c_double), ("nev", c_int32), ("cluster_rtol", c_double),
                 ("max_eig_per_sub", c_int32), ("local_prec", c_int32), ("prolong", c_int32),
                 ("two_level", c_int32), ("restart", c_int32), ("max_iter", c_int32), ("rtol", c_double),
-                ("keep_workspace", c_int32)]
+                ("keep_workspace", c_int32), ("local_factor_prec", c_int32)]
 
 
 class hkgeneo_rhs_info(ctypes.Structure):

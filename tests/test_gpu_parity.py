@@ -133,16 +133,26 @@ def test_zero_rhs_and_single_subdomain():
         assert info[0]["iters"] == 2 and info[0]["converged"]     # M^{-1} B has eigenvalues {1, 2}
 
 
-def test_mixed_precision_reaches_fp64_residual():
-    _say("[fgmres] fp32 local solves, h=1/32")
-    p = H32_K10.problem()
-    with H.Solver(p, H.options_for(H32_K10)) as S64, H.Solver(p, H.options_for(H32_K10, local_prec=32)) as S32:
-        f = torch.from_numpy(p.f).to(DEV)
-        u64, i64, _ = S64.solve(f)
-        u32, i32, st = S32.solve(f)
-        torch.cuda.synchronize()
-    assert st == H.HKG_OK and i32[0]["converged"] and i32[0]["relres_true"] <= 1e-8
-    assert abs(i32[0]["iters"] - i64[0]["iters"]) <= 2
+@pytest.mark.parametrize("wl", [H32_K10, H128_K40], ids=["h32_k10", "h128_k40"])
+def test_mixed_precision_reaches_fp64_residual(wl):
+    # float32 storage and application of the local inverses inside float64 FGMRES: the residual
+    # reaches 1e-8 and, with the inverse formed in float64, at the float64 iteration count (+-2).
+    # With the LU itself in float32 the residual is still reached; near resonance (h = 1/32, k = 10)
+    # it costs extra iterations, which the test records without bounding.
+    _say(f"[fgmres] fp32 local solves, {wl.name}")
+    p = wl.problem()
+    f = torch.from_numpy(p.f).to(DEV)
+    res = {}
+    for tag, kw in (("64", {}), ("32", dict(local_prec=32)), ("32f", dict(local_prec=32, local_factor_prec=32))):
+        with H.Solver(p, H.options_for(wl, **kw)) as S:
+            u, info, st = S.solve(f)
+            torch.cuda.synchronize()
+            res[tag] = (st, info[0])
+    for tag, (st, info) in res.items():
+        assert st == H.HKG_OK and info["converged"] and info["relres_true"] <= 1e-8, tag
+    assert abs(res["32"][1]["iters"] - res["64"][1]["iters"]) <= 2
+    _say(f"iterations fp64 {res['64'][1]['iters']} fp32-storage {res['32'][1]['iters']} "
+         f"fp32-factor {res['32f'][1]['iters']}")
 
 
 @pytest.mark.slow

@@ -191,6 +191,7 @@ static ApplyPlan make_plan(hkgeneo_ctx *c, int nrhs) {
     p.I_idx = dp<int32_t>(c->I_idx);
     p.winv_loc = dp<double>(c->wloc);
     p.Minv = c->Minv.p;
+    p.Z = dp<double>(c->Z);
     p.Zr = dp<double>(c->Zr);
     p.B0inv = dp<double>(c->B0inv);
     p.tp_ptr = dp<int32_t>(c->tp_ptr);

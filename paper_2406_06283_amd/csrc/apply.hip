@@ -3,14 +3,14 @@
 //   local:     u_D = W_D B_D^{-1} R_D r          (eq. (2.22); R_D gathers dof(D) from r)
 //   restrict:  c_i = Z_i^T R_i r                 (R_0 = Z^T on nodal residuals)
 //   coarse:    y = B_0^{-1} c
-//   prolong:   z_l = sum over the subdomains holding l of (u_D + Z_i y_i)[l]
+//   prolong:   u_D += Z_i y_i ; z_l = sum over the subdomains holding l of u_D[l]
 //
 // B_D^{-1} and B_0^{-1} are applied as products with the inverses formed at setup from the LU
 // factors (the same bytes as reading L and U, with no sequential dependency).  The local kernel
 // also forms the restriction from the same gathered residual (its last tile per subdomain reads
 // Z_i^T); the coarse product is split over column chunks whose partial sums are reduced in a fixed
-// order; the prolongation walks a transpose map (dof -> positions in the concatenated local
-// vectors) in a fixed order.  No atomics: z is bitwise reproducible.
+// order by the kernel that adds Z_i y_i; the final sum walks a transpose map (dof -> positions in
+// the concatenated local vectors) in a fixed order.  No atomics: z is bitwise reproducible.
 //
 // Every kernel is HBM-bound; the local inverses dominate (sum n_D^2 words per application).
 // Inside FGMRES every kernel first checks its right-hand side's active flag, so iterations issued
@@ -124,42 +124,42 @@ __global__ __launch_bounds__(256) void k_coarse_gemv(const double *__restrict__ 
                                                                     part[3][lane];
 }
 
-__global__ __launch_bounds__(256) void k_coarse_reduce(int m0, int nchunk, const double *__restrict__ ypart,
-                                                       double *__restrict__ y, const int32_t *__restrict__ active) {
-    const int rhs = blockIdx.y;
+// per subdomain: y_i = sum of the chunk partials (fixed order), then u_D += Z_i y_i
+__global__ __launch_bounds__(256) void k_coarse_add(const SubDev *__restrict__ subs, int m0, int nchunk,
+                                                    const double *__restrict__ ypart, const double *__restrict__ Z,
+                                                    double *__restrict__ u, int64_t ldu,
+                                                    const int32_t *__restrict__ active) {
+    __shared__ double ys[64];
+    const int rhs = blockIdx.z;
     if (active && !active[rhs]) return;
-    const int row = blockIdx.x * 256 + threadIdx.x;
-    if (row >= m0) return;
+    const SubDev sd = subs[blockIdx.y];
+    if (sd.m == 0) return;
+    if (threadIdx.x < sd.m) {
+        double s = 0.0;
+        for (int k = 0; k < nchunk; ++k) s += ypart[((int64_t)rhs * nchunk + k) * m0 + sd.offm + threadIdx.x];
+        ys[threadIdx.x] = s;
+    }
+    __syncthreads();
+    const int a = blockIdx.x * 256 + threadIdx.x;
+    if (a >= sd.nI) return;
+    const double *z = Z + sd.offZ + a;
     double s = 0.0;
-    for (int k = 0; k < nchunk; ++k) s += ypart[((int64_t)rhs * nchunk + k) * m0 + row];
-    y[(int64_t)rhs * m0 + row] = s;
+    for (int b = 0; b < sd.m; ++b) s = fma(z[(int64_t)b * sd.nI], ys[b], s);
+    u[(int64_t)rhs * ldu + sd.offI + a] += s;
 }
 
-// z_l = sum over the transpose map of u[pos] (+ Z_s[a, :] y_s when the coarse level is on)
+// z_l = sum over the transpose map of u (fixed order)
 __global__ __launch_bounds__(256) void k_prolong(int n, const int32_t *__restrict__ tp_ptr,
-                                                 const int32_t *__restrict__ tp_pos, const int32_t *__restrict__ tp_sub,
-                                                 const SubDev *__restrict__ subs, const double *__restrict__ u,
-                                                 int64_t ldu, const double *__restrict__ Zr, const double *__restrict__ y,
-                                                 int m0, double *__restrict__ z, int ldz,
+                                                 const int32_t *__restrict__ tp_pos, const double *__restrict__ u,
+                                                 int64_t ldu, double *__restrict__ z, int ldz,
                                                  const int32_t *__restrict__ active) {
     const int rhs = blockIdx.y;
     if (active && !active[rhs]) return;
     const int l = blockIdx.x * 256 + threadIdx.x;
     if (l >= n) return;
     const double *uu = u + (int64_t)rhs * ldu;
-    const double *yy = y ? y + (int64_t)rhs * m0 : nullptr;
     double s = 0.0;
-    for (int t = tp_ptr[l]; t < tp_ptr[l + 1]; ++t) {
-        const int pos = tp_pos[t];
-        double v = uu[pos];
-        if (yy) {
-            const SubDev &sd = subs[tp_sub[t]];
-            const double *zr = Zr + sd.offZ + (int64_t)(pos - sd.offI) * sd.m;
-            const double *ys = yy + sd.offm;
-            for (int b = 0; b < sd.m; ++b) v = fma(zr[b], ys[b], v);
-        }
-        s += v;
-    }
+    for (int t = tp_ptr[l]; t < tp_ptr[l + 1]; ++t) s += uu[tp_pos[t]];
     z[(int64_t)rhs * ldz + l] = s;
 }
 
@@ -185,12 +185,12 @@ int32_t apply_two_level(const ApplyPlan &p, const double *r, int ldr, double *z,
         const int nchunk = (p.m0 + CG_COLS - 1) / CG_COLS;
         hipLaunchKernelGGL(k_coarse_gemv, dim3((p.m0 + CG_ROWS - 1) / CG_ROWS, nchunk, p.nrhs), dim3(256), 0, s, p.B0inv,
                            p.m0, p.c, p.ypart, p.active);
-        hipLaunchKernelGGL(k_coarse_reduce, dim3((p.m0 + 255) / 256, p.nrhs), dim3(256), 0, s, p.m0, nchunk, p.ypart,
-                           p.y, p.active);
+        hipLaunchKernelGGL(k_coarse_add, dim3((p.maxnI + 255) / 256, p.nsub, p.nrhs), dim3(256), 0, s, p.d_sub, p.m0,
+                           nchunk, p.ypart, p.Z, p.u, ldu, p.active);
         HKG_HIP(hipGetLastError());
     }
     hipLaunchKernelGGL(k_prolong, dim3((p.n_dof + 255) / 256, p.nrhs), dim3(256), 0, s, p.n_dof, p.tp_ptr, p.tp_pos,
-                       p.tp_sub, p.d_sub, p.u, ldu, p.Zr, coarse ? p.y : nullptr, p.m0, z, ldz, p.active);
+                       p.u, ldu, z, ldz, p.active);
     HKG_HIP(hipGetLastError());
     return HKG_OK;
 }

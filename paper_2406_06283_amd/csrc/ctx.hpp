@@ -30,7 +30,7 @@ struct hkgeneo_ctx {
     hkg::DevBuf Bval, Minv, Z, Zr, B0inv;
     // factorisation workspace (kept between calls when opt.keep_workspace, freed otherwise)
     hkg::DevBuf wDk, wBIO, wCII, wGG, wGI, wS, wW, wPiv, wInfo, wFlag, wD, wE, wTau, wM, wLam, wY, wB0, wLU, wPivL,
-        wJobsZ, wGjobsY, wMisc, wPiv0, wInv;
+        wJobsZ, wGjobsY, wMisc, wPiv0, wInv, wVWV;
     // apply workspace
     hkg::DevBuf u, c, y, ypart;
     int ws_nrhs = 0;

@@ -7,78 +7,11 @@
 // instantiations accumulate in float (the mixed-precision local factors).
 #include "internal.hpp"
 #include "kernels.hpp"
+#include "tile.hpp"
 
 namespace hkg {
 
-constexpr int GT = 64;       // GEMM tile (GT x GT outputs per 256-thread block, 4 x 4 per thread)
-constexpr int GK = 16;       // GEMM k-step staged through LDS
 constexpr int LU_NB = 32;    // LU / triangular-solve block size
-
-// ------------------------------------------------------------------------------------------------
-// GEMM tile: C[tm*GT.., tn*GT..] = beta C + alpha op(A) op(B) with op(A) M x K, op(B) K x N.
-// ------------------------------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ void gemm_tile(int M, int N, int K, const T *__restrict__ A, int lda, bool ta,
-                                          const T *__restrict__ B, int ldb, bool tb, T *__restrict__ C,
-                                          int ldc, T alpha, T beta, int tm, int tn) {
-    __shared__ T sA[GK][GT + 1];
-    __shared__ T sB[GK][GT + 1];
-    const int tid = threadIdx.x;
-    const int tx = tid & 15, ty = tid >> 4;
-    const int i0 = tm * GT, j0 = tn * GT;
-    T acc[4][4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) acc[r][c] = T(0);
-
-    for (int k0 = 0; k0 < K; k0 += GK) {
-        // stage op(A)(i0 + ii, k0 + kk) into sA[kk][ii]
-        for (int e = tid; e < GK * GT; e += 256) {
-            int ii, kk;
-            if (!ta) { ii = e % GT; kk = e / GT; } else { kk = e % GK; ii = e / GK; }
-            int gi = i0 + ii, gk = k0 + kk;
-            T v = T(0);
-            if (gi < M && gk < K) v = ta ? A[gk + (int64_t)gi * lda] : A[gi + (int64_t)gk * lda];
-            sA[kk][ii] = v;
-        }
-        // stage op(B)(k0 + kk, j0 + jj) into sB[kk][jj]
-        for (int e = tid; e < GK * GT; e += 256) {
-            int jj, kk;
-            if (!tb) { kk = e % GK; jj = e / GK; } else { jj = e % GT; kk = e / GT; }
-            int gj = j0 + jj, gk = k0 + kk;
-            T v = T(0);
-            if (gj < N && gk < K) v = tb ? B[gj + (int64_t)gk * ldb] : B[gk + (int64_t)gj * ldb];
-            sB[kk][jj] = v;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int kk = 0; kk < GK; ++kk) {
-            T a[4], b[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) a[r] = sA[kk][tx + 16 * r];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) b[c] = sB[kk][ty + 16 * c];
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-#pragma unroll
-                for (int c = 0; c < 4; ++c) acc[r][c] = fma(a[r], b[c], acc[r][c]);
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        int gj = j0 + ty + 16 * c;
-        if (gj >= N) continue;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            int gi = i0 + tx + 16 * r;
-            if (gi >= M) continue;
-            T *p = C + gi + (int64_t)gj * ldc;
-            *p = (beta == T(0) ? T(0) : beta * *p) + alpha * acc[r][c];
-        }
-    }
-}
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_gemm_batched(const GemmJob *__restrict__ jobs, const T *__restrict__ Ab,
@@ -183,6 +116,99 @@ __global__ __launch_bounds__(256) void k_lu_panel(const DMat *__restrict__ mats,
     }
 }
 
+// Panel factorisation with the panel held in registers: thread t owns row j0 + t (the whole panel
+// row, LU_NB entries), so a panel of up to 1024 rows needs no memory traffic between its columns.
+// Pivot search: wave arg-max by shuffles, then across the 16 waves through LDS (ties to the
+// smallest row, as in the global-memory panel).  The pivot row and the displaced row are exchanged
+// through LDS; the pivot row is then broadcast from LDS for the rank-1 update.
+constexpr int PANEL_REG_ROWS = 1024;
+
+template <typename T>
+__global__ __launch_bounds__(PANEL_REG_ROWS) void k_lu_panel_reg(const DMat *__restrict__ mats,
+                                                                 const int64_t *__restrict__ poff, T *__restrict__ Ab,
+                                                                 int32_t *__restrict__ piv, int32_t *__restrict__ info,
+                                                                 int j0, int pivot) {
+    const DMat m = mats[blockIdx.x];
+    const int n = m.n;
+    if (j0 >= n) return;
+    T *A = Ab + m.off;
+    const int ld = m.ld;
+    const int nb = min(j0 + LU_NB, n) - j0;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int r = j0 + tid;
+    const bool own = r < n;
+    __shared__ T prow[LU_NB];
+    __shared__ T drow[LU_NB];
+    __shared__ T wval[PANEL_REG_ROWS / 64];
+    __shared__ int widx[PANEL_REG_ROWS / 64];
+    __shared__ int s_p;
+    T a[LU_NB];
+#pragma unroll
+    for (int c = 0; c < LU_NB; ++c) a[c] = (own && c < nb) ? A[r + (int64_t)(j0 + c) * ld] : T(0);
+#pragma clang loop unroll(full)
+    for (int jj = 0; jj < LU_NB; ++jj) {
+        if (jj < nb) {
+            const int j = j0 + jj;
+            int p = j;
+            if (pivot) {
+                T v = (own && r >= j) ? fabs(a[jj]) : T(-1);
+                int idx = (own && r >= j) ? r : 0x7fffffff;
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) {
+                    T ov = __shfl_xor(v, o, 64);
+                    int oi = __shfl_xor(idx, o, 64);
+                    if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
+                }
+                if (lane == 0) { wval[wv] = v; widx[wv] = idx; }
+                __syncthreads();
+                if (tid == 0) {
+                    T bv = wval[0];
+                    int bi = widx[0];
+                    for (int w = 1; w < PANEL_REG_ROWS / 64; ++w)
+                        if (wval[w] > bv || (wval[w] == bv && widx[w] < bi)) { bv = wval[w]; bi = widx[w]; }
+                    s_p = (bi < n) ? bi : j;
+                }
+                __syncthreads();
+                p = s_p;
+            }
+            if (own && r == p) {
+#pragma unroll
+                for (int c = 0; c < LU_NB; ++c) prow[c] = a[c];
+            }
+            if (own && r == j) {
+#pragma unroll
+                for (int c = 0; c < LU_NB; ++c) drow[c] = a[c];
+            }
+            __syncthreads();
+            if (own && r == j) {
+#pragma unroll
+                for (int c = 0; c < LU_NB; ++c) a[c] = prow[c];
+            } else if (own && r == p) {
+#pragma unroll
+                for (int c = 0; c < LU_NB; ++c) a[c] = drow[c];
+            }
+            const T dpiv = prow[jj];
+            const bool ok = dpiv != T(0) && isfinite(dpiv);
+            if (tid == 0) {
+                piv[poff[blockIdx.x] + j] = p;
+                if (!ok && info[blockIdx.x] == 0) info[blockIdx.x] = j + 1;
+            }
+            if (ok && own && r > j) {
+                const T l = a[jj] * (T(1) / dpiv);
+                a[jj] = l;
+#pragma unroll
+                for (int c = jj + 1; c < LU_NB; ++c) a[c] -= l * prow[c];
+            }
+            __syncthreads();
+        }
+    }
+    if (own) {
+#pragma unroll
+        for (int c = 0; c < LU_NB; ++c)
+            if (c < nb) A[r + (int64_t)(j0 + c) * ld] = a[c];
+    }
+}
+
 // apply the row exchanges of panel [j0, j0+NB) to the columns outside the panel
 template <typename T>
 __global__ __launch_bounds__(256) void k_lu_laswp(const DMat *__restrict__ mats, const int64_t *__restrict__ poff,
@@ -276,7 +302,12 @@ int32_t lu_batched(const DMat *d_mats, const int64_t *d_poff, int nbatch, int ma
     HKG_HIP(hipMemsetAsync(info, 0, sizeof(int32_t) * nbatch, s));
     if (maxn == 0) return HKG_OK;
     for (int j0 = 0; j0 < maxn; j0 += LU_NB) {
-        hipLaunchKernelGGL(k_lu_panel<T>, dim3(nbatch), dim3(256), 0, s, d_mats, d_poff, A, piv, info, j0, (int)pivot);
+        if (maxn - j0 <= PANEL_REG_ROWS)
+            hipLaunchKernelGGL(k_lu_panel_reg<T>, dim3(nbatch), dim3(PANEL_REG_ROWS), 0, s, d_mats, d_poff, A, piv, info,
+                               j0, (int)pivot);
+        else
+            hipLaunchKernelGGL(k_lu_panel<T>, dim3(nbatch), dim3(256), 0, s, d_mats, d_poff, A, piv, info, j0,
+                               (int)pivot);
         if (pivot) {
             int outside = maxn;
             hipLaunchKernelGGL(k_lu_laswp<T>, dim3((outside + 255) / 256, nbatch), dim3(256), 0, s, d_mats, d_poff, A,

@@ -58,7 +58,7 @@ int32_t upload_bytes(hkgeneo_ctx *c, DevBuf *b, const void *host, size_t bytes, 
 void free_workspace(hkgeneo_ctx *c) {
     DevBuf *w[] = {&c->wDk, &c->wBIO, &c->wCII, &c->wGG, &c->wGI, &c->wS, &c->wW, &c->wPiv, &c->wInfo,
                    &c->wFlag, &c->wD, &c->wE, &c->wTau, &c->wM, &c->wLam, &c->wY, &c->wB0, &c->wLU,
-                   &c->wPivL, &c->wJobsZ, &c->wGjobsY, &c->wMisc, &c->wPiv0, &c->wInv};
+                   &c->wPivL, &c->wJobsZ, &c->wGjobsY, &c->wMisc, &c->wPiv0, &c->wInv, &c->wVWV};
     for (DevBuf *b : w) drelease(c, b);
 }
 
@@ -290,8 +290,9 @@ int32_t coarse_space(hkgeneo_ctx *c, hipStream_t s) {
     HKG_TRY(walloc(c, &c->wD, c->sum_nI * sizeof(double)));
     HKG_TRY(walloc(c, &c->wE, c->sum_nI * sizeof(double)));
     HKG_TRY(walloc(c, &c->wTau, c->sum_nI * sizeof(double)));
-    HKG_TRY(tridiagonalize_n(dsub, ns, c->max_nI, dp<double>(c->wW), dp<double>(c->wD), dp<double>(c->wE),
-                             dp<double>(c->wTau), s));
+    HKG_TRY(walloc(c, &c->wVWV, (size_t)3 * 32 * c->sum_nI * sizeof(double)));
+    HKG_TRY(tridiagonalize_blocked(dsub, ns, c->max_nI, dp<double>(c->wW), dp<double>(c->wVWV), dp<double>(c->wD),
+                                   dp<double>(c->wE), dp<double>(c->wTau), s));
     HKG_TRY(walloc(c, &c->wM, ns * sizeof(int32_t)));
     HKG_TRY(walloc(c, &c->wLam, (size_t)ns * (mmax + 2) * sizeof(double)));
     HKG_TRY(select_eigs(dsub, ns, c->max_nI, dp<double>(c->wD), dp<double>(c->wE), o.eig_mode, o.tau, o.nev,

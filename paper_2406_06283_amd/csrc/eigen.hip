@@ -15,6 +15,7 @@
 // and finally the blocks of the coarse matrix B_0 = Z^T B Z (eq. (2.23)).
 #include "internal.hpp"
 #include "kernels.hpp"
+#include "tile.hpp"
 
 namespace hkg {
 
@@ -111,6 +112,150 @@ int32_t tridiagonalize_n(const SubDev *d_sub, int nsub, int maxnI, double *Sq, d
                          hipStream_t s) {
     size_t shm = (size_t)(2 * maxnI + 16) * sizeof(double);
     hipLaunchKernelGGL(k_sytrd, dim3(nsub), dim3(1024), shm, s, d_sub, Sq, d, e, tau);
+    HKG_HIP(hipGetLastError());
+    return HKG_OK;
+}
+
+// ------------------------------------------------------------------------------------------------
+// 1b. Blocked Householder tridiagonalisation.  Within a panel of SY_NB columns starting at j0 the
+//     trailing matrix A0 is left as it was at the panel start; with V (reflectors) and W (their
+//     images) of the panel's earlier columns the current matrix is A0 - V W^T - W V^T, so column j
+//     is corrected before its reflector is formed and the product A v needs only one pass over A0
+//     plus corrections with V and W.  After the panel one rank-2 SY_NB update (a batched GEMM over
+//     many blocks) brings the trailing matrix up to date.  Per subdomain the workspace VWV holds
+//     [V | W | V] (n x 3 SY_NB, column-major), so that the update is one GEMM with K = 2 SY_NB.
+// ------------------------------------------------------------------------------------------------
+constexpr int SY_NB = 32;
+constexpr int SY_THREADS = 1024;
+constexpr int SY_RT = 512;          // row threads of the product A0 v (two column groups)
+
+__global__ __launch_bounds__(SY_THREADS) void k_sytrd_panel(const SubDev *__restrict__ subs, double *__restrict__ Sq,
+                                                            double *__restrict__ VWVb, double *__restrict__ dout,
+                                                            double *__restrict__ eout, double *__restrict__ tout,
+                                                            int j0) {
+    extern __shared__ double sh[];
+    const SubDev sd = subs[blockIdx.x];
+    const int n = sd.nI;
+    double *A = Sq + sd.offSq;
+    double *d = dout + sd.offI, *e = eout + sd.offI, *tau = tout + sd.offI;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    if (j0 >= n - 1) return;
+    const int jb = min(SY_NB, n - 1 - j0);
+    double *V = VWVb + 3 * SY_NB * sd.offI;     // n x 3*SY_NB per subdomain (offI runs over sum n_I)
+    double *W = V + (int64_t)SY_NB * n;
+    double *V2 = V + (int64_t)2 * SY_NB * n;
+    double *v = sh;                  // n
+    double *p = sh + n;              // n (first the corrected column, then A v)
+    double *part = sh + 2 * n;       // 2 n
+    double *t12 = sh + 4 * n;        // 2 SY_NB
+    double *vw = t12 + 2 * SY_NB;    // 2 SY_NB: W[j, :], V[j, :]
+    double *red = vw + 2 * SY_NB;    // 16
+    // zero the panel's columns of V, W, V2 (rows not written below stay zero)
+    for (int64_t q = tid; q < (int64_t)3 * SY_NB * n; q += SY_THREADS) V[q] = 0.0;
+    __syncthreads();
+    for (int kk = 0; kk < jb; ++kk) {
+        const int j = j0 + kk;
+        const int L = n - j - 1;
+        // W[j, q], V[j, q] for q < kk
+        if (tid < kk) vw[tid] = W[j + (int64_t)tid * n];
+        else if (tid >= 64 && tid - 64 < kk) vw[SY_NB + tid - 64] = V[j + (int64_t)(tid - 64) * n];
+        __syncthreads();
+        // 1. corrected column j, rows j..n-1
+        for (int r = j + tid; r < n; r += SY_THREADS) {
+            double s = A[r + (int64_t)j * n];
+            for (int q = 0; q < kk; ++q) s -= V[r + (int64_t)q * n] * vw[q] + W[r + (int64_t)q * n] * vw[SY_NB + q];
+            p[r] = s;
+        }
+        __syncthreads();
+        // 2. reflector from x = p[j+1 .. n-1]
+        const double alpha = p[j + 1];
+        double acc = 0.0;
+        for (int r = j + 2 + tid; r < n; r += SY_THREADS) acc += p[r] * p[r];
+        const double xn2 = block_sum(acc, red);
+        double t = 0.0, beta = alpha, scal = 0.0;
+        if (xn2 != 0.0) {
+            beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+            t = (beta - alpha) / beta;
+            scal = 1.0 / (alpha - beta);
+        }
+        for (int r = j + 1 + tid; r < n; r += SY_THREADS) {
+            const double vr = (r == j + 1) ? 1.0 : (xn2 != 0.0 ? p[r] * scal : 0.0);
+            v[r] = vr;
+            A[r + (int64_t)j * n] = vr;
+            V[r + (int64_t)kk * n] = vr;
+            V2[r + (int64_t)kk * n] = vr;
+        }
+        if (tid == 0) {
+            d[j] = p[j];
+            e[j] = beta;
+            tau[j] = t;
+        }
+        __syncthreads();
+        if (t == 0.0) continue;          // H_j = I: W column stays zero
+        // 3. p = t (A0 v - V (W^T v) - W (V^T v)) on rows j+1..n-1
+        {
+            const int rt = tid & (SY_RT - 1), g = tid / SY_RT;
+            for (int r = j + 1 + rt; r < n; r += SY_RT) {
+                double s = 0.0;
+                for (int c = j + 1 + g; c < n; c += 2) s = fma(A[r + (int64_t)c * n], v[c], s);
+                part[g * n + r] = s;
+            }
+        }
+        for (int q2 = wv; q2 < 2 * kk; q2 += SY_THREADS / 64) {
+            const double *col = (q2 < kk) ? W + (int64_t)q2 * n : V + (int64_t)(q2 - kk) * n;
+            double s = 0.0;
+            for (int r = j + 1 + lane; r < n; r += 64) s = fma(col[r], v[r], s);
+            s = wave_sum(s);
+            if (lane == 0) t12[q2] = s;      // t12[q] = W_q . v, t12[kk + q] = V_q . v
+        }
+        __syncthreads();
+        for (int r = j + 1 + tid; r < n; r += SY_THREADS) {
+            double s = part[r] + part[n + r];
+            for (int q = 0; q < kk; ++q) s -= V[r + (int64_t)q * n] * t12[q] + W[r + (int64_t)q * n] * t12[kk + q];
+            p[r] = t * s;
+        }
+        __syncthreads();
+        // 4. w = p - (t/2)(p . v) v
+        acc = 0.0;
+        for (int r = j + 1 + tid; r < n; r += SY_THREADS) acc += p[r] * v[r];
+        const double K = 0.5 * t * block_sum(acc, red);
+        for (int r = j + 1 + tid; r < n; r += SY_THREADS) W[r + (int64_t)kk * n] = p[r] - K * v[r];
+        __syncthreads();
+    }
+}
+
+// trailing update after the panel at j0: A[j1:, j1:] -= [V W] [W V]^T (rank 2 SY_NB), j1 = j0 + jb
+__global__ __launch_bounds__(256) void k_sytrd_update(const SubDev *__restrict__ subs, double *__restrict__ Sq,
+                                                      const double *__restrict__ VWVb, int j0, int tiles_max) {
+    const SubDev sd = subs[blockIdx.y];
+    const int n = sd.nI;
+    if (j0 >= n - 1) return;
+    const int jb = min(SY_NB, n - 1 - j0);
+    const int j1 = j0 + jb;
+    const int L1 = n - j1;
+    const int tm = blockIdx.x % tiles_max, tn = blockIdx.x / tiles_max;
+    if (tm * 64 >= L1 || tn * 64 >= L1) return;
+    const double *V = VWVb + 3 * SY_NB * sd.offI;
+    double *A = Sq + sd.offSq;
+    gemm_tile<double>(L1, L1, 2 * SY_NB, V + j1, n, false, V + (int64_t)SY_NB * n + j1, n, true, A + j1 + (int64_t)j1 * n, n,
+                      -1.0, 1.0, tm, tn);
+}
+
+// the last diagonal entry, after the final trailing update
+__global__ void k_sytrd_last(const SubDev *__restrict__ subs, const double *__restrict__ Sq, double *__restrict__ dout) {
+    const SubDev sd = subs[blockIdx.x];
+    if (threadIdx.x == 0) dout[sd.offI + sd.nI - 1] = Sq[sd.offSq + (int64_t)(sd.nI - 1) * (sd.nI + 1)];
+}
+
+int32_t tridiagonalize_blocked(const SubDev *d_sub, int nsub, int maxnI, double *Sq, double *VWV, double *d, double *e,
+                               double *tau, hipStream_t s) {
+    const size_t shm = (size_t)(4 * maxnI + 4 * SY_NB + 16) * sizeof(double);
+    const int tiles = (maxnI + 63) / 64;
+    for (int j0 = 0; j0 < maxnI; j0 += SY_NB) {
+        hipLaunchKernelGGL(k_sytrd_panel, dim3(nsub), dim3(SY_THREADS), shm, s, d_sub, Sq, VWV, d, e, tau, j0);
+        hipLaunchKernelGGL(k_sytrd_update, dim3(tiles * tiles, nsub), dim3(256), 0, s, d_sub, Sq, VWV, j0, tiles);
+    }
+    hipLaunchKernelGGL(k_sytrd_last, dim3(nsub), dim3(64), 0, s, d_sub, Sq, d);
     HKG_HIP(hipGetLastError());
     return HKG_OK;
 }

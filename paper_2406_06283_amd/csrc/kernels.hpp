@@ -54,6 +54,8 @@ int32_t check_spd_pivots(const SubDev *d_sub, int nsub, const double *C, int32_t
 int32_t scale_sym(const SubDev *d_sub, int nsub, int maxnI, const double *C, double *S, hipStream_t s);
 
 // ---- eigen.hip: tridiagonalisation, selection, eigenvectors --------------------------------------
+int32_t tridiagonalize_blocked(const SubDev *d_sub, int nsub, int maxnI, double *Sq, double *VWV, double *d, double *e,
+                               double *tau, hipStream_t s);
 int32_t tridiagonalize_n(const SubDev *d_sub, int nsub, int maxnI, double *Sq, double *d, double *e, double *tau,
                          hipStream_t s);
 int32_t select_eigs(const SubDev *d_sub, int nsub, int maxnI, const double *d, const double *e, int mode, double tau,
@@ -76,6 +78,7 @@ struct ApplyPlan {
     const int32_t *I_idx;
     const double *winv_loc;     // local prolongation weights per concatenated position (1 or 1/mu)
     const void *Minv;           // local inverses (float or double), nI x nI at offSq
+    const double *Z;            // Z_i column-major (n_I x m_i) at offZ
     const double *Zr;           // Z_i row-major (n_I x m_i) at offZ
     const double *B0inv;
     const int32_t *tp_ptr, *tp_pos, *tp_sub;

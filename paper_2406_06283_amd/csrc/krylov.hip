@@ -100,10 +100,15 @@ __global__ __launch_bounds__(KB) void k_cgs_update(GmresDev G, int j, int pass) 
     const double *pin = G.part + ((int64_t)rhs * 2 * nb + (pass == 1 ? 0 : nb)) * S;
     double *h = sh;                    // j + 2
     double *red = sh + (G.restart + 2);
-    for (int i = threadIdx.x; i <= j + 1; i += KB) {
-        double s = 0.0;
-        for (int b = 0; b < nb; ++b) s += pin[(int64_t)b * S + i];
-        h[i] = s;
+    {
+        // h[i] = sum over blocks of the partials: one wave per i, lanes over blocks, fixed shuffle tree
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        for (int i = wv; i <= j + 1; i += KB / 64) {
+            double s = 0.0;
+            for (int b = lane; b < nb; b += 64) s += pin[(int64_t)b * S + i];
+            s = wsum(s);
+            if (lane == 0) h[i] = s;
+        }
     }
     __syncthreads();
     if (blockIdx.x == 0) {
@@ -146,7 +151,8 @@ __global__ __launch_bounds__(KB) void k_arnoldi_finish(GmresDev G, int j, double
     const int n = G.n, S = G.restart + 2, nb = G.nblk, m = G.restart;
     const double *pin = G.part + (int64_t)rhs * 2 * nb * S;
     double nrm2 = 0.0;
-    for (int b = 0; b < nb; ++b) nrm2 += pin[(int64_t)b * S];
+    for (int b = (threadIdx.x & 63); b < nb; b += 64) nrm2 += pin[(int64_t)b * S];
+    nrm2 = wsum(nrm2);                 // the same fixed tree in every wave of every block
     const double hn = sqrt(nrm2);
     double *V = G.V + (int64_t)rhs * n * (m + 1);
     double *w = V + (int64_t)(j + 1) * n;

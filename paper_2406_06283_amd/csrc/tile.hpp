@@ -1,0 +1,80 @@
+// GEMM tile shared by the batched dense kernels: C[tm*GT.., tn*GT..] = beta C + alpha op(A) op(B).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace hkg {
+
+constexpr int GT = 64;       // GEMM tile (GT x GT outputs per 256-thread block, 4 x 4 per thread)
+constexpr int GK = 16;       // GEMM k-step staged through LDS
+
+// ------------------------------------------------------------------------------------------------
+// GEMM tile: C[tm*GT.., tn*GT..] = beta C + alpha op(A) op(B) with op(A) M x K, op(B) K x N.
+// ------------------------------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void gemm_tile(int M, int N, int K, const T *__restrict__ A, int lda, bool ta,
+                                          const T *__restrict__ B, int ldb, bool tb, T *__restrict__ C,
+                                          int ldc, T alpha, T beta, int tm, int tn) {
+    __shared__ T sA[GK][GT + 1];
+    __shared__ T sB[GK][GT + 1];
+    const int tid = threadIdx.x;
+    const int tx = tid & 15, ty = tid >> 4;
+    const int i0 = tm * GT, j0 = tn * GT;
+    T acc[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[r][c] = T(0);
+
+    for (int k0 = 0; k0 < K; k0 += GK) {
+        // stage op(A)(i0 + ii, k0 + kk) into sA[kk][ii]
+        for (int e = tid; e < GK * GT; e += 256) {
+            int ii, kk;
+            if (!ta) { ii = e % GT; kk = e / GT; } else { kk = e % GK; ii = e / GK; }
+            int gi = i0 + ii, gk = k0 + kk;
+            T v = T(0);
+            if (gi < M && gk < K) v = ta ? A[gk + (int64_t)gi * lda] : A[gi + (int64_t)gk * lda];
+            sA[kk][ii] = v;
+        }
+        // stage op(B)(k0 + kk, j0 + jj) into sB[kk][jj]
+        for (int e = tid; e < GK * GT; e += 256) {
+            int jj, kk;
+            if (!tb) { kk = e % GK; jj = e / GK; } else { jj = e % GT; kk = e / GT; }
+            int gj = j0 + jj, gk = k0 + kk;
+            T v = T(0);
+            if (gj < N && gk < K) v = tb ? B[gj + (int64_t)gk * ldb] : B[gk + (int64_t)gj * ldb];
+            sB[kk][jj] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < GK; ++kk) {
+            T a[4], b[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) a[r] = sA[kk][tx + 16 * r];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) b[c] = sB[kk][ty + 16 * c];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[r][c] = fma(a[r], b[c], acc[r][c]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        int gj = j0 + ty + 16 * c;
+        if (gj >= N) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            int gi = i0 + tx + 16 * r;
+            if (gi >= M) continue;
+            T *p = C + gi + (int64_t)gj * ldc;
+            *p = (beta == T(0) ? T(0) : beta * *p) + alpha * acc[r][c];
+        }
+    }
+}
+
+
+}  // namespace hkg

@@ -188,6 +188,48 @@ int32_t hkgeneo_apply(hkgeneo_ctx *ctx, const double *r, double *z, int32_t nrhs
 int32_t hkgeneo_gmres_solve(hkgeneo_ctx *ctx, const double *f, double *u, int32_t nrhs, int32_t ld,
                             hkgeneo_rhs_info *info, void *stream);
 
+/*
+ * Batched solves (several set-up problems in one sequence of launches).
+ *
+ * A batch refers to nprob contexts (ctxs[p], host array of handles; a context may appear once) and
+ * solves nrhs[p] right-hand sides for problem p at every hkgeneo_batch_solve call.  One FGMRES
+ * iteration of eq. (2.23)'s preconditioner and the CGS2 Arnoldi step runs as one launch per phase
+ * for every (problem, subdomain or row block, right-hand side) item of the batch; the iteration is
+ * captured once as a HIP graph and replayed.  The local-solve launch shape is chosen by timing the
+ * candidates at creation (cached per batch shape).  Results are bitwise the same whichever other
+ * problems share the batch and whichever launch shape is picked.
+ *
+ * Every context must use the same `restart`; rtol and max_iter are taken per problem.  The contexts
+ * must outlive the batch; hkgeneo_factor on a member is allowed between solves as long as the
+ * context's sizes (n_dof, m0, local precision) do not change (HKG_EINVAL otherwise).  The batch owns
+ * its Krylov workspace and an internal stream; it is not thread-safe, and no other call may use the
+ * member contexts while a batch solve runs.
+ * Errors: HKG_EINVAL for NULL handles, nprob < 1, nrhs[p] outside 1..65535, different restart
+ * lengths, more than 65535 subdomains in total or a subdomain too large for the batched kernels;
+ * HKG_ENOMEM; HKG_EHIP.  On failure *out is NULL.
+ */
+typedef struct hkgeneo_batch hkgeneo_batch;
+int32_t hkgeneo_batch_create(hkgeneo_ctx *const *ctxs, const int32_t *nrhs, int32_t nprob,
+                             hkgeneo_batch **out);
+
+/*
+ * f[p], u[p]: device arrays n_dof(p) x nrhs[p] with leading dimension ld[p] >= n_dof(p) (host arrays
+ * of nprob pointers / ints).  Starts from u = 0.  `stream` is the caller's stream: the call waits for
+ * it before reading f and returns when every u[p] is final (synchronous).  info: host array of
+ * sum(nrhs) entries in problem order (may be NULL).  Returns HKG_OK if every column converged,
+ * HKG_ENOTCONV otherwise.
+ */
+int32_t hkgeneo_batch_solve(hkgeneo_batch *b, const double *const *f, double *const *u, const int32_t *ld,
+                            hkgeneo_rhs_info *info, void *stream);
+
+/* Device bytes held by the batch itself (workspace and descriptor tables). */
+int64_t hkgeneo_batch_bytes(const hkgeneo_batch *b);
+
+/* Launch shape the autotuner chose for the batched local solves (waves per 64-row tile). */
+int32_t hkgeneo_batch_local_waves(const hkgeneo_batch *b);
+
+void hkgeneo_batch_destroy(hkgeneo_batch *b);
+
 /* w = B x for nrhs columns (device arrays, ld >= n_dof).  Asynchronous. */
 int32_t hkgeneo_matvec(hkgeneo_ctx *ctx, const double *x, double *w, int32_t nrhs, int32_t ld,
                        void *stream);

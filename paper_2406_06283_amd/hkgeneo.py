@@ -78,6 +78,12 @@ SIGNATURES = {
     "hkgeneo_query_eigen": (c_int32, [c_void_p, c_int32, _f64p, c_int32, _f64p]),
     "hkgeneo_query_coarse_matrix": (c_int32, [c_void_p, _f64p]),
     "hkgeneo_partition": (c_int32, [POINTER(hkgeneo_problem), _i32p, _i32p, _i32p, _i32p, _i32p, _i32p]),
+    "hkgeneo_batch_create": (c_int32, [POINTER(c_void_p), _i32p, c_int32, POINTER(c_void_p)]),
+    "hkgeneo_batch_solve": (c_int32, [c_void_p, POINTER(c_void_p), POINTER(c_void_p), _i32p, POINTER(hkgeneo_rhs_info),
+                                      c_void_p]),
+    "hkgeneo_batch_bytes": (c_int64, [c_void_p]),
+    "hkgeneo_batch_local_waves": (c_int32, [c_void_p]),
+    "hkgeneo_batch_destroy": (None, [c_void_p]),
     "hkgeneo_destroy": (None, [c_void_p]),
     "hkgeneo_strerror": (c_char_p, [c_int32]),
     "hkgeneo_last_error": (c_char_p, []),
@@ -301,6 +307,79 @@ class Solver:
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:
             self.lib.hkgeneo_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class Batch:
+    """Several set-up problems solved together (hkgeneo_batch_* of the C ABI).
+
+    `solvers` are Solver objects (kept alive by the batch), `nrhs` the number of right-hand sides
+    per problem.  solve(fs) takes one (nrhs_p, n_p) float64 GPU tensor per problem.
+    """
+
+    def __init__(self, solvers, nrhs):
+        self.lib = load()
+        self.solvers = list(solvers)
+        self.nrhs = [int(r) for r in nrhs]
+        if len(self.nrhs) != len(self.solvers):
+            raise ValueError("one nrhs per solver")
+        np_ = len(self.solvers)
+        hs = (c_void_p * np_)(*[s.handle.value for s in self.solvers])
+        nr = np.asarray(self.nrhs, np.int32)
+        self.handle = c_void_p()
+        _check(self.lib.hkgeneo_batch_create(hs, _ptr(nr, c_int32), np_, ctypes.byref(self.handle)),
+               "hkgeneo_batch_create")
+
+    @property
+    def device_bytes(self) -> int:
+        return int(self.lib.hkgeneo_batch_bytes(self.handle))
+
+    @property
+    def local_waves(self) -> int:
+        return int(self.lib.hkgeneo_batch_local_waves(self.handle))
+
+    def solve(self, fs, us=None, stream=None):
+        """Returns ([u_p], [[info dict per rhs] per problem], status)."""
+        import torch
+        if len(fs) != len(self.solvers):
+            raise ValueError("one right-hand-side block per problem")
+        f2, u2 = [], []
+        for p, (S, f) in enumerate(zip(self.solvers, fs)):
+            fb = S._as_block(f)
+            if fb.shape[0] != self.nrhs[p]:
+                raise ValueError(f"problem {p}: expected {self.nrhs[p]} right-hand sides")
+            f2.append(fb)
+            u2.append(torch.empty_like(fb) if us is None else S._as_block(us[p]))
+        np_ = len(fs)
+        fp = (c_void_p * np_)(*[t.data_ptr() for t in f2])
+        up = (c_void_p * np_)(*[t.data_ptr() for t in u2])
+        ld = np.asarray([S.n for S in self.solvers], np.int32)
+        infos = (hkgeneo_rhs_info * sum(self.nrhs))()
+        st = _check(self.lib.hkgeneo_batch_solve(self.handle, fp, up, _ptr(ld, c_int32), infos, _stream_handle(stream)),
+                    "hkgeneo_batch_solve")
+        out, q = [], 0
+        for r in self.nrhs:
+            out.append([dict(iters=i.iters, converged=bool(i.converged), relres_est=i.relres_est,
+                             relres_true=i.relres_true) for i in infos[q:q + r]])
+            q += r
+        res = [u.view_as(f) for u, f in zip(u2, fs)] if us is None else list(us)
+        return res, out, st
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            self.lib.hkgeneo_batch_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -189,35 +189,40 @@ int32_t hkgeneo_gmres_solve(hkgeneo_ctx *ctx, const double *f, double *u, int32_
                             hkgeneo_rhs_info *info, void *stream);
 
 /*
- * Batched solves (several set-up problems in one sequence of launches).
+ * Batched solves: several set-up problems stepped together.
  *
- * A batch refers to nprob contexts (ctxs[p], host array of handles; a context may appear once) and
- * solves nrhs[p] right-hand sides for problem p at every hkgeneo_batch_solve call.  One FGMRES
- * iteration of eq. (2.23)'s preconditioner and the CGS2 Arnoldi step runs as one launch per phase
- * for every (problem, subdomain or row block, right-hand side) item of the batch; the iteration is
- * captured once as a HIP graph and replayed.  The local-solve launch shape is chosen by timing the
- * candidates at creation (cached per batch shape).  Results are bitwise the same whichever other
- * problems share the batch and whichever launch shape is picked.
+ * One FGMRES iteration (the preconditioner of eq. (2.23) and the CGS2 Arnoldi step) runs as one
+ * launch per phase for every (problem, subdomain or row block, right-hand side) item of the live
+ * set, whatever the sizes of the problems; the iteration is captured once as a HIP graph and
+ * replayed.  The Arnoldi index and the state of every (problem, rhs) pair live on the device, and a
+ * second captured graph (the restart phase: x update, true residual ||f - B u|| in FP64, stop or
+ * start the next cycle) serves the pairs that reach the end of a cycle, so each pair restarts on
+ * its own.  The launch shape of the local solves is chosen by timing the candidates when the live
+ * set changes (cached per shape).  A problem's iterates are bitwise the same whichever other
+ * problems share the live set and whichever launch shape is picked.  Stopping rule and results as
+ * in hkgeneo_gmres_solve, with rtol and max_iter taken from each problem's options.
  *
- * Every context must use the same `restart`; rtol and max_iter are taken per problem.  The contexts
- * must outlive the batch; hkgeneo_factor on a member is allowed between solves as long as the
- * context's sizes (n_dof, m0, local precision) do not change (HKG_EINVAL otherwise).  The batch owns
- * its Krylov workspace and an internal stream; it is not thread-safe, and no other call may use the
- * member contexts while a batch solve runs.
- * Errors: HKG_EINVAL for NULL handles, nprob < 1, nrhs[p] outside 1..65535, different restart
- * lengths, more than 65535 subdomains in total or a subdomain too large for the batched kernels;
- * HKG_ENOMEM; HKG_EHIP.  On failure *out is NULL.
+ * Common rules: contexts must outlive every batch or server call that uses them and must not be
+ * used by another call while one runs; every context must use the restart length of the batch or
+ * server; hkgeneo_factor on a context is allowed between solves.  f and u are device arrays
+ * n_dof x nrhs with leading dimension ld >= n_dof, u must not alias f.  Neither object is
+ * thread-safe.  Each owns an internal HIP stream (default priority) and its Krylov workspace.
  */
+
+/* A fixed set of nprob problems: ctxs[p] (host array of handles) with nrhs[p] right-hand sides.
+ * Errors: HKG_EINVAL for NULL handles, nprob < 1, nrhs[p] outside 1..65535 or different restart
+ * lengths; HKG_ENOMEM; HKG_EHIP.  On failure *out is NULL. */
 typedef struct hkgeneo_batch hkgeneo_batch;
 int32_t hkgeneo_batch_create(hkgeneo_ctx *const *ctxs, const int32_t *nrhs, int32_t nprob,
                              hkgeneo_batch **out);
 
 /*
- * f[p], u[p]: device arrays n_dof(p) x nrhs[p] with leading dimension ld[p] >= n_dof(p) (host arrays
- * of nprob pointers / ints).  Starts from u = 0.  `stream` is the caller's stream: the call waits for
- * it before reading f and returns when every u[p] is final (synchronous).  info: host array of
- * sum(nrhs) entries in problem order (may be NULL).  Returns HKG_OK if every column converged,
- * HKG_ENOTCONV otherwise.
+ * Solve every problem of the batch from u = 0.  f[p], u[p], ld[p]: host arrays of nprob device
+ * pointers / leading dimensions.  The call waits for `stream` (the caller's) before reading f and
+ * returns when every u[p] is final (synchronous).  info: host array of sum(nrhs) entries in problem
+ * order (may be NULL).  Returns HKG_OK if every column converged, HKG_ENOTCONV otherwise;
+ * HKG_EINVAL for a NULL pointer, ld[p] < n_dof or a subdomain too large for the batched local
+ * solve (2 |dof(D)| + 1024 doubles of LDS must fit in 160 KiB).
  */
 int32_t hkgeneo_batch_solve(hkgeneo_batch *b, const double *const *f, double *const *u, const int32_t *ld,
                             hkgeneo_rhs_info *info, void *stream);
@@ -229,6 +234,54 @@ int64_t hkgeneo_batch_bytes(const hkgeneo_batch *b);
 int32_t hkgeneo_batch_local_waves(const hkgeneo_batch *b);
 
 void hkgeneo_batch_destroy(hkgeneo_batch *b);
+
+/*
+ * Server: continuous batching of solve requests.  Requests are submitted at any time and queued;
+ * at every check period (a few iterations) the server admits queued requests in arrival order
+ * while a slot is free (at most max_requests live) and their Krylov workspace fits in
+ * workspace_budget bytes, runs the restart phase if some pair needs it, replays the iteration
+ * graph, and retires requests whose right-hand sides have all stopped.  Admission and retirement
+ * happen only at iteration boundaries; the work of all live requests shares every launch.
+ * max_nrhs bounds nrhs per request.
+ * Errors: HKG_EINVAL for max_requests outside 1..65535, max_nrhs outside 1..65535, restart < 1 or
+ * too large for the batched Arnoldi kernels, workspace_budget <= 0.
+ */
+typedef struct hkgeneo_server hkgeneo_server;
+typedef struct {
+    int32_t queued, live, live_rhs, completed_waiting, local_waves, pad_;
+    int64_t workspace_bytes;    /* Krylov workspace held, including buffers kept for reuse */
+    int64_t device_bytes;       /* all device bytes held by the server */
+    int64_t iterations;         /* iteration graph launches */
+    int64_t restarts;           /* restart graph launches */
+    int64_t captures;           /* graph captures (one pair per change of the live set) */
+    int64_t admitted, retired;
+} hkgeneo_server_stats;
+
+int32_t hkgeneo_server_create(int64_t workspace_budget, int32_t max_requests, int32_t max_nrhs,
+                              int32_t restart, hkgeneo_server **out);
+
+/* Queue a request (asynchronous): solve ctx's system for nrhs columns of f into u, from u = 0;
+ * `tag` is returned by hkgeneo_server_poll.  The server waits for `stream` (recorded now) before it
+ * reads f.  f and u must stay valid until the request is polled.
+ * Errors: HKG_EINVAL (NULL pointer, nrhs outside 1..max_nrhs, ld < n_dof, other restart, subdomain
+ * too large for the batched local solve), HKG_ENOMEM if its workspace alone exceeds the budget. */
+int32_t hkgeneo_server_submit(hkgeneo_server *s, hkgeneo_ctx *ctx, const double *f, double *u,
+                              int32_t nrhs, int32_t ld, int64_t tag, void *stream);
+
+/* Run up to `periods` check periods (returns early when nothing is live or queued).  *pending
+ * (may be NULL) receives the number of requests live or queued afterwards. */
+int32_t hkgeneo_server_pump(hkgeneo_server *s, int32_t periods, int32_t *pending);
+
+/* Pop one finished request: returns its nrhs (> 0) and fills *tag, *status (HKG_OK or
+ * HKG_ENOTCONV) and info[0..nrhs) (host, capacity cap; may be NULL); 0 if none is waiting;
+ * HKG_EINVAL if cap is too small (the request stays queued).  Its u is final. */
+int32_t hkgeneo_server_poll(hkgeneo_server *s, int64_t *tag, int32_t *status, hkgeneo_rhs_info *info,
+                            int32_t cap);
+
+int32_t hkgeneo_server_query(const hkgeneo_server *s, hkgeneo_server_stats *out);
+
+/* Waits for the server's stream; queued and live requests are dropped (their u is undefined). */
+void hkgeneo_server_destroy(hkgeneo_server *s);
 
 /* w = B x for nrhs columns (device arrays, ld >= n_dof).  Asynchronous. */
 int32_t hkgeneo_matvec(hkgeneo_ctx *ctx, const double *x, double *w, int32_t nrhs, int32_t ld,

@@ -15,6 +15,8 @@ from __future__ import annotations
 
 import dataclasses
 
+import numpy as np
+
 from . import problems as pb
 
 EIG_THRESHOLD = 0
@@ -59,9 +61,10 @@ H128_K40 = Workload(
 
 H256_K80 = Workload(
     name="p1_h256_k80_16x16", N=256, dim=2, elem_type=pb.P1, k=80.0, s=16, overlap=2, coef="lognormal",
-    rhs="one", nrhs=1, eig_mode=EIG_THRESHOLD, nev=0, tau=0.0,   # tau frozen below
+    rhs="one", nrhs=1, eig_mode=EIG_THRESHOLD, nev=0, tau=0.845,
     description="2D unit square, P1 h=1/256 (65025 dofs), k=80, lognormal a (sigma=1, l=0.1); 16x16 "
-                "subdomains, 2 layers; FGMRES(50), rel.res 1e-8")
+                "subdomains, 2 layers; tau=0.845 (5-24 vectors per subdomain, mean 9.6, at seed 0); "
+                "FGMRES(50), rel.res 1e-8")
 
 Q1_3D_H32_K10 = Workload(
     name="q1_3d_h32_k10_4x4x4", N=32, dim=3, elem_type=pb.Q1, k=10.0, s=4, overlap=2, coef="const",
@@ -70,3 +73,49 @@ Q1_3D_H32_K10 = Workload(
                 "eigenvectors per subdomain")
 
 WORKLOADS = {w.name: w for w in (H32_K10, H128_K40, H256_K80, Q1_3D_H32_K10)}
+
+
+@dataclasses.dataclass(frozen=True)
+class MixMember:
+    """One problem of the batched mix: a 2D P1 problem with its own seed, size and partition."""
+    seed: int
+    N: int
+    k: float
+    s: int
+    overlap: tuple
+    coef: str
+    nrhs: int
+    nev: int
+
+    @property
+    def name(self) -> str:
+        return f"mix{self.seed}_p1_h{self.N}_s{self.s}_{self.coef}_r{self.nrhs}"
+
+    def problem(self) -> pb.Problem:
+        return pb.make_problem(self.N, k=self.k, s=self.s, overlap=np.asarray(self.overlap, dtype=np.int32),
+                               coef=self.coef, seed=self.seed, rhs="normal", nrhs=self.nrhs, name=self.name)
+
+
+def batch_mix(count: int = 64, seed0: int = 0, n_choices=(64, 128, 192, 256), s_range=(4, 16),
+              nrhs_range=(1, 8), nev: int = 12, max_block: int | None = 32) -> list[MixMember]:
+    """Independent 2D problems for batched solves: h uniform over 1/n_choices, k = 0.3/h, an s x s
+    floor partition with s uniform in s_range, overlap uniform in {1, 2, 3} per subdomain,
+    coefficients alternating piecewise constant on 16x16 cells (log10 a ~ U[0, 2]) and lognormal,
+    nrhs uniform in nrhs_range with nodal N(0, 1) data, nev eigenvectors per subdomain.
+
+    max_block caps the elements per block side (s is raised to ceil(N / max_block)), which keeps the
+    dense local eigenproblems at the size of the single-problem workloads; None draws s unchanged.
+    """
+    out = []
+    for q in range(count):
+        seed = seed0 + q
+        rng = np.random.Generator(np.random.PCG64(seed + 104729))
+        N = int(rng.choice(np.asarray(n_choices)))
+        s = int(rng.integers(s_range[0], s_range[1] + 1))
+        if max_block is not None:
+            s = max(s, -(-N // max_block))
+        ov = tuple(int(v) for v in rng.integers(1, 4, size=s * s))
+        nrhs = int(rng.integers(nrhs_range[0], nrhs_range[1] + 1))
+        out.append(MixMember(seed=seed, N=N, k=0.3 * N, s=s, overlap=ov, coef="cells" if q % 2 == 0 else "lognormal",
+                             nrhs=nrhs, nev=nev))
+    return out

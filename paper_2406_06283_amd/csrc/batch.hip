@@ -24,7 +24,7 @@ __device__ __forceinline__ double bwsum(double v) {
 }
 
 __device__ __forceinline__ bool inactive(const ProbDev &P, int rhs, int mode) {
-    return rhs >= P.nrhs || (mode == 1 && !P.active[rhs]);
+    return rhs >= P.nrhs || (mode == 1 && P.active[rhs] != PS_ITER);
 }
 
 __device__ __forceinline__ const double *vcol(const ProbDev &P, int rhs, int j) {
@@ -367,7 +367,7 @@ __global__ __launch_bounds__(BROWS) void k_b_finish(const ProbDev *__restrict__ 
         const int itn = ++P.iters[rhs];
         sc[3] = (double)(j + 1);
         if (conv || brk || sing || j + 1 == m || itn >= P.max_iter) {
-            P.active[rhs] = 0;
+            P.active[rhs] = PS_CYCLE_END;
             sc[4] = conv ? 1.0 : 0.0;
             sc[5] = sing ? 1.0 : 0.0;
         }
@@ -375,15 +375,17 @@ __global__ __launch_bounds__(BROWS) void k_b_finish(const ProbDev *__restrict__ 
 }
 
 // advance j of every active pair (a separate launch: no block of the step reads j after this)
-__global__ void k_b_advance(const ProbDev *__restrict__ probs, int nprob, int max_nrhs) {
+__global__ void k_b_advance(const ProbDev *__restrict__ probs, const int32_t *__restrict__ live, int nlive,
+                            int max_nrhs) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nprob * max_nrhs) return;
-    const ProbDev &P = probs[t / max_nrhs];
+    if (t >= nlive * max_nrhs) return;
+    const ProbDev &P = probs[live[t / max_nrhs]];
     const int rhs = t % max_nrhs;
-    if (rhs < P.nrhs && P.active[rhs]) P.jcur[rhs] += 1;
+    if (rhs < P.nrhs && P.active[rhs] == PS_ITER) P.jcur[rhs] += 1;
 }
 
-int32_t batch_arnoldi(const BatchGeom &g, const ProbDev *probs, const WorkItem *rblk, hipStream_t s) {
+int32_t batch_arnoldi(const BatchGeom &g, const ProbDev *probs, const WorkItem *rblk, const int32_t *live,
+                      hipStream_t s) {
     const dim3 grid(g.nrblk, 1, g.max_nrhs);
     // the restart length of every problem is the same (checked at batch creation)
     hipLaunchKernelGGL(k_b_spmv_next, grid, dim3(BROWS), 0, s, probs, rblk);
@@ -393,113 +395,31 @@ int32_t batch_arnoldi(const BatchGeom &g, const ProbDev *probs, const WorkItem *
     hipLaunchKernelGGL(k_b_update, grid, dim3(BROWS), hbuf + red, s, probs, rblk, 2);
     hipLaunchKernelGGL(k_b_finish, grid, dim3(BROWS), 0, s, probs, rblk);
     const int pairs = g.nprob * g.max_nrhs;
-    hipLaunchKernelGGL(k_b_advance, dim3((pairs + 255) / 256), dim3(256), 0, s, probs, g.nprob, g.max_nrhs);
+    hipLaunchKernelGGL(k_b_advance, dim3((pairs + 255) / 256), dim3(256), 0, s, probs, live, g.nprob, g.max_nrhs);
     HKG_HIP(hipGetLastError());
     return HKG_OK;
 }
 
 // ------------------------------------------------------------------------------------------------
-// cycle start / end, residuals
+// restart phase: pairs whose cycle ended (PS_CYCLE_END) or that just joined (PS_NEW)
 // ------------------------------------------------------------------------------------------------
-// V[:, 0] = f - B x (init: x = 0, so V[:, 0] = f and x is cleared); partial squared norms
-__global__ __launch_bounds__(BROWS) void k_b_residual(const ProbDev *__restrict__ probs,
-                                                      const WorkItem *__restrict__ rblk, int init) {
-    __shared__ double red[4];
-    const WorkItem it = rblk[blockIdx.x];
-    const ProbDev &P = probs[it.p];
-    const int rhs = blockIdx.z;
-    if (rhs >= P.nrhs) return;
-    const int i = it.s * BROWS + threadIdx.x;
-    double v = 0.0;
-    if (i < P.n) {
-        const double *x = P.x + (int64_t)rhs * P.ldx;
-        v = P.f[(int64_t)rhs * P.ldf + i];
-        if (init) {
-            P.x[(int64_t)rhs * P.ldx + i] = 0.0;
-        } else {
-            double s = 0.0;
-            for (int t = P.rowptr[i]; t < P.rowptr[i + 1]; ++t) s = fma(P.Bval[t], x[P.colidx[t]], s);
-            v -= s;
-        }
-        vcol_w(P, rhs, 0)[i] = v;
-    }
-    double s = bwsum(v * v);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
-    __syncthreads();
-    if (threadIdx.x == 0)
-        P.part[(int64_t)rhs * 2 * P.nblk * (P.restart + 2) + it.s] = red[0] + red[1] + red[2] + red[3];
-}
-
-__global__ void k_b_residual_norm(const ProbDev *__restrict__ probs, int nprob, int max_nrhs, int init) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nprob * max_nrhs) return;
-    const ProbDev &P = probs[t / max_nrhs];
-    const int rhs = t % max_nrhs;
-    if (rhs >= P.nrhs) return;
-    const double *pp = P.part + (int64_t)rhs * 2 * P.nblk * (P.restart + 2);
-    double s = 0.0;
-    for (int b = 0; b < P.nblk; ++b) s += pp[b];
-    const double nr = sqrt(s);
-    P.rnorm[rhs] = nr;
-    if (init) {
-        double *sc = P.scal + (int64_t)rhs * 8;
-        for (int k = 0; k < 8; ++k) sc[k] = 0.0;
-        sc[1] = nr;
-        P.iters[rhs] = 0;
-        P.active[rhs] = 0;
-    }
-}
-
-int32_t batch_residual(const BatchGeom &g, const ProbDev *probs, const WorkItem *rblk, int init, hipStream_t s) {
-    hipLaunchKernelGGL(k_b_residual, dim3(g.nrblk, 1, g.max_nrhs), dim3(BROWS), 0, s, probs, rblk, init);
-    const int pairs = g.nprob * g.max_nrhs;
-    hipLaunchKernelGGL(k_b_residual_norm, dim3((pairs + 255) / 256), dim3(256), 0, s, probs, g.nprob, g.max_nrhs, init);
-    HKG_HIP(hipGetLastError());
-    return HKG_OK;
-}
-
-// v_0 = r / beta, g = beta e_1, j = 0, active = want
-__global__ __launch_bounds__(BROWS) void k_b_cycle_start(const ProbDev *__restrict__ probs,
-                                                         const WorkItem *__restrict__ rblk,
-                                                         const int32_t *__restrict__ want, int max_nrhs) {
-    const WorkItem it = rblk[blockIdx.x];
-    const ProbDev &P = probs[it.p];
-    const int rhs = blockIdx.z;
-    if (rhs >= P.nrhs) return;
-    const int wnt = want[it.p * max_nrhs + rhs];
-    const double beta = P.rnorm[rhs];
-    const int i = it.s * BROWS + threadIdx.x;
-    if (wnt && beta > 0.0 && i < P.n) vcol_w(P, rhs, 0)[i] *= 1.0 / beta;
-    if (it.s == 0 && threadIdx.x == 0) {
-        double *gg = P.g + (int64_t)rhs * (P.restart + 1);
-        for (int k = 0; k <= P.restart; ++k) gg[k] = 0.0;
-        gg[0] = beta;
-        double *sc = P.scal + (int64_t)rhs * 8;
-        sc[0] = beta;
-        sc[2] = beta;
-        sc[3] = 0.0;
-        sc[4] = 0.0;
-        sc[5] = 0.0;
-        P.jcur[rhs] = 0;
-        P.active[rhs] = (wnt && beta > 0.0) ? 1 : 0;
-    }
-}
-
-int32_t batch_cycle_start(const BatchGeom &g, const ProbDev *probs, const WorkItem *rblk, const int32_t *want,
-                          hipStream_t s) {
-    hipLaunchKernelGGL(k_b_cycle_start, dim3(g.nrblk, 1, g.max_nrhs), dim3(BROWS), 0, s, probs, rblk, want, g.max_nrhs);
-    HKG_HIP(hipGetLastError());
-    return HKG_OK;
-}
-
-// y = R^{-1} g on the rotated Hessenberg (each block redundantly, one thread), then x += Zk y
-__global__ __launch_bounds__(BROWS) void k_b_cycle_update(const ProbDev *__restrict__ probs,
-                                                          const WorkItem *__restrict__ rblk) {
+// x += Z_k y with y = R^{-1} g from the rotated Hessenberg (PS_CYCLE_END; each block solves the small
+// triangle redundantly on one thread), or x = 0 (PS_NEW)
+__global__ __launch_bounds__(BROWS) void k_r_update_x(const ProbDev *__restrict__ probs,
+                                                      const WorkItem *__restrict__ rblk) {
     extern __shared__ double y[];
     const WorkItem it = rblk[blockIdx.x];
     const ProbDev &P = probs[it.p];
     const int rhs = blockIdx.z;
     if (rhs >= P.nrhs) return;
+    const int st = P.active[rhs];
+    const int r = it.s * BROWS + threadIdx.x;
+    double *x = P.x + (int64_t)rhs * P.ldx;
+    if (st == PS_NEW) {
+        if (r < P.n) x[r] = 0.0;
+        return;
+    }
+    if (st != PS_CYCLE_END) return;
     const int m = P.restart;
     const int jd = (int)P.scal[(int64_t)rhs * 8 + 3];
     if (jd <= 0) return;
@@ -513,17 +433,113 @@ __global__ __launch_bounds__(BROWS) void k_b_cycle_update(const ProbDev *__restr
         }
     }
     __syncthreads();
-    const int r = it.s * BROWS + threadIdx.x;
     if (r >= P.n) return;
     const double *Zk = zcol(P, rhs, 0);
-    double s = P.x[(int64_t)rhs * P.ldx + r];
+    double s = x[r];
     for (int i = 0; i < jd; ++i) s = fma(Zk[(int64_t)i * P.n + r], y[i], s);
-    P.x[(int64_t)rhs * P.ldx + r] = s;
+    x[r] = s;
 }
 
-int32_t batch_cycle_update(const BatchGeom &g, const ProbDev *probs, const WorkItem *rblk, hipStream_t s) {
-    hipLaunchKernelGGL(k_b_cycle_update, dim3(g.nrblk, 1, g.max_nrhs), dim3(BROWS), (size_t)g.restart * sizeof(double), s,
-                       probs, rblk);
+// V[:, 0] = f - B x (PS_NEW: x = 0, so V[:, 0] = f) and partial squared norms per row block
+__global__ __launch_bounds__(BROWS) void k_r_residual(const ProbDev *__restrict__ probs,
+                                                      const WorkItem *__restrict__ rblk) {
+    __shared__ double red[BROWS / 64];
+    const WorkItem it = rblk[blockIdx.x];
+    const ProbDev &P = probs[it.p];
+    const int rhs = blockIdx.z;
+    if (rhs >= P.nrhs) return;
+    const int st = P.active[rhs];
+    if (st != PS_NEW && st != PS_CYCLE_END) return;
+    const int i = it.s * BROWS + threadIdx.x;
+    double v = 0.0;
+    if (i < P.n) {
+        v = P.f[(int64_t)rhs * P.ldf + i];
+        if (st == PS_CYCLE_END) {
+            const double *x = P.x + (int64_t)rhs * P.ldx;
+            double s = 0.0;
+            for (int t = P.rowptr[i]; t < P.rowptr[i + 1]; ++t) s = fma(P.Bval[t], x[P.colidx[t]], s);
+            v -= s;
+        }
+        vcol_w(P, rhs, 0)[i] = v;
+    }
+    const double s = bwsum(v * v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < BROWS / 64; ++w) t += red[w];
+        P.part[(int64_t)rhs * 2 * P.nblk * (P.restart + 2) + it.s] = t;
+    }
+}
+
+// per pair: ||r|| (fixed order over row blocks); stop (converged, ||f|| = 0 or out of iterations) or
+// start a new cycle: beta = ||r||, g = beta e_1, j = 0
+__global__ void k_r_decide(const ProbDev *__restrict__ probs, const int32_t *__restrict__ live, int nlive,
+                           int max_nrhs) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nlive * max_nrhs) return;
+    const ProbDev &P = probs[live[t / max_nrhs]];
+    const int rhs = t % max_nrhs;
+    if (rhs >= P.nrhs) return;
+    const int st = P.active[rhs];
+    if (st != PS_NEW && st != PS_CYCLE_END) return;
+    const double *pp = P.part + (int64_t)rhs * 2 * P.nblk * (P.restart + 2);
+    double s = 0.0;
+    for (int b = 0; b < P.nblk; ++b) s += pp[b];
+    const double rn = sqrt(s);
+    P.rnorm[rhs] = rn;
+    double *sc = P.scal + (int64_t)rhs * 8;
+    if (st == PS_NEW) {
+        for (int k = 0; k < 8; ++k) sc[k] = 0.0;
+        sc[1] = rn;
+        sc[2] = rn;
+        P.iters[rhs] = 0;
+    }
+    const double fn = sc[1];
+    if (fn == 0.0 || rn <= P.rtol * fn || P.iters[rhs] >= P.max_iter) {
+        P.active[rhs] = PS_DONE;
+        return;
+    }
+    double *g = P.g + (int64_t)rhs * (P.restart + 1);
+    for (int k = 0; k <= P.restart; ++k) g[k] = 0.0;
+    g[0] = rn;
+    sc[0] = rn;
+    sc[2] = rn;
+    sc[3] = 0.0;
+    sc[4] = 0.0;
+    sc[5] = 0.0;
+    P.jcur[rhs] = 0;
+    P.active[rhs] = PS_START;
+}
+
+// v_0 = r / beta for the pairs starting a cycle
+__global__ __launch_bounds__(BROWS) void k_r_start(const ProbDev *__restrict__ probs, const WorkItem *__restrict__ rblk) {
+    const WorkItem it = rblk[blockIdx.x];
+    const ProbDev &P = probs[it.p];
+    const int rhs = blockIdx.z;
+    if (rhs >= P.nrhs || P.active[rhs] != PS_START) return;
+    const int i = it.s * BROWS + threadIdx.x;
+    if (i < P.n) vcol_w(P, rhs, 0)[i] *= 1.0 / P.rnorm[rhs];
+}
+
+__global__ void k_r_activate(const ProbDev *__restrict__ probs, const int32_t *__restrict__ live, int nlive,
+                             int max_nrhs) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nlive * max_nrhs) return;
+    const ProbDev &P = probs[live[t / max_nrhs]];
+    const int rhs = t % max_nrhs;
+    if (rhs < P.nrhs && P.active[rhs] == PS_START) P.active[rhs] = PS_ITER;
+}
+
+int32_t batch_restart(const BatchGeom &g, const ProbDev *probs, const WorkItem *rblk, const int32_t *live,
+                      hipStream_t s) {
+    const dim3 grid(g.nrblk, 1, g.max_nrhs);
+    const int pairs = g.nprob * g.max_nrhs;
+    hipLaunchKernelGGL(k_r_update_x, grid, dim3(BROWS), (size_t)g.restart * sizeof(double), s, probs, rblk);
+    hipLaunchKernelGGL(k_r_residual, grid, dim3(BROWS), 0, s, probs, rblk);
+    hipLaunchKernelGGL(k_r_decide, dim3((pairs + 255) / 256), dim3(256), 0, s, probs, live, g.nprob, g.max_nrhs);
+    hipLaunchKernelGGL(k_r_start, grid, dim3(BROWS), 0, s, probs, rblk);
+    hipLaunchKernelGGL(k_r_activate, dim3((pairs + 255) / 256), dim3(256), 0, s, probs, live, g.nprob, g.max_nrhs);
     HKG_HIP(hipGetLastError());
     return HKG_OK;
 }

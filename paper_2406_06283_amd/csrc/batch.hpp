@@ -1,11 +1,13 @@
-// Batched FGMRES iteration over several set-up problems: descriptors shared by the host driver and
-// the kernels of batch.hip.
+// Batched FGMRES over several set-up problems: descriptors shared by the host engine and the kernels
+// of batch.hip.
 //
-// Every per-iteration kernel takes the table of ProbDev descriptors and a flattened work list, so a
-// single launch covers all (problem, subdomain or row block, right-hand side) items of the batch,
-// whatever their sizes.  The Arnoldi index j of each (problem, rhs) lives on the device (jcur) and is
-// advanced by the last kernel of the iteration, so one iteration is the same launch sequence every
-// time: it is captured once as a HIP graph and replayed.
+// Every kernel takes the table of ProbDev descriptors and a flattened work list, so a single launch
+// covers all (problem, subdomain or row block, right-hand side) items of the live set, whatever their
+// sizes.  The Arnoldi index j and the state of each (problem, rhs) pair live on the device, so one
+// iteration is the same launch sequence every time (captured once as a HIP graph and replayed), and
+// so is the restart phase that ends a pair's cycle, tests its true residual and starts the next
+// cycle or retires it.  Pairs therefore restart independently, and problems can join or leave the
+// live set at any iteration boundary.
 #pragma once
 
 #include "kernels.hpp"
@@ -13,6 +15,15 @@
 namespace hkg {
 
 constexpr int BROWS = 256;          // rows per row block (one per thread)
+
+// state of one (problem, rhs) pair, kept on the device
+enum : int32_t {
+    PS_DONE = 0,        // finished (or not started)
+    PS_ITER = 1,        // inside an FGMRES cycle: the iteration kernels advance it
+    PS_CYCLE_END = 2,   // cycle ended: the restart phase updates x and decides
+    PS_NEW = 3,         // just admitted: the restart phase starts it from x = 0
+    PS_START = 4,       // transient inside the restart phase
+};
 
 struct ProbDev {
     int32_t n, nsub, m0, maxnI, nchunk, nblk, nrhs, restart;
@@ -53,15 +64,16 @@ struct BatchGeom {
     int local_waves = 8;        // chosen by the autotuner
 };
 
+// live: table indices of the g.nprob live problems (pair t of the per-pair kernels is
+// (live[t / max_nrhs], t % max_nrhs)); work lists name table indices directly.
 // mode 0: standalone application (xin -> xout); mode 1: FGMRES iteration (V[:, j] -> Zk[:, j])
 int32_t batch_apply(const BatchGeom &g, const ProbDev *probs, const WorkItem *items, const WorkItem *rblk,
                     const WorkItem *cblk, int mode, hipStream_t s, hipEvent_t ev0 = nullptr,
                     hipEvent_t ev1 = nullptr);
-int32_t batch_arnoldi(const BatchGeom &g, const ProbDev *probs, const WorkItem *rblk, hipStream_t s);
-// residual r = f - B x into V[:, 0] and its norm into rnorm (x = 0: the norm of f into scal[1] too)
-int32_t batch_residual(const BatchGeom &g, const ProbDev *probs, const WorkItem *rblk, int init, hipStream_t s);
-int32_t batch_cycle_start(const BatchGeom &g, const ProbDev *probs, const WorkItem *rblk, const int32_t *want,
-                          hipStream_t s);
-int32_t batch_cycle_update(const BatchGeom &g, const ProbDev *probs, const WorkItem *rblk, hipStream_t s);
+int32_t batch_arnoldi(const BatchGeom &g, const ProbDev *probs, const WorkItem *rblk, const int32_t *live,
+                      hipStream_t s);
+// restart phase for PS_CYCLE_END / PS_NEW pairs: x update, true residual, stop or next cycle
+int32_t batch_restart(const BatchGeom &g, const ProbDev *probs, const WorkItem *rblk, const int32_t *live,
+                      hipStream_t s);
 
 }  // namespace hkg

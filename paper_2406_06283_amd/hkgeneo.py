@@ -61,6 +61,13 @@ class hkgeneo_stats(ctypes.Structure):
                 ("device_bytes", c_int64), ("setup_ms", c_double)]
 
 
+class hkgeneo_server_stats(ctypes.Structure):
+    _fields_ = [("queued", c_int32), ("live", c_int32), ("live_rhs", c_int32), ("completed_waiting", c_int32),
+                ("local_waves", c_int32), ("pad_", c_int32), ("workspace_bytes", c_int64), ("device_bytes", c_int64),
+                ("iterations", c_int64), ("restarts", c_int64), ("captures", c_int64), ("admitted", c_int64),
+                ("retired", c_int64)]
+
+
 # name -> (restype, argtypes); mirrors include/hkgeneo.h
 SIGNATURES = {
     "hkgeneo_default_options": (None, [POINTER(hkgeneo_options)]),
@@ -84,6 +91,12 @@ SIGNATURES = {
     "hkgeneo_batch_bytes": (c_int64, [c_void_p]),
     "hkgeneo_batch_local_waves": (c_int32, [c_void_p]),
     "hkgeneo_batch_destroy": (None, [c_void_p]),
+    "hkgeneo_server_create": (c_int32, [c_int64, c_int32, c_int32, c_int32, POINTER(c_void_p)]),
+    "hkgeneo_server_submit": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_int64, c_void_p]),
+    "hkgeneo_server_pump": (c_int32, [c_void_p, c_int32, _i32p]),
+    "hkgeneo_server_poll": (c_int32, [c_void_p, POINTER(c_int64), _i32p, POINTER(hkgeneo_rhs_info), c_int32]),
+    "hkgeneo_server_query": (c_int32, [c_void_p, POINTER(hkgeneo_server_stats)]),
+    "hkgeneo_server_destroy": (None, [c_void_p]),
     "hkgeneo_destroy": (None, [c_void_p]),
     "hkgeneo_strerror": (c_char_p, [c_int32]),
     "hkgeneo_last_error": (c_char_p, []),
@@ -381,6 +394,76 @@ class Batch:
         if getattr(self, "handle", None) is not None and self.handle.value:
             self.lib.hkgeneo_batch_destroy(self.handle)
             self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class Server:
+    """Continuous batching of solve requests (hkgeneo_server_* of the C ABI).
+
+    submit(solver, f, tag) queues a request (f: (nrhs, n) float64 GPU tensor; the solution tensor is
+    allocated here and kept with the request); pump(periods) advances the live set; poll() returns
+    the finished requests as (tag, u, [info dict per rhs], status).
+    """
+
+    def __init__(self, workspace_budget: int, max_requests: int = 64, max_nrhs: int = 8, restart: int = 50):
+        self.lib = load()
+        self.handle = c_void_p()
+        self.max_nrhs = int(max_nrhs)
+        self._reqs = {}
+        _check(self.lib.hkgeneo_server_create(int(workspace_budget), int(max_requests), self.max_nrhs, int(restart),
+                                              ctypes.byref(self.handle)), "hkgeneo_server_create")
+
+    def submit(self, solver, f, tag: int, stream=None):
+        import torch
+        fb = solver._as_block(f)
+        u = torch.empty_like(fb)
+        if tag in self._reqs:
+            raise ValueError(f"tag {tag} is already pending")
+        _check(self.lib.hkgeneo_server_submit(self.handle, solver.handle, c_void_p(fb.data_ptr()),
+                                              c_void_p(u.data_ptr()), fb.shape[0], solver.n, int(tag),
+                                              _stream_handle(stream)), "hkgeneo_server_submit")
+        self._reqs[tag] = (solver, fb, u)      # keeps f, u and the context alive until polled
+        return u
+
+    def pump(self, periods: int = 1) -> int:
+        pending = c_int32()
+        _check(self.lib.hkgeneo_server_pump(self.handle, int(periods), ctypes.byref(pending)), "hkgeneo_server_pump")
+        return pending.value
+
+    def poll(self):
+        out = []
+        infos = (hkgeneo_rhs_info * self.max_nrhs)()
+        tag, st = c_int64(), c_int32()
+        while True:
+            n = _check(self.lib.hkgeneo_server_poll(self.handle, ctypes.byref(tag), ctypes.byref(st), infos,
+                                                    self.max_nrhs), "hkgeneo_server_poll")
+            if n == 0:
+                return out
+            _, _, u = self._reqs.pop(tag.value)
+            out.append((tag.value, u, [dict(iters=i.iters, converged=bool(i.converged), relres_est=i.relres_est,
+                                            relres_true=i.relres_true) for i in infos[:n]], st.value))
+
+    def stats(self) -> dict:
+        s = hkgeneo_server_stats()
+        _check(self.lib.hkgeneo_server_query(self.handle, ctypes.byref(s)), "hkgeneo_server_query")
+        return {name: getattr(s, name) for name, _ in s._fields_ if name != "pad_"}
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            self.lib.hkgeneo_server_destroy(self.handle)
+            self.handle = None
+            self._reqs.clear()
 
     def __del__(self):
         try:

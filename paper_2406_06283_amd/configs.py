@@ -85,7 +85,9 @@ class MixMember:
     overlap: tuple
     coef: str
     nrhs: int
+    eig_mode: int
     nev: int
+    tau: float
 
     @property
     def name(self) -> str:
@@ -97,14 +99,20 @@ class MixMember:
 
 
 def batch_mix(count: int = 64, seed0: int = 0, n_choices=(64, 128, 192, 256), s_range=(4, 16),
-              nrhs_range=(1, 8), nev: int = 12, max_block: int | None = 32) -> list[MixMember]:
+              nrhs_range=(1, 8), tau: float | None = 0.85, nev: int = 12,
+              max_block: int | None = 16) -> list[MixMember]:
     """Independent 2D problems for batched solves: h uniform over 1/n_choices, k = 0.3/h, an s x s
     floor partition with s uniform in s_range, overlap uniform in {1, 2, 3} per subdomain,
     coefficients alternating piecewise constant on 16x16 cells (log10 a ~ U[0, 2]) and lognormal,
-    nrhs uniform in nrhs_range with nodal N(0, 1) data, nev eigenvectors per subdomain.
+    nrhs uniform in nrhs_range with nodal N(0, 1) data.
 
-    max_block caps the elements per block side (s is raised to ceil(N / max_block)), which keeps the
-    dense local eigenproblems at the size of the single-problem workloads; None draws s unchanged.
+    Eigenvectors: every eigenvalue below tau (the threshold rule of Def 2.15, as in the single
+    workloads), or nev per subdomain when tau is None.  A fixed count does not follow k: with
+    nev = 12, the h = 1/256 members (k = 76.8) stagnate.
+
+    max_block caps the elements per block side (s is raised to ceil(N / max_block)), which keeps
+    H k <= 0.3 max_block (4.8 by default, the regime of the single-problem workloads) and the dense
+    local eigenproblems at their size; None draws s unchanged.
     """
     out = []
     for q in range(count):
@@ -117,5 +125,13 @@ def batch_mix(count: int = 64, seed0: int = 0, n_choices=(64, 128, 192, 256), s_
         ov = tuple(int(v) for v in rng.integers(1, 4, size=s * s))
         nrhs = int(rng.integers(nrhs_range[0], nrhs_range[1] + 1))
         out.append(MixMember(seed=seed, N=N, k=0.3 * N, s=s, overlap=ov, coef="cells" if q % 2 == 0 else "lognormal",
-                             nrhs=nrhs, nev=nev))
+                             nrhs=nrhs, eig_mode=EIG_FIXED if tau is None else EIG_THRESHOLD,
+                             nev=nev if tau is None else 0, tau=0.0 if tau is None else float(tau)))
     return out
+
+
+def mix_options(m: MixMember, **overrides) -> dict:
+    """Keyword options (hkgeneo.default_options) of a mix member."""
+    kw = dict(eig_mode=m.eig_mode, nev=m.nev, tau=m.tau)
+    kw.update(overrides)
+    return kw

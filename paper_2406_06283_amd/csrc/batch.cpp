@@ -8,7 +8,8 @@
 // iterating pair) and the restart phase (x update, true residual, stop or new cycle for every pair
 // at a cycle boundary).  The host reads the pair states every `check` iterations, launches the
 // restart graph when some pair waits for it, retires finished requests and admits queued ones; a
-// change of the live set rebuilds the work lists and re-captures both graphs.
+// change of the live set rebuilds the work lists and re-captures the graphs (the iteration once per
+// parity of the double-buffered Arnoldi index, replayed alternately).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -68,11 +69,13 @@ struct hkgeneo_server {
     DevBuf d_probs, d_items, d_rblk, d_cblk, d_live, d_state, d_scratch;
     int32_t *h_state = nullptr;         // pinned mirror of d_state
     std::vector<int32_t> live;
+    std::vector<int64_t> built_sig;     // geometry of the live set the graphs were captured for
     BatchGeom geom;
     bool dirty = true, need_restart = false, any_iter = false;
     hipStream_t stream = nullptr;
-    hipGraph_t it_graph = nullptr, rs_graph = nullptr;
-    hipGraphExec_t it_exec = nullptr, rs_exec = nullptr;
+    hipGraph_t it_graph[2] = {nullptr, nullptr}, rs_graph = nullptr;
+    hipGraphExec_t it_exec[2] = {nullptr, nullptr}, rs_exec = nullptr;
+    int parity = 0;
     int64_t n_iter_launch = 0, n_restart_launch = 0, n_capture = 0, n_admitted = 0, n_retired = 0;
 };
 
@@ -118,7 +121,7 @@ void ws_sizes(const hkgeneo_ctx *c, int R, int m, size_t out[NWS]) {
                            (size_t)8 * R,                  // scal
                            (size_t)R,                      // rnorm
                            (size_t)(R + 1) / 2,            // iters (int32)
-                           (size_t)(R + 1) / 2};           // jcur (int32)
+                           (size_t)R};                     // jcur (2 int32 per rhs)
     std::memcpy(out, v, sizeof(v));
 }
 
@@ -170,8 +173,8 @@ int32_t admit_one(Engine *E, Request *q, int slot) {
     P.nsub = c->n_sub;
     P.m0 = c->opt.two_level ? c->m0 : 0;
     P.maxnI = c->max_nI;
-    P.nchunk = std::max(1, (P.m0 + 63) / 64);
     P.nblk = (P.n + BROWS - 1) / BROWS;
+    P.nchunk = std::max(1, (P.m0 + 63) / 64);
     P.nrhs = R;
     P.restart = m;
     P.local_f32 = c->opt.local_prec == 32;
@@ -282,7 +285,7 @@ int32_t autotune(Engine *E) {
         for (int rep = 0; rep < 6 && st == HKG_OK; ++rep) {
             float ms = 0.0f;
             st = batch_apply(gg, dp<ProbDev>(E->d_probs), dp<WorkItem>(E->d_items), dp<WorkItem>(E->d_rblk),
-                             dp<WorkItem>(E->d_cblk), 0, E->stream, e0, e1);
+                             dp<WorkItem>(E->d_cblk), 0, 0, E->stream, e0, e1);
             if (st == HKG_OK && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
                 st = HKG_EHIP;
             if (rep > 0) tot += ms;
@@ -303,12 +306,16 @@ int32_t autotune(Engine *E) {
 }
 
 void drop_graphs(Engine *E) {
-    if (E->it_exec) (void)hipGraphExecDestroy(E->it_exec);
+    for (int k = 0; k < 2; ++k) {
+        if (E->it_exec[k]) (void)hipGraphExecDestroy(E->it_exec[k]);
+        if (E->it_graph[k]) (void)hipGraphDestroy(E->it_graph[k]);
+        E->it_exec[k] = nullptr;
+        E->it_graph[k] = nullptr;
+    }
     if (E->rs_exec) (void)hipGraphExecDestroy(E->rs_exec);
-    if (E->it_graph) (void)hipGraphDestroy(E->it_graph);
     if (E->rs_graph) (void)hipGraphDestroy(E->rs_graph);
-    E->it_exec = E->rs_exec = nullptr;
-    E->it_graph = E->rs_graph = nullptr;
+    E->rs_exec = nullptr;
+    E->rs_graph = nullptr;
 }
 
 template <typename F>
@@ -331,13 +338,33 @@ int32_t capture(Engine *E, F &&body, hipGraph_t *graph, hipGraphExec_t *exec) {
     return HKG_OK;
 }
 
+// geometry of the live set: everything the work lists, launch shapes and graphs depend on (the
+// descriptor contents are read by the kernels at run time and may change freely)
+std::vector<int64_t> live_signature(const Engine *E) {
+    std::vector<int64_t> sig;
+    for (int s = 0; s < E->cap; ++s)
+        if (E->slot_req[s]) {
+            const ProbDev &P = E->table[s];
+            sig.insert(sig.end(), {s, P.n, P.nsub, P.maxnI, P.nblk, P.two_level, P.local_f32, P.m0});
+        }
+    return sig;
+}
+
 // work lists, descriptor table and graphs for the current live set
 int32_t rebuild(Engine *E) {
+    HKG_HIP(hipStreamSynchronize(E->stream));    // no launch of the old graphs is in flight
+    E->dirty = false;
+    std::vector<int64_t> sig = live_signature(E);
+    if (!sig.empty() && sig == E->built_sig && E->it_exec[0]) {
+        // same geometry: the lists and graphs stand, only the descriptors change
+        return upload_bytes(&E->acct, &E->d_probs, E->table.data(), E->table.size() * sizeof(ProbDev), E->stream,
+                            true);
+    }
     drop_graphs(E);
+    E->built_sig.clear();
     E->live.clear();
     for (int s = 0; s < E->cap; ++s)
         if (E->slot_req[s]) E->live.push_back(s);
-    E->dirty = false;
     BatchGeom &g = E->geom;
     const int waves = g.local_waves;
     g = BatchGeom{};
@@ -375,14 +402,16 @@ int32_t rebuild(Engine *E) {
     const ProbDev *probs = dp<ProbDev>(E->d_probs);
     const WorkItem *it = dp<WorkItem>(E->d_items), *rb = dp<WorkItem>(E->d_rblk), *cb = dp<WorkItem>(E->d_cblk);
     const int32_t *lv = dp<int32_t>(E->d_live);
-    HKG_TRY(capture(
-        E,
-        [&]() {
-            HKG_TRY(batch_apply(g, probs, it, rb, cb, 1, E->stream));
-            return batch_arnoldi(g, probs, rb, lv, E->stream);
-        },
-        &E->it_graph, &E->it_exec));
+    for (int par = 0; par < 2; ++par)
+        HKG_TRY(capture(
+            E,
+            [&]() {
+                HKG_TRY(batch_apply(g, probs, it, rb, cb, 1, par, E->stream));
+                return batch_arnoldi(g, probs, rb, par, E->stream);
+            },
+            &E->it_graph[par], &E->it_exec[par]));
     HKG_TRY(capture(E, [&]() { return batch_restart(g, probs, rb, lv, E->stream); }, &E->rs_graph, &E->rs_exec));
+    E->built_sig = std::move(sig);
     return HKG_OK;
 }
 
@@ -433,7 +462,10 @@ int32_t pump_once(Engine *E, int *pending) {
             ran = true;
         }
         if (ran || E->any_iter) {
-            for (int k = 0; k < E->check; ++k) HKG_HIP(hipGraphLaunch(E->it_exec, E->stream));
+            for (int k = 0; k < E->check; ++k) {
+                HKG_HIP(hipGraphLaunch(E->it_exec[E->parity], E->stream));
+                E->parity ^= 1;
+            }
             E->n_iter_launch += E->check;
         }
         HKG_HIP(hipMemcpyAsync(E->h_state, E->d_state.p, (size_t)E->cap * E->maxR * sizeof(int32_t),

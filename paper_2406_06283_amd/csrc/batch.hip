@@ -14,8 +14,6 @@ namespace hkg {
 
 constexpr int LS_ROWS = 64;
 constexpr int NPART = 16;        // partial sums per local-solve row (a multiple of every wave count)
-constexpr int CG_ROWS = 64;
-constexpr int CG_COLS = 64;
 
 __device__ __forceinline__ double bwsum(double v) {
 #pragma unroll
@@ -23,9 +21,37 @@ __device__ __forceinline__ double bwsum(double v) {
     return v;
 }
 
+// Loads in the loops below are never guarded by a wave-uniform branch: a branch around a load makes the
+// wave wait for it before the next one issues.  Indices are clamped into range instead and only the
+// arithmetic is masked, so every load of an unrolled group is in flight at once.
+
+// sum over the nonzeros of row i of val[t] x[col[t]], eight at a time, in index order
+__device__ __forceinline__ double csr_row_dot(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+                                              const double *__restrict__ val, const double *__restrict__ x, int i) {
+    const int t0 = rowptr[i], t1 = rowptr[i + 1];
+    double s = 0.0;
+    for (int t = t0; t < t1; t += 8) {
+        int c[8];
+        double v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int tt = min(t + k, t1 - 1);
+            c[k] = col[tt];
+            v[k] = t + k < t1 ? val[tt] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s = fma(v[k], x[c[k]], s);
+    }
+    return s;
+}
+
 __device__ __forceinline__ bool inactive(const ProbDev &P, int rhs, int mode) {
     return rhs >= P.nrhs || (mode == 1 && P.active[rhs] != PS_ITER);
 }
+
+// Arnoldi index of a pair, double-buffered: iteration graphs alternate the parity `par`; an iteration
+// reads jcur[2 rhs + par] and its last kernel writes jcur[2 rhs + 1 - par]
+__device__ __forceinline__ int jget(const ProbDev &P, int rhs, int par) { return P.jcur[2 * rhs + par]; }
 
 __device__ __forceinline__ const double *vcol(const ProbDev &P, int rhs, int j) {
     return P.V + (int64_t)rhs * P.n * (P.restart + 1) + (int64_t)j * P.n;
@@ -117,7 +143,7 @@ __device__ __forceinline__ void local_body(const ProbDev &P, const SubDev &sd, c
 
 template <int WAVES>
 __global__ __launch_bounds__(LS_ROWS *WAVES) void k_b_local(const ProbDev *__restrict__ probs,
-                                                            const WorkItem *__restrict__ items, int mode) {
+                                                            const WorkItem *__restrict__ items, int mode, int par) {
     extern __shared__ double sh[];
     const WorkItem it = items[blockIdx.y];
     const ProbDev &P = probs[it.p];
@@ -127,12 +153,16 @@ __global__ __launch_bounds__(LS_ROWS *WAVES) void k_b_local(const ProbDev *__res
     const int tiles = (sd.nI + LS_ROWS - 1) / LS_ROWS;
     const bool coarse = P.two_level && P.m0 > 0;
     if ((int)blockIdx.x > tiles || ((int)blockIdx.x == tiles && (!coarse || sd.m == 0))) return;
-    const double *r = (mode == 0) ? P.xin + (int64_t)rhs * P.ldin : vcol(P, rhs, P.jcur[rhs]);
+    const double *r = (mode == 0) ? P.xin + (int64_t)rhs * P.ldin : vcol(P, rhs, jget(P, rhs, par));
     if (P.local_f32) local_body<float, WAVES>(P, sd, r, rhs, sh);
     else local_body<double, WAVES>(P, sd, r, rhs, sh);
 }
 
-// partial coarse products: ypart[chunk][row] = sum over the chunk's columns of B_0^{-1}[row, col] c[col]
+// Coarse solve y = B_0^{-1} c in two launches: split-K partial products over (64-row tile, 64-column
+// chunk) blocks, then per subdomain the fixed-order sum of its rows' partials and u_D += Z_i y_i.
+constexpr int CG_ROWS = 64;
+constexpr int CG_COLS = 64;
+
 __global__ __launch_bounds__(256) void k_b_coarse_gemv(const ProbDev *__restrict__ probs,
                                                        const WorkItem *__restrict__ cblk, int mode) {
     __shared__ double cs[CG_COLS];
@@ -140,54 +170,69 @@ __global__ __launch_bounds__(256) void k_b_coarse_gemv(const ProbDev *__restrict
     const WorkItem it = cblk[blockIdx.x];
     const ProbDev &P = probs[it.p];
     const int rhs = blockIdx.z;
-    if (inactive(P, rhs, mode) || !P.two_level || P.m0 == 0) return;
+    if (inactive(P, rhs, mode) || !P.two_level) return;
     const int m0 = P.m0;
     const int rt = it.s / P.nchunk, ch = it.s % P.nchunk;
     const int col0 = ch * CG_COLS;
     const int ncol = min(CG_COLS, m0 - col0);
-    for (int i = threadIdx.x; i < ncol; i += 256) cs[i] = P.c[(int64_t)rhs * m0 + col0 + i];
+    if ((int)threadIdx.x < ncol) cs[threadIdx.x] = P.c[(int64_t)rhs * m0 + col0 + threadIdx.x];
     __syncthreads();
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int row = rt * CG_ROWS + lane;
+    const double *B = P.B0inv + min(row, m0 - 1) + (int64_t)col0 * m0;
+    double v[CG_COLS / 4];
+#pragma unroll
+    for (int q = 0; q < CG_COLS / 4; ++q) v[q] = B[(int64_t)min(wv + 4 * q, ncol - 1) * m0];
     double acc = 0.0;
-    if (row < m0) {
-        const double *B = P.B0inv + row + (int64_t)col0 * m0;
-#pragma unroll 4
-        for (int k = wv; k < ncol; k += 4) acc = fma(B[(int64_t)k * m0], cs[k], acc);
-    }
+#pragma unroll
+    for (int q = 0; q < CG_COLS / 4; ++q) acc = fma(v[q], wv + 4 * q < ncol ? cs[min(wv + 4 * q, ncol - 1)] : 0.0, acc);
     part[wv][lane] = acc;
     __syncthreads();
     if (wv == 0 && row < m0)
         P.ypart[((int64_t)rhs * P.nchunk + ch) * m0 + row] = part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane];
 }
 
-// per subdomain: y_i = sum of the chunk partials (fixed order), u_D += Z_i y_i
+constexpr int CA_ROWS = 16;     // columns of Z_i prefetched before the partial sums arrive
+
 __global__ __launch_bounds__(256) void k_b_coarse_add(const ProbDev *__restrict__ probs,
                                                       const WorkItem *__restrict__ items, int mode) {
     __shared__ double ys[64];
     const WorkItem it = items[blockIdx.y];
     const ProbDev &P = probs[it.p];
     const int rhs = blockIdx.z;
-    if (inactive(P, rhs, mode) || !P.two_level || P.m0 == 0) return;
+    if (inactive(P, rhs, mode) || !P.two_level) return;
     const SubDev sd = P.subs[it.s];
-    if (sd.m == 0 || (int)blockIdx.x * 256 >= sd.nI) return;
-    if (threadIdx.x < sd.m) {
+    const int m = sd.m;
+    if (m == 0 || (int)blockIdx.x * 256 >= sd.nI) return;
+    const int a = blockIdx.x * 256 + threadIdx.x, ac = min(a, sd.nI - 1);
+    const double *z = P.Z + sd.offZ + ac;
+    double zv[CA_ROWS];
+#pragma unroll
+    for (int k = 0; k < CA_ROWS; ++k) zv[k] = z[(int64_t)min(k, m - 1) * sd.nI];
+    if ((int)threadIdx.x < m) {
+        const double *yp = P.ypart + (int64_t)rhs * P.nchunk * P.m0 + sd.offm + threadIdx.x;
         double s = 0.0;
-        for (int k = 0; k < P.nchunk; ++k) s += P.ypart[((int64_t)rhs * P.nchunk + k) * P.m0 + sd.offm + threadIdx.x];
+        for (int k0 = 0; k0 < P.nchunk; k0 += 4) {
+            double v[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) v[k] = yp[(int64_t)min(k0 + k, P.nchunk - 1) * P.m0];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) s += k0 + k < P.nchunk ? v[k] : 0.0;
+        }
         ys[threadIdx.x] = s;
     }
     __syncthreads();
-    const int a = blockIdx.x * 256 + threadIdx.x;
     if (a >= sd.nI) return;
-    const double *z = P.Z + sd.offZ + a;
-    double s = 0.0;
-    for (int b = 0; b < sd.m; ++b) s = fma(z[(int64_t)b * sd.nI], ys[b], s);
-    P.u[(int64_t)rhs * P.sum_nI + sd.offI + a] += s;
+    double t = 0.0;
+#pragma unroll
+    for (int k = 0; k < CA_ROWS; ++k) t = fma(zv[k], k < m ? ys[min(k, m - 1)] : 0.0, t);
+    for (int k = CA_ROWS; k < m; ++k) t = fma(z[(int64_t)k * sd.nI], ys[k], t);
+    P.u[(int64_t)rhs * P.sum_nI + sd.offI + a] += t;
 }
 
 // z_l = sum over the transpose map of u (fixed order)
 __global__ __launch_bounds__(BROWS) void k_b_prolong(const ProbDev *__restrict__ probs,
-                                                     const WorkItem *__restrict__ rblk, int mode) {
+                                                     const WorkItem *__restrict__ rblk, int mode, int par) {
     const WorkItem it = rblk[blockIdx.x];
     const ProbDev &P = probs[it.p];
     const int rhs = blockIdx.z;
@@ -195,29 +240,35 @@ __global__ __launch_bounds__(BROWS) void k_b_prolong(const ProbDev *__restrict__
     const int l = it.s * BROWS + threadIdx.x;
     if (l >= P.n) return;
     const double *uu = P.u + (int64_t)rhs * P.sum_nI;
+    const int t0 = P.tp_ptr[l], t1 = P.tp_ptr[l + 1];
     double s = 0.0;
-    for (int t = P.tp_ptr[l]; t < P.tp_ptr[l + 1]; ++t) s += uu[P.tp_pos[t]];
-    double *z = (mode == 0) ? P.xout + (int64_t)rhs * P.ldout : zcol(P, rhs, P.jcur[rhs]);
+    for (int t = t0; t < t1; t += 4) {
+        double v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = uu[P.tp_pos[min(t + k, t1 - 1)]];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s += t + k < t1 ? v[k] : 0.0;
+    }
+    double *z = (mode == 0) ? P.xout + (int64_t)rhs * P.ldout : zcol(P, rhs, jget(P, rhs, par));
     z[l] = s;
 }
 
 int32_t batch_apply(const BatchGeom &g, const ProbDev *probs, const WorkItem *items, const WorkItem *rblk,
-                    const WorkItem *cblk, int mode, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+                    const WorkItem *cblk, int mode, int par, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     const dim3 gl(g.max_tiles + (g.any_coarse ? 1 : 0), g.nitems, g.max_nrhs);
     const size_t shm = (size_t)2 * g.max_nI * sizeof(double) + (size_t)NPART * LS_ROWS * sizeof(double);
     if (ev0) HKG_HIP(hipEventRecord(ev0, s));
     switch (g.local_waves) {
         case 4:
             hipLaunchKernelGGL(k_b_local<4>, gl, dim3(LS_ROWS * 4), shm, s, probs, items,
-                               mode);
+                               mode, par);
             break;
         case 16:
-            hipLaunchKernelGGL(k_b_local<16>, gl, dim3(LS_ROWS * 16), shm, s, probs,
-                               items, mode);
+            hipLaunchKernelGGL(k_b_local<16>, gl, dim3(LS_ROWS * 16), shm, s, probs, items, mode, par);
             break;
         default:
             hipLaunchKernelGGL(k_b_local<8>, gl, dim3(LS_ROWS * 8), shm, s, probs, items,
-                               mode);
+                               mode, par);
     }
     HKG_HIP(hipGetLastError());
     if (ev1) HKG_HIP(hipEventRecord(ev1, s));
@@ -226,7 +277,7 @@ int32_t batch_apply(const BatchGeom &g, const ProbDev *probs, const WorkItem *it
         hipLaunchKernelGGL(k_b_coarse_add, dim3((g.max_nI + 255) / 256, g.nitems, g.max_nrhs), dim3(256), 0, s, probs,
                            items, mode);
     }
-    hipLaunchKernelGGL(k_b_prolong, dim3(g.nrblk, 1, g.max_nrhs), dim3(BROWS), 0, s, probs, rblk, mode);
+    hipLaunchKernelGGL(k_b_prolong, dim3(g.nrblk, 1, g.max_nrhs), dim3(BROWS), 0, s, probs, rblk, mode, par);
     HKG_HIP(hipGetLastError());
     return HKG_OK;
 }
@@ -234,70 +285,105 @@ int32_t batch_apply(const BatchGeom &g, const ProbDev *probs, const WorkItem *it
 // ------------------------------------------------------------------------------------------------
 // Arnoldi step (CGS2) at the device-side index j = jcur
 // ------------------------------------------------------------------------------------------------
-// w = V[:, j+1] = B Zk[:, j]
-__global__ __launch_bounds__(BROWS) void k_b_spmv_next(const ProbDev *__restrict__ probs,
-                                                       const WorkItem *__restrict__ rblk) {
-    const WorkItem it = rblk[blockIdx.x];
-    const ProbDev &P = probs[it.p];
-    const int rhs = blockIdx.z;
-    if (inactive(P, rhs, 1)) return;
-    const int i = it.s * BROWS + threadIdx.x;
-    if (i >= P.n) return;
-    const int j = P.jcur[rhs];
-    const double *x = zcol(P, rhs, j);
-    double s = 0.0;
-    for (int t = P.rowptr[i]; t < P.rowptr[i + 1]; ++t) s = fma(P.Bval[t], x[P.colidx[t]], s);
-    vcol_w(P, rhs, j + 1)[i] = s;
-}
-
-// partial sums over the block's rows of x_i . w for i < ncol and of w . w (slot ncol)
-__device__ __forceinline__ void bdots(const double *__restrict__ X, int n, int ncol, double wl, int row,
-                                      double *__restrict__ out, double *red) {
+// Partial sums of one row block (BROWS rows r0 .. r0 + BROWS): slot i <= j of x_i . w, slot j + 1 of
+// w . w, written column by column (out[i * nb], the row blocks of one slot contiguous).  Wave wv takes
+// the slots congruent to wv modulo 4; lane l holds rows r0 + l + 64 q (q < 4) of w in wl[q], so a slot
+// costs 4 independent loads and one cross-lane sum.
+__device__ __forceinline__ void slot_partials(const double *__restrict__ V, int n, int r0, int j, const double wl[4],
+                                              double *__restrict__ out, int nb) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int i = 0; i <= ncol; ++i) {
-        double s = (i < ncol) ? ((row < n) ? X[(int64_t)i * n + row] * wl : 0.0) : wl * wl;
-        s = bwsum(s);
-        if (lane == 0) red[wv * (ncol + 1) + i] = s;
+    // slots i = wv + 4 (4 t + k), k < 4: four slots' loads in flight before their cross-lane sums
+    for (int i0 = wv; i0 <= j + 1; i0 += 16) {
+        double a[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int i = i0 + 4 * k;
+            const double *x = V + (int64_t)min(i, j) * n;
+            double d = 0.0, ww = 0.0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                // wl[q] is 0 for rows past n
+                d = fma(x[min(r0 + lane + 64 * q, n - 1)], wl[q], d);
+                ww = fma(wl[q], wl[q], ww);
+            }
+            a[k] = i <= j ? d : (i == j + 1 ? ww : 0.0);
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int i = i0 + 4 * k;
+            if (i <= j + 1) {
+                const double t = bwsum(a[k]);
+                if (lane == 0) out[(int64_t)i * nb] = t;
+            }
+        }
     }
-    __syncthreads();
-    for (int i = threadIdx.x; i <= ncol; i += BROWS)
-        out[i] = red[i] + red[(ncol + 1) + i] + red[2 * (ncol + 1) + i] + red[3 * (ncol + 1) + i];
 }
 
-__global__ __launch_bounds__(BROWS) void k_b_dots(const ProbDev *__restrict__ probs, const WorkItem *__restrict__ rblk) {
-    extern __shared__ double red[];
+// part region of a pair: two halves of S x nb (slot-major), the first also holding the residual
+// norm partials in slot 0
+__device__ __forceinline__ double *part_half(const ProbDev &P, int rhs, int half) {
+    const int S = P.restart + 2;
+    return P.part + ((int64_t)rhs * 2 + half) * S * P.nblk;
+}
+
+// w = V[:, j+1] = B Zk[:, j] for the block's rows, then the block's first-pass partials (they need
+// only these rows of w)
+__global__ __launch_bounds__(BROWS) void k_b_spmv_dots(const ProbDev *__restrict__ probs,
+                                                       const WorkItem *__restrict__ rblk, int par) {
+    __shared__ double wsh[BROWS];
     const WorkItem it = rblk[blockIdx.x];
     const ProbDev &P = probs[it.p];
     const int rhs = blockIdx.z;
     if (inactive(P, rhs, 1)) return;
-    const int n = P.n, S = P.restart + 2, j = P.jcur[rhs];
-    const double *V = vcol(P, rhs, 0);
-    const int row = it.s * BROWS + threadIdx.x;
-    const double wl = row < n ? V[(int64_t)(j + 1) * n + row] : 0.0;
-    double *part = P.part + ((int64_t)rhs * 2 * P.nblk + it.s) * S;
-    bdots(V, n, j + 1, wl, row, part, red);
+    const int n = P.n, j = jget(P, rhs, par), r0 = it.s * BROWS, lane = threadIdx.x & 63;
+    const double *x = zcol(P, rhs, j);
+    double *V = vcol_w(P, rhs, 0);
+    const int i = r0 + threadIdx.x;
+    double s = 0.0;
+    if (i < n) {
+        s = csr_row_dot(P.rowptr, P.colidx, P.Bval, x, i);
+        V[(int64_t)(j + 1) * n + i] = s;
+    }
+    wsh[threadIdx.x] = s;
+    __syncthreads();
+    double wl[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) wl[q] = wsh[lane + 64 * q];
+    slot_partials(V, n, r0, j, wl, part_half(P, rhs, 0) + it.s, P.nblk);
 }
 
-// reduce the pass's partials (wave per entry, fixed order), w -= V h, next partials
+// reduce the pass's partials (wave per slot, fixed order), w -= V h, next partials
 __global__ __launch_bounds__(BROWS) void k_b_update(const ProbDev *__restrict__ probs, const WorkItem *__restrict__ rblk,
-                                                    int pass) {
+                                                    int pass, int par) {
     extern __shared__ double sh[];
     const WorkItem it = rblk[blockIdx.x];
     const ProbDev &P = probs[it.p];
     const int rhs = blockIdx.z;
     if (inactive(P, rhs, 1)) return;
-    const int n = P.n, m = P.restart, S = m + 2, nb = P.nblk, j = P.jcur[rhs];
+    const int n = P.n, m = P.restart, S = m + 2, nb = P.nblk, j = jget(P, rhs, par);
     double *V = vcol_w(P, rhs, 0);
     double *w = V + (int64_t)(j + 1) * n;
-    const double *pin = P.part + ((int64_t)rhs * 2 * nb + (pass == 1 ? 0 : nb)) * S;
-    double *h = sh;
-    double *red = sh + S;
+    const double *pin = part_half(P, rhs, pass == 1 ? 0 : 1);
+    double *h = sh;              // S
+    double *wsh = sh + S;        // BROWS
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int i = wv; i <= j + 1; i += BROWS / 64) {
-        double s = 0.0;
-        for (int b = lane; b < nb; b += 64) s += pin[(int64_t)b * S + i];
-        s = bwsum(s);
-        if (lane == 0) h[i] = s;
+    for (int i0 = wv; i0 <= j + 1; i0 += 16) {
+        double a[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int b = lane; b < nb; b += 64) {
+            double v[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) v[k] = pin[(int64_t)min(i0 + 4 * k, j + 1) * nb + b];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) a[k] += v[k];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int i = i0 + 4 * k;
+            if (i <= j + 1) {
+                const double t = bwsum(a[k]);
+                if (lane == 0) h[i] = t;
+            }
+        }
     }
     __syncthreads();
     if (it.s == 0) {
@@ -305,59 +391,77 @@ __global__ __launch_bounds__(BROWS) void k_b_update(const ProbDev *__restrict__ 
         for (int i = threadIdx.x; i <= j; i += BROWS) hc[i] = (pass == 1) ? h[i] : hc[i] + h[i];
         if (pass == 1 && threadIdx.x == 0) hc[m + 1] = sqrt(h[j + 1]);
     }
-    const int row = it.s * BROWS + threadIdx.x;
+    const int r0 = it.s * BROWS, row = r0 + threadIdx.x;
     double v = 0.0;
     if (row < n) {
         v = w[row];
-        for (int i = 0; i <= j; ++i) v = fma(-V[(int64_t)i * n + row], h[i], v);
+        for (int i0 = 0; i0 <= j; i0 += 4) {
+            double x[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) x[k] = V[(int64_t)min(i0 + k, j) * n + row];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) v = fma(-x[k], i0 + k <= j ? h[min(i0 + k, j)] : 0.0, v);
+        }
         w[row] = v;
     }
-    __syncthreads();
-    double *pout = P.part + ((int64_t)rhs * 2 * nb + (pass == 1 ? nb : 0)) * S + (int64_t)it.s * S;
     if (pass == 1) {
-        bdots(V, n, j + 1, v, row, pout, red);
-    } else {
-        double s = bwsum(v * v);
-        if (lane == 0) red[wv] = s;
+        wsh[threadIdx.x] = v;
         __syncthreads();
-        if (threadIdx.x == 0) pout[0] = red[0] + red[1] + red[2] + red[3];
+        double wl[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) wl[q] = wsh[lane + 64 * q];
+        slot_partials(V, n, r0, j, wl, part_half(P, rhs, 1) + it.s, nb);
+    } else {
+        const double s = bwsum(v * v);
+        if (lane == 0) wsh[wv] = s;
+        __syncthreads();
+        if (threadIdx.x == 0) part_half(P, rhs, 0)[it.s] = wsh[0] + wsh[1] + wsh[2] + wsh[3];
     }
 }
 
 // ||w||, v_{j+1} = w / ||w||; block 0: Hessenberg column, Givens rotations, stopping tests
-__global__ __launch_bounds__(BROWS) void k_b_finish(const ProbDev *__restrict__ probs, const WorkItem *__restrict__ rblk) {
+__global__ __launch_bounds__(BROWS) void k_b_finish(const ProbDev *__restrict__ probs, const WorkItem *__restrict__ rblk,
+                                                    int par) {
+    extern __shared__ double fs[];       // hc[0..j+1], cs[0..j), sn[0..j)
     const WorkItem it = rblk[blockIdx.x];
     const ProbDev &P = probs[it.p];
     const int rhs = blockIdx.z;
     if (inactive(P, rhs, 1)) return;
-    const int n = P.n, m = P.restart, S = m + 2, nb = P.nblk, j = P.jcur[rhs];
-    const double *pin = P.part + (int64_t)rhs * 2 * nb * S;
+    const int n = P.n, m = P.restart, S = m + 2, nb = P.nblk, j = jget(P, rhs, par);
+    const double *pin = part_half(P, rhs, 0);
     double nrm2 = 0.0;
-    for (int b = (threadIdx.x & 63); b < nb; b += 64) nrm2 += pin[(int64_t)b * S];
+    for (int b = (threadIdx.x & 63); b < nb; b += 64) nrm2 += pin[b];
     nrm2 = bwsum(nrm2);
     const double hn = sqrt(nrm2);
     double *w = vcol_w(P, rhs, j + 1);
     const double inv = hn > 0.0 ? 1.0 / hn : 0.0;
     const int row = it.s * BROWS + threadIdx.x;
     if (row < n) w[row] *= inv;
-    if (it.s == 0 && threadIdx.x == 0) {
-        const double *hc = P.hcol + (int64_t)rhs * S;
-        double *H = P.H + (int64_t)rhs * (m + 1) * m + (int64_t)j * (m + 1);
-        double *cs = P.cs + (int64_t)rhs * m, *sn = P.sn + (int64_t)rhs * m, *g = P.g + (int64_t)rhs * (m + 1);
-        double *sc = P.scal + (int64_t)rhs * 8;
-        for (int i = 0; i <= j; ++i) H[i] = hc[i];
-        H[j + 1] = hn;
+    if (it.s != 0) return;
+    const double *hc = P.hcol + (int64_t)rhs * S;
+    double *H = P.H + (int64_t)rhs * (m + 1) * m + (int64_t)j * (m + 1);
+    double *cs = P.cs + (int64_t)rhs * m, *sn = P.sn + (int64_t)rhs * m, *g = P.g + (int64_t)rhs * (m + 1);
+    double *hs = fs, *css = fs + S, *sns = fs + S + m;
+    for (int i = threadIdx.x; i <= j; i += BROWS) hs[i] = hc[i];
+    for (int i = threadIdx.x; i < j; i += BROWS) {
+        css[i] = cs[i];
+        sns[i] = sn[i];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double cur = hs[0];
         for (int i = 0; i < j; ++i) {
-            double t = cs[i] * H[i] + sn[i] * H[i + 1];
-            H[i + 1] = -sn[i] * H[i] + cs[i] * H[i + 1];
-            H[i] = t;
+            const double nx = hs[i + 1];
+            hs[i] = css[i] * cur + sns[i] * nx;
+            cur = -sns[i] * cur + css[i] * nx;
         }
-        const double d = hypot(H[j], H[j + 1]);
-        const double c = d > 0.0 ? H[j] / d : 1.0, s = d > 0.0 ? H[j + 1] / d : 0.0;
+        const double d = hypot(cur, hn);
+        const double c = d > 0.0 ? cur / d : 1.0, s = d > 0.0 ? hn / d : 0.0;
         cs[j] = c;
         sn[j] = s;
-        H[j] = d;
-        H[j + 1] = 0.0;
+        hs[j] = d;
+        hs[j + 1] = 0.0;
+        double *sc = P.scal + (int64_t)rhs * 8;
         g[j + 1] = -s * g[j];
         g[j] = c * g[j];
         sc[2] = fabs(g[j + 1]);
@@ -370,32 +474,22 @@ __global__ __launch_bounds__(BROWS) void k_b_finish(const ProbDev *__restrict__ 
             P.active[rhs] = PS_CYCLE_END;
             sc[4] = conv ? 1.0 : 0.0;
             sc[5] = sing ? 1.0 : 0.0;
+        } else {
+            P.jcur[2 * rhs + 1 - par] = j + 1;
         }
     }
+    __syncthreads();
+    for (int i = threadIdx.x; i <= j + 1; i += BROWS) H[i] = hs[i];
 }
 
-// advance j of every active pair (a separate launch: no block of the step reads j after this)
-__global__ void k_b_advance(const ProbDev *__restrict__ probs, const int32_t *__restrict__ live, int nlive,
-                            int max_nrhs) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nlive * max_nrhs) return;
-    const ProbDev &P = probs[live[t / max_nrhs]];
-    const int rhs = t % max_nrhs;
-    if (rhs < P.nrhs && P.active[rhs] == PS_ITER) P.jcur[rhs] += 1;
-}
-
-int32_t batch_arnoldi(const BatchGeom &g, const ProbDev *probs, const WorkItem *rblk, const int32_t *live,
-                      hipStream_t s) {
+int32_t batch_arnoldi(const BatchGeom &g, const ProbDev *probs, const WorkItem *rblk, int par, hipStream_t s) {
     const dim3 grid(g.nrblk, 1, g.max_nrhs);
-    // the restart length of every problem is the same (checked at batch creation)
-    hipLaunchKernelGGL(k_b_spmv_next, grid, dim3(BROWS), 0, s, probs, rblk);
-    const size_t red = (size_t)4 * (g.restart + 2) * sizeof(double), hbuf = (size_t)(g.restart + 2) * sizeof(double);
-    hipLaunchKernelGGL(k_b_dots, grid, dim3(BROWS), red, s, probs, rblk);
-    hipLaunchKernelGGL(k_b_update, grid, dim3(BROWS), hbuf + red, s, probs, rblk, 1);
-    hipLaunchKernelGGL(k_b_update, grid, dim3(BROWS), hbuf + red, s, probs, rblk, 2);
-    hipLaunchKernelGGL(k_b_finish, grid, dim3(BROWS), 0, s, probs, rblk);
-    const int pairs = g.nprob * g.max_nrhs;
-    hipLaunchKernelGGL(k_b_advance, dim3((pairs + 255) / 256), dim3(256), 0, s, probs, live, g.nprob, g.max_nrhs);
+    const size_t upd = (size_t)(g.restart + 2 + BROWS) * sizeof(double);
+    const size_t fin = (size_t)(3 * g.restart + 2) * sizeof(double);
+    hipLaunchKernelGGL(k_b_spmv_dots, grid, dim3(BROWS), 0, s, probs, rblk, par);
+    hipLaunchKernelGGL(k_b_update, grid, dim3(BROWS), upd, s, probs, rblk, 1, par);
+    hipLaunchKernelGGL(k_b_update, grid, dim3(BROWS), upd, s, probs, rblk, 2, par);
+    hipLaunchKernelGGL(k_b_finish, grid, dim3(BROWS), fin, s, probs, rblk, par);
     HKG_HIP(hipGetLastError());
     return HKG_OK;
 }
@@ -403,11 +497,11 @@ int32_t batch_arnoldi(const BatchGeom &g, const ProbDev *probs, const WorkItem *
 // ------------------------------------------------------------------------------------------------
 // restart phase: pairs whose cycle ended (PS_CYCLE_END) or that just joined (PS_NEW)
 // ------------------------------------------------------------------------------------------------
-// x += Z_k y with y = R^{-1} g from the rotated Hessenberg (PS_CYCLE_END; each block solves the small
-// triangle redundantly on one thread), or x = 0 (PS_NEW)
+// x += Z_k y with y = R^{-1} g from the rotated Hessenberg (PS_CYCLE_END; every block solves the
+// small triangle redundantly from LDS, column by column), or x = 0 (PS_NEW)
 __global__ __launch_bounds__(BROWS) void k_r_update_x(const ProbDev *__restrict__ probs,
                                                       const WorkItem *__restrict__ rblk) {
-    extern __shared__ double y[];
+    extern __shared__ double ts[];       // R (jd x jd, column-major) then g / y (jd)
     const WorkItem it = rblk[blockIdx.x];
     const ProbDev &P = probs[it.p];
     const int rhs = blockIdx.z;
@@ -423,16 +517,21 @@ __global__ __launch_bounds__(BROWS) void k_r_update_x(const ProbDev *__restrict_
     const int m = P.restart;
     const int jd = (int)P.scal[(int64_t)rhs * 8 + 3];
     if (jd <= 0) return;
-    if (threadIdx.x == 0) {
-        const double *H = P.H + (int64_t)rhs * (m + 1) * m;
-        const double *g = P.g + (int64_t)rhs * (m + 1);
-        for (int i = jd - 1; i >= 0; --i) {
-            double s = g[i];
-            for (int k = i + 1; k < jd; ++k) s -= H[i + (int64_t)k * (m + 1)] * y[k];
-            y[i] = s / H[i + (int64_t)i * (m + 1)];
-        }
+    const double *H = P.H + (int64_t)rhs * (m + 1) * m;
+    double *R = ts, *y = ts + (int64_t)jd * jd;
+    for (int t = threadIdx.x; t < jd * jd; t += BROWS) {
+        const int i = t % jd, k = t / jd;
+        R[t] = i <= k ? H[i + (int64_t)k * (m + 1)] : 0.0;
     }
+    for (int t = threadIdx.x; t < jd; t += BROWS) y[t] = P.g[(int64_t)rhs * (m + 1) + t];
     __syncthreads();
+    for (int k = jd - 1; k >= 0; --k) {
+        const double yk = y[k] / R[k + k * jd];
+        __syncthreads();
+        if (threadIdx.x == 0) y[k] = yk;
+        for (int i = threadIdx.x; i < k; i += BROWS) y[i] -= R[i + k * jd] * yk;
+        __syncthreads();
+    }
     if (r >= P.n) return;
     const double *Zk = zcol(P, rhs, 0);
     double s = x[r];
@@ -455,10 +554,7 @@ __global__ __launch_bounds__(BROWS) void k_r_residual(const ProbDev *__restrict_
     if (i < P.n) {
         v = P.f[(int64_t)rhs * P.ldf + i];
         if (st == PS_CYCLE_END) {
-            const double *x = P.x + (int64_t)rhs * P.ldx;
-            double s = 0.0;
-            for (int t = P.rowptr[i]; t < P.rowptr[i + 1]; ++t) s = fma(P.Bval[t], x[P.colidx[t]], s);
-            v -= s;
+            v -= csr_row_dot(P.rowptr, P.colidx, P.Bval, P.x + (int64_t)rhs * P.ldx, i);
         }
         vcol_w(P, rhs, 0)[i] = v;
     }
@@ -468,7 +564,7 @@ __global__ __launch_bounds__(BROWS) void k_r_residual(const ProbDev *__restrict_
     if (threadIdx.x == 0) {
         double t = 0.0;
         for (int w = 0; w < BROWS / 64; ++w) t += red[w];
-        P.part[(int64_t)rhs * 2 * P.nblk * (P.restart + 2) + it.s] = t;
+        part_half(P, rhs, 0)[it.s] = t;
     }
 }
 
@@ -483,7 +579,7 @@ __global__ void k_r_decide(const ProbDev *__restrict__ probs, const int32_t *__r
     if (rhs >= P.nrhs) return;
     const int st = P.active[rhs];
     if (st != PS_NEW && st != PS_CYCLE_END) return;
-    const double *pp = P.part + (int64_t)rhs * 2 * P.nblk * (P.restart + 2);
+    const double *pp = part_half(P, rhs, 0);
     double s = 0.0;
     for (int b = 0; b < P.nblk; ++b) s += pp[b];
     const double rn = sqrt(s);
@@ -508,7 +604,8 @@ __global__ void k_r_decide(const ProbDev *__restrict__ probs, const int32_t *__r
     sc[3] = 0.0;
     sc[4] = 0.0;
     sc[5] = 0.0;
-    P.jcur[rhs] = 0;
+    P.jcur[2 * rhs] = 0;
+    P.jcur[2 * rhs + 1] = 0;
     P.active[rhs] = PS_START;
 }
 
@@ -535,7 +632,8 @@ int32_t batch_restart(const BatchGeom &g, const ProbDev *probs, const WorkItem *
                       hipStream_t s) {
     const dim3 grid(g.nrblk, 1, g.max_nrhs);
     const int pairs = g.nprob * g.max_nrhs;
-    hipLaunchKernelGGL(k_r_update_x, grid, dim3(BROWS), (size_t)g.restart * sizeof(double), s, probs, rblk);
+    hipLaunchKernelGGL(k_r_update_x, grid, dim3(BROWS), (size_t)g.restart * (g.restart + 1) * sizeof(double), s, probs,
+                       rblk);
     hipLaunchKernelGGL(k_r_residual, grid, dim3(BROWS), 0, s, probs, rblk);
     hipLaunchKernelGGL(k_r_decide, dim3((pairs + 255) / 256), dim3(256), 0, s, probs, live, g.nprob, g.max_nrhs);
     hipLaunchKernelGGL(k_r_start, grid, dim3(BROWS), 0, s, probs, rblk);

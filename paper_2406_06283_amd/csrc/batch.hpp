@@ -4,7 +4,7 @@
 // Every kernel takes the table of ProbDev descriptors and a flattened work list, so a single launch
 // covers all (problem, subdomain or row block, right-hand side) items of the live set, whatever their
 // sizes.  The Arnoldi index j and the state of each (problem, rhs) pair live on the device, so one
-// iteration is the same launch sequence every time (captured once as a HIP graph and replayed), and
+// iteration is the same launch sequence every time (captured once per index parity and replayed), and
 // so is the restart phase that ends a pair's cycle, tests its true residual and starts the next
 // cycle or retires it.  Pairs therefore restart independently, and problems can join or leave the
 // live set at any iteration boundary.
@@ -26,7 +26,7 @@ enum : int32_t {
 };
 
 struct ProbDev {
-    int32_t n, nsub, m0, maxnI, nchunk, nblk, nrhs, restart;
+    int32_t n, nsub, m0, maxnI, nblk, nrhs, restart, nchunk;
     int32_t local_f32, two_level, max_iter, ldu_pad;
     int64_t sum_nI;
     double rtol;
@@ -42,7 +42,8 @@ struct ProbDev {
     // batch workspace of this problem
     double *u, *c, *ypart;                                   // apply
     double *V, *Zk, *H, *cs, *sn, *g, *part, *hcol, *scal;   // FGMRES, per rhs strides below
-    int32_t *active, *iters, *jcur;                          // per rhs
+    int32_t *active, *iters;                                 // per rhs
+    int32_t *jcur;                                           // two per rhs (parity double buffer)
     double *rnorm;                                           // per rhs
     // vectors of the current call: apply input/output, solve right-hand sides and iterates
     const double *xin;
@@ -67,11 +68,12 @@ struct BatchGeom {
 // live: table indices of the g.nprob live problems (pair t of the per-pair kernels is
 // (live[t / max_nrhs], t % max_nrhs)); work lists name table indices directly.
 // mode 0: standalone application (xin -> xout); mode 1: FGMRES iteration (V[:, j] -> Zk[:, j])
+// par: parity of the iteration (which half of the double-buffered Arnoldi index it reads)
+// cblk: (problem, row tile * nchunk + column chunk) blocks of the split coarse product
 int32_t batch_apply(const BatchGeom &g, const ProbDev *probs, const WorkItem *items, const WorkItem *rblk,
-                    const WorkItem *cblk, int mode, hipStream_t s, hipEvent_t ev0 = nullptr,
+                    const WorkItem *cblk, int mode, int par, hipStream_t s, hipEvent_t ev0 = nullptr,
                     hipEvent_t ev1 = nullptr);
-int32_t batch_arnoldi(const BatchGeom &g, const ProbDev *probs, const WorkItem *rblk, const int32_t *live,
-                      hipStream_t s);
+int32_t batch_arnoldi(const BatchGeom &g, const ProbDev *probs, const WorkItem *rblk, int par, hipStream_t s);
 // restart phase for PS_CYCLE_END / PS_NEW pairs: x update, true residual, stop or next cycle
 int32_t batch_restart(const BatchGeom &g, const ProbDev *probs, const WorkItem *rblk, const int32_t *live,
                       hipStream_t s);

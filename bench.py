@@ -1,12 +1,24 @@
 """Benchmark: Helmholtz solves/s to relative residual 1e-8 on one MI355X.
 
-A step is one pass of the whole hot path for one right-hand side of the named workload with its
-inputs resident in device memory: the numeric setup (local blocks, local H_k-GenEO eigenproblems,
-coarse space, coarse and local factors; hkgeneo_factor) followed by the FGMRES solve
-(hkgeneo_gmres_solve).  The host analysis (partition, index sets, uploads) runs once before the
-timed region.  The JSON line also carries the solve-only latency percentiles (factors resident),
-the FP32-local variant, the roofline of the local-solve kernel (timed with HIP events on its own
-stream inside the timed region) and the CPU oracle timed on a bounded sample.
+Default workload (h = 1/128, k = 40, 8 x 8 subdomains).  A step is one pass of the whole hot path
+for one right-hand side with its inputs resident in device memory: the numeric setup (local blocks,
+local H_k-GenEO eigenproblems, coarse space, coarse and local factors; hkgeneo_factor) followed by
+the FGMRES solve.  The host analysis (partition, index sets, uploads) runs once before the timed
+region.  Three forms are timed, each over the same steps:
+
+  * mixed  - float32 local inverses (formed in float64) inside float64 FGMRES, solved by the
+             batched engine (hkgeneo_batch_solve: graph-captured iteration).  This is `value`.
+  * fp64   - everything in float64, same batched engine.
+  * plain  - everything in float64, single-problem path (hkgeneo_gmres_solve).
+
+The mixed form's timed region runs with the engine's measurement hook on: HIP events around every
+batched local-solve launch on the engine's stream give the roofline of that kernel (the hook
+launches the iteration directly instead of replaying its graph; the unprofiled step time is
+reported beside it).  The line also carries solve-only latency percentiles (factors resident), an
+8-right-hand-side solve-only throughput, and the CPU oracle timed on a bounded sample.
+
+Other workloads: --workload mix64 (64 independent problems in one batch, setup timed apart) and
+--workload serve (Poisson request stream through the continuous-batching server).
 
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--cpu-sample N]
 """
@@ -15,6 +27,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -27,59 +40,101 @@ METRIC = "Helmholtz solves/s to rel.res 1e-8 (mixed vs FP64); p50/p99 solve late
 HBM_PEAK_GBS = 8000.0
 
 
-def local_solve_bytes(nI: np.ndarray, m: np.ndarray, word: int) -> int:
-    """Algorithmic bytes of one local-solve launch (one right-hand side): the local inverses
-    (sum n_D^2 words), the gathered residual entries with their indices, the weights and the output,
-    and the coarse restriction fused into the same kernel (Z_i^T: sum n_D m_i doubles, m0 outputs)."""
+def local_solve_bytes(nI: np.ndarray, m: np.ndarray, word: int, nrhs: int = 1) -> int:
+    """Algorithmic bytes of one batched local-solve launch: the local inverses (sum n_D^2 words, read
+    once whatever nrhs), and per right-hand side the gathered residual entries with their indices,
+    the weights, the output, and the coarse restriction fused into the same launch (Z_i^T: sum n_D m_i
+    doubles read, m0 outputs written)."""
     s = int(nI.sum())
     nI64 = nI.astype(np.int64)
-    return int(word * int((nI64 ** 2).sum()) + s * (8 + 4) + s * 8 + s * 8
-               + 8 * int((nI64 * m.astype(np.int64)).sum()) + 8 * int(m.sum()))
+    per_rhs = s * (8 + 4) + s * 8 + s * 8 + 8 * int(m.sum())
+    return int(word * int((nI64 ** 2).sum()) + 8 * int((nI64 * m.astype(np.int64)).sum()) + nrhs * per_rhs)
 
 
-def run_gpu(args, w, p):
+def progress(msg):
+    """Progress of the longer workloads on stderr (the JSON line alone goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def pct(a, q):
+    return float(np.percentile(np.asarray(a), q))
+
+
+def sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def timed_steps(S, solve, steps, warmup):
+    """warmup + `steps` timed (factor, solve) passes; returns per-step lists."""
+    for _ in range(warmup):
+        S.factor()
+        solve()
+    sync()
+    fac, sol, it, rel = [], [], [], []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        a = time.perf_counter()
+        S.factor()
+        b = time.perf_counter()
+        info = solve()
+        c = time.perf_counter()
+        fac.append(1e3 * (b - a))
+        sol.append(1e3 * (c - b))
+        it.append(info["iters"])
+        rel.append(info["relres_true"])
+    sync()
+    return dict(total_s=time.perf_counter() - t0, fac_ms=fac, sol_ms=sol, iters=it, relres=rel)
+
+
+def latency(solve, n):
+    lat = []
+    for _ in range(n):
+        a = time.perf_counter()
+        solve()
+        lat.append(1e3 * (time.perf_counter() - a))
+    return lat
+
+
+def run_default(args, w, p):
     import torch
     from paper_2406_06283_amd import hkgeneo as H
-
     dev = torch.device("cuda:0")
     f = torch.from_numpy(p.f).to(dev)
+    p8 = w.problem(seed=0, nrhs=8)
+    f8 = torch.from_numpy(p8.f).to(dev)
     out = {}
-    for prec in (64, 32):
+    # plain float64 single-problem path
+    S = H.Solver(p, H.options_for(w, keep_workspace=1))
+    r = timed_steps(S, lambda: S.solve(f)[1][0], args.steps, args.warmup)
+    r["lat"] = latency(lambda: S.solve(f), max(args.steps, 20))
+    r["lat8"] = latency(lambda: S.solve(f8), 5)
+    r["m0"] = S.stats()["m0"]
+    out["plain"] = r
+    S.close()
+    # batched engine, float64 and mixed
+    for tag, prec in (("fp64", 64), ("mixed", 32)):
         S = H.Solver(p, H.options_for(w, local_prec=prec, keep_workspace=1))
-        for _ in range(args.warmup):
-            S.factor()
-            S.solve(f)
-        torch.cuda.synchronize()
-        S.profile(True)
-        fac_ms, sol_ms, step_ms, iters, relres = [], [], [], [], []
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            a = time.perf_counter()
-            S.factor()
-            b = time.perf_counter()
-            u, info, st = S.solve(f)
-            c = time.perf_counter()
-            fac_ms.append(1e3 * (b - a))
-            sol_ms.append(1e3 * (c - b))
-            step_ms.append(1e3 * (c - a))
-            iters.append(info[0]["iters"])
-            relres.append(info[0]["relres_true"])
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        local_ms, launches = S.profile_read()
-        S.profile(False)
-        nI, nG, m = S.subdomains()
-        st = S.stats()
-        # solve-only latency with resident factors
-        lat = []
-        for _ in range(max(args.steps, 20)):
-            a = time.perf_counter()
-            S.solve(f)
-            lat.append(1e3 * (time.perf_counter() - a))
+        B = H.Batch([S], [1])
+        B8 = H.Batch([S], [8])
+        solve = lambda: B.solve([f])[1][0][0]
+        r = timed_steps(S, solve, args.steps, args.warmup)       # graph replay
+        if tag == "mixed":
+            B.profile(True)
+            rp = timed_steps(S, solve, args.steps, 0)             # measurement hook on
+            local_ms, launches = B.profile_read()
+            B.profile(False)
+            rp["local_ms"], rp["launches"], rp["waves"] = local_ms, launches, B.local_waves
+            r["profiled"] = rp
+            nI, _, m = S.subdomains()
+            r["nI"], r["m"] = nI, m
+        r["lat"] = latency(lambda: B.solve([f]), max(args.steps, 20))
+        r["lat8"] = latency(lambda: B8.solve([f8]), 5)
+        r["m0"] = S.stats()["m0"]
+        out[tag] = r
+        B.close()
+        B8.close()
         S.close()
-        out[prec] = dict(total_s=t1 - t0, fac_ms=fac_ms, sol_ms=sol_ms, step_ms=step_ms, iters=iters, relres=relres,
-                         local_ms=local_ms, launches=launches, nI=nI, m=m, stats=st, lat=lat)
     return out
 
 
@@ -95,7 +150,7 @@ def run_cpu_baseline(w, p, sample: int):
     iters = []
     for _ in range(sample):
         M = schwarz.TwoLevelSchwarz(p, opts)
-        x, info = fgmres.solve(p, M)
+        x, info = fgmres.solve(p, M, restart=w.restart)
         iters.append(info["iters"])
     dt = time.perf_counter() - t0
     return dict(value=sample / dt, unit="solves/s", cores=int(threads), kind="oracle",
@@ -103,8 +158,185 @@ def run_cpu_baseline(w, p, sample: int):
                        f"{dt:.1f} s, {iters[0]} iterations", iters=iters[0])
 
 
-def pct(a, q):
-    return float(np.percentile(np.asarray(a), q))
+def summary(r, steps):
+    return {"steps_per_s": round(steps / r["total_s"], 3), "ms_per_step": round(1e3 * r["total_s"] / steps, 3),
+            "iters": int(np.median(r["iters"])), "relres_max": max(r["relres"]),
+            "factor_ms_p50": round(pct(r["fac_ms"], 50), 3), "solve_ms_p50": round(pct(r["sol_ms"], 50), 3),
+            "solve_only_p50_ms": round(pct(r["lat"], 50), 3), "solve_only_p99_ms": round(pct(r["lat"], 99), 3),
+            "rhs8_solves_per_s": round(8e3 / np.median(r["lat8"]), 1)}
+
+
+def main_default(args):
+    from paper_2406_06283_amd.configs import WORKLOADS
+    w = WORKLOADS[args.workload]
+    p = w.problem(seed=0)
+    r = run_default(args, w, p)
+    mx, f64, plain = r["mixed"], r["fp64"], r["plain"]
+    rp = mx["profiled"]
+    ok = all(x <= 1e-8 for x in rp["relres"]) and abs(int(np.median(rp["iters"])) - int(np.median(plain["iters"]))) <= 2
+    word = 4
+    bpl = local_solve_bytes(mx["nI"], mx["m"], word)
+    avg_s = rp["local_ms"] / max(rp["launches"], 1) / 1e3
+    achieved = bpl / avg_s / 1e9
+    line = {
+        "metric": METRIC,
+        "value": round(args.steps / rp["total_s"], 3) if ok else 0.0,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * rp["total_s"] / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 (f32 local inverses)",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n_dof": p.n_dof, "n_sub": p.n_sub, "k": w.k,
+                   "eig": "tau=%g" % w.tau if w.eig_mode == 0 else "nev=%d" % w.nev, "m0": int(mx["m0"]), "nrhs": 1,
+                   "restart": w.restart, "rtol": 1e-8,
+                   "step": "numeric setup + FGMRES solve (batched engine, mixed precision), inputs resident"},
+        "iters": int(np.median(rp["iters"])),
+        "relres_max": max(rp["relres"]),
+        "factor_ms_p50": round(pct(rp["fac_ms"], 50), 3),
+        "solve_ms_p50": round(pct(rp["sol_ms"], 50), 3),
+        "solve_only": {"p50_ms": round(pct(mx["lat"], 50), 3), "p99_ms": round(pct(mx["lat"], 99), 3),
+                       "solves_per_s": round(1e3 / np.mean(mx["lat"]), 2)},
+        "unprofiled_graph_replay": summary(mx, args.steps),
+        "fp64_batched": summary(f64, args.steps),
+        "fp64_plain": summary(plain, args.steps),
+        "roofline": {"kernel": "k_b_local<%d> (float32 inverses)" % rp["waves"], "bound": "hbm",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "bytes_per_launch": bpl,
+                     "avg_launch_us": round(avg_s * 1e6, 3), "launches": int(rp["launches"])},
+    }
+    if not args.no_cpu_baseline:
+        cb = run_cpu_baseline(w, p, args.cpu_sample)
+        line["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+    print(json.dumps(line), flush=True)
+
+
+def main_mix(args):
+    """64 independent problems (1-8 right-hand sides each) solved in one batch per step."""
+    import torch
+    from paper_2406_06283_amd import hkgeneo as H
+    from paper_2406_06283_amd.configs import batch_mix, mix_options
+    mix = batch_mix(64)
+    t = time.perf_counter()
+    probs = [m.problem() for m in mix]
+    gen_s = time.perf_counter() - t
+    progress(f"generated 64 problems in {gen_s:.1f} s")
+    dev = torch.device("cuda:0")
+    fs = [torch.from_numpy(np.ascontiguousarray(q.f)).to(dev) for q in probs]
+    nrhs = sum(m.nrhs for m in mix)
+    res = {}
+    for tag, prec in (("mixed", 32), ("fp64", 64)):
+        sync()
+        t = time.perf_counter()
+        Ss = [H.Solver(q, H.default_options(**mix_options(m, local_prec=prec))) for m, q in zip(mix, probs)]
+        sync()
+        setup_s = time.perf_counter() - t
+        progress(f"{tag}: set up 64 problems in {setup_s:.1f} s")
+        B = H.Batch(Ss, [m.nrhs for m in mix])
+        for _ in range(args.warmup):
+            B.solve(fs)
+        sync()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            _, infos, st = B.solve(fs)
+        sync()
+        total = time.perf_counter() - t
+        its = [i["iters"] for pi in infos for i in pi]
+        ok = all(i["converged"] and i["relres_true"] <= 1e-8 for pi in infos for i in pi)
+        sync()
+        t = time.perf_counter()
+        for S, fq in zip(Ss, fs):
+            S.solve(fq)
+        sync()
+        seq = time.perf_counter() - t
+        progress(f"{tag}: {args.steps} batched steps in {total:.2f} s, sequential single-path pass {seq:.2f} s")
+        res[tag] = dict(solves_per_s=nrhs * args.steps / total if ok else 0.0, ms_per_step=1e3 * total / args.steps,
+                        setup_s=setup_s, iters_min=min(its), iters_med=statistics.median(its), iters_max=max(its),
+                        converged=ok, waves=B.local_waves, sequential_plain_solves_per_s=nrhs / seq,
+                        m0_range=[min(S.stats()["m0"] for S in Ss), max(S.stats()["m0"] for S in Ss)])
+        B.close()
+        for S in Ss:
+            S.close()
+    mx = res["mixed"]
+    line = {"metric": METRIC, "value": round(mx["solves_per_s"], 2), "unit": "solves/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(mx["ms_per_step"], 3),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64 (f32 local inverses)",
+            "data": "synthetic",
+            "config": {"workload": "mix64_p1_h64-256_k0.3/h", "problems": 64, "rhs": nrhs,
+                       "step": "one batched solve of every right-hand side of every problem (factors resident)",
+                       "generation_s": round(gen_s, 1)},
+            "mixed": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in mx.items()},
+            "fp64": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in res["fp64"].items()}}
+    print(json.dumps(line), flush=True)
+
+
+def main_serve(args):
+    """Poisson request stream through the continuous-batching server."""
+    import torch
+    from paper_2406_06283_amd import hkgeneo as H, problems as pb, serve
+    from paper_2406_06283_amd.configs import serve_options, serve_problem, serve_stream
+    dev = torch.device("cuda:0")
+    n_req = args.requests
+    problems = {}
+
+    def payload(stream, tag0, rhs_offset=0):
+        reqs = []
+        for q, (arr, key, nrhs, rseed) in enumerate(stream):
+            rseed += rhs_offset
+            if key not in problems:
+                problems[key] = serve_problem(key)
+            pr = problems[key]
+            g = np.random.Generator(np.random.PCG64(rseed)).standard_normal((nrhs, pr.coords.shape[0]))
+            f = np.stack([pb.load_vector(pr.elem_vert, pr.vert_dof, pr.elem_M, g[r], pr.n_dof) for r in range(nrhs)])
+            reqs.append(serve.Request(tag=tag0 + q, arrival=arr, key=key, f=torch.from_numpy(f).to(dev)))
+        return reqs
+
+    def make_solver(key, stream):
+        return H.Solver(problems[key], H.default_options(**serve_options(key)), stream=stream)
+
+    def estimate(key):
+        o = serve_options(key)
+        return serve.footprint_estimate(problems[key], o["local_prec"], max(o["nev"], 12))
+
+    from paper_2406_06283_amd.configs import MIX_RESTART
+    kw = dict(ctx_budget=96 << 30, workspace_budget=48 << 30, max_requests=64, max_nrhs=8, restart=MIX_RESTART)
+    cache = serve.ContextCache(kw["ctx_budget"])
+    out = {}
+    t = time.perf_counter()
+    # closed loop, cold cache: every request at t = 0 (setups included)
+    cold = payload(serve_stream(n_req, 0.0, seed=1), 0)
+    gen_s = time.perf_counter() - t
+    progress(f"payload of {n_req} requests ({len(problems)} problems) in {gen_s:.1f} s")
+    _, s_cold = serve.run_stream(cold, make_solver, estimate, cache=cache, **kw)
+    out["closed_loop_cold"] = s_cold
+    progress(f"closed loop, cold cache: {s_cold['wall_s']:.1f} s, {s_cold['setups']} setups")
+    # closed loop, warm cache (the same keys, other right-hand sides): capacity
+    warm = payload(serve_stream(n_req, 0.0, seed=1), 10 ** 6, rhs_offset=7919)
+    _, s_warm = serve.run_stream(warm, make_solver, estimate, cache=cache, **kw)
+    out["closed_loop_warm"] = s_warm
+    progress(f"closed loop, warm cache: {s_warm['wall_s']:.1f} s, {s_warm['solves_per_s']:.1f} solves/s")
+    cap_req = s_warm["requests"] / s_warm["wall_s"]
+    for k, frac in enumerate((0.25, 0.5, 1.0, 2.0)):
+        reqs = payload(serve_stream(n_req, frac * cap_req, seed=10 + k), (k + 2) * 10 ** 6)
+        _, s = serve.run_stream(reqs, make_solver, estimate, cache=cache, **kw)
+        out[f"rate_{frac:g}x"] = s
+        progress(f"rate {frac:g}x capacity: p50 {s['p50_ms']:.1f} ms p99 {s['p99_ms']:.1f} ms")
+    cache.close()
+    rnd = lambda d: {k: (round(v, 3) if isinstance(v, float) else v) for k, v in d.items()}
+    line = {"metric": METRIC, "value": round(s_warm["solves_per_s"], 2), "unit": "solves/s", "n_gpus": 1,
+            "steps": n_req, "warmup": 0, "ms_per_step": round(1e3 * s_warm["wall_s"] / n_req, 3),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64 (f32 local inverses)",
+            "data": "synthetic",
+            "config": {"workload": "serve_p1_h64-256_q1_h32", "requests_per_run": n_req,
+                       "capacity_req_per_s": round(cap_req, 2), "payload_generation_s": round(gen_s, 1),
+                       "step": "one request (1-8 right-hand sides)"},
+            "p50_ms": round(s_warm["p50_ms"], 3), "p99_ms": round(s_warm["p99_ms"], 3),
+            "runs": {k: rnd(v) for k, v in out.items()}}
+    print(json.dumps(line), flush=True)
 
 
 def main():
@@ -114,6 +346,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="p1_h128_k40_8x8")
     ap.add_argument("--cpu-sample", type=int, default=1)
+    ap.add_argument("--requests", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -121,56 +354,12 @@ def main():
                                    "independent problems shard across GPUs without communication, see DESIGN.md",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
-    from paper_2406_06283_amd.configs import WORKLOADS
-    w = WORKLOADS[args.workload]
-    p = w.problem(seed=0)
-    r = run_gpu(args, w, p)
-    r64, r32 = r[64], r[32]
-    ms_step = 1e3 * r64["total_s"] / args.steps
-    ok64 = all(x <= 1e-8 for x in r64["relres"])
-    ok32 = all(x <= 1e-8 for x in r32["relres"])
-    # roofline of the local-solve kernel (fp64 path): algorithmic bytes per launch / mean duration
-    word = 8
-    bpl = local_solve_bytes(r64["nI"], r64["m"], word)
-    avg_s = r64["local_ms"] / max(r64["launches"], 1) / 1e3
-    achieved = bpl / avg_s / 1e9
-    line = {
-        "metric": METRIC,
-        "value": round(args.steps / r64["total_s"], 3) if ok64 else 0.0,
-        "unit": "solves/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 3),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": w.name, "n_dof": p.n_dof, "n_sub": p.n_sub, "k": w.k, "eig": "tau=%g" % w.tau
-                   if w.eig_mode == 0 else "nev=%d" % w.nev, "m0": int(r64["stats"]["m0"]), "nrhs": 1,
-                   "restart": 50, "rtol": 1e-8, "step": "numeric setup + FGMRES solve, inputs resident"},
-        "iters": int(np.median(r64["iters"])),
-        "relres_max": max(r64["relres"]),
-        "factor_ms_p50": round(pct(r64["fac_ms"], 50), 3),
-        "solve_ms_p50": round(pct(r64["sol_ms"], 50), 3),
-        "solve_only": {"p50_ms": round(pct(r64["lat"], 50), 3), "p99_ms": round(pct(r64["lat"], 99), 3),
-                       "solves_per_s": round(1e3 / np.mean(r64["lat"]), 2)},
-        "mixed_fp32_local": {"value": round(args.steps / r32["total_s"], 3) if ok32 else 0.0,
-                             "iters": int(np.median(r32["iters"])), "relres_max": max(r32["relres"]),
-                             "factor_ms_p50": round(pct(r32["fac_ms"], 50), 3),
-                             "solve_ms_p50": round(pct(r32["sol_ms"], 50), 3),
-                             "solve_only_p50_ms": round(pct(r32["lat"], 50), 3),
-                             "solve_only_p99_ms": round(pct(r32["lat"], 99), 3)},
-        "roofline": {"kernel": "k_local_solve<double>", "bound": "hbm", "achieved": round(achieved, 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "bytes_per_launch": bpl, "avg_launch_us": round(avg_s * 1e6, 3),
-                     "launches": int(r64["launches"])},
-    }
-    if not args.no_cpu_baseline:
-        cb = run_cpu_baseline(w, p, args.cpu_sample)
-        line["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
-    print(json.dumps(line), flush=True)
+    if args.workload == "mix64":
+        main_mix(args)
+    elif args.workload == "serve":
+        main_serve(args)
+    else:
+        main_default(args)
 
 
 if __name__ == "__main__":

@@ -233,6 +233,13 @@ int64_t hkgeneo_batch_bytes(const hkgeneo_batch *b);
 /* Launch shape the autotuner chose for the batched local solves (waves per 64-row tile). */
 int32_t hkgeneo_batch_local_waves(const hkgeneo_batch *b);
 
+/* Measurement hook.  enable = 1 clears earlier records and, until disabled, launches the iterations
+ * directly instead of replaying the graph (same kernels and launch shapes) with HIP events around
+ * every batched local-solve launch on the batch's stream; 0 returns to graph replay.
+ * hkgeneo_batch_profile_read sums the recorded durations (ms) and counts the launches. */
+int32_t hkgeneo_batch_profile(hkgeneo_batch *b, int32_t enable);
+int32_t hkgeneo_batch_profile_read(hkgeneo_batch *b, double *total_ms, int64_t *launches);
+
 void hkgeneo_batch_destroy(hkgeneo_batch *b);
 
 /*
@@ -243,8 +250,8 @@ void hkgeneo_batch_destroy(hkgeneo_batch *b);
  * graph, and retires requests whose right-hand sides have all stopped.  Admission and retirement
  * happen only at iteration boundaries; the work of all live requests shares every launch.
  * max_nrhs bounds nrhs per request.
- * Errors: HKG_EINVAL for max_requests outside 1..65535, max_nrhs outside 1..65535, restart < 1 or
- * too large for the batched Arnoldi kernels, workspace_budget <= 0.
+ * Errors: HKG_EINVAL for max_requests outside 1..65535, max_nrhs outside 1..65535, restart outside
+ * 1..1024, workspace_budget <= 0.
  */
 typedef struct hkgeneo_server hkgeneo_server;
 typedef struct {

@@ -5,6 +5,10 @@ threshold (it has no numerical section); these workloads follow the usual model 
 method: the unit square/cube, P1 on right triangles or Q1, kh about 0.3, block partitions with two
 element layers of overlap, heterogeneous coefficients with a_min near 1.
 
+Restart: FGMRES(50) unless stated.  At k near 80 (h = 1/256, 256 subdomains) the unrestarted
+iteration needs 85-135 steps and GMRES(50) stagnates, so those workloads (and the batched mix and
+the serving stream, which include them) restart after 150.
+
 Eigenvector selection (Def 2.15): ``eig_mode`` 1 keeps a fixed count ``nev`` per subdomain,
 ``eig_mode`` 0 keeps every eigenvalue below ``tau``; both are raised to every eigenvalue <= 0 and
 to the end of a cluster.  The thresholds below were frozen by ``tests/golden/freeze_tau.py`` so
@@ -39,6 +43,7 @@ class Workload:
     nev: int
     tau: float
     description: str
+    restart: int = 50
 
     def problem(self, seed: int = 0, nrhs: int | None = None) -> pb.Problem:
         return pb.make_problem(self.N, dim=self.dim, elem_type=self.elem_type, k=self.k, s=self.s,
@@ -64,7 +69,7 @@ H256_K80 = Workload(
     rhs="one", nrhs=1, eig_mode=EIG_THRESHOLD, nev=0, tau=0.845,
     description="2D unit square, P1 h=1/256 (65025 dofs), k=80, lognormal a (sigma=1, l=0.1); 16x16 "
                 "subdomains, 2 layers; tau=0.845 (5-24 vectors per subdomain, mean 9.6, at seed 0); "
-                "FGMRES(50), rel.res 1e-8")
+                "FGMRES(150), rel.res 1e-8", restart=150)
 
 Q1_3D_H32_K10 = Workload(
     name="q1_3d_h32_k10_4x4x4", N=32, dim=3, elem_type=pb.Q1, k=10.0, s=4, overlap=2, coef="const",
@@ -130,8 +135,57 @@ def batch_mix(count: int = 64, seed0: int = 0, n_choices=(64, 128, 192, 256), s_
     return out
 
 
+MIX_RESTART = 150
+
+
 def mix_options(m: MixMember, **overrides) -> dict:
     """Keyword options (hkgeneo.default_options) of a mix member."""
-    kw = dict(eig_mode=m.eig_mode, nev=m.nev, tau=m.tau)
+    kw = dict(eig_mode=m.eig_mode, nev=m.nev, tau=m.tau, restart=MIX_RESTART)
     kw.update(overrides)
     return kw
+
+
+# ----------------------------------------------------------------------------
+# serving stream: requests over a set of problem keys
+# ----------------------------------------------------------------------------
+
+SERVE_2D_N = (64, 128, 192, 256)
+
+
+def serve_problem(key: tuple) -> pb.Problem:
+    """Problem of a serving key: ("p1", N, seed) is the 2D unit square with P1, k = 0.3 N, blocks of
+    16 x 16 elements, two overlap layers and coefficients on 16 x 16 cells (log10 a ~ U[0, 2]);
+    ("q1", 32, seed) is the 3D unit cube with Q1, h = 1/32, k = 10, 4 x 4 x 4 subdomains."""
+    kind, N, seed = key
+    if kind == "p1":
+        return pb.make_problem(N, k=0.3 * N, s=N // 16, overlap=2, coef="cells", seed=seed, n_cells=16, rhs="zero",
+                               nrhs=1, name=f"serve_p1_h{N}_s{seed}")
+    return pb.make_problem(N, dim=3, elem_type=pb.Q1, k=10.0, s=4, overlap=2, coef="cells", seed=seed, n_cells=4,
+                           rhs="zero", nrhs=1, name=f"serve_q1_h{N}_s{seed}")
+
+
+def serve_options(key: tuple) -> dict:
+    """Options of a serving key: float32 local solves; threshold selection (tau = 0.85) in 2D, ten
+    eigenvectors per subdomain in 3D; FGMRES(150) (the stream includes h = 1/256, k = 76.8)."""
+    if key[0] == "p1":
+        return dict(eig_mode=EIG_THRESHOLD, tau=0.85, nev=0, local_prec=32, restart=MIX_RESTART)
+    return dict(eig_mode=EIG_FIXED, nev=10, local_prec=32, restart=MIX_RESTART)
+
+
+def serve_stream(n_requests: int, rate: float, seed: int = 0, frac_3d: float = 0.25, n_seeds: int = 16,
+                 zipf_a: float = 1.1, nrhs_range=(1, 8)) -> list[tuple]:
+    """Poisson arrivals at `rate` requests/s: (arrival_s, key, nrhs, rhs_seed).  Keys: 2D P1 with h
+    uniform over 1/SERVE_2D_N, or (probability frac_3d) the 3D Q1 cube; the coefficient seed is
+    drawn from n_seeds values with Zipf(zipf_a) weights, so keys repeat and set-up contexts get
+    reused."""
+    rng = np.random.Generator(np.random.PCG64(seed + 2718))
+    w = 1.0 / np.arange(1, n_seeds + 1) ** zipf_a
+    w /= w.sum()
+    t = np.cumsum(rng.exponential(1.0 / rate, size=n_requests)) if rate > 0 else np.zeros(n_requests)
+    out = []
+    for q in range(n_requests):
+        cseed = int(rng.choice(n_seeds, p=w))
+        key = ("q1", 32, cseed) if rng.random() < frac_3d else ("p1", int(rng.choice(SERVE_2D_N)), cseed)
+        nrhs = int(rng.integers(nrhs_range[0], nrhs_range[1] + 1))
+        out.append((float(t[q]), key, nrhs, int(seed * 100003 + q)))
+    return out

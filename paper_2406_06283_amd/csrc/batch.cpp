@@ -77,6 +77,11 @@ struct hkgeneo_server {
     hipGraphExec_t it_exec[2] = {nullptr, nullptr}, rs_exec = nullptr;
     int parity = 0;
     int64_t n_iter_launch = 0, n_restart_launch = 0, n_capture = 0, n_admitted = 0, n_retired = 0;
+    // measurement hook: with prof set, iterations are launched directly (same kernels, same shapes)
+    // with HIP events around every local-solve launch
+    bool prof = false;
+    std::vector<hipEvent_t> ev;
+    size_t ev_used = 0;
 };
 
 namespace {
@@ -463,7 +468,22 @@ int32_t pump_once(Engine *E, int *pending) {
         }
         if (ran || E->any_iter) {
             for (int k = 0; k < E->check; ++k) {
-                HKG_HIP(hipGraphLaunch(E->it_exec[E->parity], E->stream));
+                if (E->prof) {
+                    if (E->ev_used + 2 > E->ev.size())
+                        for (int q = 0; q < 256; ++q) {
+                            hipEvent_t e;
+                            HKG_HIP(hipEventCreate(&e));
+                            E->ev.push_back(e);
+                        }
+                    const ProbDev *probs = dp<ProbDev>(E->d_probs);
+                    HKG_TRY(batch_apply(E->geom, probs, dp<WorkItem>(E->d_items), dp<WorkItem>(E->d_rblk),
+                                        dp<WorkItem>(E->d_cblk), 1, E->parity, E->stream, E->ev[E->ev_used],
+                                        E->ev[E->ev_used + 1]));
+                    E->ev_used += 2;
+                    HKG_TRY(batch_arnoldi(E->geom, probs, dp<WorkItem>(E->d_rblk), E->parity, E->stream));
+                } else {
+                    HKG_HIP(hipGraphLaunch(E->it_exec[E->parity], E->stream));
+                }
                 E->parity ^= 1;
             }
             E->n_iter_launch += E->check;
@@ -508,6 +528,7 @@ void engine_free(Engine *E) {
     DevBuf *bufs[] = {&E->d_probs, &E->d_items, &E->d_rblk, &E->d_cblk, &E->d_live, &E->d_state, &E->d_scratch};
     for (DevBuf *x : bufs) drelease(&E->acct, x);
     if (E->h_state) (void)hipHostFree(E->h_state);
+    for (hipEvent_t e : E->ev) (void)hipEventDestroy(e);
     if (E->stream) (void)hipStreamDestroy(E->stream);
     delete E;
 }
@@ -515,7 +536,7 @@ void engine_free(Engine *E) {
 int32_t engine_create(int cap, int maxR, int restart, int64_t budget, Engine **out) {
     *out = nullptr;
     if (cap < 1 || cap > 65535 || maxR < 1 || maxR > 65535 || restart < 1 || budget <= 0) return HKG_EINVAL;
-    if ((size_t)5 * (restart + 2) * sizeof(double) > 64 * 1024) {
+    if (restart > 4 * BROWS) {
         set_last_error("restart too large for the batched kernels");
         return HKG_EINVAL;
     }
@@ -645,6 +666,30 @@ extern "C" int32_t hkgeneo_batch_solve(hkgeneo_batch *b, const double *const *f,
 extern "C" int64_t hkgeneo_batch_bytes(const hkgeneo_batch *b) { return b ? b->E->acct.device_bytes : 0; }
 
 extern "C" int32_t hkgeneo_batch_local_waves(const hkgeneo_batch *b) { return b ? b->E->geom.local_waves : 0; }
+
+extern "C" int32_t hkgeneo_batch_profile(hkgeneo_batch *b, int32_t enable) {
+    if (!b) return HKG_EINVAL;
+    Engine *E = b->E;
+    HKG_HIP(hipStreamSynchronize(E->stream));
+    E->prof = enable != 0;
+    if (E->prof) E->ev_used = 0;
+    return HKG_OK;
+}
+
+extern "C" int32_t hkgeneo_batch_profile_read(hkgeneo_batch *b, double *total_ms, int64_t *launches) {
+    if (!b || !total_ms || !launches) return HKG_EINVAL;
+    Engine *E = b->E;
+    HKG_HIP(hipStreamSynchronize(E->stream));
+    double t = 0.0;
+    for (size_t k = 0; k + 1 < E->ev_used; k += 2) {
+        float ms = 0.0f;
+        HKG_HIP(hipEventElapsedTime(&ms, E->ev[k], E->ev[k + 1]));
+        t += ms;
+    }
+    *total_ms = t;
+    *launches = (int64_t)(E->ev_used / 2);
+    return HKG_OK;
+}
 
 extern "C" void hkgeneo_batch_destroy(hkgeneo_batch *b) {
     if (!b) return;

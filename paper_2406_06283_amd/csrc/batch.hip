@@ -497,11 +497,55 @@ int32_t batch_arnoldi(const BatchGeom &g, const ProbDev *probs, const WorkItem *
 // ------------------------------------------------------------------------------------------------
 // restart phase: pairs whose cycle ended (PS_CYCLE_END) or that just joined (PS_NEW)
 // ------------------------------------------------------------------------------------------------
-// x += Z_k y with y = R^{-1} g from the rotated Hessenberg (PS_CYCLE_END; every block solves the
-// small triangle redundantly from LDS, column by column), or x = 0 (PS_NEW)
+// y = R^{-1} g on the rotated Hessenberg of a pair whose cycle ended (one block per pair; column
+// oriented back substitution, the next column's entries loaded while the current one is applied),
+// stored in the pair's hcol (free once its cycle has ended)
+constexpr int TS_Q = 4;         // restart <= TS_Q * BROWS
+
+__global__ __launch_bounds__(BROWS) void k_r_solve_y(const ProbDev *__restrict__ probs, const int32_t *__restrict__ live,
+                                                     int max_nrhs) {
+    extern __shared__ double y[];        // restart
+    const int t = blockIdx.x;
+    const ProbDev &P = probs[live[t / max_nrhs]];
+    const int rhs = t % max_nrhs;
+    if (rhs >= P.nrhs || P.active[rhs] != PS_CYCLE_END) return;
+    const int m = P.restart;
+    const int jd = (int)P.scal[(int64_t)rhs * 8 + 3];
+    if (jd <= 0) return;
+    const double *H = P.H + (int64_t)rhs * (m + 1) * m;
+    const double *g = P.g + (int64_t)rhs * (m + 1);
+    for (int i = threadIdx.x; i < jd; i += BROWS) y[i] = g[i];
+    double cur[TS_Q], nxt[TS_Q];
+    int k = jd - 1;
+#pragma unroll
+    for (int q = 0; q < TS_Q; ++q) cur[q] = H[min((int)threadIdx.x + BROWS * q, k) + (int64_t)k * (m + 1)];
+    double dcur = H[k + (int64_t)k * (m + 1)], dnxt = 0.0;
+    __syncthreads();
+    for (; k >= 0; --k) {
+        const int kn = max(k - 1, 0);
+#pragma unroll
+        for (int q = 0; q < TS_Q; ++q) nxt[q] = H[min((int)threadIdx.x + BROWS * q, kn) + (int64_t)kn * (m + 1)];
+        dnxt = H[kn + (int64_t)kn * (m + 1)];
+        const double yk = y[k] / dcur;
+        __syncthreads();
+        if (threadIdx.x == 0) y[k] = yk;
+#pragma unroll
+        for (int q = 0; q < TS_Q; ++q) {
+            const int i = threadIdx.x + BROWS * q;
+            if (i < k) y[i] -= cur[q] * yk;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < TS_Q; ++q) cur[q] = nxt[q];
+        dcur = dnxt;
+    }
+    for (int i = threadIdx.x; i < jd; i += BROWS) P.hcol[(int64_t)rhs * (m + 2) + i] = y[i];
+}
+
+// x += Z_k y (PS_CYCLE_END, y from k_r_solve_y), or x = 0 (PS_NEW)
 __global__ __launch_bounds__(BROWS) void k_r_update_x(const ProbDev *__restrict__ probs,
                                                       const WorkItem *__restrict__ rblk) {
-    extern __shared__ double ts[];       // R (jd x jd, column-major) then g / y (jd)
+    extern __shared__ double ys[];       // restart
     const WorkItem it = rblk[blockIdx.x];
     const ProbDev &P = probs[it.p];
     const int rhs = blockIdx.z;
@@ -517,25 +561,18 @@ __global__ __launch_bounds__(BROWS) void k_r_update_x(const ProbDev *__restrict_
     const int m = P.restart;
     const int jd = (int)P.scal[(int64_t)rhs * 8 + 3];
     if (jd <= 0) return;
-    const double *H = P.H + (int64_t)rhs * (m + 1) * m;
-    double *R = ts, *y = ts + (int64_t)jd * jd;
-    for (int t = threadIdx.x; t < jd * jd; t += BROWS) {
-        const int i = t % jd, k = t / jd;
-        R[t] = i <= k ? H[i + (int64_t)k * (m + 1)] : 0.0;
-    }
-    for (int t = threadIdx.x; t < jd; t += BROWS) y[t] = P.g[(int64_t)rhs * (m + 1) + t];
+    for (int i = threadIdx.x; i < jd; i += BROWS) ys[i] = P.hcol[(int64_t)rhs * (m + 2) + i];
     __syncthreads();
-    for (int k = jd - 1; k >= 0; --k) {
-        const double yk = y[k] / R[k + k * jd];
-        __syncthreads();
-        if (threadIdx.x == 0) y[k] = yk;
-        for (int i = threadIdx.x; i < k; i += BROWS) y[i] -= R[i + k * jd] * yk;
-        __syncthreads();
-    }
     if (r >= P.n) return;
     const double *Zk = zcol(P, rhs, 0);
     double s = x[r];
-    for (int i = 0; i < jd; ++i) s = fma(Zk[(int64_t)i * P.n + r], y[i], s);
+    for (int i0 = 0; i0 < jd; i0 += 4) {
+        double zv[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) zv[k] = Zk[(int64_t)min(i0 + k, jd - 1) * P.n + r];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s = fma(zv[k], i0 + k < jd ? ys[min(i0 + k, jd - 1)] : 0.0, s);
+    }
     x[r] = s;
 }
 
@@ -632,8 +669,9 @@ int32_t batch_restart(const BatchGeom &g, const ProbDev *probs, const WorkItem *
                       hipStream_t s) {
     const dim3 grid(g.nrblk, 1, g.max_nrhs);
     const int pairs = g.nprob * g.max_nrhs;
-    hipLaunchKernelGGL(k_r_update_x, grid, dim3(BROWS), (size_t)g.restart * (g.restart + 1) * sizeof(double), s, probs,
-                       rblk);
+    hipLaunchKernelGGL(k_r_solve_y, dim3(pairs), dim3(BROWS), (size_t)g.restart * sizeof(double), s, probs, live,
+                       g.max_nrhs);
+    hipLaunchKernelGGL(k_r_update_x, grid, dim3(BROWS), (size_t)g.restart * sizeof(double), s, probs, rblk);
     hipLaunchKernelGGL(k_r_residual, grid, dim3(BROWS), 0, s, probs, rblk);
     hipLaunchKernelGGL(k_r_decide, dim3((pairs + 255) / 256), dim3(256), 0, s, probs, live, g.nprob, g.max_nrhs);
     hipLaunchKernelGGL(k_r_start, grid, dim3(BROWS), 0, s, probs, rblk);

@@ -90,6 +90,8 @@ SIGNATURES = {
                                       c_void_p]),
     "hkgeneo_batch_bytes": (c_int64, [c_void_p]),
     "hkgeneo_batch_local_waves": (c_int32, [c_void_p]),
+    "hkgeneo_batch_profile": (c_int32, [c_void_p, c_int32]),
+    "hkgeneo_batch_profile_read": (c_int32, [c_void_p, POINTER(c_double), POINTER(c_int64)]),
     "hkgeneo_batch_destroy": (None, [c_void_p]),
     "hkgeneo_server_create": (c_int32, [c_int64, c_int32, c_int32, c_int32, POINTER(c_void_p)]),
     "hkgeneo_server_submit": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_int64, c_void_p]),
@@ -363,6 +365,16 @@ class Batch:
     def local_waves(self) -> int:
         return int(self.lib.hkgeneo_batch_local_waves(self.handle))
 
+    def profile(self, enable: bool):
+        _check(self.lib.hkgeneo_batch_profile(self.handle, int(enable)), "hkgeneo_batch_profile")
+
+    def profile_read(self):
+        t = c_double()
+        n = c_int64()
+        _check(self.lib.hkgeneo_batch_profile_read(self.handle, ctypes.byref(t), ctypes.byref(n)),
+               "hkgeneo_batch_profile_read")
+        return t.value, n.value
+
     def solve(self, fs, us=None, stream=None):
         """Returns ([u_p], [[info dict per rhs] per problem], status)."""
         import torch
@@ -480,6 +492,6 @@ class Server:
 
 def options_for(workload, **overrides) -> hkgeneo_options:
     """Options of a named workload (configs.Workload) with keyword overrides."""
-    kw = dict(eig_mode=workload.eig_mode, nev=workload.nev, tau=workload.tau)
+    kw = dict(eig_mode=workload.eig_mode, nev=workload.nev, tau=workload.tau, restart=workload.restart)
     kw.update(overrides)
     return default_options(**kw)

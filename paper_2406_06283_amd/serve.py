@@ -139,6 +139,7 @@ def run_stream(requests, make_solver, estimate, *, ctx_budget: int, workspace_bu
     setup_times = []
     hbm_peak = 0
     srv = H.Server(workspace_budget, max_requests=max_requests, max_nrhs=max_nrhs, restart=restart)
+    counts0 = (cache.hits, cache.misses, cache.evictions)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     nxt, done = 0, 0
@@ -212,7 +213,8 @@ def run_stream(requests, make_solver, estimate, *, ctx_budget: int, workspace_bu
     nrhs = sum(int(r.f.shape[0]) for r in requests)
     summary = dict(requests=len(requests), rhs=nrhs, wall_s=wall, solves_per_s=nrhs / wall,
                    p50_ms=float(np.percentile(lat, 50) * 1e3), p99_ms=float(np.percentile(lat, 99) * 1e3),
-                   mean_ms=float(lat.mean() * 1e3), hits=cache.hits, misses=cache.misses, evictions=cache.evictions,
+                   mean_ms=float(lat.mean() * 1e3), hits=cache.hits - counts0[0], misses=cache.misses - counts0[1],
+                   evictions=cache.evictions - counts0[2],
                    setups=len(setup_times), setup_ms_mean=float(np.mean(setup_times) * 1e3) if setup_times else 0.0,
                    hbm_peak_bytes=int(hbm_peak), iterations=stats["iterations"], captures=stats["captures"],
                    converged=all(i["converged"] for r in requests for i in r.info))

@@ -142,3 +142,29 @@ def test_batch_rejects_different_restart():
         with pytest.raises(H.HkgError) as e:
             H.Batch([S1, S2], [1, 1])
         assert e.value.status == H.HKG_EINVAL
+
+
+@pytest.mark.parametrize("restart", [8, 150])
+def test_batch_restarted_cycles_match_oracle(restart):
+    # restart = 8: every right-hand side needs several cycles, so the device-side restart phase
+    # (x update from the cycle's triangle, true residual, next cycle) runs repeatedly; 150: the
+    # long-restart sizes of the restart kernels
+    _say(f"[batch] FGMRES({restart}) cycles vs oracle")
+    p = pb.make_problem(20, k=7.0, s=3, overlap=2, coef="cells", seed=9, n_cells=4, rhs="normal", nrhs=2)
+    M = schwarz.TwoLevelSchwarz(p, schwarz.Options(eig_mode=local.EIG_FIXED, nev=4))
+    with H.Solver(p, H.default_options(eig_mode=H.HKG_EIG_FIXED, nev=4, restart=restart)) as S, \
+            H.Batch([S], [2]) as B:
+        (u,), (info,), st = B.solve([_rhs(p)])
+        us, infos, _ = S.solve(_rhs(p))
+        torch.cuda.synchronize()
+        U, Us = u.cpu().numpy(), us.cpu().numpy()
+    assert st == H.HKG_OK
+    for r in range(2):
+        x, oinfo = fgmres.solve(p, M, f=p.f[r], restart=restart)
+        assert info[r]["converged"] and abs(info[r]["iters"] - oinfo["iters"]) <= 2, (info[r]["iters"], oinfo["iters"])
+        assert abs(info[r]["iters"] - infos[r]["iters"]) <= 1
+        assert np.linalg.norm(p.f[r] - M.B @ U[r]) / np.linalg.norm(p.f[r]) <= 1e-8
+        assert np.linalg.norm(U[r] - x) / np.linalg.norm(x) <= 1e-8
+        assert np.linalg.norm(U[r] - Us[r]) / np.linalg.norm(Us[r]) <= 1e-8
+    if restart == 8:
+        assert min(i["iters"] for i in info) > 2 * restart

@@ -87,6 +87,43 @@ def timed_steps(S, solve, steps, warmup):
     return dict(total_s=time.perf_counter() - t0, fac_ms=fac, sol_ms=sol, iters=it, relres=rel)
 
 
+def kernel_source_hash() -> str:
+    """sha256 of the batched kernels' source (the traffic figures below belong to one version)."""
+    import hashlib
+    with open(os.path.join(ROOT, "paper_2406_06283_amd", "csrc", "batch.hip"), "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()
+
+
+def recorded_traffic(workload: str):
+    """HBM bytes per local-solve launch from the committed counter summary of this workload, if it
+    was taken on the current kernel source; None otherwise."""
+    path = os.path.join(ROOT, "profiles", f"traffic_k_b_local_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for ln in fh:
+            if ln.startswith("- ") and ":" in ln:
+                k, v = ln[2:].split(":", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel source sha256") != kernel_source_hash():
+        return None
+    try:
+        return int(vals["traffic bytes per launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def calibrate_copy(nbytes: int):
+    """An elementwise copy of nbytes (read once, written once) for counter calibration."""
+    import torch
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    torch.mul(a, 1.0, out=b)
+    sync()
+    progress(f"calibration copy: {nbytes} bytes read and written by one elementwise kernel")
+
+
 def latency(solve, n):
     lat = []
     for _ in range(n):
@@ -107,8 +144,8 @@ def run_default(args, w, p):
     # plain float64 single-problem path
     S = H.Solver(p, H.options_for(w, keep_workspace=1))
     r = timed_steps(S, lambda: S.solve(f)[1][0], args.steps, args.warmup)
-    r["lat"] = latency(lambda: S.solve(f), max(args.steps, 20))
-    r["lat8"] = latency(lambda: S.solve(f8), 5)
+    r["lat"] = latency(lambda: S.solve(f), max(args.steps, args.lat_reps))
+    r["lat8"] = latency(lambda: S.solve(f8), max(1, args.lat_reps // 4))
     r["m0"] = S.stats()["m0"]
     out["plain"] = r
     S.close()
@@ -128,8 +165,8 @@ def run_default(args, w, p):
             r["profiled"] = rp
             nI, _, m = S.subdomains()
             r["nI"], r["m"] = nI, m
-        r["lat"] = latency(lambda: B.solve([f]), max(args.steps, 20))
-        r["lat8"] = latency(lambda: B8.solve([f8]), 5)
+        r["lat"] = latency(lambda: B.solve([f]), max(args.steps, args.lat_reps))
+        r["lat8"] = latency(lambda: B8.solve([f8]), max(1, args.lat_reps // 4))
         r["m0"] = S.stats()["m0"]
         out[tag] = r
         B.close()
@@ -206,7 +243,8 @@ def main_default(args):
         "fp64_plain": summary(plain, args.steps),
         "roofline": {"kernel": "k_b_local<%d> (float32 inverses)" % rp["waves"], "bound": "hbm",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "bytes_per_launch": bpl,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": recorded_traffic(w.name),
+                     "bytes_per_launch": bpl,
                      "avg_launch_us": round(avg_s * 1e6, 3), "launches": int(rp["launches"])},
     }
     if not args.no_cpu_baseline:
@@ -347,6 +385,9 @@ def main():
     ap.add_argument("--workload", default="p1_h128_k40_8x8")
     ap.add_argument("--cpu-sample", type=int, default=1)
     ap.add_argument("--requests", type=int, default=200)
+    ap.add_argument("--lat-reps", type=int, default=20)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="after the run, one elementwise copy of BYTES for hardware-counter calibration")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -360,6 +401,8 @@ def main():
         main_serve(args)
     else:
         main_default(args)
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy)
 
 
 if __name__ == "__main__":

@@ -119,6 +119,8 @@ def calibrate_copy(nbytes: int):
     import torch
     a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
     b = torch.empty_like(a)
+    evict = torch.zeros(1 << 27, dtype=torch.float64, device="cuda:0")   # 1 GiB: pushes a out of L2 and MALL
+    evict += 1.0
     torch.mul(a, 1.0, out=b)
     sync()
     progress(f"calibration copy: {nbytes} bytes read and written by one elementwise kernel")
@@ -141,16 +143,20 @@ def run_default(args, w, p):
     p8 = w.problem(seed=0, nrhs=8)
     f8 = torch.from_numpy(p8.f).to(dev)
     out = {}
+    forms = args.forms.split(",") + ["mixed"]
     # plain float64 single-problem path
-    S = H.Solver(p, H.options_for(w, keep_workspace=1))
-    r = timed_steps(S, lambda: S.solve(f)[1][0], args.steps, args.warmup)
-    r["lat"] = latency(lambda: S.solve(f), max(args.steps, args.lat_reps))
-    r["lat8"] = latency(lambda: S.solve(f8), max(1, args.lat_reps // 4))
-    r["m0"] = S.stats()["m0"]
-    out["plain"] = r
-    S.close()
+    if "plain" in forms:
+        S = H.Solver(p, H.options_for(w, keep_workspace=1))
+        r = timed_steps(S, lambda: S.solve(f)[1][0], args.steps, args.warmup)
+        r["lat"] = latency(lambda: S.solve(f), max(args.steps, args.lat_reps))
+        r["lat8"] = latency(lambda: S.solve(f8), max(1, args.lat_reps // 4))
+        r["m0"] = S.stats()["m0"]
+        out["plain"] = r
+        S.close()
     # batched engine, float64 and mixed
     for tag, prec in (("fp64", 64), ("mixed", 32)):
+        if tag not in forms:
+            continue
         S = H.Solver(p, H.options_for(w, local_prec=prec, keep_workspace=1))
         B = H.Batch([S], [1])
         B8 = H.Batch([S], [8])
@@ -208,9 +214,11 @@ def main_default(args):
     w = WORKLOADS[args.workload]
     p = w.problem(seed=0)
     r = run_default(args, w, p)
-    mx, f64, plain = r["mixed"], r["fp64"], r["plain"]
+    mx, f64, plain = r["mixed"], r.get("fp64"), r.get("plain")
     rp = mx["profiled"]
-    ok = all(x <= 1e-8 for x in rp["relres"]) and abs(int(np.median(rp["iters"])) - int(np.median(plain["iters"]))) <= 2
+    ref = plain or f64          # float64 iteration count the mixed form must stay within 2 of
+    ok = all(x <= 1e-8 for x in rp["relres"]) and (
+        ref is None or abs(int(np.median(rp["iters"])) - int(np.median(ref["iters"]))) <= 2)
     word = 4
     bpl = local_solve_bytes(mx["nI"], mx["m"], word)
     avg_s = rp["local_ms"] / max(rp["launches"], 1) / 1e3
@@ -239,8 +247,8 @@ def main_default(args):
         "solve_only": {"p50_ms": round(pct(mx["lat"], 50), 3), "p99_ms": round(pct(mx["lat"], 99), 3),
                        "solves_per_s": round(1e3 / np.mean(mx["lat"]), 2)},
         "unprofiled_graph_replay": summary(mx, args.steps),
-        "fp64_batched": summary(f64, args.steps),
-        "fp64_plain": summary(plain, args.steps),
+        "fp64_batched": summary(f64, args.steps) if f64 else None,
+        "fp64_plain": summary(plain, args.steps) if plain else None,
         "roofline": {"kernel": "k_b_local<%d> (float32 inverses)" % rp["waves"], "bound": "hbm",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": recorded_traffic(w.name),
@@ -386,6 +394,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1)
     ap.add_argument("--requests", type=int, default=200)
     ap.add_argument("--lat-reps", type=int, default=20)
+    ap.add_argument("--forms", default="plain,fp64,mixed",
+                    help="forms of the default workload to run (mixed is always run: it gives value)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="after the run, one elementwise copy of BYTES for hardware-counter calibration")
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -66,9 +66,14 @@ extern "C" void hkgeneo_destroy(hkgeneo_ctx *c) {
                       &c->u,      &c->c,      &c->y,       &c->ypart, &c->itersd,       &c->V,      &c->Zk,      &c->H,          &c->cs,
                       &c->sn,     &c->g,      &c->part,    &c->hcol,   &c->scal,    &c->active,     &c->want,
                       &c->rnorm,  &c->npart,  &c->fnorm};
+    if (c->s2) (void)hipStreamSynchronize(c->s2);
     for (DevBuf *b : bufs) drelease(c, b);
     free_workspace(c);
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+    if (c->h_infoL) (void)hipHostFree(c->h_infoL);
+    if (c->s2) (void)hipStreamDestroy(c->s2);
     delete c;
 }
 

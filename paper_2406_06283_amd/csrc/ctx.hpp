@@ -30,7 +30,13 @@ struct hkgeneo_ctx {
     hkg::DevBuf Bval, Minv, Z, Zr, B0inv;
     // factorisation workspace (kept between calls when opt.keep_workspace, freed otherwise)
     hkg::DevBuf wDk, wBIO, wCII, wGG, wGI, wS, wW, wPiv, wInfo, wFlag, wD, wE, wTau, wM, wLam, wY, wB0, wLU, wPivL,
-        wJobsZ, wGjobsY, wMisc, wPiv0, wInv, wVWV;
+        wJobsZ, wGjobsY, wMisc, wPiv0, wInv, wVWV, wInfoL, wSL;
+    // the local-inverse pipeline of the factorisation runs on a second stream beside the coarse-space
+    // pipeline; its pivot flags come back through pinned host memory
+    hipStream_t s2 = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    int32_t *h_infoL = nullptr;
+    int h_infoL_n = 0;
     // apply workspace
     hkg::DevBuf u, c, y, ypart;
     int ws_nrhs = 0;

@@ -58,7 +58,7 @@ int32_t upload_bytes(hkgeneo_ctx *c, DevBuf *b, const void *host, size_t bytes, 
 void free_workspace(hkgeneo_ctx *c) {
     DevBuf *w[] = {&c->wDk, &c->wBIO, &c->wCII, &c->wGG, &c->wGI, &c->wS, &c->wW, &c->wPiv, &c->wInfo,
                    &c->wFlag, &c->wD, &c->wE, &c->wTau, &c->wM, &c->wLam, &c->wY, &c->wB0, &c->wLU,
-                   &c->wPivL, &c->wJobsZ, &c->wGjobsY, &c->wMisc, &c->wPiv0, &c->wInv, &c->wVWV};
+                   &c->wPivL, &c->wJobsZ, &c->wGjobsY, &c->wMisc, &c->wPiv0, &c->wInv, &c->wVWV, &c->wInfoL, &c->wSL};
     for (DevBuf *b : w) drelease(c, b);
 }
 
@@ -194,25 +194,20 @@ int32_t read_flags(hkgeneo_ctx *c, const DevBuf &buf, int n, std::vector<int32_t
     return HKG_OK;
 }
 
-// B_D = P L U and B_D^{-1} = U^{-1} L^{-1} P, computed in precision T into `out` (nSq entries)
+// B_D = P L U and B_D^{-1} = U^{-1} L^{-1} P, computed in precision T into `out` (nSq entries).
+// Issued without waiting: the pivot flags are copied to c->h_infoL and checked by the caller.
 template <typename T>
 int32_t local_inverses(hkgeneo_ctx *c, T *out, hipStream_t s) {
     const int ns = c->n_sub;
     const SubDev *dsub = dp<SubDev>(c->subs_d);
     HKG_TRY(walloc(c, &c->wLU, c->nSq * sizeof(T)));
     HKG_TRY(walloc(c, &c->wPivL, c->sum_nI * sizeof(int32_t)));
-    HKG_TRY(walloc(c, &c->wInfo, ns * sizeof(int32_t)));
+    HKG_TRY(walloc(c, &c->wInfoL, ns * sizeof(int32_t)));
     if (sizeof(T) == 8) HKG_TRY(copy_bii(dsub, ns, c->max_nI, dp<double>(c->wBIO), (double *)c->wLU.p, s));
     else HKG_TRY(copy_bii_f32(dsub, ns, c->max_nI, dp<double>(c->wBIO), (float *)c->wLU.p, s));
     HKG_TRY(lu_batched<T>(dp<DMat>(c->matsSq), dp<int64_t>(c->poffLoc), ns, c->max_nI, dp<T>(c->wLU),
-                          dp<int32_t>(c->wPivL), dp<int32_t>(c->wInfo), true, s));
-    std::vector<int32_t> info;
-    HKG_TRY(read_flags(c, c->wInfo, ns, &info, s));
-    for (int i = 0; i < ns; ++i)
-        if (info[i]) {
-            set_last_error("zero pivot in the local Dirichlet matrix of subdomain " + std::to_string(i));
-            return HKG_ESINGULAR_LOCAL;
-        }
+                          dp<int32_t>(c->wPivL), dp<int32_t>(c->wInfoL), true, s));
+    HKG_HIP(hipMemcpyAsync(c->h_infoL, c->wInfoL.p, ns * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HKG_TRY(perm_identity_batched<T>(dp<DMat>(c->matsSq), dp<int64_t>(c->poffLoc), ns, c->max_nI,
                                      dp<int32_t>(c->wPivL), out, s));
     HKG_TRY(tri_solve_batched<T>(dp<TriJob>(c->jobsSq), ns, c->max_nI, c->max_nI, dp<T>(c->wLU), out, TRI_LOWER_UNIT,
@@ -229,9 +224,9 @@ int32_t local_operators(hkgeneo_ctx *c, hipStream_t s) {
     if (c->Minv.bytes != bytes) HKG_TRY(dalloc(c, &c->Minv, bytes));
     if (!store32) return local_inverses<double>(c, dp<double>(c->Minv), s);
     if (c->opt.local_factor_prec == 32) return local_inverses<float>(c, dp<float>(c->Minv), s);
-    HKG_TRY(walloc(c, &c->wS, c->nSq * sizeof(double)));
-    HKG_TRY(local_inverses<double>(c, dp<double>(c->wS), s));
-    return cast_f64_f32(dp<double>(c->wS), dp<float>(c->Minv), c->nSq, s);
+    HKG_TRY(walloc(c, &c->wSL, c->nSq * sizeof(double)));
+    HKG_TRY(local_inverses<double>(c, dp<double>(c->wSL), s));
+    return cast_f64_f32(dp<double>(c->wSL), dp<float>(c->Minv), c->nSq, s);
 }
 
 int32_t coarse_space(hkgeneo_ctx *c, hipStream_t s) {
@@ -412,6 +407,18 @@ int32_t coarse_space(hkgeneo_ctx *c, hipStream_t s) {
 int32_t factor(hkgeneo_ctx *c, hipStream_t s) {
     const int ns = c->n_sub;
     const SubDev *dsub = dp<SubDev>(c->subs_d);
+    if (!c->s2) {
+        HKG_HIP(hipStreamCreateWithFlags(&c->s2, hipStreamNonBlocking));
+        HKG_HIP(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+        HKG_HIP(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+    }
+    if (c->h_infoL_n < ns) {
+        if (c->h_infoL) (void)hipHostFree(c->h_infoL);
+        c->h_infoL = nullptr;
+        c->h_infoL_n = 0;
+        HKG_HIP(hipHostMalloc((void **)&c->h_infoL, ns * sizeof(int32_t)));
+        c->h_infoL_n = ns;
+    }
     HKG_TRY(walloc(c, &c->wDk, c->nnz * sizeof(double)));
     if (c->Bval.bytes != (size_t)c->nnz * sizeof(double)) HKG_TRY(dalloc(c, &c->Bval, c->nnz * sizeof(double)));
     HKG_TRY(form_operator(dp<double>(c->Aval), dp<double>(c->Sval), c->k * c->k, dp<double>(c->Bval), dp<double>(c->wDk),
@@ -423,9 +430,26 @@ int32_t factor(hkgeneo_ctx *c, hipStream_t s) {
     HKG_TRY(extract_blocks(dsub, ns, c->max_nI, dp<int32_t>(c->rowptr), dp<int32_t>(c->colidx), dp<double>(c->Bval),
                            dp<double>(c->wDk), dp<int32_t>(c->I_idx), dp<int32_t>(c->G_idx), dp<double>(c->winv),
                            dp<double>(c->wBIO), dp<double>(c->wCII), s));
-    if (c->opt.two_level) HKG_TRY(coarse_space(c, s));
-    HKG_TRY(local_operators(c, s));
-    HKG_HIP(hipStreamSynchronize(s));
+    // the local inverses (reading B_II) on the second stream, the coarse space on the caller's: the
+    // two pipelines share no buffer written after this point
+    HKG_HIP(hipEventRecord(c->ev_fork, s));
+    HKG_HIP(hipStreamWaitEvent(c->s2, c->ev_fork, 0));
+    int32_t st = local_operators(c, c->s2);
+    if (st == HKG_OK && c->opt.two_level) st = coarse_space(c, s);
+    // join before returning, whatever happened on either side
+    const hipError_t e1 = hipEventRecord(c->ev_join, c->s2);
+    const hipError_t e2 = hipStreamWaitEvent(s, c->ev_join, 0);
+    const hipError_t e3 = hipStreamSynchronize(s);
+    HKG_TRY(st);
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+        set_last_error("joining the local-inverse stream");
+        return HKG_EHIP;
+    }
+    for (int i = 0; i < ns; ++i)
+        if (c->h_infoL[i]) {
+            set_last_error("zero pivot in the local Dirichlet matrix of subdomain " + std::to_string(i));
+            return HKG_ESINGULAR_LOCAL;
+        }
     return HKG_OK;
 }
 

@@ -163,7 +163,18 @@ __global__ __launch_bounds__(SY_THREADS) void k_sytrd_panel(const SubDev *__rest
         // 1. corrected column j, rows j..n-1
         for (int r = j + tid; r < n; r += SY_THREADS) {
             double s = A[r + (int64_t)j * n];
-            for (int q = 0; q < kk; ++q) s -= V[r + (int64_t)q * n] * vw[q] + W[r + (int64_t)q * n] * vw[SY_NB + q];
+            for (int q0 = 0; q0 < kk; q0 += 4) {
+                double a[4], b[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int q = min(q0 + u, kk - 1);
+                    a[u] = V[r + (int64_t)q * n];
+                    b[u] = W[r + (int64_t)q * n];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (q0 + u < kk) s -= a[u] * vw[q0 + u] + b[u] * vw[SY_NB + q0 + u];
+            }
             p[r] = s;
         }
         __syncthreads();
@@ -194,10 +205,18 @@ __global__ __launch_bounds__(SY_THREADS) void k_sytrd_panel(const SubDev *__rest
         if (t == 0.0) continue;          // H_j = I: W column stays zero
         // 3. p = t (A0 v - V (W^T v) - W (V^T v)) on rows j+1..n-1
         {
+            // eight column loads in flight per thread (indices clamped into range, the surplus
+            // terms masked), summed in column order
             const int rt = tid & (SY_RT - 1), g = tid / SY_RT;
             for (int r = j + 1 + rt; r < n; r += SY_RT) {
                 double s = 0.0;
-                for (int c = j + 1 + g; c < n; c += 2) s = fma(A[r + (int64_t)c * n], v[c], s);
+                for (int c0 = j + 1 + g; c0 < n; c0 += 16) {
+                    double a[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) a[u] = A[r + (int64_t)min(c0 + 2 * u, n - 1) * n];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) s = fma(a[u], c0 + 2 * u < n ? v[min(c0 + 2 * u, n - 1)] : 0.0, s);
+                }
                 part[g * n + r] = s;
             }
         }
@@ -211,7 +230,18 @@ __global__ __launch_bounds__(SY_THREADS) void k_sytrd_panel(const SubDev *__rest
         __syncthreads();
         for (int r = j + 1 + tid; r < n; r += SY_THREADS) {
             double s = part[r] + part[n + r];
-            for (int q = 0; q < kk; ++q) s -= V[r + (int64_t)q * n] * t12[q] + W[r + (int64_t)q * n] * t12[kk + q];
+            for (int q0 = 0; q0 < kk; q0 += 4) {
+                double a[4], b[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int q = min(q0 + u, kk - 1);
+                    a[u] = V[r + (int64_t)q * n];
+                    b[u] = W[r + (int64_t)q * n];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (q0 + u < kk) s -= a[u] * t12[q0 + u] + b[u] * t12[kk + q0 + u];
+            }
             p[r] = t * s;
         }
         __syncthreads();

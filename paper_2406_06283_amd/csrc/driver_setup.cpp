@@ -58,7 +58,7 @@ int32_t upload_bytes(hkgeneo_ctx *c, DevBuf *b, const void *host, size_t bytes, 
 void free_workspace(hkgeneo_ctx *c) {
     DevBuf *w[] = {&c->wDk, &c->wBIO, &c->wCII, &c->wGG, &c->wGI, &c->wS, &c->wW, &c->wPiv, &c->wInfo,
                    &c->wFlag, &c->wD, &c->wE, &c->wTau, &c->wM, &c->wLam, &c->wY, &c->wB0, &c->wLU,
-                   &c->wPivL, &c->wJobsZ, &c->wGjobsY, &c->wMisc, &c->wPiv0, &c->wInv, &c->wVWV, &c->wInfoL, &c->wSL};
+                   &c->wPivL, &c->wJobsZ, &c->wGjobsY, &c->wMisc, &c->wPiv0, &c->wInv, &c->wVWV, &c->wInfoL, &c->wSL, &c->wIv};
     for (DevBuf *b : w) drelease(c, b);
 }
 
@@ -290,8 +290,10 @@ int32_t coarse_space(hkgeneo_ctx *c, hipStream_t s) {
                                    dp<double>(c->wE), dp<double>(c->wTau), s));
     HKG_TRY(walloc(c, &c->wM, ns * sizeof(int32_t)));
     HKG_TRY(walloc(c, &c->wLam, (size_t)ns * (mmax + 2) * sizeof(double)));
+    HKG_TRY(walloc(c, &c->wIv, (size_t)3 * ns * sizeof(double)));
     HKG_TRY(select_eigs(dsub, ns, c->max_nI, dp<double>(c->wD), dp<double>(c->wE), o.eig_mode, o.tau, o.nev,
-                        o.cluster_rtol, mmax, dp<int32_t>(c->wM), dp<double>(c->wLam), dp<int32_t>(c->wFlag), s));
+                        o.cluster_rtol, mmax, dp<int32_t>(c->wM), dp<double>(c->wLam), dp<int32_t>(c->wFlag),
+                        dp<double>(c->wIv), s));
     c->m_host.assign(ns, 0);
     c->lam_host.assign((size_t)ns * (mmax + 2), 0.0);
     HKG_HIP(hipMemcpyAsync(c->m_host.data(), c->wM.p, ns * sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -330,7 +332,9 @@ int32_t coarse_space(hkgeneo_ctx *c, hipStream_t s) {
     // eigenvectors -> coarse basis Z_i = X_I P_i
     if (c->Z.bytes != (size_t)offZ * sizeof(double)) HKG_TRY(dalloc(c, &c->Z, offZ * sizeof(double)));
     HKG_TRY(walloc(c, &c->wInv, (size_t)offZ * (5 * sizeof(double) + 1)));
-    HKG_TRY(tridiag_vectors_n(dsub, ns, c->max_nI, dp<double>(c->wD), dp<double>(c->wE), dp<double>(c->wLam), mmax,
+    int64_t max_nm = 0;
+    for (int i = 0; i < ns; ++i) max_nm = std::max(max_nm, (int64_t)c->subs[i].nI * c->subs[i].m);
+    HKG_TRY(tridiag_vectors_n(dsub, ns, max_nm, dp<double>(c->wD), dp<double>(c->wE), dp<double>(c->wLam), mmax,
                               dp<double>(c->Z), dp<double>(c->wInv),
                               reinterpret_cast<unsigned char *>(dp<double>(c->wInv) + 5 * offZ), s));
     HKG_TRY(back_transform_n(dsub, ns, c->max_nI, c->max_m, dp<double>(c->wW), dp<double>(c->wTau), dp<double>(c->Z),

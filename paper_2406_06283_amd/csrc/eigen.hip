@@ -319,21 +319,20 @@ __device__ double bisect_kth(const double *d, const double *e2, int n, int k, do
     return 0.5 * (lo + hi);
 }
 
-// one wave per subdomain; T staged in LDS as (d, e^2)
-__global__ __launch_bounds__(64) void k_select(const SubDev *__restrict__ subs, const double *__restrict__ dbuf,
-                                               const double *__restrict__ ebuf, int mode, double tau, int nev,
-                                               double rtol, int mmax, int32_t *__restrict__ m_out,
-                                               double *__restrict__ lam_out, int32_t *__restrict__ flag) {
-    extern __shared__ double sh[];
-    const SubDev sd = subs[blockIdx.x];
-    const int n = sd.nI;
-    const double *dg = dbuf + sd.offI, *eg = ebuf + sd.offI;
-    double *d = sh, *e2 = sh + n;
-    const int lane = threadIdx.x;
-    // Gershgorin interval and the pivot floor of the Sturm recurrence
+// Selection runs in three launches.  (1) One wave per subdomain: Gershgorin interval, pivot floor of
+// the Sturm recurrence and m from the counts at tau (or nev) and at 0.  (2) One wave per (subdomain,
+// eigenvalue k <= m): the k-th smallest eigenvalue by multisection, the 64 lanes testing 64 interior
+// shifts of the current bracket at once.  (3) One wave per subdomain: the cluster at the cut is
+// closed (Def. 2.15 keeps lambda_{m+1} away from lambda_m), extending m by serial bisection when
+// needed.
+
+// T staged in LDS as (d, e^2) by the whole wave; returns the Gershgorin interval, widened, and pivmin
+__device__ void stage_tridiagonal(const double *__restrict__ dg, const double *__restrict__ eg, int n, double *d,
+                                  double *e2, double *lo_out, double *hi_out, double *piv_out) {
+    const int lane = threadIdx.x & 63;
     double lo = 1e300, hi = -1e300, emax2 = 0.0;
     for (int i = lane; i < n; i += 64) {
-        double r = (i > 0 ? fabs(eg[i - 1]) : 0.0) + (i + 1 < n ? fabs(eg[i]) : 0.0);
+        const double r = (i > 0 ? fabs(eg[i - 1]) : 0.0) + (i + 1 < n ? fabs(eg[i]) : 0.0);
         lo = fmin(lo, dg[i] - r);
         hi = fmax(hi, dg[i] + r);
         d[i] = dg[i];
@@ -350,35 +349,103 @@ __global__ __launch_bounds__(64) void k_select(const SubDev *__restrict__ subs, 
     __syncthreads();
     const double tnorm = fmax(fabs(lo), fabs(hi));
     const double pivmin = fmax(2.2250738585072014e-308, 2.2204460492503131e-16 * 2.2204460492503131e-16 * emax2);
-    lo -= 2.2204460492503131e-16 * tnorm * n + pivmin;
-    hi += 2.2204460492503131e-16 * tnorm * n + pivmin;
-    int m = (mode == HKG_EIG_THRESHOLD) ? sturm_count(d, e2, n, tau, pivmin) : nev;
-    m = max(m, sturm_count(d, e2, n, 0.0, pivmin));   // every lambda <= 0 (Def. 2.15: lambda_{m+1} > 0)
-    m = min(m, n);
-    double *lam = lam_out + (int64_t)blockIdx.x * (mmax + 2);
-    if (m > mmax) {
-        if (lane == 0) { flag[blockIdx.x] = 1; m_out[blockIdx.x] = m; }
-        return;
-    }
-    const int need = min(n, m + 1);
-    for (int k = lane; k < need; k += 64) lam[k] = bisect_kth(d, e2, n, k, lo, hi, pivmin);
-    __syncthreads();
+    *lo_out = lo - (2.2204460492503131e-16 * tnorm * n + pivmin);
+    *hi_out = hi + (2.2204460492503131e-16 * tnorm * n + pivmin);
+    *piv_out = pivmin;
+}
+
+__global__ __launch_bounds__(64) void k_select_count(const SubDev *__restrict__ subs, const double *__restrict__ dbuf,
+                                                     const double *__restrict__ ebuf, int mode, double tau, int nev,
+                                                     int mmax, int32_t *__restrict__ m_out, int32_t *__restrict__ flag,
+                                                     double *__restrict__ iv) {
+    extern __shared__ double sh[];
+    const SubDev sd = subs[blockIdx.x];
+    const int n = sd.nI;
+    double *d = sh, *e2 = sh + n;
+    double lo, hi, pivmin;
+    stage_tridiagonal(dbuf + sd.offI, ebuf + sd.offI, n, d, e2, &lo, &hi, &pivmin);
+    const int lane = threadIdx.x;
+    // lane 0 counts below tau, lane 1 below 0 (the rest idle)
+    int c = 0;
+    if (lane == 0) c = (mode == HKG_EIG_THRESHOLD) ? sturm_count(d, e2, n, tau, pivmin) : nev;
+    else if (lane == 1) c = sturm_count(d, e2, n, 0.0, pivmin);
+    const int c0 = __shfl(c, 0, 64), c1 = __shfl(c, 1, 64);
+    const int m = min(max(c0, c1), n);     // every lambda <= 0 joins (Def. 2.15: lambda_{m+1} > 0)
     if (lane == 0) {
-        // close a cluster at the cut: lambda_{m+1} - lambda_m <= rtol max(1, |lambda_m|)
-        while (m > 0 && m < n && lam[m] - lam[m - 1] <= rtol * fmax(1.0, fabs(lam[m - 1]))) {
-            ++m;
-            if (m > mmax) break;
-            if (m < n) lam[m] = bisect_kth(d, e2, n, m, lo, hi, pivmin);
-        }
-        flag[blockIdx.x] = (m > mmax) ? 1 : 0;
         m_out[blockIdx.x] = m;
+        flag[blockIdx.x] = m > mmax ? 1 : 0;
+        iv[3 * blockIdx.x] = lo;
+        iv[3 * blockIdx.x + 1] = hi;
+        iv[3 * blockIdx.x + 2] = pivmin;
     }
 }
 
+// wave (subdomain, k): lambda_k in (a, b] with count(a) <= k < count(b), narrowed 65-fold per round
+__global__ __launch_bounds__(64) void k_select_refine(const SubDev *__restrict__ subs, const double *__restrict__ dbuf,
+                                                      const double *__restrict__ ebuf, int mmax,
+                                                      const int32_t *__restrict__ m_in, const int32_t *__restrict__ flag,
+                                                      const double *__restrict__ iv, double *__restrict__ lam_out) {
+    extern __shared__ double sh[];
+    const int sub = blockIdx.x, k = blockIdx.y;
+    const SubDev sd = subs[sub];
+    const int n = sd.nI;
+    if (flag[sub] || k >= min(n, m_in[sub] + 1)) return;
+    double *d = sh, *e2 = sh + n;
+    double lo0, hi0, pv0;
+    stage_tridiagonal(dbuf + sd.offI, ebuf + sd.offI, n, d, e2, &lo0, &hi0, &pv0);
+    const double pivmin = iv[3 * sub + 2];
+    double a = iv[3 * sub], b = iv[3 * sub + 1];
+    const int lane = threadIdx.x;
+    for (int it = 0; it < 40; ++it) {
+        const double sig = a + (b - a) * ((double)(lane + 1) / 65.0);
+        const bool inside = sig > a && sig < b;
+        const int cnt = inside ? sturm_count(d, e2, n, sig, pivmin) : 0;
+        double na = (inside && cnt <= k) ? sig : a;
+        double nb = (inside && cnt > k) ? sig : b;
+        for (int o = 32; o > 0; o >>= 1) {
+            na = fmax(na, __shfl_xor(na, o, 64));
+            nb = fmin(nb, __shfl_xor(nb, o, 64));
+        }
+        if (na == a && nb == b) break;     // the bracket cannot be split further
+        a = na;
+        b = nb;
+    }
+    if (lane == 0) lam_out[(int64_t)sub * (mmax + 2) + k] = 0.5 * (a + b);
+}
+
+// close a cluster at the cut: lambda_{m+1} - lambda_m <= rtol max(1, |lambda_m|) moves the cut up
+__global__ __launch_bounds__(64) void k_select_close(const SubDev *__restrict__ subs, const double *__restrict__ dbuf,
+                                                     const double *__restrict__ ebuf, double rtol, int mmax,
+                                                     int32_t *__restrict__ m_io, int32_t *__restrict__ flag,
+                                                     const double *__restrict__ iv, double *__restrict__ lam_out) {
+    extern __shared__ double sh[];
+    const int sub = blockIdx.x;
+    const SubDev sd = subs[sub];
+    const int n = sd.nI;
+    if (flag[sub]) return;
+    double *d = sh, *e2 = sh + n;
+    double lo, hi, pivmin;
+    stage_tridiagonal(dbuf + sd.offI, ebuf + sd.offI, n, d, e2, &lo, &hi, &pivmin);
+    if (threadIdx.x != 0) return;
+    double *lam = lam_out + (int64_t)sub * (mmax + 2);
+    int m = m_io[sub];
+    while (m > 0 && m < n && lam[m] - lam[m - 1] <= rtol * fmax(1.0, fabs(lam[m - 1]))) {
+        ++m;
+        if (m > mmax) break;
+        if (m < n) lam[m] = bisect_kth(d, e2, n, m, iv[3 * sub], iv[3 * sub + 1], pivmin);
+    }
+    flag[sub] = (m > mmax) ? 1 : 0;
+    m_io[sub] = m;
+}
+
 int32_t select_eigs(const SubDev *d_sub, int nsub, int maxnI, const double *d, const double *e, int mode, double tau,
-                    int nev, double rtol, int mmax, int32_t *m_out, double *lam_out, int32_t *flag, hipStream_t s) {
-    hipLaunchKernelGGL(k_select, dim3(nsub), dim3(64), (size_t)2 * maxnI * sizeof(double), s, d_sub, d, e, mode, tau, nev,
-                       rtol, mmax, m_out, lam_out, flag);
+                    int nev, double rtol, int mmax, int32_t *m_out, double *lam_out, int32_t *flag, double *iv,
+                    hipStream_t s) {
+    const size_t shm = (size_t)2 * maxnI * sizeof(double);
+    hipLaunchKernelGGL(k_select_count, dim3(nsub), dim3(64), shm, s, d_sub, d, e, mode, tau, nev, mmax, m_out, flag, iv);
+    hipLaunchKernelGGL(k_select_refine, dim3(nsub, mmax + 1), dim3(64), shm, s, d_sub, d, e, mmax, m_out, flag, iv,
+                       lam_out);
+    hipLaunchKernelGGL(k_select_close, dim3(nsub), dim3(64), shm, s, d_sub, d, e, rtol, mmax, m_out, flag, iv, lam_out);
     HKG_HIP(hipGetLastError());
     return HKG_OK;
 }
@@ -397,18 +464,29 @@ __device__ __forceinline__ double start_value(int i, int k) {
     return ((double)(h & 0xffffff) / 16777216.0) * 2.0 - 1.0;
 }
 
+// The iterates live in LDS when n m doubles fit (LDSB), else in the global scratch; the factors of
+// T - lambda I stay in the global scratch (read-only in the sweeps).  Running values of the
+// recurrences are carried in registers, the reciprocal pivots are stored, and the loads of four
+// steps are issued before their arithmetic.
+template <bool LDSB>
 __global__ __launch_bounds__(64) void k_inverse_iteration(const SubDev *__restrict__ subs, const double *__restrict__ dbuf,
                                                           const double *__restrict__ ebuf, const double *__restrict__ lam_all,
                                                           int mmax, double *__restrict__ Zb, double *__restrict__ scratch,
                                                           unsigned char *__restrict__ swp_all) {
+    extern __shared__ double sb[];
     const SubDev sd = subs[blockIdx.x];
     const int n = sd.nI, m = sd.m;
     if (m == 0) return;
     const double *d = dbuf + sd.offI, *e = ebuf + sd.offI;
     const double *lam = lam_all + (int64_t)blockIdx.x * (mmax + 2);
     const int64_t nm = (int64_t)n * m;
-    double *dd = scratch + 5 * sd.offZ, *du = dd + nm, *du2 = du + nm, *fac = du2 + nm, *b = fac + nm;
-    unsigned char *swp = swp_all + sd.offZ;
+    double *__restrict__ rdd = scratch + 5 * sd.offZ;
+    double *__restrict__ du = rdd + nm;
+    double *__restrict__ du2 = du + nm;
+    double *__restrict__ fac = du2 + nm;
+    double *__restrict__ b = LDSB ? sb : fac + nm;
+    const unsigned char *__restrict__ swp = swp_all + sd.offZ;
+    unsigned char *__restrict__ swpw = swp_all + sd.offZ;
     double *Z = Zb + sd.offZ;
     const int lane = threadIdx.x;
     double tnorm = 0.0;
@@ -430,18 +508,18 @@ __global__ __launch_bounds__(64) void k_inverse_iteration(const SubDev *__restri
             if (fabs(ddi) >= fabs(sub)) {
                 if (ddi == 0.0) ddi = pert;
                 const double f = sub / ddi;
-                swp[q] = 0;
+                swpw[q] = 0;
                 fac[q] = f;
-                dd[q] = ddi;
+                rdd[q] = 1.0 / ddi;
                 du[q] = dui;
                 du2[q] = 0.0;
                 ddi = dnext - f * dui;
                 dui = unext;
             } else {
                 const double f = ddi / sub;
-                swp[q] = 1;
+                swpw[q] = 1;
                 fac[q] = f;
-                dd[q] = sub;
+                rdd[q] = 1.0 / sub;
                 du[q] = dnext;
                 du2[q] = unext;
                 ddi = dui - f * dnext;
@@ -449,33 +527,62 @@ __global__ __launch_bounds__(64) void k_inverse_iteration(const SubDev *__restri
             }
         }
         if (ddi == 0.0) ddi = pert;
-        dd[(int64_t)(n - 1) * m + k] = ddi;
+        rdd[(int64_t)(n - 1) * m + k] = 1.0 / ddi;
         for (int i = 0; i < n; ++i) b[(int64_t)i * m + k] = start_value(i, k);
     }
     __syncthreads();
     for (int sweep = 0; sweep < 3; ++sweep) {
         for (int k = lane; k < m; k += 64) {
-            for (int i = 0; i + 1 < n; ++i) {
-                const int64_t q = (int64_t)i * m + k;
-                const double bi = b[q], bn = b[q + m];
-                if (!swp[q]) {
-                    b[q + m] = bn - fac[q] * bi;
-                } else {
-                    b[q] = bn;
-                    b[q + m] = bi - fac[q] * bn;
+            // forward elimination with the row exchanges; cur = running entry of row i
+            double cur = b[k];
+            for (int i0 = 0; i0 + 1 < n; i0 += 4) {
+                double bn[4], f[4];
+                int sw[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int i = min(i0 + u, n - 2);
+                    const int64_t q = (int64_t)i * m + k;
+                    bn[u] = b[q + m];
+                    f[u] = fac[q];
+                    sw[u] = swp[q];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    if (i0 + u + 1 < n) {
+                        const double out = sw[u] ? bn[u] : cur;
+                        cur = sw[u] ? cur - f[u] * bn[u] : bn[u] - f[u] * cur;
+                        b[(int64_t)(i0 + u) * m + k] = out;
+                    }
                 }
             }
-            double x2 = 0.0, x1 = 0.0, mx = 0.0;     // x_{i+2}, x_{i+1}
-            for (int i = n - 1; i >= 0; --i) {
-                const int64_t q = (int64_t)i * m + k;
-                double v = b[q];
-                if (i + 1 < n) v -= du[q] * x1;
-                if (i + 2 < n) v -= du2[q] * x2;
-                v /= dd[q];
-                b[q] = v;
-                x2 = x1;
-                x1 = v;
-                mx = fmax(mx, fabs(v));
+            b[(int64_t)(n - 1) * m + k] = cur;
+            // back substitution with U (diagonal, two super-diagonals); x1 = x_{i+1}, x2 = x_{i+2}
+            double x1 = 0.0, x2 = 0.0, mx = 0.0;
+            for (int i0 = n - 1; i0 >= 0; i0 -= 4) {
+                double bv[4], u1[4], u2[4], r[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int i = max(i0 - u, 0);
+                    const int64_t q = (int64_t)i * m + k;
+                    bv[u] = b[q];
+                    u1[u] = du[q];
+                    u2[u] = du2[q];
+                    r[u] = rdd[q];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int i = i0 - u;
+                    if (i >= 0) {
+                        double v = bv[u];
+                        if (i + 1 < n) v -= u1[u] * x1;
+                        if (i + 2 < n) v -= u2[u] * x2;
+                        v *= r[u];
+                        b[(int64_t)i * m + k] = v;
+                        x2 = x1;
+                        x1 = v;
+                        mx = fmax(mx, fabs(v));
+                    }
+                }
             }
             const double inv = mx > 0.0 ? 1.0 / mx : 1.0;
             for (int i = 0; i < n; ++i) b[(int64_t)i * m + k] *= inv;
@@ -503,10 +610,17 @@ __global__ __launch_bounds__(64) void k_inverse_iteration(const SubDev *__restri
         for (int i = lane; i < n; i += 64) Z[(int64_t)k * n + i] = b[(int64_t)i * m + k];
 }
 
-int32_t tridiag_vectors_n(const SubDev *d_sub, int nsub, int maxnI, const double *d, const double *e, const double *lam,
-                          int mmax, double *Z, double *scratch, unsigned char *swp, hipStream_t s) {
-    (void)maxnI;
-    hipLaunchKernelGGL(k_inverse_iteration, dim3(nsub), dim3(64), 0, s, d_sub, d, e, lam, mmax, Z, scratch, swp);
+constexpr size_t II_LDS_MAX = 150 * 1024;
+
+int32_t tridiag_vectors_n(const SubDev *d_sub, int nsub, int64_t max_nm, const double *d, const double *e,
+                          const double *lam, int mmax, double *Z, double *scratch, unsigned char *swp, hipStream_t s) {
+    const size_t shm = (size_t)max_nm * sizeof(double);
+    if (shm <= II_LDS_MAX)
+        hipLaunchKernelGGL(k_inverse_iteration<true>, dim3(nsub), dim3(64), shm, s, d_sub, d, e, lam, mmax, Z, scratch,
+                           swp);
+    else
+        hipLaunchKernelGGL(k_inverse_iteration<false>, dim3(nsub), dim3(64), 0, s, d_sub, d, e, lam, mmax, Z, scratch,
+                           swp);
     HKG_HIP(hipGetLastError());
     return HKG_OK;
 }

@@ -59,9 +59,12 @@ int32_t tridiagonalize_blocked(const SubDev *d_sub, int nsub, int maxnI, double 
 int32_t tridiagonalize_n(const SubDev *d_sub, int nsub, int maxnI, double *Sq, double *d, double *e, double *tau,
                          hipStream_t s);
 int32_t select_eigs(const SubDev *d_sub, int nsub, int maxnI, const double *d, const double *e, int mode, double tau,
-                    int nev, double rtol, int mmax, int32_t *m_out, double *lam_out, int32_t *flag, hipStream_t s);
-int32_t tridiag_vectors_n(const SubDev *d_sub, int nsub, int maxnI, const double *d, const double *e, const double *lam,
-                          int mmax, double *Z, double *scratch, unsigned char *swp, hipStream_t s);
+                    int nev, double rtol, int mmax, int32_t *m_out, double *lam_out, int32_t *flag, double *iv,
+                    hipStream_t s);
+// inverse iteration for the selected eigenvectors of T (one wave per subdomain); max_nm = the
+// largest n_I m_i (the iterates are staged in LDS when they fit)
+int32_t tridiag_vectors_n(const SubDev *d_sub, int nsub, int64_t max_nm, const double *d, const double *e,
+                          const double *lam, int mmax, double *Z, double *scratch, unsigned char *swp, hipStream_t s);
 int32_t back_transform_n(const SubDev *d_sub, int nsub, int maxnI, int max_m, const double *Sq, const double *tau,
                          double *Z, hipStream_t s);
 int32_t scale_rows_invsqrt_diag(const SubDev *d_sub, int nsub, const double *C, double *Z, hipStream_t s);

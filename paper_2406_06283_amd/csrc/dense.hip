@@ -118,16 +118,31 @@ __global__ __launch_bounds__(256) void k_lu_panel(const DMat *__restrict__ mats,
 
 // Panel factorisation with the panel held in registers: thread t owns row j0 + t (the whole panel
 // row, LU_NB entries), so a panel of up to 1024 rows needs no memory traffic between its columns.
-// Pivot search: wave arg-max by shuffles, then across the 16 waves through LDS (ties to the
-// smallest row, as in the global-memory panel).  The pivot row and the displaced row are exchanged
-// through LDS; the pivot row is then broadcast from LDS for the rank-1 update.
+// Two barriers per column.  The pivot candidates of column j + 1 are searched right after the
+// rank-1 update of column j (wave arg-max by shuffles, ties to the smallest row, as in the
+// global-memory panel); after the barrier every wave reduces the 16 wave candidates by shuffles, the
+// owners of the pivot row and of row j publish them in LDS, and after the second barrier the rows
+// are exchanged and the next update is applied.
 constexpr int PANEL_REG_ROWS = 1024;
+
+template <typename T>
+__device__ __forceinline__ void argmax_wave(T &v, int &idx, int width) {
+    for (int o = width / 2; o > 0; o >>= 1) {
+        const T ov = __shfl_xor(v, o, 64);
+        const int oi = __shfl_xor(idx, o, 64);
+        if (ov > v || (ov == v && oi < idx)) {
+            v = ov;
+            idx = oi;
+        }
+    }
+}
 
 template <typename T>
 __global__ __launch_bounds__(PANEL_REG_ROWS) void k_lu_panel_reg(const DMat *__restrict__ mats,
                                                                  const int64_t *__restrict__ poff, T *__restrict__ Ab,
                                                                  int32_t *__restrict__ piv, int32_t *__restrict__ info,
                                                                  int j0, int pivot) {
+    constexpr int NW = PANEL_REG_ROWS / 64;
     const DMat m = mats[blockIdx.x];
     const int n = m.n;
     if (j0 >= n) return;
@@ -137,57 +152,52 @@ __global__ __launch_bounds__(PANEL_REG_ROWS) void k_lu_panel_reg(const DMat *__r
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int r = j0 + tid;
     const bool own = r < n;
-    __shared__ T prow[LU_NB];
-    __shared__ T drow[LU_NB];
-    __shared__ T wval[PANEL_REG_ROWS / 64];
-    __shared__ int widx[PANEL_REG_ROWS / 64];
-    __shared__ int s_p;
+    __shared__ T prow[2][LU_NB];
+    __shared__ T drow[2][LU_NB];
+    __shared__ T wval[2][NW];
+    __shared__ int widx[2][NW];
     T a[LU_NB];
 #pragma unroll
     for (int c = 0; c < LU_NB; ++c) a[c] = (own && c < nb) ? A[r + (int64_t)(j0 + c) * ld] : T(0);
+    if (pivot) {
+        T v = own ? fabs(a[0]) : T(-1);
+        int idx = own ? r : 0x7fffffff;
+        argmax_wave(v, idx, 64);
+        if (lane == 0) {
+            wval[0][wv] = v;
+            widx[0][wv] = idx;
+        }
+    }
+    __syncthreads();
 #pragma clang loop unroll(full)
     for (int jj = 0; jj < LU_NB; ++jj) {
         if (jj < nb) {
-            const int j = j0 + jj;
+            const int j = j0 + jj, buf = jj & 1;
             int p = j;
             if (pivot) {
-                T v = (own && r >= j) ? fabs(a[jj]) : T(-1);
-                int idx = (own && r >= j) ? r : 0x7fffffff;
-#pragma unroll
-                for (int o = 32; o > 0; o >>= 1) {
-                    T ov = __shfl_xor(v, o, 64);
-                    int oi = __shfl_xor(idx, o, 64);
-                    if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
-                }
-                if (lane == 0) { wval[wv] = v; widx[wv] = idx; }
-                __syncthreads();
-                if (tid == 0) {
-                    T bv = wval[0];
-                    int bi = widx[0];
-                    for (int w = 1; w < PANEL_REG_ROWS / 64; ++w)
-                        if (wval[w] > bv || (wval[w] == bv && widx[w] < bi)) { bv = wval[w]; bi = widx[w]; }
-                    s_p = (bi < n) ? bi : j;
-                }
-                __syncthreads();
-                p = s_p;
+                T v = lane < NW ? wval[buf][lane] : T(-1);
+                int idx = lane < NW ? widx[buf][lane] : 0x7fffffff;
+                argmax_wave(v, idx, NW);
+                const int bi = __shfl(idx, 0, 64);
+                p = bi < n ? bi : j;
             }
             if (own && r == p) {
 #pragma unroll
-                for (int c = 0; c < LU_NB; ++c) prow[c] = a[c];
+                for (int c = 0; c < LU_NB; ++c) prow[buf][c] = a[c];
             }
             if (own && r == j) {
 #pragma unroll
-                for (int c = 0; c < LU_NB; ++c) drow[c] = a[c];
+                for (int c = 0; c < LU_NB; ++c) drow[buf][c] = a[c];
             }
             __syncthreads();
             if (own && r == j) {
 #pragma unroll
-                for (int c = 0; c < LU_NB; ++c) a[c] = prow[c];
+                for (int c = 0; c < LU_NB; ++c) a[c] = prow[buf][c];
             } else if (own && r == p) {
 #pragma unroll
-                for (int c = 0; c < LU_NB; ++c) a[c] = drow[c];
+                for (int c = 0; c < LU_NB; ++c) a[c] = drow[buf][c];
             }
-            const T dpiv = prow[jj];
+            const T dpiv = prow[buf][jj];
             const bool ok = dpiv != T(0) && isfinite(dpiv);
             if (tid == 0) {
                 piv[poff[blockIdx.x] + j] = p;
@@ -197,7 +207,16 @@ __global__ __launch_bounds__(PANEL_REG_ROWS) void k_lu_panel_reg(const DMat *__r
                 const T l = a[jj] * (T(1) / dpiv);
                 a[jj] = l;
 #pragma unroll
-                for (int c = jj + 1; c < LU_NB; ++c) a[c] -= l * prow[c];
+                for (int c = jj + 1; c < LU_NB; ++c) a[c] -= l * prow[buf][c];
+            }
+            if (pivot && jj + 1 < nb) {
+                T v = (own && r > j) ? fabs(a[jj + 1 < LU_NB ? jj + 1 : jj]) : T(-1);
+                int idx = (own && r > j) ? r : 0x7fffffff;
+                argmax_wave(v, idx, 64);
+                if (lane == 0) {
+                    wval[buf ^ 1][wv] = v;
+                    widx[buf ^ 1][wv] = idx;
+                }
             }
             __syncthreads();
         }

@@ -1,0 +1,107 @@
+"""GPU parity at full workload sizes.
+
+h = 1/256, k = 80, 16 x 16 subdomains (65,025 dofs, m0 about 2,500): the complete FP64 oracle
+(all 256 local eigenproblems, B_0, FGMRES(150)) against the library, in the configurations
+bench.py and the batched engine run.  3D Q1, h = 1/32, 4 x 4 x 4 subdomains (29,791 dofs, local
+problems of 1,331 dofs with 866 Gamma dofs): the oracle's local eigenproblems on sampled
+subdomains, and properties of the solves that hold at any size.
+
+Bars as in test_gpu_parity: index sets exact, m_i exact, eigenvalues within 1e-10 of the spectral
+radius, true residual <= 1e-8 recomputed here in FP64, iterations within 2 of the oracle (and of
+FP64 for the mixed form), solution within 1e-8 of the oracle's FGMRES solution (the same Krylov
+iterates up to rounding).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_2406_06283_amd import hkgeneo as H  # noqa: E402
+from paper_2406_06283_amd import problems as pb  # noqa: E402
+from paper_2406_06283_amd.configs import H256_K80, Q1_3D_H32_K10  # noqa: E402
+from oracle import decomposition, fgmres, local, schwarz  # noqa: E402
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+DEV = "cuda:0"
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _relres(B, f, u):
+    return np.linalg.norm(f - B @ u) / np.linalg.norm(f)
+
+
+def test_h256_k80_full_size_matches_oracle():
+    wl = H256_K80
+    p = wl.problem()
+    _say("[full] h=1/256 k=80 16x16: oracle setup")
+    M = schwarz.TwoLevelSchwarz(p, schwarz.Options(eig_mode=local.EIG_THRESHOLD, tau=wl.tau))
+    x, oinfo = fgmres.solve(p, M, restart=wl.restart)
+    f = torch.from_numpy(p.f).to(DEV)
+    _say(f"[full] oracle: m0 {M.m0}, {oinfo['iters']} iterations; library FP64 single path")
+    with H.Solver(p, H.options_for(wl)) as S:
+        nI, nG, m = S.subdomains()
+        for i, s in enumerate(M.subs):
+            assert nI[i] == s.dof.size and nG[i] == s.gamma.size and m[i] == M.m[i], i
+        assert S.stats()["m0"] == M.m0
+        for i in (0, 17, 136, 255):
+            lam, _ = S.eigen(i)
+            lo = M.eigvals[i][:lam.size]
+            assert np.abs(lam - lo).max() <= 1e-10 * np.abs(M.eigvals[i]).max(), i
+        u64, info64, st = S.solve(f)
+        torch.cuda.synchronize()
+        u64 = u64.cpu().numpy()[0]
+    _say("[full] library mixed precision, batched engine")
+    with H.Solver(p, H.options_for(wl, local_prec=32)) as S32, H.Batch([S32], [1]) as B:
+        (u32,), (info32,), st32 = B.solve([f])
+        torch.cuda.synchronize()
+        u32 = u32.cpu().numpy()[0]
+    Bm = M.B
+    assert st == H.HKG_OK and st32 == H.HKG_OK
+    assert _relres(Bm, p.f[0], u64) <= 1e-8 and _relres(Bm, p.f[0], u32) <= 1e-8
+    assert abs(info64[0]["iters"] - oinfo["iters"]) <= 2, (info64[0]["iters"], oinfo["iters"])
+    assert abs(info32[0]["iters"] - info64[0]["iters"]) <= 2, (info32[0]["iters"], info64[0]["iters"])
+    e64 = np.linalg.norm(u64 - x) / np.linalg.norm(x)
+    e32 = np.linalg.norm(u32 - x) / np.linalg.norm(x)
+    _say(f"[full] iterations oracle {oinfo['iters']} fp64 {info64[0]['iters']} mixed {info32[0]['iters']}; "
+         f"solution vs oracle: fp64 {e64:.2e} mixed {e32:.2e}")
+    assert e64 <= 1e-8 and e32 <= 1e-8
+
+
+def test_q1_3d_h32_full_size_sampled():
+    wl = Q1_3D_H32_K10
+    p = pb.make_problem(32, dim=3, elem_type=pb.Q1, k=10.0, s=4, overlap=2, coef="cells", seed=1, n_cells=4,
+                        rhs="normal", nrhs=2)
+    subs = decomposition.decompose(p)
+    mu = decomposition.multiplicity(subs, p.n_dof)
+    f = torch.from_numpy(p.f).to(DEV)
+    _say("[full] 3D Q1 h=1/32 4x4x4: library FP64")
+    with H.Solver(p, H.options_for(wl)) as S:
+        nI, nG, m = S.subdomains()
+        for i, s in enumerate(subs):
+            assert nI[i] == s.dof.size and nG[i] == s.gamma.size, i
+        for i in (0, 21, 42, 63):          # a corner, two interior and the opposite corner
+            Bt, C = local.geneo_pencil(p, subs[i], mu)
+            lam_o, _ = local.geneo_eigenpairs(Bt, C, subs[i].dof.size)
+            assert m[i] == local.select_count(lam_o, local.EIG_FIXED, nev=wl.nev), i
+            lam, _ = S.eigen(i)
+            assert np.abs(lam - lam_o[:lam.size]).max() <= 1e-10 * np.abs(lam_o).max(), i
+        u64, info64, st = S.solve(f)
+        torch.cuda.synchronize()
+        u64 = u64.cpu().numpy()
+    with H.Solver(p, H.options_for(wl, local_prec=32)) as S32, H.Batch([S32], [2]) as B:
+        (u32,), (info32,), st32 = B.solve([f])
+        torch.cuda.synchronize()
+        u32 = u32.cpu().numpy()
+    Bm = schwarz.system_matrix(p)
+    assert st == H.HKG_OK and st32 == H.HKG_OK
+    for r in range(2):
+        assert _relres(Bm, p.f[r], u64[r]) <= 1e-8 and _relres(Bm, p.f[r], u32[r]) <= 1e-8
+        assert abs(info32[r]["iters"] - info64[r]["iters"]) <= 2
+    d = np.linalg.norm(u32 - u64) / np.linalg.norm(u64)
+    assert d <= 1e-8
+    _say(f"[full] 3D iterations fp64 {[i['iters'] for i in info64]} mixed {[i['iters'] for i in info32]}; "
+         f"mixed vs fp64 solution {d:.2e}")

@@ -30,7 +30,7 @@ struct hkgeneo_ctx {
     hkg::DevBuf Bval, Minv, Z, Zr, B0inv;
     // factorisation workspace (kept between calls when opt.keep_workspace, freed otherwise)
     hkg::DevBuf wDk, wBIO, wCII, wGG, wGI, wS, wW, wPiv, wInfo, wFlag, wD, wE, wTau, wM, wLam, wY, wB0, wLU, wPivL,
-        wJobsZ, wGjobsY, wMisc, wPiv0, wInv, wVWV, wInfoL, wSL, wIv;
+        wJobsZ, wGjobsY, wMisc, wPiv0, wInv, wVWV, wInfoL, wSL, wIv, wLinv, wJobsInv;
     // the local-inverse pipeline of the factorisation runs on a second stream beside the coarse-space
     // pipeline; its pivot flags come back through pinned host memory
     hipStream_t s2 = nullptr;

@@ -11,7 +11,7 @@
 
 namespace hkg {
 
-constexpr int LU_NB = 32;    // LU / triangular-solve block size
+constexpr int LU_NB = LU_BLOCK;    // LU / triangular-solve block size
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_gemm_batched(const GemmJob *__restrict__ jobs, const T *__restrict__ Ab,
@@ -444,6 +444,83 @@ int32_t tri_solve_batched(const TriJob *d_jobs, int nbatch, int maxn, int maxcol
 }
 template int32_t tri_solve_batched<double>(const TriJob *, int, int, int, const double *, double *, int, hipStream_t);
 template int32_t tri_solve_batched<float>(const TriJob *, int, int, int, const float *, float *, int, hipStream_t);
+
+// ------------------------------------------------------------------------------------------------
+// Inverse of one packed LU (P A = L U) by recursive block triangular inversion: the LU_NB diagonal
+// blocks of L (unit lower) and U are inverted here; the driver then joins neighbouring blocks level
+// by level with GEMMs ([[A, 0], [C, D]]^{-1} has off-diagonal block -D^{-1} C A^{-1}), forms
+// U^{-1} (L^{-1} P) and A^{-1} = U^{-1} L^{-1} P.
+// ------------------------------------------------------------------------------------------------
+// grid (diagonal blocks, 2): y = 0 inverts the L block, y = 1 the U block; thread t computes column
+// t of the block inverse from the block staged in LDS
+__global__ __launch_bounds__(LU_NB) void k_tri_diag_inv(const double *__restrict__ LU, int n, int ld,
+                                                        double *__restrict__ Linv, double *__restrict__ Uinv,
+                                                        int ldo) {
+    __shared__ double Ts[LU_NB][LU_NB + 1];
+    __shared__ double Xs[LU_NB][LU_NB + 1];
+    const int r0 = blockIdx.x * LU_NB, nb = min(LU_NB, n - r0), t = threadIdx.x;
+    const bool upper = blockIdx.y == 1;
+    for (int e = t; e < LU_NB * LU_NB; e += LU_NB) {
+        const int i = e % LU_NB, j = e / LU_NB;
+        Ts[i][j] = (i < nb && j < nb) ? LU[(r0 + i) + (int64_t)(r0 + j) * ld] : 0.0;
+    }
+    __syncthreads();
+    if (t < nb) {
+        if (!upper) {
+            for (int i = 0; i < nb; ++i) {
+                double s = (i == t) ? 1.0 : 0.0;
+                for (int k = t; k < i; ++k) s -= Ts[i][k] * Xs[k][t];
+                Xs[i][t] = (i < t) ? 0.0 : s;
+            }
+        } else {
+            for (int i = nb - 1; i >= 0; --i) {
+                double s = (i == t) ? 1.0 : 0.0;
+                for (int k = i + 1; k <= t; ++k) s -= Ts[i][k] * Xs[k][t];
+                Xs[i][t] = (i > t) ? 0.0 : s / Ts[i][i];
+            }
+        }
+    }
+    __syncthreads();
+    double *out = upper ? Uinv : Linv;
+    for (int e = t; e < nb * nb; e += LU_NB) {
+        const int i = e % nb, j = e / nb;
+        out[(r0 + i) + (int64_t)(r0 + j) * ldo] = Xs[i][j];
+    }
+}
+
+int32_t tri_diag_inverse(const double *LU, int n, int ld, double *Linv, double *Uinv, int ldo, hipStream_t s) {
+    const int nblk = (n + LU_NB - 1) / LU_NB;
+    hipLaunchKernelGGL(k_tri_diag_inv, dim3(nblk, 2), dim3(LU_NB), 0, s, LU, n, ld, Linv, Uinv, ldo);
+    HKG_HIP(hipGetLastError());
+    return HKG_OK;
+}
+
+// out[:, c] = X[:, sigma(c)] with P e_c = e_{sigma(c)} for the row exchanges piv applied in order
+__global__ __launch_bounds__(256) void k_gather_pivot_columns(int n, const double *__restrict__ X, int ldx,
+                                                              const int32_t *__restrict__ piv,
+                                                              double *__restrict__ out, int ldo) {
+    __shared__ int sig;
+    const int c = blockIdx.x;
+    if (threadIdx.x == 0) {
+        int r = c;
+        for (int j = 0; j < n; ++j) {
+            const int p = piv[j];
+            if (r == j) r = p;
+            else if (r == p) r = j;
+        }
+        sig = r;
+    }
+    __syncthreads();
+    const double *src = X + (int64_t)sig * ldx;
+    double *dst = out + (int64_t)c * ldo;
+    for (int i = threadIdx.x; i < n; i += 256) dst[i] = src[i];
+}
+
+int32_t gather_pivot_columns(int n, const double *X, int ldx, const int32_t *piv, double *out, int ldo, hipStream_t s) {
+    hipLaunchKernelGGL(k_gather_pivot_columns, dim3(n), dim3(256), 0, s, n, X, ldx, piv, out, ldo);
+    HKG_HIP(hipGetLastError());
+    return HKG_OK;
+}
 
 // ------------------------------------------------------------------------------------------------
 // helpers: X = P * I (row exchanges of an LU applied to the identity), transposes, copies

@@ -10,6 +10,7 @@
 //   B_0 = Z^T B Z over neighbouring pairs, B_0 = P L U, B_0^{-1}                     (eq. 2.23)
 //   B_D = P L U and B_D^{-1} in float64 or float32                                     (eq. 2.22)
 #include <algorithm>
+#include <array>
 #include <cstring>
 
 #include "ctx.hpp"
@@ -58,7 +59,8 @@ int32_t upload_bytes(hkgeneo_ctx *c, DevBuf *b, const void *host, size_t bytes, 
 void free_workspace(hkgeneo_ctx *c) {
     DevBuf *w[] = {&c->wDk, &c->wBIO, &c->wCII, &c->wGG, &c->wGI, &c->wS, &c->wW, &c->wPiv, &c->wInfo,
                    &c->wFlag, &c->wD, &c->wE, &c->wTau, &c->wM, &c->wLam, &c->wY, &c->wB0, &c->wLU,
-                   &c->wPivL, &c->wJobsZ, &c->wGjobsY, &c->wMisc, &c->wPiv0, &c->wInv, &c->wVWV, &c->wInfoL, &c->wSL, &c->wIv};
+                   &c->wPivL, &c->wJobsZ, &c->wGjobsY, &c->wMisc, &c->wPiv0, &c->wInv, &c->wVWV, &c->wInfoL, &c->wSL, &c->wIv,
+                   &c->wLinv, &c->wJobsInv};
     for (DevBuf *b : w) drelease(c, b);
 }
 
@@ -227,6 +229,66 @@ int32_t local_operators(hkgeneo_ctx *c, hipStream_t s) {
     HKG_TRY(walloc(c, &c->wSL, c->nSq * sizeof(double)));
     HKG_TRY(local_inverses<double>(c, dp<double>(c->wSL), s));
     return cast_f64_f32(dp<double>(c->wSL), dp<float>(c->Minv), c->nSq, s);
+}
+
+// A^{-1} = U^{-1} L^{-1} P for one packed n x n LU (ld = n): the diagonal blocks of L^{-1} and
+// U^{-1} first, then level by level the off-diagonal block of each pair of neighbouring blocks
+// (L: X21 = -X22 L21 X11;  U: X12 = -X11 U12 X22) by batched GEMMs, then L^{-1} P by a column
+// gather and the product with U^{-1}.  About 4 log2(n / 32) + 4 launches.
+int32_t lu_inverse(hkgeneo_ctx *c, int n, const double *LU, const int32_t *piv, double *out, hipStream_t s) {
+    const size_t nn = (size_t)n * n;
+    HKG_TRY(walloc(c, &c->wLinv, 3 * nn * sizeof(double)));
+    double *Linv = dp<double>(c->wLinv), *Uinv = Linv + nn, *tmp = Uinv + nn;
+    HKG_HIP(hipMemsetAsync(Linv, 0, 2 * nn * sizeof(double), s));
+    HKG_TRY(tri_diag_inverse(LU, n, n, Linv, Uinv, n, s));
+    // jobs of every level: [L first product | L second | U first | U second] per level
+    struct Level {
+        int first, count, maxM, maxN;
+    };
+    std::vector<GemmJob> jobs;
+    std::vector<std::array<Level, 4>> levels;
+    const int nblk = (n + LU_BLOCK - 1) / LU_BLOCK;
+    for (int half = LU_BLOCK; half < n && (nblk > 1); half *= 2) {
+        std::array<Level, 4> lv{};
+        std::array<std::vector<GemmJob>, 4> js;
+        for (int r0 = 0; r0 + half < n; r0 += 2 * half) {
+            const int r1 = r0 + half, r2 = std::min(r0 + 2 * half, n);
+            const int a = r1 - r0, b = r2 - r1;
+            // L: T = L21 X11 (b x a), X21 = -X22 T
+            js[0].push_back({r1 + (int64_t)r0 * n, r0 + (int64_t)r0 * n, r1 + (int64_t)r0 * n, b, a, a, n, n, n});
+            js[1].push_back({r1 + (int64_t)r1 * n, r1 + (int64_t)r0 * n, r1 + (int64_t)r0 * n, b, a, b, n, n, n});
+            // U: T = U12 Y22 (a x b), Y12 = -Y11 T
+            js[2].push_back({r0 + (int64_t)r1 * n, r1 + (int64_t)r1 * n, r0 + (int64_t)r1 * n, a, b, b, n, n, n});
+            js[3].push_back({r0 + (int64_t)r0 * n, r0 + (int64_t)r1 * n, r0 + (int64_t)r1 * n, a, b, a, n, n, n});
+        }
+        for (int q = 0; q < 4; ++q) {
+            lv[q].first = (int)jobs.size();
+            lv[q].count = (int)js[q].size();
+            lv[q].maxM = 0;
+            lv[q].maxN = 0;
+            for (auto &j : js[q]) {
+                lv[q].maxM = std::max(lv[q].maxM, (int)j.M);
+                lv[q].maxN = std::max(lv[q].maxN, (int)j.N);
+            }
+            jobs.insert(jobs.end(), js[q].begin(), js[q].end());
+        }
+        levels.push_back(lv);
+    }
+    jobs.push_back({0, 0, 0, n, n, n, n, n, n});      // out = Uinv (L^{-1} P)
+    HKG_TRY(upload(c, &c->wJobsInv, jobs.data(), jobs.size(), s, true));
+    const GemmJob *dj = dp<GemmJob>(c->wJobsInv);
+    for (auto &lv : levels) {
+        HKG_TRY(gemm_batched<double>(dj + lv[0].first, lv[0].count, lv[0].maxM, lv[0].maxN, LU, Linv, tmp, 1.0, 0.0,
+                                     false, false, s));
+        HKG_TRY(gemm_batched<double>(dj + lv[1].first, lv[1].count, lv[1].maxM, lv[1].maxN, Linv, tmp, Linv, -1.0,
+                                     0.0, false, false, s));
+        HKG_TRY(gemm_batched<double>(dj + lv[2].first, lv[2].count, lv[2].maxM, lv[2].maxN, LU, Uinv, tmp, 1.0, 0.0,
+                                     false, false, s));
+        HKG_TRY(gemm_batched<double>(dj + lv[3].first, lv[3].count, lv[3].maxM, lv[3].maxN, Uinv, tmp, Uinv, -1.0,
+                                     0.0, false, false, s));
+    }
+    HKG_TRY(gather_pivot_columns(n, Linv, n, piv, tmp, n, s));
+    return gemm_batched<double>(dj + (jobs.size() - 1), 1, n, n, Uinv, tmp, out, 1.0, 0.0, false, false, s);
 }
 
 int32_t coarse_space(hkgeneo_ctx *c, hipStream_t s) {
@@ -400,10 +462,8 @@ int32_t coarse_space(hkgeneo_ctx *c, hipStream_t s) {
         return HKG_ESINGULAR_COARSE;
     }
     if (c->B0inv.bytes != (size_t)m0 * m0 * sizeof(double)) HKG_TRY(dalloc(c, &c->B0inv, (size_t)m0 * m0 * sizeof(double)));
-    HKG_TRY(perm_identity_batched<double>(dm, dpo, 1, m0, dp<int32_t>(c->wPiv0), dp<double>(c->B0inv), s));
-    HKG_TRY(tri_solve_batched<double>(dj, 1, m0, m0, dp<double>(c->wB0), dp<double>(c->B0inv), TRI_LOWER_UNIT, s));
-    HKG_TRY(tri_solve_batched<double>(dj, 1, m0, m0, dp<double>(c->wB0), dp<double>(c->B0inv), TRI_UPPER, s));
-    return HKG_OK;
+    (void)dj;
+    return lu_inverse(c, m0, dp<double>(c->wB0), dp<int32_t>(c->wPiv0), dp<double>(c->B0inv), s);
 }
 
 }  // namespace

@@ -17,6 +17,12 @@ int32_t lu_batched(const DMat *d_mats, const int64_t *d_poff, int nbatch, int ma
 template <typename T>
 int32_t tri_solve_batched(const TriJob *d_jobs, int nbatch, int maxn, int maxcol, const T *Tm, T *X, int mode,
                           hipStream_t s);
+constexpr int LU_BLOCK = 32;    // block size of the dense LU, triangular solves and inversions
+
+// diagonal LU_BLOCK blocks of L^{-1} (unit lower) and U^{-1} of one packed LU, into Linv / Uinv
+int32_t tri_diag_inverse(const double *LU, int n, int ld, double *Linv, double *Uinv, int ldo, hipStream_t s);
+// out[:, c] = X[:, sigma(c)], P e_c = e_{sigma(c)} for the LU's row exchanges (so out = X P)
+int32_t gather_pivot_columns(int n, const double *X, int ldx, const int32_t *piv, double *out, int ldo, hipStream_t s);
 template <typename T>
 int32_t perm_identity_batched(const DMat *d_mats, const int64_t *d_poff, int nbatch, int maxn, const int32_t *piv,
                               T *X, hipStream_t s);

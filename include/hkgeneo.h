@@ -222,7 +222,7 @@ int32_t hkgeneo_batch_create(hkgeneo_ctx *const *ctxs, const int32_t *nrhs, int3
  * returns when every u[p] is final (synchronous).  info: host array of sum(nrhs) entries in problem
  * order (may be NULL).  Returns HKG_OK if every column converged, HKG_ENOTCONV otherwise;
  * HKG_EINVAL for a NULL pointer, ld[p] < n_dof or a subdomain too large for the batched local
- * solve (2 |dof(D)| + 1024 doubles of LDS must fit in 160 KiB).
+ * solve (2 |dof(D)| + 2048 doubles of LDS must fit in 160 KiB).
  */
 int32_t hkgeneo_batch_solve(hkgeneo_batch *b, const double *const *f, double *const *u, const int32_t *ld,
                             hkgeneo_rhs_info *info, void *stream);

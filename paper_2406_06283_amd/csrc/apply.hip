@@ -73,21 +73,22 @@ __global__ __launch_bounds__(LS_ROWS * LS_WAVES) void k_local_solve(const SubDev
         return;
     }
     const int row = blockIdx.x * LS_ROWS + lane;
-    const T *M = Minv + sd.offSq;
+    const T *M = Minv + sd.offM;
+    const int ldm = sd.ldM;
     T acc = T(0);
     if (row < n) {
         int col = wv;
         for (; col + 3 * LS_WAVES < n; col += 4 * LS_WAVES) {
-            T a0 = M[row + (int64_t)col * n];
-            T a1 = M[row + (int64_t)(col + LS_WAVES) * n];
-            T a2 = M[row + (int64_t)(col + 2 * LS_WAVES) * n];
-            T a3 = M[row + (int64_t)(col + 3 * LS_WAVES) * n];
+            T a0 = M[row + (int64_t)col * ldm];
+            T a1 = M[row + (int64_t)(col + LS_WAVES) * ldm];
+            T a2 = M[row + (int64_t)(col + 2 * LS_WAVES) * ldm];
+            T a3 = M[row + (int64_t)(col + 3 * LS_WAVES) * ldm];
             acc = fma(a0, xt[col], acc);
             acc = fma(a1, xt[col + LS_WAVES], acc);
             acc = fma(a2, xt[col + 2 * LS_WAVES], acc);
             acc = fma(a3, xt[col + 3 * LS_WAVES], acc);
         }
-        for (; col < n; col += LS_WAVES) acc = fma(M[row + (int64_t)col * n], xt[col], acc);
+        for (; col < n; col += LS_WAVES) acc = fma(M[row + (int64_t)col * ldm], xt[col], acc);
     }
     part[wv * LS_ROWS + lane] = (double)acc;
     __syncthreads();

@@ -280,24 +280,30 @@ int32_t autotune(Engine *E) {
         (void)hipEventDestroy(e0);
         return HKG_EHIP;
     }
-    int best = 8;
-    float best_ms = 1e30f;
+    // two warm-up launches per shape, then the median of nine timed launches (shapes interleaved so
+    // that clock and cache drift affect all alike)
+    const int cand[3] = {4, 8, 16};
+    std::vector<float> t[3];
     int32_t st = HKG_OK;
-    for (int waves : {4, 8, 16}) {
-        BatchGeom gg = g;
-        gg.local_waves = waves;
-        float tot = 0.0f;
-        for (int rep = 0; rep < 6 && st == HKG_OK; ++rep) {
+    for (int rep = 0; rep < 11 && st == HKG_OK; ++rep)
+        for (int w = 0; w < 3 && st == HKG_OK; ++w) {
+            BatchGeom gg = g;
+            gg.local_waves = cand[w];
             float ms = 0.0f;
             st = batch_apply(gg, dp<ProbDev>(E->d_probs), dp<WorkItem>(E->d_items), dp<WorkItem>(E->d_rblk),
                              dp<WorkItem>(E->d_cblk), 0, 0, E->stream, e0, e1);
             if (st == HKG_OK && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
                 st = HKG_EHIP;
-            if (rep > 0) tot += ms;
+            if (rep >= 2) t[w].push_back(ms);
         }
-        if (st == HKG_OK && tot < best_ms) {
-            best_ms = tot;
-            best = waves;
+    int best = 8;
+    float best_ms = 1e30f;
+    for (int w = 0; w < 3 && st == HKG_OK; ++w) {
+        std::sort(t[w].begin(), t[w].end());
+        const float med = t[w][t[w].size() / 2];
+        if (med < best_ms) {
+            best_ms = med;
+            best = cand[w];
         }
     }
     (void)hipEventDestroy(e0);
@@ -382,7 +388,7 @@ int32_t rebuild(Engine *E) {
     for (int s : E->live) {
         const ProbDev &P = E->table[s];
         g.max_nI = std::max(g.max_nI, P.maxnI);
-        g.max_tiles = std::max(g.max_tiles, (P.maxnI + 63) / 64);
+        g.max_tiles = std::max(g.max_tiles, (P.maxnI + LTILE - 1) / LTILE);
         g.any_coarse = g.any_coarse || P.two_level;
         for (int k = 0; k < P.nsub; ++k) items.push_back({s, k});
         for (int k = 0; k < P.nblk; ++k) rblk.push_back({s, k});
@@ -573,7 +579,7 @@ int32_t check_request(const Engine *E, const hkgeneo_ctx *c, const double *f, co
         set_last_error("the context's restart length differs from the engine's");
         return HKG_EINVAL;
     }
-    if ((size_t)2 * c->max_nI * sizeof(double) + 16 * 64 * sizeof(double) > 160 * 1024) {
+    if ((size_t)2 * c->max_nI * sizeof(double) + 16 * LTILE * sizeof(double) > 160 * 1024) {
         set_last_error("subdomain too large for the batched local solve");
         return HKG_EINVAL;
     }

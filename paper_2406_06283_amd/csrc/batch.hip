@@ -71,19 +71,33 @@ __device__ __forceinline__ double *zcol(const ProbDev &P, int rhs, int j) {
 // The column sums of the product with the inverse are split into NPART partial sums (partial q takes
 // the columns congruent to q modulo NPART, in increasing order) and the partials are added in order
 // q = 0, 1, ...: the rounding does not depend on how many waves share the columns, so every launch
-// shape the autotuner may pick gives the same bits.
+// shape the autotuner may pick gives the same bits.  A tile is LTILE rows; each lane owns two
+// consecutive rows and reads them with one aligned 2-element vector load (the inverses' leading
+// dimension is padded to a multiple of 32 entries, rows past n_I are padding and discarded).
+template <typename T>
+struct Pair2;
+template <>
+struct Pair2<float> {
+    using type = float2;
+};
+template <>
+struct Pair2<double> {
+    using type = double2;
+};
+
 template <typename T, int WAVES>
 __device__ __forceinline__ void local_body(const ProbDev &P, const SubDev &sd, const double *__restrict__ r, int rhs,
                                            double *sh) {
+    using V2 = typename Pair2<T>::type;
     constexpr int PW = NPART / WAVES;                 // partials per wave
-    constexpr int UNR = PW >= 4 ? 1 : 4 / PW;         // loads in flight per thread: PW * UNR
+    constexpr int UNR = PW >= 4 ? 1 : 4 / PW;         // vector loads in flight per thread: PW * UNR
     const int n = sd.nI;
-    const int tiles = (n + LS_ROWS - 1) / LS_ROWS;
+    const int tiles = (n + LTILE - 1) / LTILE;
     const bool coarse = P.two_level && P.m0 > 0;
     const bool restrict_tile = (int)blockIdx.x == tiles;
     double *xd = sh;
     T *xt = reinterpret_cast<T *>(sh + n);
-    double *part = sh + n + (n * sizeof(T) + 7) / 8;  // NPART x LS_ROWS
+    double *part = sh + n + (n * sizeof(T) + 7) / 8;  // NPART x LTILE
     const int32_t *I = P.I_idx + sd.offI;
     for (int i = threadIdx.x; i < n; i += LS_ROWS * WAVES) {
         const double v = r[I[i]];
@@ -100,43 +114,54 @@ __device__ __forceinline__ void local_body(const ProbDev &P, const SubDev &sd, c
             double acc = 0.0;
             if (lane < m)
                 for (int p = q; p < n; p += NPART) acc = fma(Zt[lane + (int64_t)p * m], xd[p], acc);
-            part[q * LS_ROWS + lane] = acc;
+            part[q * LTILE + lane] = acc;
         }
         __syncthreads();
         if (wv == 0 && lane < m && coarse) {
             double s = 0.0;
-            for (int q = 0; q < NPART; ++q) s += part[q * LS_ROWS + lane];
+            for (int q = 0; q < NPART; ++q) s += part[q * LTILE + lane];
             P.c[(int64_t)rhs * P.m0 + sd.offm + lane] = s;
         }
         return;
     }
-    const int row = blockIdx.x * LS_ROWS + lane;
-    const T *M = reinterpret_cast<const T *>(P.Minv) + sd.offSq + row;
-    T acc[PW];
+    const int row0 = blockIdx.x * LTILE + 2 * lane;
+    const T *M = reinterpret_cast<const T *>(P.Minv) + sd.offM + row0;
+    const int64_t ldm = sd.ldM;
+    T acc[PW][2];
 #pragma unroll
-    for (int k = 0; k < PW; ++k) acc[k] = T(0);
-    if (row < n) {
+    for (int k = 0; k < PW; ++k) acc[k][0] = acc[k][1] = T(0);
+    if (row0 < n) {
         int c0 = 0;
 #pragma unroll UNR
         for (; c0 + NPART <= n; c0 += NPART) {
 #pragma unroll
             for (int k = 0; k < PW; ++k) {
                 const int col = c0 + wv + k * WAVES;
-                acc[k] = fma(M[(int64_t)col * n], xt[col], acc[k]);
+                const V2 v = *reinterpret_cast<const V2 *>(M + col * ldm);
+                acc[k][0] = fma(v.x, xt[col], acc[k][0]);
+                acc[k][1] = fma(v.y, xt[col], acc[k][1]);
             }
         }
 #pragma unroll
         for (int k = 0; k < PW; ++k) {
             const int col = c0 + wv + k * WAVES;
-            if (col < n) acc[k] = fma(M[(int64_t)col * n], xt[col], acc[k]);
+            if (col < n) {
+                const V2 v = *reinterpret_cast<const V2 *>(M + col * ldm);
+                acc[k][0] = fma(v.x, xt[col], acc[k][0]);
+                acc[k][1] = fma(v.y, xt[col], acc[k][1]);
+            }
         }
     }
 #pragma unroll
-    for (int k = 0; k < PW; ++k) part[(wv + k * WAVES) * LS_ROWS + lane] = (double)acc[k];
+    for (int k = 0; k < PW; ++k) {
+        part[(wv + k * WAVES) * LTILE + 2 * lane] = (double)acc[k][0];
+        part[(wv + k * WAVES) * LTILE + 2 * lane + 1] = (double)acc[k][1];
+    }
     __syncthreads();
-    if (wv == 0 && row < n) {
+    const int t = threadIdx.x, row = blockIdx.x * LTILE + t;
+    if (t < LTILE && row < n) {
         T s = T(0);
-        for (int q = 0; q < NPART; ++q) s += (T)part[q * LS_ROWS + lane];
+        for (int q = 0; q < NPART; ++q) s += (T)part[q * LTILE + t];
         P.u[(int64_t)rhs * P.sum_nI + sd.offI + row] = P.wloc[sd.offI + row] * (double)s;
     }
 }
@@ -150,7 +175,7 @@ __global__ __launch_bounds__(LS_ROWS *WAVES) void k_b_local(const ProbDev *__res
     const int rhs = blockIdx.z;
     if (inactive(P, rhs, mode)) return;
     const SubDev sd = P.subs[it.s];
-    const int tiles = (sd.nI + LS_ROWS - 1) / LS_ROWS;
+    const int tiles = (sd.nI + LTILE - 1) / LTILE;
     const bool coarse = P.two_level && P.m0 > 0;
     if ((int)blockIdx.x > tiles || ((int)blockIdx.x == tiles && (!coarse || sd.m == 0))) return;
     const double *r = (mode == 0) ? P.xin + (int64_t)rhs * P.ldin : vcol(P, rhs, jget(P, rhs, par));
@@ -256,7 +281,7 @@ __global__ __launch_bounds__(BROWS) void k_b_prolong(const ProbDev *__restrict__
 int32_t batch_apply(const BatchGeom &g, const ProbDev *probs, const WorkItem *items, const WorkItem *rblk,
                     const WorkItem *cblk, int mode, int par, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     const dim3 gl(g.max_tiles + (g.any_coarse ? 1 : 0), g.nitems, g.max_nrhs);
-    const size_t shm = (size_t)2 * g.max_nI * sizeof(double) + (size_t)NPART * LS_ROWS * sizeof(double);
+    const size_t shm = (size_t)2 * g.max_nI * sizeof(double) + (size_t)NPART * LTILE * sizeof(double);
     if (ev0) HKG_HIP(hipEventRecord(ev0, s));
     switch (g.local_waves) {
         case 4:

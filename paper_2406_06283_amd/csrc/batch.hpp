@@ -15,6 +15,7 @@
 namespace hkg {
 
 constexpr int BROWS = 256;          // rows per row block (one per thread)
+constexpr int LTILE = 128;          // rows of the local inverse per local-solve tile (two per lane)
 
 // state of one (problem, rhs) pair, kept on the device
 enum : int32_t {

@@ -12,7 +12,7 @@
 struct hkgeneo_ctx {
     hkgeneo_options opt{};
     int n_dof = 0, nnz = 0, n_sub = 0, m0 = 0, max_nI = 0, max_nG = 0, max_m = 0, npe = 0, dim = 2;
-    int64_t sum_nI = 0, nBIO = 0, nSq = 0, nGG = 0, nGI = 0, nPiv = 0;
+    int64_t sum_nI = 0, nBIO = 0, nSq = 0, nGG = 0, nGI = 0, nPiv = 0, nM = 0;
     double k = 0.0;
     hkg::Partition P;
     hkg::CoarsePairs CP;
@@ -25,7 +25,7 @@ struct hkgeneo_ctx {
     // resident inputs and static descriptors (analysis phase)
     hkg::DevBuf rowptr, colidx, Aval, Sval, I_idx, G_idx, winv, wloc, tp_ptr, tp_pos, tp_sub, subs_d;
     hkg::DevBuf bandK, bandM, bandLoc, pairs;
-    hkg::DevBuf matsGG, matsSq, poffSub, jobsGI, jobsSq, gjobsSchur, matsLoc, poffLoc, jobsLoc;
+    hkg::DevBuf matsGG, matsSq, poffSub, jobsGI, jobsSq, gjobsSchur, matsLoc, poffLoc, jobsLoc, matsM, jobsM;
     // numeric results (factorisation phase)
     hkg::DevBuf Bval, Minv, Z, Zr, B0inv;
     // factorisation workspace (kept between calls when opt.keep_workspace, freed otherwise)

@@ -73,7 +73,7 @@ int32_t analyze(hkgeneo_ctx *c, const hkgeneo_problem *p, hipStream_t s, int32_t
     const Partition &P = c->P;
     const int ns = c->n_sub;
     c->subs.resize(ns);
-    int64_t oBIO = 0, oSq = 0, oGG = 0, oGI = 0, oPiv = 0;
+    int64_t oBIO = 0, oSq = 0, oGG = 0, oGI = 0, oPiv = 0, oM = 0;
     for (int i = 0; i < ns; ++i) {
         SubDev &sd = c->subs[i];
         sd = SubDev{};
@@ -86,10 +86,13 @@ int32_t analyze(hkgeneo_ctx *c, const hkgeneo_problem *p, hipStream_t s, int32_t
         sd.offGG = oGG;
         sd.offGI = oGI;
         sd.offPiv = oPiv;
+        sd.ldM = (sd.nI + 31) / 32 * 32;
+        sd.offM = oM;
         sd.bandBeg = P.band_ptr[i];
         sd.bandEnd = P.band_ptr[i + 1];
         oBIO += (int64_t)sd.nI * (sd.nI + sd.nG);
         oSq += (int64_t)sd.nI * sd.nI;
+        oM += (int64_t)sd.ldM * sd.nI;
         oGG += (int64_t)sd.nG * sd.nG;
         oGI += (int64_t)sd.nG * sd.nI;
         oPiv += std::max(sd.nI, sd.nG);
@@ -98,6 +101,7 @@ int32_t analyze(hkgeneo_ctx *c, const hkgeneo_problem *p, hipStream_t s, int32_t
     }
     c->nBIO = oBIO;
     c->nSq = oSq;
+    c->nM = oM;
     c->nGG = oGG;
     c->nGI = oGI;
     c->nPiv = oPiv;
@@ -145,7 +149,8 @@ int32_t analyze(hkgeneo_ctx *c, const hkgeneo_problem *p, hipStream_t s, int32_t
     // descriptors for the batched dense kernels
     std::vector<DMat> hGG(ns), hSq(ns);
     std::vector<int64_t> hpo(ns), hpl(ns);
-    std::vector<TriJob> jGI(ns), jSq(ns);
+    std::vector<TriJob> jGI(ns), jSq(ns), jM(ns);
+    std::vector<DMat> hM(ns);
     std::vector<GemmJob> gS(ns);
     int64_t pl = 0;
     for (int i = 0; i < ns; ++i) {
@@ -158,6 +163,8 @@ int32_t analyze(hkgeneo_ctx *c, const hkgeneo_problem *p, hipStream_t s, int32_t
         pl += sd.nI;
         jGI[i] = {sd.offGG, sd.offGI, sd.nG, ldG, sd.nI, ldG};
         jSq[i] = {sd.offSq, sd.offSq, sd.nI, sd.nI, sd.nI, sd.nI};
+        hM[i] = {sd.offM, sd.nI, sd.ldM};
+        jM[i] = {sd.offSq, sd.offM, sd.nI, sd.nI, sd.nI, sd.ldM};
         gS[i] = {sd.offBIO + (int64_t)sd.nI * sd.nI, sd.offGI, sd.offSq, sd.nI, sd.nI, sd.nG, sd.nI, ldG, sd.nI};
     }
     HKG_TRY(upload(c, &c->matsGG, hGG.data(), ns, s));
@@ -166,6 +173,8 @@ int32_t analyze(hkgeneo_ctx *c, const hkgeneo_problem *p, hipStream_t s, int32_t
     HKG_TRY(upload(c, &c->poffLoc, hpl.data(), ns, s));
     HKG_TRY(upload(c, &c->jobsGI, jGI.data(), ns, s));
     HKG_TRY(upload(c, &c->jobsSq, jSq.data(), ns, s));
+    HKG_TRY(upload(c, &c->matsM, hM.data(), ns, s));
+    HKG_TRY(upload(c, &c->jobsM, jM.data(), ns, s));
     HKG_TRY(upload(c, &c->gjobsSchur, gS.data(), ns, s));
 
     // neighbouring pairs of the coarse matrix
@@ -196,7 +205,8 @@ int32_t read_flags(hkgeneo_ctx *c, const DevBuf &buf, int n, std::vector<int32_t
     return HKG_OK;
 }
 
-// B_D = P L U and B_D^{-1} = U^{-1} L^{-1} P, computed in precision T into `out` (nSq entries).
+// B_D = P L U and B_D^{-1} = U^{-1} L^{-1} P, computed in precision T into `out` (the padded layout
+// offM / ldM, nM entries).
 // Issued without waiting: the pivot flags are copied to c->h_infoL and checked by the caller.
 template <typename T>
 int32_t local_inverses(hkgeneo_ctx *c, T *out, hipStream_t s) {
@@ -210,11 +220,11 @@ int32_t local_inverses(hkgeneo_ctx *c, T *out, hipStream_t s) {
     HKG_TRY(lu_batched<T>(dp<DMat>(c->matsSq), dp<int64_t>(c->poffLoc), ns, c->max_nI, dp<T>(c->wLU),
                           dp<int32_t>(c->wPivL), dp<int32_t>(c->wInfoL), true, s));
     HKG_HIP(hipMemcpyAsync(c->h_infoL, c->wInfoL.p, ns * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HKG_TRY(perm_identity_batched<T>(dp<DMat>(c->matsSq), dp<int64_t>(c->poffLoc), ns, c->max_nI,
+    HKG_TRY(perm_identity_batched<T>(dp<DMat>(c->matsM), dp<int64_t>(c->poffLoc), ns, c->max_nI,
                                      dp<int32_t>(c->wPivL), out, s));
-    HKG_TRY(tri_solve_batched<T>(dp<TriJob>(c->jobsSq), ns, c->max_nI, c->max_nI, dp<T>(c->wLU), out, TRI_LOWER_UNIT,
+    HKG_TRY(tri_solve_batched<T>(dp<TriJob>(c->jobsM), ns, c->max_nI, c->max_nI, dp<T>(c->wLU), out, TRI_LOWER_UNIT,
                                  s));
-    HKG_TRY(tri_solve_batched<T>(dp<TriJob>(c->jobsSq), ns, c->max_nI, c->max_nI, dp<T>(c->wLU), out, TRI_UPPER, s));
+    HKG_TRY(tri_solve_batched<T>(dp<TriJob>(c->jobsM), ns, c->max_nI, c->max_nI, dp<T>(c->wLU), out, TRI_UPPER, s));
     return HKG_OK;
 }
 
@@ -222,13 +232,13 @@ int32_t local_inverses(hkgeneo_ctx *c, T *out, hipStream_t s) {
 // opt.local_factor_prec (a float64 inverse rounded to float32 storage, or all in float32)
 int32_t local_operators(hkgeneo_ctx *c, hipStream_t s) {
     const bool store32 = c->opt.local_prec == 32;
-    const size_t bytes = (size_t)c->nSq * (store32 ? sizeof(float) : sizeof(double));
+    const size_t bytes = (size_t)c->nM * (store32 ? sizeof(float) : sizeof(double));
     if (c->Minv.bytes != bytes) HKG_TRY(dalloc(c, &c->Minv, bytes));
     if (!store32) return local_inverses<double>(c, dp<double>(c->Minv), s);
     if (c->opt.local_factor_prec == 32) return local_inverses<float>(c, dp<float>(c->Minv), s);
-    HKG_TRY(walloc(c, &c->wSL, c->nSq * sizeof(double)));
+    HKG_TRY(walloc(c, &c->wSL, c->nM * sizeof(double)));
     HKG_TRY(local_inverses<double>(c, dp<double>(c->wSL), s));
-    return cast_f64_f32(dp<double>(c->wSL), dp<float>(c->Minv), c->nSq, s);
+    return cast_f64_f32(dp<double>(c->wSL), dp<float>(c->Minv), c->nM, s);
 }
 
 // A^{-1} = U^{-1} L^{-1} P for one packed n x n LU (ld = n): the diagonal blocks of L^{-1} and

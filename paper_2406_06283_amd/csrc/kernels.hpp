@@ -43,6 +43,8 @@ struct SubDev {             // per-subdomain device descriptors
     int64_t offZ;           // nI x m, ld nI
     int64_t offY;           // m x (nI + nG), ld m
     int32_t m, offm;        // eigenvectors kept, coarse offset
+    int64_t offM;           // local inverse B_D^{-1}: nI x nI, ld ldM
+    int32_t ldM, pad_;      // nI rounded up to 32 entries: every 64-row column segment starts on a line
 };
 
 int32_t form_operator(const double *A, const double *S, double k2, double *B, double *Dk, int64_t nnz, hipStream_t s);
@@ -86,7 +88,7 @@ struct ApplyPlan {
     const SubDev *d_sub;
     const int32_t *I_idx;
     const double *winv_loc;     // local prolongation weights per concatenated position (1 or 1/mu)
-    const void *Minv;           // local inverses (float or double), nI x nI at offSq
+    const void *Minv;           // local inverses (float or double), nI x nI at offM, ld ldM
     const double *Z;            // Z_i column-major (n_I x m_i) at offZ
     const double *Zr;           // Z_i row-major (n_I x m_i) at offZ
     const double *B0inv;

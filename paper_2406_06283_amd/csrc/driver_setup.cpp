@@ -11,6 +11,8 @@
 //   B_D = P L U and B_D^{-1} in float64 or float32                                     (eq. 2.22)
 #include <algorithm>
 #include <array>
+#include <string>
+#include <thread>
 #include <cstring>
 
 #include "ctx.hpp"
@@ -206,15 +208,12 @@ int32_t read_flags(hkgeneo_ctx *c, const DevBuf &buf, int n, std::vector<int32_t
 }
 
 // B_D = P L U and B_D^{-1} = U^{-1} L^{-1} P, computed in precision T into `out` (the padded layout
-// offM / ldM, nM entries).
-// Issued without waiting: the pivot flags are copied to c->h_infoL and checked by the caller.
+// offM / ldM, nM entries).  Launches only (buffers come from local_buffers): the pivot flags are
+// copied to c->h_infoL and checked by the caller.
 template <typename T>
 int32_t local_inverses(hkgeneo_ctx *c, T *out, hipStream_t s) {
     const int ns = c->n_sub;
     const SubDev *dsub = dp<SubDev>(c->subs_d);
-    HKG_TRY(walloc(c, &c->wLU, c->nSq * sizeof(T)));
-    HKG_TRY(walloc(c, &c->wPivL, c->sum_nI * sizeof(int32_t)));
-    HKG_TRY(walloc(c, &c->wInfoL, ns * sizeof(int32_t)));
     if (sizeof(T) == 8) HKG_TRY(copy_bii(dsub, ns, c->max_nI, dp<double>(c->wBIO), (double *)c->wLU.p, s));
     else HKG_TRY(copy_bii_f32(dsub, ns, c->max_nI, dp<double>(c->wBIO), (float *)c->wLU.p, s));
     HKG_TRY(lu_batched<T>(dp<DMat>(c->matsSq), dp<int64_t>(c->poffLoc), ns, c->max_nI, dp<T>(c->wLU),
@@ -228,15 +227,25 @@ int32_t local_inverses(hkgeneo_ctx *c, T *out, hipStream_t s) {
     return HKG_OK;
 }
 
+// every buffer of the local-inverse pipeline, allocated by the calling thread
+int32_t local_buffers(hkgeneo_ctx *c) {
+    const bool store32 = c->opt.local_prec == 32;
+    const bool factor32 = store32 && c->opt.local_factor_prec == 32;
+    const size_t bytes = (size_t)c->nM * (store32 ? sizeof(float) : sizeof(double));
+    if (c->Minv.bytes != bytes) HKG_TRY(dalloc(c, &c->Minv, bytes));
+    HKG_TRY(walloc(c, &c->wLU, c->nSq * (factor32 ? sizeof(float) : sizeof(double))));
+    HKG_TRY(walloc(c, &c->wPivL, c->sum_nI * sizeof(int32_t)));
+    HKG_TRY(walloc(c, &c->wInfoL, c->n_sub * sizeof(int32_t)));
+    if (store32 && !factor32) HKG_TRY(walloc(c, &c->wSL, c->nM * sizeof(double)));
+    return HKG_OK;
+}
+
 // the resident local operators in the storage precision of opt.local_prec, factorised in
 // opt.local_factor_prec (a float64 inverse rounded to float32 storage, or all in float32)
 int32_t local_operators(hkgeneo_ctx *c, hipStream_t s) {
     const bool store32 = c->opt.local_prec == 32;
-    const size_t bytes = (size_t)c->nM * (store32 ? sizeof(float) : sizeof(double));
-    if (c->Minv.bytes != bytes) HKG_TRY(dalloc(c, &c->Minv, bytes));
     if (!store32) return local_inverses<double>(c, dp<double>(c->Minv), s);
     if (c->opt.local_factor_prec == 32) return local_inverses<float>(c, dp<float>(c->Minv), s);
-    HKG_TRY(walloc(c, &c->wSL, c->nM * sizeof(double)));
     HKG_TRY(local_inverses<double>(c, dp<double>(c->wSL), s));
     return cast_f64_f32(dp<double>(c->wSL), dp<float>(c->Minv), c->nM, s);
 }
@@ -506,10 +515,23 @@ int32_t factor(hkgeneo_ctx *c, hipStream_t s) {
                            dp<double>(c->wBIO), dp<double>(c->wCII), s));
     // the local inverses (reading B_II) on the second stream, the coarse space on the caller's: the
     // two pipelines share no buffer written after this point
+    HKG_TRY(local_buffers(c));
     HKG_HIP(hipEventRecord(c->ev_fork, s));
     HKG_HIP(hipStreamWaitEvent(c->s2, c->ev_fork, 0));
-    int32_t st = local_operators(c, c->s2);
-    if (st == HKG_OK && c->opt.two_level) st = coarse_space(c, s);
+    // the local pipeline is enqueued by a helper thread (about a hundred launches) while this
+    // thread enqueues the coarse space, which waits on the device several times
+    int32_t st_local = HKG_OK;
+    std::string err_local;
+    std::thread enq([&]() {
+        st_local = local_operators(c, c->s2);
+        if (st_local != HKG_OK) err_local = g_last_error;
+    });
+    int32_t st = c->opt.two_level ? coarse_space(c, s) : HKG_OK;
+    enq.join();
+    if (st == HKG_OK && st_local != HKG_OK) {
+        set_last_error(err_local);
+        st = st_local;
+    }
     // join before returning, whatever happened on either side
     const hipError_t e1 = hipEventRecord(c->ev_join, c->s2);
     const hipError_t e2 = hipStreamWaitEvent(s, c->ev_join, 0);

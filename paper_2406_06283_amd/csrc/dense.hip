@@ -8,6 +8,7 @@
 #include "internal.hpp"
 #include "kernels.hpp"
 #include "tile.hpp"
+#include "wave.hpp"
 
 namespace hkg {
 
@@ -119,23 +120,12 @@ __global__ __launch_bounds__(256) void k_lu_panel(const DMat *__restrict__ mats,
 // Panel factorisation with the panel held in registers: thread t owns row j0 + t (the whole panel
 // row, LU_NB entries), so a panel of up to 1024 rows needs no memory traffic between its columns.
 // Two barriers per column.  The pivot candidates of column j + 1 are searched right after the
-// rank-1 update of column j (wave arg-max by shuffles, ties to the smallest row, as in the
-// global-memory panel); after the barrier every wave reduces the 16 wave candidates by shuffles, the
+// rank-1 update of column j (wave arg-max by DPP lane moves, ties to the smallest row, as in the
+// global-memory panel); after the barrier every wave reduces the 16 wave candidates within one DPP row, the
 // owners of the pivot row and of row j publish them in LDS, and after the second barrier the rows
 // are exchanged and the next update is applied.
 constexpr int PANEL_REG_ROWS = 1024;
 
-template <typename T>
-__device__ __forceinline__ void argmax_wave(T &v, int &idx, int width) {
-    for (int o = width / 2; o > 0; o >>= 1) {
-        const T ov = __shfl_xor(v, o, 64);
-        const int oi = __shfl_xor(idx, o, 64);
-        if (ov > v || (ov == v && oi < idx)) {
-            v = ov;
-            idx = oi;
-        }
-    }
-}
 
 template <typename T>
 __global__ __launch_bounds__(PANEL_REG_ROWS) void k_lu_panel_reg(const DMat *__restrict__ mats,
@@ -162,7 +152,7 @@ __global__ __launch_bounds__(PANEL_REG_ROWS) void k_lu_panel_reg(const DMat *__r
     if (pivot) {
         T v = own ? fabs(a[0]) : T(-1);
         int idx = own ? r : 0x7fffffff;
-        argmax_wave(v, idx, 64);
+        argmax_wave64(v, idx);
         if (lane == 0) {
             wval[0][wv] = v;
             widx[0][wv] = idx;
@@ -177,8 +167,9 @@ __global__ __launch_bounds__(PANEL_REG_ROWS) void k_lu_panel_reg(const DMat *__r
             if (pivot) {
                 T v = lane < NW ? wval[buf][lane] : T(-1);
                 int idx = lane < NW ? widx[buf][lane] : 0x7fffffff;
-                argmax_wave(v, idx, NW);
-                const int bi = __shfl(idx, 0, 64);
+                static_assert(NW <= 16, "wave candidates must fit one DPP row");
+                argmax_row16(v, idx);
+                const int bi = __builtin_amdgcn_readlane(idx, 0);
                 p = bi < n ? bi : j;
             }
             if (own && r == p) {
@@ -212,7 +203,7 @@ __global__ __launch_bounds__(PANEL_REG_ROWS) void k_lu_panel_reg(const DMat *__r
             if (pivot && jj + 1 < nb) {
                 T v = (own && r > j) ? fabs(a[jj + 1 < LU_NB ? jj + 1 : jj]) : T(-1);
                 int idx = (own && r > j) ? r : 0x7fffffff;
-                argmax_wave(v, idx, 64);
+                argmax_wave64(v, idx);
                 if (lane == 0) {
                     wval[buf ^ 1][wv] = v;
                     widx[buf ^ 1][wv] = idx;

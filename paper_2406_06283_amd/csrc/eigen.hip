@@ -16,14 +16,12 @@
 #include "internal.hpp"
 #include "kernels.hpp"
 #include "tile.hpp"
+#include "wave.hpp"
 
 namespace hkg {
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
+// sum over the 64 lanes of a wave (all lanes active); every lane gets the result
+__device__ __forceinline__ double wave_sum(double v) { return wave_sum64(v); }
 
 // block-wide sum; every thread gets the result. red must hold one double per wave.
 __device__ __forceinline__ double block_sum(double v, double *red) {
@@ -163,16 +161,16 @@ __global__ __launch_bounds__(SY_THREADS) void k_sytrd_panel(const SubDev *__rest
         // 1. corrected column j, rows j..n-1
         for (int r = j + tid; r < n; r += SY_THREADS) {
             double s = A[r + (int64_t)j * n];
-            for (int q0 = 0; q0 < kk; q0 += 4) {
-                double a[4], b[4];
+            for (int q0 = 0; q0 < kk; q0 += 8) {
+                double a[8], b[8];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+                for (int u = 0; u < 8; ++u) {
                     const int q = min(q0 + u, kk - 1);
                     a[u] = V[r + (int64_t)q * n];
                     b[u] = W[r + (int64_t)q * n];
                 }
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
+                for (int u = 0; u < 8; ++u)
                     if (q0 + u < kk) s -= a[u] * vw[q0 + u] + b[u] * vw[SY_NB + q0 + u];
             }
             p[r] = s;
@@ -205,17 +203,17 @@ __global__ __launch_bounds__(SY_THREADS) void k_sytrd_panel(const SubDev *__rest
         if (t == 0.0) continue;          // H_j = I: W column stays zero
         // 3. p = t (A0 v - V (W^T v) - W (V^T v)) on rows j+1..n-1
         {
-            // eight column loads in flight per thread (indices clamped into range, the surplus
+            // sixteen column loads in flight per thread (indices clamped into range, the surplus
             // terms masked), summed in column order
             const int rt = tid & (SY_RT - 1), g = tid / SY_RT;
             for (int r = j + 1 + rt; r < n; r += SY_RT) {
                 double s = 0.0;
-                for (int c0 = j + 1 + g; c0 < n; c0 += 16) {
-                    double a[8];
+                for (int c0 = j + 1 + g; c0 < n; c0 += 32) {
+                    double a[16];
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) a[u] = A[r + (int64_t)min(c0 + 2 * u, n - 1) * n];
+                    for (int u = 0; u < 16; ++u) a[u] = A[r + (int64_t)min(c0 + 2 * u, n - 1) * n];
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) s = fma(a[u], c0 + 2 * u < n ? v[min(c0 + 2 * u, n - 1)] : 0.0, s);
+                    for (int u = 0; u < 16; ++u) s = fma(a[u], c0 + 2 * u < n ? v[min(c0 + 2 * u, n - 1)] : 0.0, s);
                 }
                 part[g * n + r] = s;
             }
@@ -230,16 +228,16 @@ __global__ __launch_bounds__(SY_THREADS) void k_sytrd_panel(const SubDev *__rest
         __syncthreads();
         for (int r = j + 1 + tid; r < n; r += SY_THREADS) {
             double s = part[r] + part[n + r];
-            for (int q0 = 0; q0 < kk; q0 += 4) {
-                double a[4], b[4];
+            for (int q0 = 0; q0 < kk; q0 += 8) {
+                double a[8], b[8];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+                for (int u = 0; u < 8; ++u) {
                     const int q = min(q0 + u, kk - 1);
                     a[u] = V[r + (int64_t)q * n];
                     b[u] = W[r + (int64_t)q * n];
                 }
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
+                for (int u = 0; u < 8; ++u)
                     if (q0 + u < kk) s -= a[u] * t12[q0 + u] + b[u] * t12[kk + q0 + u];
             }
             p[r] = t * s;
@@ -627,8 +625,11 @@ int32_t tridiag_vectors_n(const SubDev *d_sub, int nsub, int64_t max_nm, const d
 
 // ------------------------------------------------------------------------------------------------
 // 4. back-transformation y <- Q y with Q = H_0 H_1 ... H_{n-2} (reflectors applied last-first), one
-//    wave per eigenvector with the vector staged in LDS
+//    wave per eigenvector with the vector staged in LDS.  Reflector j - 1 is loaded into registers
+//    while reflector j is applied, so each step costs a dot product and an update, not a memory
+//    round trip.  NB = ceil(n / 64) registers per lane hold a reflector.
 // ------------------------------------------------------------------------------------------------
+template <int NB>
 __global__ __launch_bounds__(64) void k_back_transform(const SubDev *__restrict__ subs, const double *__restrict__ Sq,
                                                        const double *__restrict__ taub, double *__restrict__ Zb) {
     extern __shared__ double zs[];
@@ -641,16 +642,45 @@ __global__ __launch_bounds__(64) void k_back_transform(const SubDev *__restrict_
     double *z = Zb + sd.offZ + (int64_t)c * n;
     for (int i = lane; i < n; i += 64) zs[i] = z[i];
     __syncthreads();
-    for (int j = n - 2; j >= 0; --j) {
-        const double t = tau[j];
-        if (t == 0.0) continue;
+    if (n < 2) {
+        for (int i = lane; i < n; i += 64) z[i] = zs[i];
+        return;
+    }
+    // reflector j: v = A[j+1 .. n-1, j]; entry i of it (i < L = n - j - 1) in lane i % 64, slot i / 64
+    double vc[NB], vn[NB];
+    auto load = [&](int j, double *dst) {
         const int L = n - j - 1;
         const double *v = A + (j + 1) + (int64_t)j * n;
-        double s = 0.0;
-        for (int i = lane; i < L; i += 64) s += v[i] * zs[j + 1 + i];
-        s = t * wave_sum(s);
-        for (int i = lane; i < L; i += 64) zs[j + 1 + i] -= s * v[i];
+#pragma unroll
+        for (int q = 0; q < NB; ++q) dst[q] = v[min(lane + 64 * q, L - 1)];
+    };
+    load(n - 2, vc);
+    double tc = tau[n - 2];
+    for (int j = n - 2; j >= 0; --j) {
+        double tn = 0.0;
+        if (j > 0) {
+            load(j - 1, vn);
+            tn = tau[j - 1];
+        }
+        if (tc != 0.0) {
+            const int L = n - j - 1;
+            double s = 0.0;
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                const int i = lane + 64 * q;
+                if (i < L) s = fma(vc[q], zs[j + 1 + i], s);
+            }
+            s = tc * wave_sum(s);
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                const int i = lane + 64 * q;
+                if (i < L) zs[j + 1 + i] -= s * vc[q];
+            }
+        }
         __syncthreads();
+#pragma unroll
+        for (int q = 0; q < NB; ++q) vc[q] = vn[q];
+        tc = tn;
     }
     for (int i = lane; i < n; i += 64) z[i] = zs[i];
 }
@@ -658,8 +688,15 @@ __global__ __launch_bounds__(64) void k_back_transform(const SubDev *__restrict_
 int32_t back_transform_n(const SubDev *d_sub, int nsub, int maxnI, int max_m, const double *Sq, const double *tau,
                          double *Z, hipStream_t s) {
     if (max_m == 0) return HKG_OK;
-    hipLaunchKernelGGL(k_back_transform, dim3(nsub, max_m), dim3(64), (size_t)maxnI * sizeof(double), s, d_sub, Sq, tau,
-                       Z);
+    const size_t shm = (size_t)maxnI * sizeof(double);
+    if (maxnI <= 8 * 64)
+        hipLaunchKernelGGL(k_back_transform<8>, dim3(nsub, max_m), dim3(64), shm, s, d_sub, Sq, tau, Z);
+    else if (maxnI <= 24 * 64)
+        hipLaunchKernelGGL(k_back_transform<24>, dim3(nsub, max_m), dim3(64), shm, s, d_sub, Sq, tau, Z);
+    else {
+        set_last_error("back-transformation supports at most 1536 unknowns per subdomain");
+        return HKG_EINVAL;
+    }
     HKG_HIP(hipGetLastError());
     return HKG_OK;
 }

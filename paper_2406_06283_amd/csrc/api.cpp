@@ -62,7 +62,7 @@ extern "C" void hkgeneo_destroy(hkgeneo_ctx *c) {
     DevBuf *bufs[] = {&c->rowptr, &c->colidx, &c->Aval,    &c->Sval,   &c->I_idx,   &c->G_idx,      &c->winv,
                       &c->wloc,   &c->tp_ptr, &c->tp_pos,  &c->tp_sub, &c->subs_d, &c->bandK,   &c->bandM,      &c->bandLoc,
                       &c->pairs,  &c->matsGG, &c->matsSq,  &c->poffSub, &c->jobsGI, &c->jobsSq,     &c->gjobsSchur,
-                      &c->matsLoc, &c->poffLoc, &c->jobsLoc, &c->matsM, &c->jobsM, &c->Bval, &c->Minv,    &c->Z, &c->Zr,  &c->B0inv,
+                      &c->matsLoc, &c->poffLoc, &c->jobsLoc, &c->matsM, &c->jobsM, &c->Bval, &c->Minv,    &c->Z, &c->Zr,  &c->B0inv, &c->B0copy,
                       &c->u,      &c->c,      &c->y,       &c->ypart, &c->itersd,       &c->V,      &c->Zk,      &c->H,          &c->cs,
                       &c->sn,     &c->g,      &c->part,    &c->hcol,   &c->scal,    &c->active,     &c->want,
                       &c->rnorm,  &c->npart,  &c->fnorm};
@@ -439,8 +439,9 @@ extern "C" int32_t hkgeneo_query_eigen(const hkgeneo_ctx *c, int32_t sub, double
 
 extern "C" int32_t hkgeneo_query_coarse_matrix(const hkgeneo_ctx *c, double *B0) {
     if (!c || !B0) return HKG_EINVAL;
-    if (c->B0_host.size() != (size_t)c->m0 * c->m0) return HKG_EINVAL;
-    std::memcpy(B0, c->B0_host.data(), c->B0_host.size() * sizeof(double));
+    const size_t bytes = (size_t)c->m0 * c->m0 * sizeof(double);
+    if (c->m0 == 0 || !c->B0copy.p || c->B0copy.bytes < bytes) return HKG_EINVAL;
+    HKG_HIP(hipMemcpy(B0, c->B0copy.p, bytes, hipMemcpyDeviceToHost));
     return HKG_OK;
 }
 

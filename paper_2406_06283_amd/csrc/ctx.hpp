@@ -19,7 +19,6 @@ struct hkgeneo_ctx {
     std::vector<hkg::SubDev> subs;        // host copy of the per-subdomain descriptors
     std::vector<int32_t> m_host;
     std::vector<double> lam_host;         // n_sub x (max_eig_per_sub + 2)
-    std::vector<double> B0_host;          // kept for queries when m0 is small
     int64_t device_bytes = 0;
 
     // resident inputs and static descriptors (analysis phase)
@@ -28,9 +27,10 @@ struct hkgeneo_ctx {
     hkg::DevBuf matsGG, matsSq, poffSub, jobsGI, jobsSq, gjobsSchur, matsLoc, poffLoc, jobsLoc, matsM, jobsM;
     // numeric results (factorisation phase)
     hkg::DevBuf Bval, Minv, Z, Zr, B0inv;
+    hkg::DevBuf B0copy;                   // B_0 kept on the device for queries when m0 <= 2048
     // factorisation workspace (kept between calls when opt.keep_workspace, freed otherwise)
     hkg::DevBuf wDk, wBIO, wCII, wGG, wGI, wS, wW, wPiv, wInfo, wFlag, wD, wE, wTau, wM, wLam, wY, wB0, wLU, wPivL,
-        wJobsZ, wGjobsY, wMisc, wPiv0, wInv, wVWV, wInfoL, wSL, wIv, wLinv, wJobsInv;
+        wJobsZ, wGjobsY, wMisc, wPiv0, wInv, wVWV, wInfoL, wSL, wIv, wLinv, wJobsInv, wT;
     // the local-inverse pipeline of the factorisation runs on a second stream beside the coarse-space
     // pipeline; its pivot flags come back through pinned host memory
     hipStream_t s2 = nullptr;

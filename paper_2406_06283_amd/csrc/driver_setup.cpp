@@ -62,7 +62,7 @@ void free_workspace(hkgeneo_ctx *c) {
     DevBuf *w[] = {&c->wDk, &c->wBIO, &c->wCII, &c->wGG, &c->wGI, &c->wS, &c->wW, &c->wPiv, &c->wInfo,
                    &c->wFlag, &c->wD, &c->wE, &c->wTau, &c->wM, &c->wLam, &c->wY, &c->wB0, &c->wLU,
                    &c->wPivL, &c->wJobsZ, &c->wGjobsY, &c->wMisc, &c->wPiv0, &c->wInv, &c->wVWV, &c->wInfoL, &c->wSL, &c->wIv,
-                   &c->wLinv, &c->wJobsInv};
+                   &c->wLinv, &c->wJobsInv, &c->wT};
     for (DevBuf *b : w) drelease(c, b);
 }
 
@@ -361,13 +361,14 @@ int32_t coarse_space(hkgeneo_ctx *c, hipStream_t s) {
     HKG_TRY(transpose_batched<double>(dp<DMat>(c->matsSq), ns, c->max_nI, dp<double>(c->wS), dp<double>(c->wW), s));
     HKG_TRY(tri_solve_batched<double>(dp<TriJob>(c->jobsSq), ns, c->max_nI, c->max_nI, dp<double>(c->wCII),
                                       dp<double>(c->wW), TRI_LOWER_UNIT, s));
-    HKG_TRY(scale_sym(dsub, ns, c->max_nI, dp<double>(c->wCII), dp<double>(c->wW), s));
+    HKG_TRY(walloc(c, &c->wT, (size_t)c->nM * sizeof(double)));
+    HKG_TRY(scale_sym(dsub, ns, c->max_nI, dp<double>(c->wCII), dp<double>(c->wW), dp<double>(c->wT), s));
     // tridiagonal form and selection
     HKG_TRY(walloc(c, &c->wD, c->sum_nI * sizeof(double)));
     HKG_TRY(walloc(c, &c->wE, c->sum_nI * sizeof(double)));
     HKG_TRY(walloc(c, &c->wTau, c->sum_nI * sizeof(double)));
     HKG_TRY(walloc(c, &c->wVWV, (size_t)3 * 32 * c->sum_nI * sizeof(double)));
-    HKG_TRY(tridiagonalize_blocked(dsub, ns, c->max_nI, dp<double>(c->wW), dp<double>(c->wVWV), dp<double>(c->wD),
+    HKG_TRY(tridiagonalize_blocked(dsub, ns, c->max_nI, dp<double>(c->wT), dp<double>(c->wVWV), dp<double>(c->wD),
                                    dp<double>(c->wE), dp<double>(c->wTau), s));
     HKG_TRY(walloc(c, &c->wM, ns * sizeof(int32_t)));
     HKG_TRY(walloc(c, &c->wLam, (size_t)ns * (mmax + 2) * sizeof(double)));
@@ -418,7 +419,7 @@ int32_t coarse_space(hkgeneo_ctx *c, hipStream_t s) {
     HKG_TRY(tridiag_vectors_n(dsub, ns, max_nm, dp<double>(c->wD), dp<double>(c->wE), dp<double>(c->wLam), mmax,
                               dp<double>(c->Z), dp<double>(c->wInv),
                               reinterpret_cast<unsigned char *>(dp<double>(c->wInv) + 5 * offZ), s));
-    HKG_TRY(back_transform_n(dsub, ns, c->max_nI, c->max_m, dp<double>(c->wW), dp<double>(c->wTau), dp<double>(c->Z),
+    HKG_TRY(back_transform_n(dsub, ns, c->max_nI, c->max_m, dp<double>(c->wT), dp<double>(c->wTau), dp<double>(c->Z),
                              s));
     HKG_TRY(scale_rows_invsqrt_diag(dsub, ns, dp<double>(c->wCII), dp<double>(c->Z), s));
     {
@@ -454,11 +455,11 @@ int32_t coarse_space(hkgeneo_ctx *c, hipStream_t s) {
                          pp + 3 * npairs + 1 + CP.qi.size(), dsub, dp<double>(c->wY), dp<double>(c->Z),
                          dp<double>(c->wB0), m0, s));
     if ((int64_t)m0 * m0 <= (int64_t)2048 * 2048) {
-        c->B0_host.resize((size_t)m0 * m0);
-        HKG_HIP(hipMemcpyAsync(c->B0_host.data(), c->wB0.p, c->B0_host.size() * sizeof(double), hipMemcpyDeviceToHost,
-                               s));
+        // a device copy for queries (the LU below overwrites B_0); read back only when asked
+        HKG_TRY(walloc(c, &c->B0copy, (size_t)m0 * m0 * sizeof(double)));
+        HKG_HIP(hipMemcpyAsync(c->B0copy.p, c->wB0.p, (size_t)m0 * m0 * sizeof(double), hipMemcpyDeviceToDevice, s));
     } else {
-        c->B0_host.clear();
+        drelease(c, &c->B0copy);
     }
     // B_0 = P L U and B_0^{-1}
     DMat hm{0, m0, m0};

@@ -36,86 +36,11 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
 }
 
 // ------------------------------------------------------------------------------------------------
-// 1. Householder tridiagonalisation of the full symmetric nI x nI matrix at offSq (both triangles
-//    kept up to date).  Reflector j is stored in column j below the diagonal (its first entry, 1,
-//    explicitly), with tau[j]; d and e receive the diagonal and sub-diagonal of T.
-// ------------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_sytrd(const SubDev *__restrict__ subs, double *__restrict__ Sq,
-                                                double *__restrict__ dout, double *__restrict__ eout,
-                                                double *__restrict__ tout) {
-    extern __shared__ double sh[];
-    const SubDev sd = subs[blockIdx.x];
-    const int n = sd.nI;
-    double *A = Sq + sd.offSq;
-    const int ld = n;
-    double *v = sh;           // n
-    double *p = sh + n;       // n
-    double *red = sh + 2 * n; // 16
-    double *d = dout + sd.offI, *e = eout + sd.offI, *tau = tout + sd.offI;
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
-
-    for (int j = 0; j + 1 < n; ++j) {
-        const int L = n - j - 1;
-        double *x = A + (j + 1) + (int64_t)j * ld;        // A[j+1:, j]
-        for (int i = tid; i < L; i += blockDim.x) v[i] = x[i];
-        __syncthreads();
-        const double alpha = v[0];
-        double part = 0.0;
-        for (int i = 1 + tid; i < L; i += blockDim.x) part += v[i] * v[i];
-        const double xn2 = block_sum(part, red);
-        if (tid == 0) d[j] = A[j + (int64_t)j * ld];
-        if (xn2 == 0.0) {
-            if (tid == 0) { e[j] = alpha; tau[j] = 0.0; }
-            __syncthreads();
-            continue;
-        }
-        const double beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
-        const double t = (beta - alpha) / beta;
-        const double scal = 1.0 / (alpha - beta);
-        __syncthreads();
-        for (int i = tid; i < L; i += blockDim.x) {
-            double vi = (i == 0) ? 1.0 : v[i] * scal;
-            v[i] = vi;
-            x[i] = vi;
-        }
-        if (tid == 0) { e[j] = beta; tau[j] = t; }
-        __syncthreads();
-        // p = tau A22 v, one wave per column of the symmetric A22 (column c dotted with v)
-        double *A22 = A + (j + 1) + (int64_t)(j + 1) * ld;
-        for (int c = wv; c < L; c += nw) {
-            const double *col = A22 + (int64_t)c * ld;
-            double s = 0.0;
-            for (int i = lane; i < L; i += 64) s += col[i] * v[i];
-            s = wave_sum(s);
-            if (lane == 0) p[c] = t * s;
-        }
-        __syncthreads();
-        part = 0.0;
-        for (int i = tid; i < L; i += blockDim.x) part += p[i] * v[i];
-        const double K = 0.5 * t * block_sum(part, red);
-        for (int i = tid; i < L; i += blockDim.x) p[i] -= K * v[i];     // p becomes w
-        __syncthreads();
-        // A22 -= v w^T + w v^T
-        const int64_t LL = (int64_t)L * L;
-        for (int64_t q = tid; q < LL; q += blockDim.x) {
-            int r = (int)(q % L), c = (int)(q / L);
-            A22[r + (int64_t)c * ld] -= v[r] * p[c] + p[r] * v[c];
-        }
-        __syncthreads();
-    }
-    if (tid == 0) d[n - 1] = A[(n - 1) + (int64_t)(n - 1) * ld];
-}
-
-int32_t tridiagonalize_n(const SubDev *d_sub, int nsub, int maxnI, double *Sq, double *d, double *e, double *tau,
-                         hipStream_t s) {
-    size_t shm = (size_t)(2 * maxnI + 16) * sizeof(double);
-    hipLaunchKernelGGL(k_sytrd, dim3(nsub), dim3(1024), shm, s, d_sub, Sq, d, e, tau);
-    HKG_HIP(hipGetLastError());
-    return HKG_OK;
-}
-
-// ------------------------------------------------------------------------------------------------
-// 1b. Blocked Householder tridiagonalisation.  Within a panel of SY_NB columns starting at j0 the
+// 1. Blocked Householder tridiagonalisation of the symmetric nI x nI matrix T of each subdomain,
+//    stored at offM with the padded leading dimension ldM (both triangles kept up to date; every
+//    column starts on a 256-byte boundary).  Reflector j is stored in column j below the diagonal
+//    (its first entry, 1, explicitly), with tau[j]; d and e receive the diagonal and sub-diagonal.
+//    Within a panel of SY_NB columns starting at j0 the
 //     trailing matrix A0 is left as it was at the panel start; with V (reflectors) and W (their
 //     images) of the panel's earlier columns the current matrix is A0 - V W^T - W V^T, so column j
 //     is corrected before its reflector is formed and the product A v needs only one pass over A0
@@ -125,7 +50,8 @@ int32_t tridiagonalize_n(const SubDev *d_sub, int nsub, int maxnI, double *Sq, d
 // ------------------------------------------------------------------------------------------------
 constexpr int SY_NB = 32;
 constexpr int SY_THREADS = 1024;
-constexpr int SY_RT = 512;          // row threads of the product A0 v (two column groups)
+constexpr int SY_RT = 256;          // row-pair threads of the product A0 v
+constexpr int SY_G = SY_THREADS / SY_RT;   // column groups of the product
 
 __global__ __launch_bounds__(SY_THREADS) void k_sytrd_panel(const SubDev *__restrict__ subs, double *__restrict__ Sq,
                                                             double *__restrict__ VWVb, double *__restrict__ dout,
@@ -134,7 +60,8 @@ __global__ __launch_bounds__(SY_THREADS) void k_sytrd_panel(const SubDev *__rest
     extern __shared__ double sh[];
     const SubDev sd = subs[blockIdx.x];
     const int n = sd.nI;
-    double *A = Sq + sd.offSq;
+    double *A = Sq + sd.offM;
+    const int ld = sd.ldM;
     double *d = dout + sd.offI, *e = eout + sd.offI, *tau = tout + sd.offI;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     if (j0 >= n - 1) return;
@@ -144,8 +71,8 @@ __global__ __launch_bounds__(SY_THREADS) void k_sytrd_panel(const SubDev *__rest
     double *V2 = V + (int64_t)2 * SY_NB * n;
     double *v = sh;                  // n
     double *p = sh + n;              // n (first the corrected column, then A v)
-    double *part = sh + 2 * n;       // 2 n
-    double *t12 = sh + 4 * n;        // 2 SY_NB
+    double *part = sh + 2 * n;       // SY_G (n + 1): partial products per column group
+    double *t12 = part + SY_G * (n + 1);   // 2 SY_NB
     double *vw = t12 + 2 * SY_NB;    // 2 SY_NB: W[j, :], V[j, :]
     double *red = vw + 2 * SY_NB;    // 16
     // zero the panel's columns of V, W, V2 (rows not written below stay zero)
@@ -160,7 +87,7 @@ __global__ __launch_bounds__(SY_THREADS) void k_sytrd_panel(const SubDev *__rest
         __syncthreads();
         // 1. corrected column j, rows j..n-1
         for (int r = j + tid; r < n; r += SY_THREADS) {
-            double s = A[r + (int64_t)j * n];
+            double s = A[r + (int64_t)j * ld];
             for (int q0 = 0; q0 < kk; q0 += 8) {
                 double a[8], b[8];
 #pragma unroll
@@ -190,7 +117,7 @@ __global__ __launch_bounds__(SY_THREADS) void k_sytrd_panel(const SubDev *__rest
         for (int r = j + 1 + tid; r < n; r += SY_THREADS) {
             const double vr = (r == j + 1) ? 1.0 : (xn2 != 0.0 ? p[r] * scal : 0.0);
             v[r] = vr;
-            A[r + (int64_t)j * n] = vr;
+            A[r + (int64_t)j * ld] = vr;
             V[r + (int64_t)kk * n] = vr;
             V2[r + (int64_t)kk * n] = vr;
         }
@@ -203,19 +130,27 @@ __global__ __launch_bounds__(SY_THREADS) void k_sytrd_panel(const SubDev *__rest
         if (t == 0.0) continue;          // H_j = I: W column stays zero
         // 3. p = t (A0 v - V (W^T v) - W (V^T v)) on rows j+1..n-1
         {
-            // sixteen column loads in flight per thread (indices clamped into range, the surplus
-            // terms masked), summed in column order
+            // row pairs (16-byte loads: ld and the pair's first row are even) times four column
+            // groups, eight column loads in flight per thread (indices clamped into range, the
+            // surplus terms masked), summed in column order
             const int rt = tid & (SY_RT - 1), g = tid / SY_RT;
-            for (int r = j + 1 + rt; r < n; r += SY_RT) {
-                double s = 0.0;
-                for (int c0 = j + 1 + g; c0 < n; c0 += 32) {
-                    double a[16];
+            const int rp0 = (j + 1) & ~1;
+            for (int r = rp0 + 2 * rt; r < n; r += 2 * SY_RT) {
+                double s0 = 0.0, s1 = 0.0;
+                for (int c0 = j + 1 + g; c0 < n; c0 += 8 * SY_G) {
+                    double2 a[8];
 #pragma unroll
-                    for (int u = 0; u < 16; ++u) a[u] = A[r + (int64_t)min(c0 + 2 * u, n - 1) * n];
+                    for (int u = 0; u < 8; ++u)
+                        a[u] = *reinterpret_cast<const double2 *>(A + r + (int64_t)min(c0 + SY_G * u, n - 1) * ld);
 #pragma unroll
-                    for (int u = 0; u < 16; ++u) s = fma(a[u], c0 + 2 * u < n ? v[min(c0 + 2 * u, n - 1)] : 0.0, s);
+                    for (int u = 0; u < 8; ++u) {
+                        const double vc = c0 + SY_G * u < n ? v[min(c0 + SY_G * u, n - 1)] : 0.0;
+                        s0 = fma(a[u].x, vc, s0);
+                        s1 = fma(a[u].y, vc, s1);
+                    }
                 }
-                part[g * n + r] = s;
+                part[g * (n + 1) + r] = s0;
+                part[g * (n + 1) + r + 1] = s1;
             }
         }
         for (int q2 = wv; q2 < 2 * kk; q2 += SY_THREADS / 64) {
@@ -227,7 +162,7 @@ __global__ __launch_bounds__(SY_THREADS) void k_sytrd_panel(const SubDev *__rest
         }
         __syncthreads();
         for (int r = j + 1 + tid; r < n; r += SY_THREADS) {
-            double s = part[r] + part[n + r];
+            double s = (part[r] + part[(n + 1) + r]) + (part[2 * (n + 1) + r] + part[3 * (n + 1) + r]);
             for (int q0 = 0; q0 < kk; q0 += 8) {
                 double a[8], b[8];
 #pragma unroll
@@ -264,20 +199,21 @@ __global__ __launch_bounds__(256) void k_sytrd_update(const SubDev *__restrict__
     const int tm = blockIdx.x % tiles_max, tn = blockIdx.x / tiles_max;
     if (tm * 64 >= L1 || tn * 64 >= L1) return;
     const double *V = VWVb + 3 * SY_NB * sd.offI;
-    double *A = Sq + sd.offSq;
-    gemm_tile<double>(L1, L1, 2 * SY_NB, V + j1, n, false, V + (int64_t)SY_NB * n + j1, n, true, A + j1 + (int64_t)j1 * n, n,
+    double *A = Sq + sd.offM;
+    const int ld = sd.ldM;
+    gemm_tile<double>(L1, L1, 2 * SY_NB, V + j1, n, false, V + (int64_t)SY_NB * n + j1, n, true, A + j1 + (int64_t)j1 * ld, ld,
                       -1.0, 1.0, tm, tn);
 }
 
 // the last diagonal entry, after the final trailing update
 __global__ void k_sytrd_last(const SubDev *__restrict__ subs, const double *__restrict__ Sq, double *__restrict__ dout) {
     const SubDev sd = subs[blockIdx.x];
-    if (threadIdx.x == 0) dout[sd.offI + sd.nI - 1] = Sq[sd.offSq + (int64_t)(sd.nI - 1) * (sd.nI + 1)];
+    if (threadIdx.x == 0) dout[sd.offI + sd.nI - 1] = Sq[sd.offM + (int64_t)(sd.nI - 1) * (sd.ldM + 1)];
 }
 
 int32_t tridiagonalize_blocked(const SubDev *d_sub, int nsub, int maxnI, double *Sq, double *VWV, double *d, double *e,
                                double *tau, hipStream_t s) {
-    const size_t shm = (size_t)(4 * maxnI + 4 * SY_NB + 16) * sizeof(double);
+    const size_t shm = (size_t)(2 * maxnI + SY_G * (maxnI + 1) + 4 * SY_NB + 16) * sizeof(double);
     const int tiles = (maxnI + 63) / 64;
     for (int j0 = 0; j0 < maxnI; j0 += SY_NB) {
         hipLaunchKernelGGL(k_sytrd_panel, dim3(nsub), dim3(SY_THREADS), shm, s, d_sub, Sq, VWV, d, e, tau, j0);
@@ -466,6 +402,10 @@ __device__ __forceinline__ double start_value(int i, int k) {
 // T - lambda I stay in the global scratch (read-only in the sweeps).  Running values of the
 // recurrences are carried in registers, the reciprocal pivots are stored, and the loads of four
 // steps are issued before their arithmetic.
+// rows per group of the substitution sweeps: the group's loads are issued together, so a sweep
+// waits on memory once per IU rows
+constexpr int IU = 16;
+
 template <bool LDSB>
 __global__ __launch_bounds__(64) void k_inverse_iteration(const SubDev *__restrict__ subs, const double *__restrict__ dbuf,
                                                           const double *__restrict__ ebuf, const double *__restrict__ lam_all,
@@ -533,11 +473,11 @@ __global__ __launch_bounds__(64) void k_inverse_iteration(const SubDev *__restri
         for (int k = lane; k < m; k += 64) {
             // forward elimination with the row exchanges; cur = running entry of row i
             double cur = b[k];
-            for (int i0 = 0; i0 + 1 < n; i0 += 4) {
-                double bn[4], f[4];
-                int sw[4];
+            for (int i0 = 0; i0 + 1 < n; i0 += IU) {
+                double bn[IU], f[IU];
+                int sw[IU];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+                for (int u = 0; u < IU; ++u) {
                     const int i = min(i0 + u, n - 2);
                     const int64_t q = (int64_t)i * m + k;
                     bn[u] = b[q + m];
@@ -545,7 +485,7 @@ __global__ __launch_bounds__(64) void k_inverse_iteration(const SubDev *__restri
                     sw[u] = swp[q];
                 }
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+                for (int u = 0; u < IU; ++u) {
                     if (i0 + u + 1 < n) {
                         const double out = sw[u] ? bn[u] : cur;
                         cur = sw[u] ? cur - f[u] * bn[u] : bn[u] - f[u] * cur;
@@ -556,10 +496,10 @@ __global__ __launch_bounds__(64) void k_inverse_iteration(const SubDev *__restri
             b[(int64_t)(n - 1) * m + k] = cur;
             // back substitution with U (diagonal, two super-diagonals); x1 = x_{i+1}, x2 = x_{i+2}
             double x1 = 0.0, x2 = 0.0, mx = 0.0;
-            for (int i0 = n - 1; i0 >= 0; i0 -= 4) {
-                double bv[4], u1[4], u2[4], r[4];
+            for (int i0 = n - 1; i0 >= 0; i0 -= IU) {
+                double bv[IU], u1[IU], u2[IU], r[IU];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+                for (int u = 0; u < IU; ++u) {
                     const int i = max(i0 - u, 0);
                     const int64_t q = (int64_t)i * m + k;
                     bv[u] = b[q];
@@ -568,7 +508,7 @@ __global__ __launch_bounds__(64) void k_inverse_iteration(const SubDev *__restri
                     r[u] = rdd[q];
                 }
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+                for (int u = 0; u < IU; ++u) {
                     const int i = i0 - u;
                     if (i >= 0) {
                         double v = bv[u];
@@ -637,7 +577,8 @@ __global__ __launch_bounds__(64) void k_back_transform(const SubDev *__restrict_
     const int c = blockIdx.y;
     if (c >= sd.m) return;
     const int n = sd.nI, lane = threadIdx.x;
-    const double *A = Sq + sd.offSq;
+    const double *A = Sq + sd.offM;
+    const int ld = sd.ldM;
     const double *tau = taub + sd.offI;
     double *z = Zb + sd.offZ + (int64_t)c * n;
     for (int i = lane; i < n; i += 64) zs[i] = z[i];
@@ -650,7 +591,7 @@ __global__ __launch_bounds__(64) void k_back_transform(const SubDev *__restrict_
     double vc[NB], vn[NB];
     auto load = [&](int j, double *dst) {
         const int L = n - j - 1;
-        const double *v = A + (j + 1) + (int64_t)j * n;
+        const double *v = A + (j + 1) + (int64_t)j * ld;
 #pragma unroll
         for (int q = 0; q < NB; ++q) dst[q] = v[min(lane + 64 * q, L - 1)];
     };

@@ -43,7 +43,7 @@ struct SubDev {             // per-subdomain device descriptors
     int64_t offZ;           // nI x m, ld nI
     int64_t offY;           // m x (nI + nG), ld m
     int32_t m, offm;        // eigenvectors kept, coarse offset
-    int64_t offM;           // local inverse B_D^{-1}: nI x nI, ld ldM
+    int64_t offM;           // nI x nI, ld ldM: the local inverse B_D^{-1}, and the matrix tridiagonalised
     int32_t ldM, pad_;      // nI rounded up to 32 entries: every 64-row column segment starts on a line
 };
 
@@ -59,13 +59,12 @@ int32_t apply_pivots_rows(const SubDev *d_sub, int nsub, int maxcol, const int32
 int32_t copy_bii(const SubDev *d_sub, int nsub, int maxnI, const double *BIO, double *out, hipStream_t s);
 int32_t copy_bii_f32(const SubDev *d_sub, int nsub, int maxnI, const double *BIO, float *out, hipStream_t s);
 int32_t check_spd_pivots(const SubDev *d_sub, int nsub, const double *C, int32_t *flag, hipStream_t s);
-int32_t scale_sym(const SubDev *d_sub, int nsub, int maxnI, const double *C, double *S, hipStream_t s);
+// T = D^{-1/2} S D^{-1/2} into the padded (offM, ldM) layout
+int32_t scale_sym(const SubDev *d_sub, int nsub, int maxnI, const double *C, const double *S, double *T, hipStream_t s);
 
 // ---- eigen.hip: tridiagonalisation, selection, eigenvectors --------------------------------------
 int32_t tridiagonalize_blocked(const SubDev *d_sub, int nsub, int maxnI, double *Sq, double *VWV, double *d, double *e,
                                double *tau, hipStream_t s);
-int32_t tridiagonalize_n(const SubDev *d_sub, int nsub, int maxnI, double *Sq, double *d, double *e, double *tau,
-                         hipStream_t s);
 int32_t select_eigs(const SubDev *d_sub, int nsub, int maxnI, const double *d, const double *e, int mode, double tau,
                     int nev, double rtol, int mmax, int32_t *m_out, double *lam_out, int32_t *flag, double *iv,
                     hipStream_t s);

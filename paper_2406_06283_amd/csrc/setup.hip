@@ -195,21 +195,22 @@ int32_t check_spd_pivots(const SubDev *d_sub, int nsub, const double *C, int32_t
     return HKG_OK;
 }
 
-// S <- D^{-1/2} S D^{-1/2} with D = diag(U) of C_II = L U (so C_II = (L D^{1/2}) (L D^{1/2})^T)
+// T = D^{-1/2} S D^{-1/2} with D = diag(U) of C_II = L U (so C_II = (L D^{1/2}) (L D^{1/2})^T); S has
+// leading dimension nI at offSq, T the padded leading dimension ldM at offM
 __global__ __launch_bounds__(256) void k_scale_sym(const SubDev *__restrict__ subs, const double *__restrict__ C,
-                                                   double *__restrict__ S) {
+                                                   const double *__restrict__ S, double *__restrict__ T) {
     const SubDev sd = subs[blockIdx.y];
     const int64_t n2 = (int64_t)sd.nI * sd.nI;
     for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n2; i += (int64_t)gridDim.x * 256) {
         int r = (int)(i % sd.nI), c = (int)(i / sd.nI);
         double dr = C[sd.offSq + r + (int64_t)r * sd.nI], dc = C[sd.offSq + c + (int64_t)c * sd.nI];
-        S[sd.offSq + i] /= sqrt(dr) * sqrt(dc);
+        T[sd.offM + r + (int64_t)c * sd.ldM] = S[sd.offSq + i] / (sqrt(dr) * sqrt(dc));
     }
 }
 
-int32_t scale_sym(const SubDev *d_sub, int nsub, int maxnI, const double *C, double *S, hipStream_t s) {
+int32_t scale_sym(const SubDev *d_sub, int nsub, int maxnI, const double *C, const double *S, double *T, hipStream_t s) {
     int blocks = std::max(1, std::min(256, (maxnI * maxnI + 255) / 256));
-    hipLaunchKernelGGL(k_scale_sym, dim3(blocks, nsub), dim3(256), 0, s, d_sub, C, S);
+    hipLaunchKernelGGL(k_scale_sym, dim3(blocks, nsub), dim3(256), 0, s, d_sub, C, S, T);
     HKG_HIP(hipGetLastError());
     return HKG_OK;
 }

@@ -67,13 +67,17 @@ extern "C" void hkgeneo_destroy(hkgeneo_ctx *c) {
                       &c->sn,     &c->g,      &c->part,    &c->hcol,   &c->scal,    &c->active,     &c->want,
                       &c->rnorm,  &c->npart,  &c->fnorm};
     if (c->s2) (void)hipStreamSynchronize(c->s2);
+    if (c->s3) (void)hipStreamSynchronize(c->s3);
     for (DevBuf *b : bufs) drelease(c, b);
     free_workspace(c);
     for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
     if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     if (c->h_infoL) (void)hipHostFree(c->h_infoL);
+    if (c->ev_fork3) (void)hipEventDestroy(c->ev_fork3);
+    if (c->ev_join3) (void)hipEventDestroy(c->ev_join3);
     if (c->s2) (void)hipStreamDestroy(c->s2);
+    if (c->s3) (void)hipStreamDestroy(c->s3);
     delete c;
 }
 

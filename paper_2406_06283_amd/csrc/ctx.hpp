@@ -30,11 +30,14 @@ struct hkgeneo_ctx {
     hkg::DevBuf B0copy;                   // B_0 kept on the device for queries when m0 <= 2048
     // factorisation workspace (kept between calls when opt.keep_workspace, freed otherwise)
     hkg::DevBuf wDk, wBIO, wCII, wGG, wGI, wS, wW, wPiv, wInfo, wFlag, wD, wE, wTau, wM, wLam, wY, wB0, wLU, wPivL,
-        wJobsZ, wGjobsY, wMisc, wPiv0, wInv, wVWV, wInfoL, wSL, wIv, wLinv, wJobsInv, wT;
+        wJobsZ, wGjobsY, wMisc, wPiv0, wInv, wVWV, wInfoL, wSL, wIv, wLinv, wJobsInv, wT, wPivC, wInfoC, wFlagSpd;
     // the local-inverse pipeline of the factorisation runs on a second stream beside the coarse-space
     // pipeline; its pivot flags come back through pinned host memory
     hipStream_t s2 = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    // a third stream factors C_II while the Gamma block and the Schur complement are formed
+    hipStream_t s3 = nullptr;
+    hipEvent_t ev_fork3 = nullptr, ev_join3 = nullptr;
     int32_t *h_infoL = nullptr;
     int h_infoL_n = 0;
     // apply workspace

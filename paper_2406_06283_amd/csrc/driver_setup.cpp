@@ -62,7 +62,7 @@ void free_workspace(hkgeneo_ctx *c) {
     DevBuf *w[] = {&c->wDk, &c->wBIO, &c->wCII, &c->wGG, &c->wGI, &c->wS, &c->wW, &c->wPiv, &c->wInfo,
                    &c->wFlag, &c->wD, &c->wE, &c->wTau, &c->wM, &c->wLam, &c->wY, &c->wB0, &c->wLU,
                    &c->wPivL, &c->wJobsZ, &c->wGjobsY, &c->wMisc, &c->wPiv0, &c->wInv, &c->wVWV, &c->wInfoL, &c->wSL, &c->wIv,
-                   &c->wLinv, &c->wJobsInv, &c->wT};
+                   &c->wLinv, &c->wJobsInv, &c->wT, &c->wPivC, &c->wInfoC, &c->wFlagSpd};
     for (DevBuf *b : w) drelease(c, b);
 }
 
@@ -323,6 +323,17 @@ int32_t coarse_space(hkgeneo_ctx *c, hipStream_t s) {
     HKG_TRY(walloc(c, &c->wPiv, c->nPiv * sizeof(int32_t)));
     HKG_TRY(walloc(c, &c->wInfo, ns * sizeof(int32_t)));
     HKG_TRY(walloc(c, &c->wFlag, ns * sizeof(int32_t)));
+    HKG_TRY(walloc(c, &c->wPivC, c->nPiv * sizeof(int32_t)));
+    HKG_TRY(walloc(c, &c->wInfoC, ns * sizeof(int32_t)));
+    HKG_TRY(walloc(c, &c->wFlagSpd, ns * sizeof(int32_t)));
+    // C_II = L U without exchanges (positive pivots <=> SPD) on the third stream, concurrently with
+    // the Gamma block's LU and the Schur complement; the flags are read back after the selection
+    HKG_HIP(hipEventRecord(c->ev_fork3, s));
+    HKG_HIP(hipStreamWaitEvent(c->s3, c->ev_fork3, 0));
+    HKG_TRY(lu_batched<double>(dp<DMat>(c->matsSq), dp<int64_t>(c->poffSub), ns, c->max_nI, dp<double>(c->wCII),
+                               dp<int32_t>(c->wPivC), dp<int32_t>(c->wInfoC), false, c->s3));
+    HKG_TRY(check_spd_pivots(dsub, ns, dp<double>(c->wCII), dp<int32_t>(c->wFlagSpd), c->s3));
+    HKG_HIP(hipEventRecord(c->ev_join3, c->s3));
     // B~_GG and its LU
     HKG_HIP(hipMemsetAsync(c->wGG.p, 0, c->wGG.bytes, s));
     HKG_TRY(assemble_gamma(dsub, ns, c->npe, nullptr, dp<int32_t>(c->bandLoc), dp<double>(c->bandK),
@@ -330,12 +341,6 @@ int32_t coarse_space(hkgeneo_ctx *c, hipStream_t s) {
     HKG_TRY(lu_batched<double>(dp<DMat>(c->matsGG), dp<int64_t>(c->poffSub), ns, c->max_nG, dp<double>(c->wGG),
                                dp<int32_t>(c->wPiv), dp<int32_t>(c->wInfo), true, s));
     std::vector<int32_t> flags;
-    HKG_TRY(read_flags(c, c->wInfo, ns, &flags, s));
-    for (int i = 0; i < ns; ++i)
-        if (flags[i]) {
-            set_last_error("the Gamma block of the local Neumann matrix is singular in subdomain " + std::to_string(i));
-            return HKG_EEIG;
-        }
     // X = B~_GG^{-1} B_GI ; S = B_II - B_IG X
     HKG_TRY(gather_gamma_rows(dsub, ns, c->max_nI, dp<double>(c->wBIO), dp<double>(c->wGI), s));
     HKG_TRY(apply_pivots_rows<double>(dsub, ns, c->max_nI, dp<int32_t>(c->wPiv), dp<double>(c->wGI), 0, s));
@@ -346,16 +351,8 @@ int32_t coarse_space(hkgeneo_ctx *c, hipStream_t s) {
     HKG_TRY(copy_bii(dsub, ns, c->max_nI, dp<double>(c->wBIO), dp<double>(c->wS), s));
     HKG_TRY(gemm_batched<double>(dp<GemmJob>(c->gjobsSchur), ns, c->max_nI, c->max_nI, dp<double>(c->wBIO),
                                  dp<double>(c->wGI), dp<double>(c->wS), -1.0, 1.0, false, false, s));
-    // C_II = L U without exchanges (positive pivots <=> SPD); S^ = D^{-1/2} L^{-1} S L^{-T} D^{-1/2}
-    HKG_TRY(lu_batched<double>(dp<DMat>(c->matsSq), dp<int64_t>(c->poffSub), ns, c->max_nI, dp<double>(c->wCII),
-                               dp<int32_t>(c->wPiv), dp<int32_t>(c->wInfo), false, s));
-    HKG_TRY(check_spd_pivots(dsub, ns, dp<double>(c->wCII), dp<int32_t>(c->wFlag), s));
-    HKG_TRY(read_flags(c, c->wFlag, ns, &flags, s));
-    for (int i = 0; i < ns; ++i)
-        if (flags[i]) {
-            set_last_error("C_II is not positive definite in subdomain " + std::to_string(i));
-            return HKG_EEIG;
-        }
+    // S^ = D^{-1/2} L^{-1} S L^{-T} D^{-1/2} once C_II = L U is done
+    HKG_HIP(hipStreamWaitEvent(s, c->ev_join3, 0));
     HKG_TRY(tri_solve_batched<double>(dp<TriJob>(c->jobsSq), ns, c->max_nI, c->max_nI, dp<double>(c->wCII),
                                       dp<double>(c->wS), TRI_LOWER_UNIT, s));
     HKG_TRY(transpose_batched<double>(dp<DMat>(c->matsSq), ns, c->max_nI, dp<double>(c->wS), dp<double>(c->wW), s));
@@ -381,6 +378,19 @@ int32_t coarse_space(hkgeneo_ctx *c, hipStream_t s) {
     HKG_HIP(hipMemcpyAsync(c->m_host.data(), c->wM.p, ns * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HKG_HIP(hipMemcpyAsync(c->lam_host.data(), c->wLam.p, c->lam_host.size() * sizeof(double), hipMemcpyDeviceToHost,
                            s));
+    // the checks deferred to this point, in the order the quantities were computed
+    HKG_TRY(read_flags(c, c->wInfo, ns, &flags, s));
+    for (int i = 0; i < ns; ++i)
+        if (flags[i]) {
+            set_last_error("the Gamma block of the local Neumann matrix is singular in subdomain " + std::to_string(i));
+            return HKG_EEIG;
+        }
+    HKG_TRY(read_flags(c, c->wFlagSpd, ns, &flags, s));
+    for (int i = 0; i < ns; ++i)
+        if (flags[i]) {
+            set_last_error("C_II is not positive definite in subdomain " + std::to_string(i));
+            return HKG_EEIG;
+        }
     HKG_TRY(read_flags(c, c->wFlag, ns, &flags, s));
     for (int i = 0; i < ns; ++i)
         if (flags[i]) {
@@ -496,6 +506,11 @@ int32_t factor(hkgeneo_ctx *c, hipStream_t s) {
         HKG_HIP(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
         HKG_HIP(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
     }
+    if (!c->s3) {
+        HKG_HIP(hipStreamCreateWithFlags(&c->s3, hipStreamNonBlocking));
+        HKG_HIP(hipEventCreateWithFlags(&c->ev_fork3, hipEventDisableTiming));
+        HKG_HIP(hipEventCreateWithFlags(&c->ev_join3, hipEventDisableTiming));
+    }
     if (c->h_infoL_n < ns) {
         if (c->h_infoL) (void)hipHostFree(c->h_infoL);
         c->h_infoL = nullptr;
@@ -537,9 +552,10 @@ int32_t factor(hkgeneo_ctx *c, hipStream_t s) {
     const hipError_t e1 = hipEventRecord(c->ev_join, c->s2);
     const hipError_t e2 = hipStreamWaitEvent(s, c->ev_join, 0);
     const hipError_t e3 = hipStreamSynchronize(s);
+    const hipError_t e4 = hipStreamSynchronize(c->s3);
     HKG_TRY(st);
-    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
-        set_last_error("joining the local-inverse stream");
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess) {
+        set_last_error("joining the side streams of the factorisation");
         return HKG_EHIP;
     }
     for (int i = 0; i < ns; ++i)

@@ -181,6 +181,58 @@ def run_default(args, w, p):
     return out
 
 
+def run_in_flight(w, n_flight: int, steps: int, warmup: int):
+    """Independent problems of the same workload (seeds 0 .. n_flight-1) stepped concurrently, one host
+    thread and one stream each: whole-device throughput when setups and solves of different problems
+    overlap (each problem uses a fraction of the CUs in its latency-bound setup phases)."""
+    import threading
+    import torch
+    from paper_2406_06283_amd import hkgeneo as H
+    res, errs = {}, []
+    bar = threading.Barrier(n_flight)
+
+    def worker(seed):
+        try:
+            st = torch.cuda.Stream()
+            with torch.cuda.stream(st):
+                p = w.problem(seed=seed)
+                f = torch.from_numpy(p.f).to("cuda:0")
+                S = H.Solver(p, H.options_for(w, local_prec=32, keep_workspace=1))
+                B = H.Batch([S], [1])
+                for _ in range(warmup):
+                    S.factor()
+                    B.solve([f])
+                st.synchronize()
+                bar.wait()
+                t0 = time.perf_counter()
+                infos = []
+                for _ in range(steps):
+                    S.factor()
+                    infos.append(B.solve([f])[1][0][0])
+                st.synchronize()
+                res[seed] = (time.perf_counter() - t0, infos)
+                bar.wait()
+                B.close()
+                S.close()
+        except Exception as e:      # reported below
+            errs.append(repr(e))
+            bar.abort()
+
+    th = [threading.Thread(target=worker, args=(sd,)) for sd in range(n_flight)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    if errs or len(res) != n_flight:
+        return {"error": errs[:1]}
+    wall = max(v[0] for v in res.values())
+    infos = [i for v in res.values() for i in v[1]]
+    return {"in_flight": n_flight, "seeds": list(range(n_flight)), "steps_per_problem": steps,
+            "steps_per_s": round(n_flight * steps / wall, 3),
+            "converged": all(i["converged"] and i["relres_true"] <= 1e-8 for i in infos),
+            "iters": [int(v[1][0]["iters"]) for _, v in sorted(res.items())]}
+
+
 def run_cpu_baseline(w, p, sample: int):
     from oracle import fgmres, local, schwarz
     try:
@@ -247,6 +299,8 @@ def main_default(args):
         "solve_only": {"p50_ms": round(pct(mx["lat"], 50), 3), "p99_ms": round(pct(mx["lat"], 99), 3),
                        "solves_per_s": round(1e3 / np.mean(mx["lat"]), 2)},
         "unprofiled_graph_replay": summary(mx, args.steps),
+        "independent_problems_in_flight": run_in_flight(w, args.in_flight, args.steps, args.warmup)
+        if args.in_flight > 1 else None,
         "fp64_batched": summary(f64, args.steps) if f64 else None,
         "fp64_plain": summary(plain, args.steps) if plain else None,
         "roofline": {"kernel": "k_b_local<%d> (float32 inverses)" % rp["waves"], "bound": "hbm",
@@ -399,10 +453,12 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="after the run, one elementwise copy of BYTES for hardware-counter calibration")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--in-flight", type=int, default=3,
+                    help="independent problems stepped concurrently for the extra throughput field (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU: the path is a single-device kernel set; "
-                                   "independent problems shard across GPUs without communication, see DESIGN.md",
+                                   "independent problems shard across GPUs without communication",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
     if args.workload == "mix64":

@@ -28,6 +28,8 @@ struct hkgeneo_ctx {
     // numeric results (factorisation phase)
     hkg::DevBuf Bval, Minv, Z, Zr, B0inv;
     hkg::DevBuf B0copy;                   // B_0 kept on the device for queries when m0 <= 2048
+    int b0_band = -1;                     // half-bandwidth of B_0 used by its LU (-1: dense)
+    int band_I = -1;                      // half-bandwidth of B[I, I] and C_II (-1: treated as dense)
     // factorisation workspace (kept between calls when opt.keep_workspace, freed otherwise)
     hkg::DevBuf wDk, wBIO, wCII, wGG, wGI, wS, wW, wPiv, wInfo, wFlag, wD, wE, wTau, wM, wLam, wY, wB0, wLU, wPivL,
         wJobsZ, wGjobsY, wMisc, wPiv0, wInv, wVWV, wInfoL, wSL, wIv, wLinv, wJobsInv, wT, wPivC, wInfoC, wFlagSpd;

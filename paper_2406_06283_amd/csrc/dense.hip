@@ -123,16 +123,17 @@ __global__ __launch_bounds__(256) void k_lu_panel(const DMat *__restrict__ mats,
 // rank-1 update of column j (wave arg-max by DPP lane moves, ties to the smallest row, as in the
 // global-memory panel); after the barrier every wave reduces the 16 wave candidates within one DPP row, the
 // owners of the pivot row and of row j publish them in LDS, and after the second barrier the rows
-// are exchanged and the next update is applied.
+// are exchanged and the next update is applied.  NT threads (a multiple of 64, at most 1024) cover
+// the panel rows j0 .. min(n, mlim) - 1; rows from mlim on are known to be zero in the panel columns
+// (a banded matrix) and are left alone.
 constexpr int PANEL_REG_ROWS = 1024;
 
 
-template <typename T>
-__global__ __launch_bounds__(PANEL_REG_ROWS) void k_lu_panel_reg(const DMat *__restrict__ mats,
-                                                                 const int64_t *__restrict__ poff, T *__restrict__ Ab,
-                                                                 int32_t *__restrict__ piv, int32_t *__restrict__ info,
-                                                                 int j0, int pivot) {
-    constexpr int NW = PANEL_REG_ROWS / 64;
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_lu_panel_reg(const DMat *__restrict__ mats, const int64_t *__restrict__ poff,
+                                                     T *__restrict__ Ab, int32_t *__restrict__ piv,
+                                                     int32_t *__restrict__ info, int j0, int pivot, int mlim) {
+    constexpr int NW = NT / 64;
     const DMat m = mats[blockIdx.x];
     const int n = m.n;
     if (j0 >= n) return;
@@ -141,7 +142,7 @@ __global__ __launch_bounds__(PANEL_REG_ROWS) void k_lu_panel_reg(const DMat *__r
     const int nb = min(j0 + LU_NB, n) - j0;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int r = j0 + tid;
-    const bool own = r < n;
+    const bool own = r < min(n, mlim);
     __shared__ T prow[2][LU_NB];
     __shared__ T drow[2][LU_NB];
     __shared__ T wval[2][NW];
@@ -266,9 +267,10 @@ __device__ __forceinline__ void solve_block_lds(T (*Ls)[LU_NB + 1], T (*xs)[TRI_
 
 // U12 = L11^{-1} A12 for the panel rows (the block is padded to LU_NB with the identity)
 template <typename T>
-__global__ __launch_bounds__(TRI_COLS) void k_lu_trsm_row(const DMat *__restrict__ mats, T *__restrict__ Ab, int j0) {
+__global__ __launch_bounds__(TRI_COLS) void k_lu_trsm_row(const DMat *__restrict__ mats, T *__restrict__ Ab, int j0,
+                                                          int clim) {
     const DMat m = mats[blockIdx.y];
-    const int n = m.n;
+    const int n = min(m.n, clim);          // columns from clim on are zero in the panel rows
     const int jend = min(j0 + LU_NB, n);
     if (jend >= n) return;
     __shared__ T L[LU_NB][LU_NB + 1];
@@ -288,33 +290,46 @@ __global__ __launch_bounds__(TRI_COLS) void k_lu_trsm_row(const DMat *__restrict
         for (int r = 0; r < nb; ++r) A[j0 + r + (int64_t)c * ld] = xs[r][threadIdx.x];
 }
 
-// A22 -= L21 U12
+// A22 -= L21 U12 on rows [jend, rlim) and columns [jend, clim) (both limits capped at n)
 template <typename T>
 __global__ __launch_bounds__(256) void k_lu_update(const DMat *__restrict__ mats, T *__restrict__ Ab, int j0,
-                                                   int tiles_m_max) {
+                                                   int tiles_m_max, int rlim, int clim) {
     const DMat m = mats[blockIdx.y];
     const int n = m.n;
     const int jend = min(j0 + LU_NB, n);
-    const int rem = n - jend;
-    if (rem <= 0) return;
+    const int rows = min(n, rlim) - jend, cols = min(n, clim) - jend;
+    if (rows <= 0 || cols <= 0) return;
     const int tm = blockIdx.x % tiles_m_max, tn = blockIdx.x / tiles_m_max;
-    if (tm * GT >= rem || tn * GT >= rem) return;
+    if (tm * GT >= rows || tn * GT >= cols) return;
     T *A = Ab + m.off;
     const int ld = m.ld;
-    gemm_tile<T>(rem, rem, jend - j0, A + jend + (int64_t)j0 * ld, ld, false, A + j0 + (int64_t)jend * ld, ld, false,
+    gemm_tile<T>(rows, cols, jend - j0, A + jend + (int64_t)j0 * ld, ld, false, A + j0 + (int64_t)jend * ld, ld, false,
                  A + jend + (int64_t)jend * ld, ld, T(-1), T(1), tm, tn);
 }
 
 template <typename T>
 int32_t lu_batched(const DMat *d_mats, const int64_t *d_poff, int nbatch, int maxn, T *A, int32_t *piv,
-                   int32_t *info, bool pivot, hipStream_t s) {
+                   int32_t *info, bool pivot, hipStream_t s, int band) {
     if (nbatch == 0) return HKG_OK;
     HKG_HIP(hipMemsetAsync(info, 0, sizeof(int32_t) * nbatch, s));
     if (maxn == 0) return HKG_OK;
+    // a band of half-width `band` (band < 0: dense): column j has no entry below row j + band, and
+    // with row exchanges the rows of a panel reach at most 2 band columns past their diagonal
+    const bool banded = band >= 0;
     for (int j0 = 0; j0 < maxn; j0 += LU_NB) {
-        if (maxn - j0 <= PANEL_REG_ROWS)
-            hipLaunchKernelGGL(k_lu_panel_reg<T>, dim3(nbatch), dim3(PANEL_REG_ROWS), 0, s, d_mats, d_poff, A, piv, info,
-                               j0, (int)pivot);
+        const int jend = std::min(j0 + LU_NB, maxn);
+        const int mlim = banded ? std::min(maxn, jend + band) : maxn;           // panel rows end
+        const int clim = banded ? std::min(maxn, jend + 2 * band) : maxn;       // columns reached
+        const int rows = mlim - j0;
+        if (rows <= 256)
+            hipLaunchKernelGGL((k_lu_panel_reg<T, 256>), dim3(nbatch), dim3(256), 0, s, d_mats, d_poff, A, piv, info, j0,
+                               (int)pivot, mlim);
+        else if (rows <= 512)
+            hipLaunchKernelGGL((k_lu_panel_reg<T, 512>), dim3(nbatch), dim3(512), 0, s, d_mats, d_poff, A, piv, info, j0,
+                               (int)pivot, mlim);
+        else if (rows <= PANEL_REG_ROWS)
+            hipLaunchKernelGGL((k_lu_panel_reg<T, PANEL_REG_ROWS>), dim3(nbatch), dim3(PANEL_REG_ROWS), 0, s, d_mats,
+                               d_poff, A, piv, info, j0, (int)pivot, mlim);
         else
             hipLaunchKernelGGL(k_lu_panel<T>, dim3(nbatch), dim3(256), 0, s, d_mats, d_poff, A, piv, info, j0,
                                (int)pivot);
@@ -323,21 +338,24 @@ int32_t lu_batched(const DMat *d_mats, const int64_t *d_poff, int nbatch, int ma
             hipLaunchKernelGGL(k_lu_laswp<T>, dim3((outside + 255) / 256, nbatch), dim3(256), 0, s, d_mats, d_poff, A,
                                piv, j0);
         }
-        int rem = maxn - j0 - LU_NB;
-        if (rem > 0) {
-            hipLaunchKernelGGL(k_lu_trsm_row<T>, dim3((rem + TRI_COLS - 1) / TRI_COLS, nbatch), dim3(TRI_COLS), 0, s,
-                               d_mats, A, j0);
-            int tiles = (rem + GT - 1) / GT;
-            hipLaunchKernelGGL(k_lu_update<T>, dim3(tiles * tiles, nbatch), dim3(256), 0, s, d_mats, A, j0, tiles);
+        const int ccols = clim - jend, crows = mlim - jend;
+        if (ccols > 0) {
+            hipLaunchKernelGGL(k_lu_trsm_row<T>, dim3((ccols + TRI_COLS - 1) / TRI_COLS, nbatch), dim3(TRI_COLS), 0, s,
+                               d_mats, A, j0, clim);
+            if (crows > 0) {
+                const int tm = (crows + GT - 1) / GT, tn = (ccols + GT - 1) / GT;
+                hipLaunchKernelGGL(k_lu_update<T>, dim3(tm * tn, nbatch), dim3(256), 0, s, d_mats, A, j0, tm, mlim,
+                                   clim);
+            }
         }
     }
     HKG_HIP(hipGetLastError());
     return HKG_OK;
 }
 template int32_t lu_batched<double>(const DMat *, const int64_t *, int, int, double *, int32_t *, int32_t *, bool,
-                                    hipStream_t);
+                                    hipStream_t, int);
 template int32_t lu_batched<float>(const DMat *, const int64_t *, int, int, float *, int32_t *, int32_t *, bool,
-                                   hipStream_t);
+                                   hipStream_t, int);
 
 // ------------------------------------------------------------------------------------------------
 // Blocked triangular solves op(T) X = X with many right-hand sides (T n x n, X n x ncol):
@@ -376,39 +394,43 @@ __global__ __launch_bounds__(TRI_COLS) void k_tri_diag(const TriJob *__restrict_
 
 template <typename T, int MODE>
 __global__ __launch_bounds__(256) void k_tri_update(const TriJob *__restrict__ jobs, const T *__restrict__ Tb,
-                                                    T *__restrict__ Xb, int k0, int tiles_m_max) {
+                                                    T *__restrict__ Xb, int k0, int tiles_m_max, int band) {
     const TriJob J = jobs[blockIdx.y];
     if (k0 >= J.n) return;
     const int k1 = min(k0 + LU_NB, J.n);
     const T *Tm = Tb + J.offT;
     T *X = Xb + J.offX;
     const int tm = blockIdx.x % tiles_m_max, tn = blockIdx.x / tiles_m_max;
+    // band >= 0: op(T) has no entry farther than `band` from the diagonal, so only that many rows
+    // next to the block are updated
     if (MODE == TRI_LOWER_UNIT) {
         // rows below: X[k1:, :] -= T[k1:, k0:k1] X[k0:k1, :]
-        int M = J.n - k1;
+        const int r1 = band >= 0 ? min(J.n, k1 + band) : J.n;
+        int M = r1 - k1;
         if (M <= 0 || tm * GT >= M || tn * GT >= J.ncol) return;
         gemm_tile<T>(M, J.ncol, k1 - k0, Tm + k1 + (int64_t)k0 * J.ldT, J.ldT, false, X + k0, J.ldX, false, X + k1,
                      J.ldX, T(-1), T(1), tm, tn);
-    } else if (MODE == TRI_UPPER) {
-        // rows above: X[:k0, :] -= T[:k0, k0:k1] X[k0:k1, :]
-        int M = k0;
-        if (M <= 0 || tm * GT >= M || tn * GT >= J.ncol) return;
-        gemm_tile<T>(M, J.ncol, k1 - k0, Tm + (int64_t)k0 * J.ldT, J.ldT, false, X + k0, J.ldX, false, X, J.ldX, T(-1),
-                     T(1), tm, tn);
     } else {
-        // rows above: X[:k0, :] -= (T[k0:k1, :k0])^T X[k0:k1, :]
-        int M = k0;
+        // rows above: X[r0:k0, :] -= op(T)[r0:k0, k0:k1] X[k0:k1, :]
+        const int r0 = band >= 0 ? max(0, k0 - band) : 0;
+        int M = k0 - r0;
         if (M <= 0 || tm * GT >= M || tn * GT >= J.ncol) return;
-        gemm_tile<T>(M, J.ncol, k1 - k0, Tm + k0, J.ldT, true, X + k0, J.ldX, false, X, J.ldX, T(-1), T(1), tm, tn);
+        if (MODE == TRI_UPPER)
+            gemm_tile<T>(M, J.ncol, k1 - k0, Tm + r0 + (int64_t)k0 * J.ldT, J.ldT, false, X + k0, J.ldX, false, X + r0,
+                         J.ldX, T(-1), T(1), tm, tn);
+        else
+            gemm_tile<T>(M, J.ncol, k1 - k0, Tm + k0 + (int64_t)r0 * J.ldT, J.ldT, true, X + k0, J.ldX, false, X + r0,
+                         J.ldX, T(-1), T(1), tm, tn);
     }
 }
 
 template <typename T>
 int32_t tri_solve_batched(const TriJob *d_jobs, int nbatch, int maxn, int maxcol, const T *Tm, T *X, int mode,
-                          hipStream_t s) {
+                          hipStream_t s, int band) {
     if (nbatch == 0 || maxn == 0 || maxcol == 0) return HKG_OK;
     const int nblk = (maxn + LU_NB - 1) / LU_NB;
-    const int tiles_m = (maxn + GT - 1) / GT, tiles_n = (maxcol + GT - 1) / GT;
+    const int urows = band >= 0 ? std::min(maxn, band) : maxn;      // rows of one update at most
+    const int tiles_m = (urows + GT - 1) / GT, tiles_n = (maxcol + GT - 1) / GT;
     const dim3 gd((maxcol + TRI_COLS - 1) / TRI_COLS, nbatch), gu(tiles_m * tiles_n, nbatch);
     for (int b = 0; b < nblk; ++b) {
         // block boundaries sit at multiples of LU_NB in every matrix, so one k0 serves the whole
@@ -417,24 +439,25 @@ int32_t tri_solve_batched(const TriJob *d_jobs, int nbatch, int maxn, int maxcol
         if (mode == TRI_LOWER_UNIT) {
             int k0 = b * LU_NB;
             hipLaunchKernelGGL((k_tri_diag<T, TRI_LOWER_UNIT>), gd, dim3(TRI_COLS), 0, s, d_jobs, Tm, X, k0);
-            hipLaunchKernelGGL((k_tri_update<T, TRI_LOWER_UNIT>), gu, dim3(256), 0, s, d_jobs, Tm, X, k0, tiles_m);
+            hipLaunchKernelGGL((k_tri_update<T, TRI_LOWER_UNIT>), gu, dim3(256), 0, s, d_jobs, Tm, X, k0, tiles_m, band);
         } else {
             int k0 = (nblk - 1 - b) * LU_NB;
             if (mode == TRI_UPPER) {
                 hipLaunchKernelGGL((k_tri_diag<T, TRI_UPPER>), gd, dim3(TRI_COLS), 0, s, d_jobs, Tm, X, k0);
-                hipLaunchKernelGGL((k_tri_update<T, TRI_UPPER>), gu, dim3(256), 0, s, d_jobs, Tm, X, k0, tiles_m);
+                hipLaunchKernelGGL((k_tri_update<T, TRI_UPPER>), gu, dim3(256), 0, s, d_jobs, Tm, X, k0, tiles_m, band);
             } else {
                 hipLaunchKernelGGL((k_tri_diag<T, TRI_LOWER_UNIT_TRANS>), gd, dim3(TRI_COLS), 0, s, d_jobs, Tm, X, k0);
                 hipLaunchKernelGGL((k_tri_update<T, TRI_LOWER_UNIT_TRANS>), gu, dim3(256), 0, s, d_jobs, Tm, X, k0,
-                                   tiles_m);
+                                   tiles_m, band);
             }
         }
     }
     HKG_HIP(hipGetLastError());
     return HKG_OK;
 }
-template int32_t tri_solve_batched<double>(const TriJob *, int, int, int, const double *, double *, int, hipStream_t);
-template int32_t tri_solve_batched<float>(const TriJob *, int, int, int, const float *, float *, int, hipStream_t);
+template int32_t tri_solve_batched<double>(const TriJob *, int, int, int, const double *, double *, int, hipStream_t,
+                                           int);
+template int32_t tri_solve_batched<float>(const TriJob *, int, int, int, const float *, float *, int, hipStream_t, int);
 
 // ------------------------------------------------------------------------------------------------
 // Inverse of one packed LU (P A = L U) by recursive block triangular inversion: the LU_NB diagonal

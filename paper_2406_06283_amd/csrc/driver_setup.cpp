@@ -112,6 +112,25 @@ int32_t analyze(hkgeneo_ctx *c, const hkgeneo_problem *p, hipStream_t s, int32_t
     std::vector<double> winv(c->n_dof), wloc(c->sum_nI);
     for (int d = 0; d < c->n_dof; ++d) winv[d] = 1.0 / (double)P.mu[d];
     for (int64_t t = 0; t < c->sum_nI; ++t) wloc[t] = (c->opt.prolong == HKG_PROLONG_POU) ? winv[P.I_idx[t]] : 1.0;
+    // half-bandwidth of the local matrices B[I, I] and C_II in the ascending dof order of each
+    // subdomain (the same sparsity as the global operator): their LUs and triangular solves
+    // touch only that band (and the fill of row exchanges)
+    {
+        std::vector<int32_t> loc(c->n_dof, -1);
+        int band = 0;
+        for (int i = 0; i < ns; ++i) {
+            for (int64_t t = P.offI[i]; t < P.offI[i + 1]; ++t) loc[P.I_idx[t]] = (int32_t)(t - P.offI[i]);
+            for (int64_t t = P.offI[i]; t < P.offI[i + 1]; ++t) {
+                const int g = P.I_idx[t], lg = (int)(t - P.offI[i]);
+                for (int32_t q = p->row_ptr[g]; q < p->row_ptr[g + 1]; ++q) {
+                    const int h = loc[p->col_idx[q]];
+                    if (h >= 0) band = std::max(band, std::abs(h - lg));
+                }
+            }
+            for (int64_t t = P.offI[i]; t < P.offI[i + 1]; ++t) loc[P.I_idx[t]] = -1;
+        }
+        c->band_I = (3 * band + LU_BLOCK < c->max_nI) ? band : -1;
+    }
     HKG_TRY(upload(c, &c->rowptr, p->row_ptr, c->n_dof + 1, s));
     HKG_TRY(upload(c, &c->colidx, p->col_idx, c->nnz, s));
     HKG_TRY(upload(c, &c->Aval, p->A_val, c->nnz, s));
@@ -217,13 +236,16 @@ int32_t local_inverses(hkgeneo_ctx *c, T *out, hipStream_t s) {
     if (sizeof(T) == 8) HKG_TRY(copy_bii(dsub, ns, c->max_nI, dp<double>(c->wBIO), (double *)c->wLU.p, s));
     else HKG_TRY(copy_bii_f32(dsub, ns, c->max_nI, dp<double>(c->wBIO), (float *)c->wLU.p, s));
     HKG_TRY(lu_batched<T>(dp<DMat>(c->matsSq), dp<int64_t>(c->poffLoc), ns, c->max_nI, dp<T>(c->wLU),
-                          dp<int32_t>(c->wPivL), dp<int32_t>(c->wInfoL), true, s));
+                          dp<int32_t>(c->wPivL), dp<int32_t>(c->wInfoL), true, s, c->band_I));
     HKG_HIP(hipMemcpyAsync(c->h_infoL, c->wInfoL.p, ns * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HKG_TRY(perm_identity_batched<T>(dp<DMat>(c->matsM), dp<int64_t>(c->poffLoc), ns, c->max_nI,
                                      dp<int32_t>(c->wPivL), out, s));
     HKG_TRY(tri_solve_batched<T>(dp<TriJob>(c->jobsM), ns, c->max_nI, c->max_nI, dp<T>(c->wLU), out, TRI_LOWER_UNIT,
                                  s));
-    HKG_TRY(tri_solve_batched<T>(dp<TriJob>(c->jobsM), ns, c->max_nI, c->max_nI, dp<T>(c->wLU), out, TRI_UPPER, s));
+    // U of a banded LU with row exchanges has half-bandwidth 2 band (L, with the exchanges applied to
+    // its earlier columns, is not banded)
+    HKG_TRY(tri_solve_batched<T>(dp<TriJob>(c->jobsM), ns, c->max_nI, c->max_nI, dp<T>(c->wLU), out, TRI_UPPER, s,
+                                 c->band_I >= 0 ? 2 * c->band_I : -1));
     return HKG_OK;
 }
 
@@ -328,12 +350,28 @@ int32_t coarse_space(hkgeneo_ctx *c, hipStream_t s) {
     HKG_TRY(walloc(c, &c->wFlagSpd, ns * sizeof(int32_t)));
     // C_II = L U without exchanges (positive pivots <=> SPD) on the third stream, concurrently with
     // the Gamma block's LU and the Schur complement; the flags are read back after the selection
+    // (enqueued by a helper thread, so that this thread's launches for the Gamma block start at once)
     HKG_HIP(hipEventRecord(c->ev_fork3, s));
     HKG_HIP(hipStreamWaitEvent(c->s3, c->ev_fork3, 0));
-    HKG_TRY(lu_batched<double>(dp<DMat>(c->matsSq), dp<int64_t>(c->poffSub), ns, c->max_nI, dp<double>(c->wCII),
-                               dp<int32_t>(c->wPivC), dp<int32_t>(c->wInfoC), false, c->s3));
-    HKG_TRY(check_spd_pivots(dsub, ns, dp<double>(c->wCII), dp<int32_t>(c->wFlagSpd), c->s3));
-    HKG_HIP(hipEventRecord(c->ev_join3, c->s3));
+    int32_t st_cii = HKG_OK;
+    std::string err_cii;
+    std::thread enq_cii([&]() {
+        st_cii = lu_batched<double>(dp<DMat>(c->matsSq), dp<int64_t>(c->poffSub), ns, c->max_nI, dp<double>(c->wCII),
+                                    dp<int32_t>(c->wPivC), dp<int32_t>(c->wInfoC), false, c->s3, c->band_I);
+        if (st_cii == HKG_OK) st_cii = check_spd_pivots(dsub, ns, dp<double>(c->wCII), dp<int32_t>(c->wFlagSpd), c->s3);
+        if (st_cii == HKG_OK && hipEventRecord(c->ev_join3, c->s3) != hipSuccess) {
+            set_last_error("recording the end of the C_II factorisation");
+            st_cii = HKG_EHIP;
+        }
+        if (st_cii != HKG_OK) err_cii = g_last_error;
+    });
+    // joined (and its status checked) before anything waits on its event
+    struct Joiner {
+        std::thread &t;
+        ~Joiner() {
+            if (t.joinable()) t.join();
+        }
+    } join_cii{enq_cii};
     // B~_GG and its LU
     HKG_HIP(hipMemsetAsync(c->wGG.p, 0, c->wGG.bytes, s));
     HKG_TRY(assemble_gamma(dsub, ns, c->npe, nullptr, dp<int32_t>(c->bandLoc), dp<double>(c->bandK),
@@ -352,12 +390,17 @@ int32_t coarse_space(hkgeneo_ctx *c, hipStream_t s) {
     HKG_TRY(gemm_batched<double>(dp<GemmJob>(c->gjobsSchur), ns, c->max_nI, c->max_nI, dp<double>(c->wBIO),
                                  dp<double>(c->wGI), dp<double>(c->wS), -1.0, 1.0, false, false, s));
     // S^ = D^{-1/2} L^{-1} S L^{-T} D^{-1/2} once C_II = L U is done
+    enq_cii.join();
+    if (st_cii != HKG_OK) {
+        set_last_error(err_cii);
+        return st_cii;
+    }
     HKG_HIP(hipStreamWaitEvent(s, c->ev_join3, 0));
     HKG_TRY(tri_solve_batched<double>(dp<TriJob>(c->jobsSq), ns, c->max_nI, c->max_nI, dp<double>(c->wCII),
-                                      dp<double>(c->wS), TRI_LOWER_UNIT, s));
+                                      dp<double>(c->wS), TRI_LOWER_UNIT, s, c->band_I));
     HKG_TRY(transpose_batched<double>(dp<DMat>(c->matsSq), ns, c->max_nI, dp<double>(c->wS), dp<double>(c->wW), s));
     HKG_TRY(tri_solve_batched<double>(dp<TriJob>(c->jobsSq), ns, c->max_nI, c->max_nI, dp<double>(c->wCII),
-                                      dp<double>(c->wW), TRI_LOWER_UNIT, s));
+                                      dp<double>(c->wW), TRI_LOWER_UNIT, s, c->band_I));
     HKG_TRY(walloc(c, &c->wT, (size_t)c->nM * sizeof(double)));
     HKG_TRY(scale_sym(dsub, ns, c->max_nI, dp<double>(c->wCII), dp<double>(c->wW), dp<double>(c->wT), s));
     // tridiagonal form and selection
@@ -445,7 +488,7 @@ int32_t coarse_space(hkgeneo_ctx *c, hipStream_t s) {
         HKG_TRY(upload(c, &c->wJobsZ, hj.data(), ns, s, true));
         HKG_TRY(upload(c, &c->wGjobsY, hg.data(), ns, s, true));
         HKG_TRY(tri_solve_batched<double>(dp<TriJob>(c->wJobsZ), ns, c->max_nI, c->max_m, dp<double>(c->wCII),
-                                          dp<double>(c->Z), TRI_LOWER_UNIT_TRANS, s));
+                                          dp<double>(c->Z), TRI_LOWER_UNIT_TRANS, s, c->band_I));
         HKG_TRY(finish_basis(dsub, ns, dp<int32_t>(c->I_idx), dp<double>(c->winv), dp<double>(c->Z), s));
         if (c->Zr.bytes != (size_t)offZ * sizeof(double)) HKG_TRY(dalloc(c, &c->Zr, offZ * sizeof(double)));
         HKG_TRY(transpose_basis(dsub, ns, dp<double>(c->Z), dp<double>(c->Zr), s));
@@ -484,8 +527,18 @@ int32_t coarse_space(hkgeneo_ctx *c, hipStream_t s) {
     const int64_t *dpo = reinterpret_cast<const int64_t *>((uint8_t *)c->wMisc.p + sizeof(DMat));
     const TriJob *dj = reinterpret_cast<const TriJob *>((uint8_t *)c->wMisc.p + sizeof(DMat) + sizeof(int64_t));
     HKG_TRY(walloc(c, &c->wPiv0, m0 * sizeof(int32_t)));
+    // B_0 couples only overlapping subdomains: its half-bandwidth in the subdomain ordering bounds
+    // the rows and columns each panel of the LU touches (dense when the band is not narrow)
+    int band = 0;
+    for (size_t t = 0; t < CP.pi.size(); ++t) {
+        const SubDev &a = c->subs[CP.pi[t]], &b = c->subs[CP.pj[t]];
+        if (a.m == 0 || b.m == 0) continue;
+        band = std::max(band, std::max(a.offm + a.m - 1 - b.offm, b.offm + b.m - 1 - a.offm));
+    }
+    if (3 * band + LU_BLOCK >= m0) band = -1;
+    c->b0_band = band;
     HKG_TRY(lu_batched<double>(dm, dpo, 1, m0, dp<double>(c->wB0), dp<int32_t>(c->wPiv0), dp<int32_t>(c->wInfo), true,
-                               s));
+                               s, band));
     HKG_TRY(read_flags(c, c->wInfo, 1, &flags, s));
     if (flags[0]) {
         set_last_error("zero pivot in the coarse matrix B_0");

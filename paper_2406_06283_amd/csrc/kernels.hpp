@@ -12,11 +12,14 @@ template <typename T>
 int32_t gemm_batched(const GemmJob *d_jobs, int nbatch, int maxM, int maxN, const T *A, const T *B, T *C, T alpha,
                      T beta, bool ta, bool tb, hipStream_t s);
 template <typename T>
+// P A = L U of every matrix (partial pivoting if `pivot`); band >= 0: the matrices are banded with that
+// half-width, and the work is restricted to the band and the fill of the row exchanges
 int32_t lu_batched(const DMat *d_mats, const int64_t *d_poff, int nbatch, int maxn, T *A, int32_t *piv,
-                   int32_t *info, bool pivot, hipStream_t s);
+                   int32_t *info, bool pivot, hipStream_t s, int band = -1);
 template <typename T>
+// band >= 0: op(T) has no entry farther than `band` from the diagonal
 int32_t tri_solve_batched(const TriJob *d_jobs, int nbatch, int maxn, int maxcol, const T *Tm, T *X, int mode,
-                          hipStream_t s);
+                          hipStream_t s, int band = -1);
 constexpr int LU_BLOCK = 32;    // block size of the dense LU, triangular solves and inversions
 
 // diagonal LU_BLOCK blocks of L^{-1} (unit lower) and U^{-1} of one packed LU, into Linv / Uinv

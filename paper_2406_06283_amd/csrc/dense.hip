@@ -537,6 +537,146 @@ int32_t gather_pivot_columns(int n, const double *X, int ldx, const int32_t *piv
 }
 
 // ------------------------------------------------------------------------------------------------
+// A^{-1} from one packed LU (P A = L U, leading dimension ld), column by column: column j of A^{-1}
+// solves L U x = P e_j.  The columns are independent, so each block takes INV_CB of them and runs
+// both triangular sweeps itself with its vectors in LDS; the whole inverse is one launch (no
+// sequence of block steps across the grid).  A sweep goes by blocks of LU_NB rows: the block's rows
+// subtract the product with the part already solved (one thread per row and column, reading the
+// factor from L2), then are multiplied by the inverse of the diagonal block (from tri_diag_inverse,
+// at (i0, i0) of Dinv with leading dimension ldd).
+// ------------------------------------------------------------------------------------------------
+constexpr int INV_CB = 8;         // right-hand sides per block
+constexpr int INV_NT = 1024;      // threads: LU_NB rows x INV_KQ groups of the summation index
+constexpr int INV_KQ = INV_NT / LU_NB;
+
+// acc(r, c) over k in [ka, kb) for every column c: thread (r, q) sums k = ka + q, ka + q + INV_KQ, ...
+// (eight loads in flight), then the INV_KQ partial sums of each (r, c) are added in q order
+__device__ __forceinline__ void inv_partial(const double *__restrict__ LU, int ld, int i0, int nb, int ka, int kb,
+                                            const double *ys, double *part, int tid) {
+    const int r = tid % LU_NB, q = tid / LU_NB;
+
+    double acc[INV_CB];
+#pragma unroll
+    for (int c = 0; c < INV_CB; ++c) acc[c] = 0.0;
+    const double *rp = LU + i0 + min(r, nb - 1);     // rows past the block's end repeat its last
+    for (int k0 = ka + q; k0 < kb; k0 += 8 * INV_KQ) {
+        double a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = rp[(int64_t)min(k0 + u * INV_KQ, kb - 1) * ld];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int k = k0 + u * INV_KQ;
+            if (k < kb) {
+#pragma unroll
+                for (int c = 0; c < INV_CB; ++c) acc[c] = fma(a[u], ys[k * INV_CB + c], acc[c]);
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < INV_CB; ++c) part[(q * LU_NB + r) * INV_CB + c] = acc[c];
+}
+
+// y_B = Dinv_BB (y_B - acc): the partial sums are added, then the block is multiplied by the
+// inverted diagonal block
+__device__ __forceinline__ void inv_block_step(const double *__restrict__ Dinv, int ldd, int i0, int nb, double *ys,
+                                               const double *part, double (*Ts)[LU_NB + 1], double (*tb)[INV_CB],
+                                               int tid) {
+    for (int e = tid; e < LU_NB * LU_NB; e += INV_NT) {
+        const int rr = e % LU_NB, cc = e / LU_NB;
+        Ts[rr][cc] = (rr < nb && cc < nb) ? Dinv[i0 + rr + (int64_t)(i0 + cc) * ldd] : 0.0;
+    }
+    __syncthreads();
+    if (tid < LU_NB * INV_CB) {
+        const int r = tid / INV_CB, c = tid % INV_CB;
+        double acc = 0.0;
+        for (int q = 0; q < INV_KQ; ++q) acc += part[(q * LU_NB + r) * INV_CB + c];
+        tb[r][c] = r < nb ? ys[(i0 + r) * INV_CB + c] - acc : 0.0;
+    }
+    __syncthreads();
+    if (tid < LU_NB * INV_CB) {
+        const int r = tid / INV_CB, c = tid % INV_CB;
+        if (r < nb) {
+            double v = 0.0;
+#pragma unroll 8
+            for (int kk = 0; kk < LU_NB; ++kk) v = fma(Ts[r][kk], tb[kk][c], v);
+            ys[(i0 + r) * INV_CB + c] = v;
+        }
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(INV_NT) void k_lu_inverse_cols(const double *__restrict__ LU, int n, int ld,
+                                                            const int32_t *__restrict__ piv,
+                                                            const double *__restrict__ Linv,
+                                                            const double *__restrict__ Uinv, int ldd,
+                                                            double *__restrict__ X, int ldx, int uband) {
+    extern __shared__ double sh[];
+    double *ys = sh;                               // n x INV_CB, entry (i, c) at i * INV_CB + c
+    double *part = sh + (int64_t)n * INV_CB;       // INV_KQ x LU_NB x INV_CB partial sums
+    __shared__ double Ts[LU_NB][LU_NB + 1];        // inverse of the current diagonal block
+    __shared__ double tb[LU_NB][INV_CB];
+    __shared__ int tstart[INV_CB];
+    __shared__ int tmin;
+    const int tid = threadIdx.x;
+    const int c0 = blockIdx.x * INV_CB;
+    // P e_j = e_t: follow index j through the exchanges in order
+    if (tid < INV_CB) {
+        int t = c0 + tid;
+        if (t < n) {
+            for (int k = 0; k < n; ++k) {
+                const int p = piv[k];
+                if (t == k) t = p;
+                else if (t == p) t = k;
+            }
+        }
+        tstart[tid] = t;
+    }
+    for (int q = tid; q < n * INV_CB; q += INV_NT) ys[q] = 0.0;
+    __syncthreads();
+    if (tid < INV_CB && c0 + tid < n) ys[tstart[tid] * INV_CB + tid] = 1.0;
+    if (tid == 0) {
+        int t = n;
+        for (int c = 0; c < INV_CB; ++c)
+            if (c0 + c < n) t = min(t, tstart[c]);
+        tmin = t;
+    }
+    __syncthreads();
+    const int nblk = (n + LU_NB - 1) / LU_NB;
+    // forward sweep, L unit lower: y_B = L_BB^{-1} (y_B - L[B, :i0] y[:i0]); the blocks above the
+    // first nonzero start entry stay zero
+    const int bfirst = tmin / LU_NB;
+    for (int b = bfirst; b < nblk; ++b) {
+        const int i0 = b * LU_NB, nb = min(LU_NB, n - i0);
+        inv_partial(LU, ld, i0, nb, bfirst * LU_NB, i0, ys, part, tid);
+        inv_block_step(Linv, ldd, i0, nb, ys, part, Ts, tb, tid);
+    }
+    // backward sweep, U upper: x_B = U_BB^{-1} (y_B - U[B, i1:] x[i1:]); U has no entry farther
+    // than uband from the diagonal when uband >= 0
+    for (int b = nblk - 1; b >= 0; --b) {
+        const int i0 = b * LU_NB, nb = min(LU_NB, n - i0), i1 = i0 + nb;
+        inv_partial(LU, ld, i0, nb, i1, uband >= 0 ? min(n, i1 + uband) : n, ys, part, tid);
+        inv_block_step(Uinv, ldd, i0, nb, ys, part, Ts, tb, tid);
+    }
+    for (int q = tid; q < n * INV_CB; q += INV_NT) {
+        const int cc = q / n, ii = q % n;
+        if (c0 + cc < n) X[ii + (int64_t)(c0 + cc) * ldx] = ys[ii * INV_CB + cc];
+    }
+}
+
+int64_t lu_inverse_cols_lds(int n) {
+    return ((int64_t)n * INV_CB + (int64_t)INV_KQ * LU_NB * INV_CB) * (int64_t)sizeof(double);
+}
+
+int32_t lu_inverse_cols(const double *LU, int n, int ld, const int32_t *piv, const double *Linv, const double *Uinv,
+                        int ldd, double *X, int ldx, int uband, hipStream_t s) {
+    const size_t shm = (size_t)lu_inverse_cols_lds(n);
+    hipLaunchKernelGGL(k_lu_inverse_cols, dim3((n + INV_CB - 1) / INV_CB), dim3(INV_NT), shm, s, LU, n, ld, piv, Linv,
+                       Uinv, ldd, X, ldx, uband);
+    HKG_HIP(hipGetLastError());
+    return HKG_OK;
+}
+
+// ------------------------------------------------------------------------------------------------
 // helpers: X = P * I (row exchanges of an LU applied to the identity), transposes, copies
 // ------------------------------------------------------------------------------------------------
 template <typename T>

@@ -276,10 +276,15 @@ int32_t local_operators(hkgeneo_ctx *c, hipStream_t s) {
 // U^{-1} first, then level by level the off-diagonal block of each pair of neighbouring blocks
 // (L: X21 = -X22 L21 X11;  U: X12 = -X11 U12 X22) by batched GEMMs, then L^{-1} P by a column
 // gather and the product with U^{-1}.  About 4 log2(n / 32) + 4 launches.
-int32_t lu_inverse(hkgeneo_ctx *c, int n, const double *LU, const int32_t *piv, double *out, hipStream_t s) {
+int32_t lu_inverse(hkgeneo_ctx *c, int n, const double *LU, const int32_t *piv, double *out, int uband, hipStream_t s) {
     const size_t nn = (size_t)n * n;
     HKG_TRY(walloc(c, &c->wLinv, 3 * nn * sizeof(double)));
     double *Linv = dp<double>(c->wLinv), *Uinv = Linv + nn, *tmp = Uinv + nn;
+    if (lu_inverse_cols_lds(n) <= (int64_t)144 * 1024) {
+        // independent column solves with the inverted diagonal blocks: one launch after the blocks
+        HKG_TRY(tri_diag_inverse(LU, n, n, Linv, Uinv, n, s));
+        return lu_inverse_cols(LU, n, n, piv, Linv, Uinv, n, out, n, uband, s);
+    }
     HKG_HIP(hipMemsetAsync(Linv, 0, 2 * nn * sizeof(double), s));
     HKG_TRY(tri_diag_inverse(LU, n, n, Linv, Uinv, n, s));
     // jobs of every level: [L first product | L second | U first | U second] per level
@@ -546,7 +551,9 @@ int32_t coarse_space(hkgeneo_ctx *c, hipStream_t s) {
     }
     if (c->B0inv.bytes != (size_t)m0 * m0 * sizeof(double)) HKG_TRY(dalloc(c, &c->B0inv, (size_t)m0 * m0 * sizeof(double)));
     (void)dj;
-    return lu_inverse(c, m0, dp<double>(c->wB0), dp<int32_t>(c->wPiv0), dp<double>(c->B0inv), s);
+    // U of the banded LU (row exchanges included) has half-bandwidth 2 band
+    return lu_inverse(c, m0, dp<double>(c->wB0), dp<int32_t>(c->wPiv0), dp<double>(c->B0inv),
+                      c->b0_band >= 0 ? 2 * c->b0_band : -1, s);
 }
 
 }  // namespace

@@ -24,6 +24,12 @@ constexpr int LU_BLOCK = 32;    // block size of the dense LU, triangular solves
 
 // diagonal LU_BLOCK blocks of L^{-1} (unit lower) and U^{-1} of one packed LU, into Linv / Uinv
 int32_t tri_diag_inverse(const double *LU, int n, int ld, double *Linv, double *Uinv, int ldo, hipStream_t s);
+// A^{-1} from a packed LU (P A = L U) by independent column solves in one launch, given the
+// inverted LU_BLOCK diagonal blocks of L and U (tri_diag_inverse); needs lu_inverse_cols_lds(n)
+// bytes of LDS per block; uband >= 0: U has no entry farther than uband above the diagonal
+int64_t lu_inverse_cols_lds(int n);
+int32_t lu_inverse_cols(const double *LU, int n, int ld, const int32_t *piv, const double *Linv, const double *Uinv,
+                        int ldd, double *X, int ldx, int uband, hipStream_t s);
 // out[:, c] = X[:, sigma(c)], P e_c = e_{sigma(c)} for the LU's row exchanges (so out = X P)
 int32_t gather_pivot_columns(int n, const double *X, int ldx, const int32_t *piv, double *out, int ldo, hipStream_t s);
 template <typename T>

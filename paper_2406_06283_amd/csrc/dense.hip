@@ -60,6 +60,7 @@ __global__ __launch_bounds__(256) void k_lu_panel(const DMat *__restrict__ mats,
     __shared__ int sidx[256];
     __shared__ int s_p;
     const int tid = threadIdx.x;
+    int32_t *pv = piv + poff[blockIdx.x];
     for (int j = j0; j < jend; ++j) {
         int p = j;
         if (pivot) {
@@ -85,7 +86,7 @@ __global__ __launch_bounds__(256) void k_lu_panel(const DMat *__restrict__ mats,
             __syncthreads();
             p = s_p;
         }
-        if (tid == 0) piv[poff[blockIdx.x] + j] = p;
+        if (tid == 0) pv[j] = p;
         // swap rows j and p inside the panel columns
         if (p != j) {
             for (int c = j0 + tid; c < jend; c += 256) {
@@ -143,6 +144,11 @@ __global__ __launch_bounds__(NT) void k_lu_panel_reg(const DMat *__restrict__ ma
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int r = j0 + tid;
     const bool own = r < min(n, mlim);
+    // loaded once: a global load inside the column loop would stall its wave at every column
+    int32_t *pv = piv + poff[blockIdx.x];
+    int bad = 0;                        // first zero (or non-finite) pivot column + 1
+    int pmine = 0;                      // thread jj keeps the pivot of column jj: one store at the end
+                                        // (a store per column would stall on its completion)
     __shared__ T prow[2][LU_NB];
     __shared__ T drow[2][LU_NB];
     __shared__ T wval[2][NW];
@@ -191,10 +197,8 @@ __global__ __launch_bounds__(NT) void k_lu_panel_reg(const DMat *__restrict__ ma
             }
             const T dpiv = prow[buf][jj];
             const bool ok = dpiv != T(0) && isfinite(dpiv);
-            if (tid == 0) {
-                piv[poff[blockIdx.x] + j] = p;
-                if (!ok && info[blockIdx.x] == 0) info[blockIdx.x] = j + 1;
-            }
+            if (tid == jj) pmine = p;
+            if (!ok && bad == 0) bad = j + 1;
             if (ok && own && r > j) {
                 const T l = a[jj] * (T(1) / dpiv);
                 a[jj] = l;
@@ -218,6 +222,113 @@ __global__ __launch_bounds__(NT) void k_lu_panel_reg(const DMat *__restrict__ ma
         for (int c = 0; c < LU_NB; ++c)
             if (c < nb) A[r + (int64_t)(j0 + c) * ld] = a[c];
     }
+    if (tid < nb) pv[j0 + tid] = pmine;
+    if (tid == 0 && bad && info[blockIdx.x] == 0) info[blockIdx.x] = bad;
+}
+
+// Panel factorisation by one wave: lane l owns the physical rows j0 + l + 64 q (q < RPL), so panels
+// of up to 64 RPL rows (banded matrices) need no barrier and no LDS.  Row exchanges are deferred:
+// every physical row carries its logical row index, the pivot search runs over the rows whose
+// logical index is still >= j (arg-max by DPP, ties to the smallest logical row, as in
+// k_lu_panel_reg), an exchange swaps two logical indices, and the pivot row's entries reach the
+// other lanes by v_readlane.  At the end each physical row is stored at its logical position, which
+// gives the same factors as exchanging the rows as they are chosen.
+template <typename T, int RPL>
+__global__ __launch_bounds__(64) void k_lu_panel_wave(const DMat *__restrict__ mats, const int64_t *__restrict__ poff,
+                                                      T *__restrict__ Ab, int32_t *__restrict__ piv,
+                                                      int32_t *__restrict__ info, int j0, int pivot, int mlim) {
+    const DMat m = mats[blockIdx.x];
+    const int n = m.n;
+    if (j0 >= n) return;
+    T *A = Ab + m.off;
+    const int ld = m.ld;
+    const int nb = min(j0 + LU_NB, n) - j0;
+    const int lane = threadIdx.x;
+    const int rend = min(n, mlim);
+    int32_t *pv = piv + poff[blockIdx.x];
+    int bad = 0;
+    int pmine = 0;                      // lane jj keeps the pivot of column jj (one store at the end)
+    T a[RPL][LU_NB];
+    int lrow[RPL];                      // logical row of each physical row (>= rend: absent)
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+        const int r = j0 + lane + 64 * q;
+        lrow[q] = r < rend ? r : 0x3fffffff;
+#pragma unroll
+        for (int c = 0; c < LU_NB; ++c) a[q][c] = (r < rend && c < nb) ? A[r + (int64_t)(j0 + c) * ld] : T(0);
+    }
+#pragma clang loop unroll(full)
+    for (int jj = 0; jj < LU_NB; ++jj) {
+        if (jj < nb) {
+            const int j = j0 + jj;
+            // winner: key = logical row * 256 + physical slot (smallest logical row on ties); the row
+            // holding logical row j is always a candidate, and a NaN entry wins (the LU then fails)
+            int key;
+            if (pivot) {
+                T v = T(-1);
+                int kk = 0x7fffffff;
+#pragma unroll
+                for (int q = 0; q < RPL; ++q) {
+                    const T t = fabs(a[q][jj]);
+                    const T x = (lrow[q] >= j && lrow[q] < rend) ? (t != t ? T(INFINITY) : t) : T(-1);
+                    const int k2 = (lrow[q] << 8) | (lane + 64 * q);
+                    if (x > v || (x == v && k2 < kk)) {
+                        v = x;
+                        kk = k2;
+                    }
+                }
+                argmax_wave64(v, kk);
+                key = kk;
+            } else {
+                key = (j << 8) | (j - j0);     // no exchanges: logical row j is physical row j
+            }
+            const int p = key >> 8, slot = key & 255;
+            const int lp = slot & 63, qp = slot >> 6;
+            // the pivot row's entries c >= jj, from lane lp
+            T prow[LU_NB];
+#pragma unroll
+            for (int c = jj; c < LU_NB; ++c) {
+                T src = a[0][c];
+#pragma unroll
+                for (int q = 1; q < RPL; ++q) src = qp == q ? a[q][c] : src;
+                prow[c] = readlane_any(src, lp);
+            }
+            // logical exchange of rows j and p
+#pragma unroll
+            for (int q = 0; q < RPL; ++q) {
+                const bool is_p = lane == lp && q == qp;
+                if (is_p) lrow[q] = j;
+                else if (lrow[q] == j) lrow[q] = p;
+            }
+            const T dpiv = prow[jj];
+            const bool ok = dpiv != T(0) && isfinite(dpiv);
+            if (lane == jj) pmine = p;
+            if (!ok && bad == 0) bad = j + 1;
+            if (ok) {
+                const T rdp = T(1) / dpiv;
+#pragma unroll
+                for (int q = 0; q < RPL; ++q) {
+                    if (lrow[q] > j && lrow[q] < rend) {
+                        const T l = a[q][jj] * rdp;
+                        a[q][jj] = l;
+#pragma unroll
+                        for (int c = jj + 1; c < LU_NB; ++c) a[q][c] -= l * prow[c];
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+        const int lr = lrow[q];
+        if (lr < rend) {
+#pragma unroll
+            for (int c = 0; c < LU_NB; ++c)
+                if (c < nb) A[lr + (int64_t)(j0 + c) * ld] = a[q][c];
+        }
+    }
+    if (lane < nb) pv[j0 + lane] = pmine;
+    if (lane == 0 && bad && info[blockIdx.x] == 0) info[blockIdx.x] = bad;
 }
 
 // apply the row exchanges of panel [j0, j0+NB) to the columns outside the panel
@@ -321,7 +432,18 @@ int32_t lu_batched(const DMat *d_mats, const int64_t *d_poff, int nbatch, int ma
         const int mlim = banded ? std::min(maxn, jend + band) : maxn;           // panel rows end
         const int clim = banded ? std::min(maxn, jend + 2 * band) : maxn;       // columns reached
         const int rows = mlim - j0;
-        if (rows <= 256)
+        // one wave for narrow panels (float: up to 64 rows, where its registers suffice)
+        const bool wide_wave = sizeof(T) == 8;
+        if (rows <= 64)
+            hipLaunchKernelGGL((k_lu_panel_wave<T, 1>), dim3(nbatch), dim3(64), 0, s, d_mats, d_poff, A, piv, info, j0,
+                               (int)pivot, mlim);
+        else if (wide_wave && rows <= 128)
+            hipLaunchKernelGGL((k_lu_panel_wave<T, 2>), dim3(nbatch), dim3(64), 0, s, d_mats, d_poff, A, piv, info, j0,
+                               (int)pivot, mlim);
+        else if (wide_wave && rows <= 192)
+            hipLaunchKernelGGL((k_lu_panel_wave<T, 3>), dim3(nbatch), dim3(64), 0, s, d_mats, d_poff, A, piv, info, j0,
+                               (int)pivot, mlim);
+        else if (rows <= 256)
             hipLaunchKernelGGL((k_lu_panel_reg<T, 256>), dim3(nbatch), dim3(256), 0, s, d_mats, d_poff, A, piv, info, j0,
                                (int)pivot, mlim);
         else if (rows <= 512)

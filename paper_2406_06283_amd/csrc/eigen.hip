@@ -75,6 +75,7 @@ __global__ __launch_bounds__(SY_THREADS) void k_sytrd_panel(const SubDev *__rest
     double *t12 = part + SY_G * (n + 1);   // 2 SY_NB
     double *vw = t12 + 2 * SY_NB;    // 2 SY_NB: W[j, :], V[j, :]
     double *red = vw + 2 * SY_NB;    // 16
+    double dmine = 0.0, emine = 0.0, tmine = 0.0;   // column tid's d, e, tau (tid < jb)
     // zero the panel's columns of V, W, V2 (rows not written below stay zero)
     for (int64_t q = tid; q < (int64_t)3 * SY_NB * n; q += SY_THREADS) V[q] = 0.0;
     __syncthreads();
@@ -121,10 +122,10 @@ __global__ __launch_bounds__(SY_THREADS) void k_sytrd_panel(const SubDev *__rest
             V[r + (int64_t)kk * n] = vr;
             V2[r + (int64_t)kk * n] = vr;
         }
-        if (tid == 0) {
-            d[j] = p[j];
-            e[j] = beta;
-            tau[j] = t;
+        if (tid == kk) {            // stored after the panel (a store per column stalls its wave)
+            dmine = p[j];
+            emine = beta;
+            tmine = t;
         }
         __syncthreads();
         if (t == 0.0) continue;          // H_j = I: W column stays zero
@@ -184,6 +185,11 @@ __global__ __launch_bounds__(SY_THREADS) void k_sytrd_panel(const SubDev *__rest
         const double K = 0.5 * t * block_sum(acc, red);
         for (int r = j + 1 + tid; r < n; r += SY_THREADS) W[r + (int64_t)kk * n] = p[r] - K * v[r];
         __syncthreads();
+    }
+    if (tid < jb) {
+        d[j0 + tid] = dmine;
+        e[j0 + tid] = emine;
+        tau[j0 + tid] = tmine;
     }
 }
 

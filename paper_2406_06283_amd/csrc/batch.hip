@@ -99,13 +99,27 @@ __device__ __forceinline__ void local_body(const ProbDev &P, const SubDev &sd, c
     T *xt = reinterpret_cast<T *>(sh + n);
     double *part = sh + n + (n * sizeof(T) + 7) / 8;  // NPART x LTILE
     const int32_t *I = P.I_idx + sd.offI;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    // the row tile's first UNR column groups are loaded before the gather of r, so that their
+    // latency overlaps the gather's two dependent loads (same summation order as the loop below)
+    const int row0 = blockIdx.x * LTILE + 2 * lane;
+    const T *M = reinterpret_cast<const T *>(P.Minv) + sd.offM + row0;
+    const int64_t ldm = sd.ldM;
+    const bool rows_ok = !restrict_tile && row0 < n;
+    V2 pre[UNR][PW];
+#pragma unroll
+    for (int g = 0; g < UNR; ++g)
+#pragma unroll
+        for (int k = 0; k < PW; ++k) {
+            const int col = min(g * NPART + wv + k * WAVES, n - 1);
+            pre[g][k] = rows_ok ? *reinterpret_cast<const V2 *>(M + col * ldm) : V2{};
+        }
     for (int i = threadIdx.x; i < n; i += LS_ROWS * WAVES) {
         const double v = r[I[i]];
         xd[i] = v;
         xt[i] = (T)v;
     }
     __syncthreads();
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     if (restrict_tile) {
         // c_i = Z_i^T r on dof(D_i), same partial-sum order
         const int m = sd.m;
@@ -124,14 +138,22 @@ __device__ __forceinline__ void local_body(const ProbDev &P, const SubDev &sd, c
         }
         return;
     }
-    const int row0 = blockIdx.x * LTILE + 2 * lane;
-    const T *M = reinterpret_cast<const T *>(P.Minv) + sd.offM + row0;
-    const int64_t ldm = sd.ldM;
     T acc[PW][2];
 #pragma unroll
     for (int k = 0; k < PW; ++k) acc[k][0] = acc[k][1] = T(0);
     if (row0 < n) {
         int c0 = 0;
+        if (UNR * NPART <= n) {
+#pragma unroll
+            for (int g = 0; g < UNR; ++g)
+#pragma unroll
+                for (int k = 0; k < PW; ++k) {
+                    const int col = g * NPART + wv + k * WAVES;
+                    acc[k][0] = fma(pre[g][k].x, xt[col], acc[k][0]);
+                    acc[k][1] = fma(pre[g][k].y, xt[col], acc[k][1]);
+                }
+            c0 = UNR * NPART;
+        }
 #pragma unroll UNR
         for (; c0 + NPART <= n; c0 += NPART) {
 #pragma unroll

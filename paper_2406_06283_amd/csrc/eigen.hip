@@ -48,11 +48,15 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
 //     many blocks) brings the trailing matrix up to date.  Per subdomain the workspace VWV holds
 //     [V | W | V] (n x 3 SY_NB, column-major), so that the update is one GEMM with K = 2 SY_NB.
 // ------------------------------------------------------------------------------------------------
-constexpr int SY_NB = 32;
+constexpr int SY_NB = 32;           // panel width when V and W stay in global memory
+constexpr int SY_NB_LDS = 16;       // panel width when V and W of the panel fit in LDS
 constexpr int SY_THREADS = 1024;
 constexpr int SY_RT = 256;          // row-pair threads of the product A0 v
 constexpr int SY_G = SY_THREADS / SY_RT;   // column groups of the product
 
+// NB: panel width; LDSVW: V and W of the panel are kept in LDS (every access of the corrections and
+// of W^T v, V^T v is then an LDS access) and copied to the global [V | W | V] at the end
+template <int NB, bool LDSVW>
 __global__ __launch_bounds__(SY_THREADS) void k_sytrd_panel(const SubDev *__restrict__ subs, double *__restrict__ Sq,
                                                             double *__restrict__ VWVb, double *__restrict__ dout,
                                                             double *__restrict__ eout, double *__restrict__ tout,
@@ -65,26 +69,28 @@ __global__ __launch_bounds__(SY_THREADS) void k_sytrd_panel(const SubDev *__rest
     double *d = dout + sd.offI, *e = eout + sd.offI, *tau = tout + sd.offI;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     if (j0 >= n - 1) return;
-    const int jb = min(SY_NB, n - 1 - j0);
-    double *V = VWVb + 3 * SY_NB * sd.offI;     // n x 3*SY_NB per subdomain (offI runs over sum n_I)
-    double *W = V + (int64_t)SY_NB * n;
-    double *V2 = V + (int64_t)2 * SY_NB * n;
+    const int jb = min(NB, n - 1 - j0);
+    double *Vg = VWVb + 3 * NB * sd.offI;      // n x 3 NB per subdomain (offI runs over sum n_I)
     double *v = sh;                  // n
     double *p = sh + n;              // n (first the corrected column, then A v)
     double *part = sh + 2 * n;       // SY_G (n + 1): partial products per column group
-    double *t12 = part + SY_G * (n + 1);   // 2 SY_NB
-    double *vw = t12 + 2 * SY_NB;    // 2 SY_NB: W[j, :], V[j, :]
-    double *red = vw + 2 * SY_NB;    // 16
+    double *t12 = part + SY_G * (n + 1);   // 2 NB
+    double *vw = t12 + 2 * NB;       // 2 NB: W[j, :], V[j, :]
+    double *red = vw + 2 * NB;       // 16
+    // V and W of the panel (column q at q n): in LDS after red, or the global workspace
+    double *V = LDSVW ? red + 16 : Vg;
+    double *W = V + (int64_t)NB * n;
+    double *V2 = Vg + (int64_t)2 * NB * n;
     double dmine = 0.0, emine = 0.0, tmine = 0.0;   // column tid's d, e, tau (tid < jb)
-    // zero the panel's columns of V, W, V2 (rows not written below stay zero)
-    for (int64_t q = tid; q < (int64_t)3 * SY_NB * n; q += SY_THREADS) V[q] = 0.0;
+    // zero the panel's columns of V, W (and V2 in global memory; rows not written stay zero)
+    for (int64_t q = tid; q < (int64_t)(LDSVW ? 2 : 3) * NB * n; q += SY_THREADS) V[q] = 0.0;
     __syncthreads();
     for (int kk = 0; kk < jb; ++kk) {
         const int j = j0 + kk;
         const int L = n - j - 1;
         // W[j, q], V[j, q] for q < kk
         if (tid < kk) vw[tid] = W[j + (int64_t)tid * n];
-        else if (tid >= 64 && tid - 64 < kk) vw[SY_NB + tid - 64] = V[j + (int64_t)(tid - 64) * n];
+        else if (tid >= 64 && tid - 64 < kk) vw[NB + tid - 64] = V[j + (int64_t)(tid - 64) * n];
         __syncthreads();
         // 1. corrected column j, rows j..n-1
         for (int r = j + tid; r < n; r += SY_THREADS) {
@@ -99,7 +105,7 @@ __global__ __launch_bounds__(SY_THREADS) void k_sytrd_panel(const SubDev *__rest
                 }
 #pragma unroll
                 for (int u = 0; u < 8; ++u)
-                    if (q0 + u < kk) s -= a[u] * vw[q0 + u] + b[u] * vw[SY_NB + q0 + u];
+                    if (q0 + u < kk) s -= a[u] * vw[q0 + u] + b[u] * vw[NB + q0 + u];
             }
             p[r] = s;
         }
@@ -120,7 +126,7 @@ __global__ __launch_bounds__(SY_THREADS) void k_sytrd_panel(const SubDev *__rest
             v[r] = vr;
             A[r + (int64_t)j * ld] = vr;
             V[r + (int64_t)kk * n] = vr;
-            V2[r + (int64_t)kk * n] = vr;
+            if (!LDSVW) V2[r + (int64_t)kk * n] = vr;
         }
         if (tid == kk) {            // stored after the panel (a store per column stalls its wave)
             dmine = p[j];
@@ -191,23 +197,33 @@ __global__ __launch_bounds__(SY_THREADS) void k_sytrd_panel(const SubDev *__rest
         e[j0 + tid] = emine;
         tau[j0 + tid] = tmine;
     }
+    if (LDSVW) {
+        __syncthreads();
+        for (int64_t q = tid; q < (int64_t)NB * n; q += SY_THREADS) {
+            const double x = V[q], y = W[q];
+            Vg[q] = x;
+            Vg[q + (int64_t)NB * n] = y;
+            Vg[q + (int64_t)2 * NB * n] = x;
+        }
+    }
 }
 
-// trailing update after the panel at j0: A[j1:, j1:] -= [V W] [W V]^T (rank 2 SY_NB), j1 = j0 + jb
+// trailing update after the panel at j0: A[j1:, j1:] -= [V W] [W V]^T (rank 2 NB), j1 = j0 + jb
+template <int NB>
 __global__ __launch_bounds__(256) void k_sytrd_update(const SubDev *__restrict__ subs, double *__restrict__ Sq,
                                                       const double *__restrict__ VWVb, int j0, int tiles_max) {
     const SubDev sd = subs[blockIdx.y];
     const int n = sd.nI;
     if (j0 >= n - 1) return;
-    const int jb = min(SY_NB, n - 1 - j0);
+    const int jb = min(NB, n - 1 - j0);
     const int j1 = j0 + jb;
     const int L1 = n - j1;
     const int tm = blockIdx.x % tiles_max, tn = blockIdx.x / tiles_max;
     if (tm * 64 >= L1 || tn * 64 >= L1) return;
-    const double *V = VWVb + 3 * SY_NB * sd.offI;
+    const double *V = VWVb + 3 * NB * sd.offI;
     double *A = Sq + sd.offM;
     const int ld = sd.ldM;
-    gemm_tile<double>(L1, L1, 2 * SY_NB, V + j1, n, false, V + (int64_t)SY_NB * n + j1, n, true, A + j1 + (int64_t)j1 * ld, ld,
+    gemm_tile<double>(L1, L1, 2 * NB, V + j1, n, false, V + (int64_t)NB * n + j1, n, true, A + j1 + (int64_t)j1 * ld, ld,
                       -1.0, 1.0, tm, tn);
 }
 
@@ -219,11 +235,24 @@ __global__ void k_sytrd_last(const SubDev *__restrict__ subs, const double *__re
 
 int32_t tridiagonalize_blocked(const SubDev *d_sub, int nsub, int maxnI, double *Sq, double *VWV, double *d, double *e,
                                double *tau, hipStream_t s) {
-    const size_t shm = (size_t)(2 * maxnI + SY_G * (maxnI + 1) + 4 * SY_NB + 16) * sizeof(double);
     const int tiles = (maxnI + 63) / 64;
-    for (int j0 = 0; j0 < maxnI; j0 += SY_NB) {
-        hipLaunchKernelGGL(k_sytrd_panel, dim3(nsub), dim3(SY_THREADS), shm, s, d_sub, Sq, VWV, d, e, tau, j0);
-        hipLaunchKernelGGL(k_sytrd_update, dim3(tiles * tiles, nsub), dim3(256), 0, s, d_sub, Sq, VWV, j0, tiles);
+    const size_t base = (size_t)(2 * maxnI + SY_G * (maxnI + 1) + 16);
+    const size_t shm_lds = (base + 4 * SY_NB_LDS + (size_t)2 * SY_NB_LDS * maxnI) * sizeof(double);
+    if (shm_lds <= (size_t)156 * 1024) {
+        for (int j0 = 0; j0 < maxnI; j0 += SY_NB_LDS) {
+            hipLaunchKernelGGL((k_sytrd_panel<SY_NB_LDS, true>), dim3(nsub), dim3(SY_THREADS), shm_lds, s, d_sub, Sq, VWV,
+                               d, e, tau, j0);
+            hipLaunchKernelGGL(k_sytrd_update<SY_NB_LDS>, dim3(tiles * tiles, nsub), dim3(256), 0, s, d_sub, Sq, VWV, j0,
+                               tiles);
+        }
+    } else {
+        const size_t shm = (base + 4 * SY_NB) * sizeof(double);
+        for (int j0 = 0; j0 < maxnI; j0 += SY_NB) {
+            hipLaunchKernelGGL((k_sytrd_panel<SY_NB, false>), dim3(nsub), dim3(SY_THREADS), shm, s, d_sub, Sq, VWV, d, e,
+                               tau, j0);
+            hipLaunchKernelGGL(k_sytrd_update<SY_NB>, dim3(tiles * tiles, nsub), dim3(256), 0, s, d_sub, Sq, VWV, j0,
+                               tiles);
+        }
     }
     hipLaunchKernelGGL(k_sytrd_last, dim3(nsub), dim3(64), 0, s, d_sub, Sq, d);
     HKG_HIP(hipGetLastError());

@@ -546,10 +546,105 @@ __global__ __launch_bounds__(256) void k_tri_update(const TriJob *__restrict__ j
     }
 }
 
+// Banded triangular solve in one launch: op(T) has no entry farther than `band` from the diagonal.
+// Each block takes TB_COLS right-hand sides of one matrix and sweeps all its row blocks itself,
+// the vectors in LDS: per row block, the band rows of op(T) next to it (and its diagonal block)
+// are staged in LDS, every (row, column) subtracts its band product, and the diagonal block is
+// solved wave-synchronously (lanes 0-31 and 32-63 of a wave hold one column each; a wave's LDS
+// operations complete in order).
+constexpr int TB_COLS = 8;
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void k_tri_band(const TriJob *__restrict__ jobs, const T *__restrict__ Tb,
+                                                  T *__restrict__ Xb, int band) {
+    const TriJob J = jobs[blockIdx.y];
+    const int c0 = blockIdx.x * TB_COLS;
+    const int n = J.n;
+    if (c0 >= J.ncol || n == 0) return;
+    extern __shared__ double shb[];
+    T *ys = reinterpret_cast<T *>(shb);                    // n x TB_COLS, (i, c) at i * TB_COLS + c
+    T *Ls = ys + (int64_t)n * TB_COLS;                     // LU_NB rows x (band + LU_NB) of op(T)
+    const int W = band + LU_NB;
+    const T *Tm = Tb + J.offT;
+    T *X = Xb + J.offX;
+    const int tid = threadIdx.x, r = tid & 31, c = tid >> 5;
+    for (int q = tid; q < n * TB_COLS; q += 256) {
+        const int cc = q / n, i = q % n;
+        ys[i * TB_COLS + cc] = (c0 + cc < J.ncol) ? X[i + (int64_t)(c0 + cc) * J.ldX] : T(0);
+    }
+    const bool fwd = MODE == TRI_LOWER_UNIT;
+    const int nblk = (n + LU_NB - 1) / LU_NB;
+    for (int bb = 0; bb < nblk; ++bb) {
+        const int b = fwd ? bb : nblk - 1 - bb;
+        const int i0 = b * LU_NB, nb = min(LU_NB, n - i0);
+        // columns k of op(T) staged: forward [ka, i0 + nb), backward [i0, kb)
+        const int ka = fwd ? max(0, i0 - band) : i0;
+        const int kb = fwd ? i0 + nb : min(n, i0 + nb + band);
+        const int w = kb - ka;
+        __syncthreads();      // previous block done with Ls and with its rows of ys
+        if (MODE == TRI_LOWER_UNIT_TRANS) {
+            // op(T)[i][k] = T[k][i]: consecutive k are contiguous
+            for (int e = tid; e < LU_NB * w; e += 256) {
+                const int kk = e % w, rr = e / w;
+                Ls[rr * W + kk] = rr < nb ? Tm[(ka + kk) + (int64_t)(i0 + rr) * J.ldT] : T(0);
+            }
+        } else {
+            for (int e = tid; e < LU_NB * w; e += 256) {
+                const int rr = e % LU_NB, kk = e / LU_NB;
+                Ls[rr * W + kk] = rr < nb ? Tm[(i0 + rr) + (int64_t)(ka + kk) * J.ldT] : T(0);
+            }
+        }
+        __syncthreads();
+        // band product with the rows already solved
+        if (r < nb) {
+            T acc = T(0);
+            if (fwd) {
+                for (int k = ka; k < i0; ++k) acc = fma(Ls[r * W + (k - ka)], ys[k * TB_COLS + c], acc);
+            } else {
+                for (int k = i0 + nb; k < kb; ++k) acc = fma(Ls[r * W + (k - ka)], ys[k * TB_COLS + c], acc);
+            }
+            ys[(i0 + r) * TB_COLS + c] -= acc;
+        }
+        // the diagonal block, wave-synchronously within each column
+        const int dofs = fwd ? i0 - ka : 0;     // column offset of the block in Ls
+        if (fwd) {
+            for (int k = 0; k < nb - 1; ++k) {
+                const T yk = ys[(i0 + k) * TB_COLS + c];
+                if (r > k && r < nb) ys[(i0 + r) * TB_COLS + c] -= Ls[r * W + dofs + k] * yk;
+            }
+        } else {
+            for (int k = nb - 1; k >= 0; --k) {
+                if (MODE == TRI_UPPER && r == k) ys[(i0 + k) * TB_COLS + c] /= Ls[k * W + dofs + k];
+                const T yk = ys[(i0 + k) * TB_COLS + c];
+                if (r < k) ys[(i0 + r) * TB_COLS + c] -= Ls[r * W + dofs + k] * yk;
+            }
+        }
+    }
+    __syncthreads();
+    for (int q = tid; q < n * TB_COLS; q += 256) {
+        const int cc = q / n, i = q % n;
+        if (c0 + cc < J.ncol) X[i + (int64_t)(c0 + cc) * J.ldX] = ys[i * TB_COLS + cc];
+    }
+}
+
 template <typename T>
 int32_t tri_solve_batched(const TriJob *d_jobs, int nbatch, int maxn, int maxcol, const T *Tm, T *X, int mode,
                           hipStream_t s, int band) {
     if (nbatch == 0 || maxn == 0 || maxcol == 0) return HKG_OK;
+    if (band >= 0) {
+        const size_t shm = ((size_t)maxn * TB_COLS + (size_t)LU_NB * (band + LU_NB)) * sizeof(T);
+        if (shm <= (size_t)144 * 1024) {
+            const dim3 g((maxcol + TB_COLS - 1) / TB_COLS, nbatch);
+            if (mode == TRI_LOWER_UNIT)
+                hipLaunchKernelGGL((k_tri_band<T, TRI_LOWER_UNIT>), g, dim3(256), shm, s, d_jobs, Tm, X, band);
+            else if (mode == TRI_UPPER)
+                hipLaunchKernelGGL((k_tri_band<T, TRI_UPPER>), g, dim3(256), shm, s, d_jobs, Tm, X, band);
+            else
+                hipLaunchKernelGGL((k_tri_band<T, TRI_LOWER_UNIT_TRANS>), g, dim3(256), shm, s, d_jobs, Tm, X, band);
+            HKG_HIP(hipGetLastError());
+            return HKG_OK;
+        }
+    }
     const int nblk = (maxn + LU_NB - 1) / LU_NB;
     const int urows = band >= 0 ? std::min(maxn, band) : maxn;      // rows of one update at most
     const int tiles_m = (urows + GT - 1) / GT, tiles_n = (maxcol + GT - 1) / GT;

@@ -14,6 +14,21 @@ namespace hkg {
 
 constexpr int LU_NB = LU_BLOCK;    // LU / triangular-solve block size
 
+// Copy `total` elements with `nt` threads, U loads in flight per thread: load(e) for e < total
+// (called only with such e), store(e, value).  A plain loop whose iterations each load and then
+// store would wait for every load in turn.
+template <int U, typename F, typename G>
+__device__ __forceinline__ void staged_copy(int total, int tid, int nt, F load, G store) {
+    for (int e0 = tid; e0 < total; e0 += nt * U) {
+        decltype(load(0)) v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = load(min(e0 + u * nt, total - 1));
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (e0 + u * nt < total) store(e0 + u * nt, v[u]);
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_gemm_batched(const GemmJob *__restrict__ jobs, const T *__restrict__ Ab,
                                                       const T *__restrict__ Bb, T *__restrict__ Cb, T alpha, T beta,
@@ -334,14 +349,15 @@ __global__ __launch_bounds__(64) void k_lu_panel_wave(const DMat *__restrict__ m
 // apply the row exchanges of panel [j0, j0+NB) to the columns outside the panel
 template <typename T>
 __global__ __launch_bounds__(256) void k_lu_laswp(const DMat *__restrict__ mats, const int64_t *__restrict__ poff,
-                                                  T *__restrict__ Ab, const int32_t *__restrict__ piv, int j0) {
+                                                  T *__restrict__ Ab, const int32_t *__restrict__ piv, int j0,
+                                                  int tmax) {
     const DMat m = mats[blockIdx.y];
     const int n = m.n;
     if (j0 >= n) return;
     const int jend = min(j0 + LU_NB, n);
     const int outside = n - (jend - j0);
     const int t = blockIdx.x * 256 + threadIdx.x;
-    if (t >= outside) return;
+    if (t >= outside || t >= tmax) return;     // tmax = j0: the columns left of the panel only
     const int c = t < j0 ? t : t + (jend - j0);
     T *A = Ab + m.off + (int64_t)c * m.ld;
     const int32_t *pv = piv + poff[blockIdx.y];
@@ -394,7 +410,13 @@ __global__ __launch_bounds__(TRI_COLS) void k_lu_trsm_row(const DMat *__restrict
     }
     const int c = jend + blockIdx.x * TRI_COLS + threadIdx.x;
     const bool valid = c < n;
-    for (int r = 0; r < LU_NB; ++r) xs[r][threadIdx.x] = (valid && r < nb) ? A[j0 + r + (int64_t)c * ld] : T(0);
+    {
+        T v[LU_NB];
+#pragma unroll
+        for (int r = 0; r < LU_NB; ++r) v[r] = valid ? A[j0 + min(r, nb - 1) + (int64_t)c * ld] : T(0);
+#pragma unroll
+        for (int r = 0; r < LU_NB; ++r) xs[r][threadIdx.x] = r < nb ? v[r] : T(0);
+    }
     __syncthreads();
     solve_block_lds<T, TRI_LOWER_UNIT>(L, xs, threadIdx.x);
     if (valid)
@@ -418,6 +440,169 @@ __global__ __launch_bounds__(256) void k_lu_update(const DMat *__restrict__ mats
                  A + jend + (int64_t)jend * ld, ld, T(-1), T(1), tm, tn);
 }
 
+// x <- L^{-1} x for a unit lower LU_NB x LU_NB block (entry (r, k) at L[r * ldl + k]),
+// right-looking in registers: once x[k] is final every
+// later row subtracts its term, so the dependent chain is LU_NB steps long (each row still
+// subtracts its terms in increasing k, as a left-looking substitution does)
+template <typename T>
+__device__ __forceinline__ void unit_lower_solve_regs(T (&x)[LU_NB], const T *__restrict__ L, int ldl) {
+#pragma unroll
+    for (int k = 0; k < LU_NB - 1; ++k) {
+        const T xk = x[k];
+#pragma unroll
+        for (int r = k + 1; r < LU_NB; ++r) x[r] = fma(-L[r * ldl + k], xk, x[r]);
+        // keep the loads of later steps from being hoisted (register pressure)
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// Everything after a panel in one launch, for panels of at most LP_MAXROWS rows (rows [j0, mlim)):
+// each block takes LP_COLS columns right of the panel (up to clim) with the panel staged in LDS,
+// exchanges their rows, solves U12 = L11^{-1} A12 and updates rows [jend, mlim) with L21 U12, all
+// in LDS.  The exchanges of the columns left of the panel (the L factor) are deferred to
+// k_lu_swap_left: nothing reads those columns before the factorisation ends, so applying a
+// column's later exchanges at the end gives the same result.
+constexpr int LP_COLS = 32;
+constexpr int LP_MAXROWS = 256;
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_lu_post(const DMat *__restrict__ mats, const int64_t *__restrict__ poff,
+                                                 T *__restrict__ Ab, const int32_t *__restrict__ piv, int j0, int mlim,
+                                                 int clim, int pivot) {
+    const DMat m = mats[blockIdx.y];
+    const int n = m.n;
+    if (j0 >= n) return;
+    T *A = Ab + m.off;
+    const int ld = m.ld;
+    const int jend = min(j0 + LU_NB, n), nb = jend - j0;
+    const int rend = min(n, mlim), cend = min(n, clim);
+    const int32_t *pv = piv + poff[blockIdx.y];
+    const int tid = threadIdx.x;
+    const int cs = jend + blockIdx.x * LP_COLS;               // first column of this strip
+    if (cs >= cend) return;
+    const int ncs = min(LP_COLS, cend - cs);
+    const int rw = rend - j0;                                   // rows [j0, rend)
+    extern __shared__ double shp[];
+    T *Ps = reinterpret_cast<T *>(shp);                         // rw x (LU_NB + 1): the panel
+    T *Xs = Ps + (int64_t)rw * (LU_NB + 1);                     // rw x (LP_COLS + 1): the strip
+    __shared__ int lp[LU_NB];
+    staged_copy<8>(
+        rw * LU_NB, tid, 256, [&](int e) { return A[(j0 + e % rw) + (int64_t)(j0 + min(e / rw, nb - 1)) * ld]; },
+        [&](int e, T v) { Ps[(e % rw) * (LU_NB + 1) + e / rw] = e / rw < nb ? v : T(0); });
+    staged_copy<8>(
+        rw * LP_COLS, tid, 256, [&](int e) { return A[(j0 + e % rw) + (int64_t)(cs + min(e / rw, ncs - 1)) * ld]; },
+        [&](int e, T v) { Xs[(e % rw) * (LP_COLS + 1) + e / rw] = e / rw < ncs ? v : T(0); });
+    if (tid < LU_NB) lp[tid] = (pivot && tid < nb) ? pv[j0 + tid] - j0 : tid;
+    __syncthreads();
+    if (pivot && tid < LP_COLS) {
+        for (int jj = 0; jj < nb; ++jj) {
+            const int p = lp[jj];
+            if (p != jj) {
+                const T x = Xs[jj * (LP_COLS + 1) + tid];
+                Xs[jj * (LP_COLS + 1) + tid] = Xs[p * (LP_COLS + 1) + tid];
+                Xs[p * (LP_COLS + 1) + tid] = x;
+            }
+        }
+    }
+    __syncthreads();
+    // U12 = L11^{-1} A12: one thread per column (a full panel: the column in registers)
+    if (tid < LP_COLS) {
+        if (nb == LU_NB) {
+            T x[LU_NB];
+#pragma unroll
+            for (int r = 0; r < LU_NB; ++r) x[r] = Xs[r * (LP_COLS + 1) + tid];
+            unit_lower_solve_regs(x, Ps, LU_NB + 1);
+#pragma unroll
+            for (int r = 0; r < LU_NB; ++r) Xs[r * (LP_COLS + 1) + tid] = x[r];
+        } else {
+            for (int r = 1; r < nb; ++r) {
+                T v = Xs[r * (LP_COLS + 1) + tid];
+                for (int k = 0; k < r; ++k) v -= Ps[r * (LU_NB + 1) + k] * Xs[k * (LP_COLS + 1) + tid];
+                Xs[r * (LP_COLS + 1) + tid] = v;
+            }
+        }
+    }
+    __syncthreads();
+    // rows [jend, rend): X -= L21 U12, each thread a block of rows (stride 32) x 4 columns
+    {
+        constexpr int RB = LP_MAXROWS / 32;
+        const int cg = tid & 7, rg = tid >> 3;
+        const int nr = rw - nb;
+        T acc[RB][4];
+#pragma unroll
+        for (int i = 0; i < RB; ++i)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc[i][u] = T(0);
+        for (int k = 0; k < nb; ++k) {
+            T x[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) x[u] = Xs[k * (LP_COLS + 1) + 4 * cg + u];
+#pragma unroll
+            for (int i = 0; i < RB; ++i) {
+                const int r = nb + rg + 32 * i;
+                const T l = r < rw ? Ps[r * (LU_NB + 1) + k] : T(0);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) acc[i][u] = fma(l, x[u], acc[i][u]);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+            const int r = nb + rg + 32 * i;
+            if (rg + 32 * i < nr) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) Xs[r * (LP_COLS + 1) + 4 * cg + u] -= acc[i][u];
+            }
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < rw * LP_COLS; e += 256) {
+        const int r = e % rw, c = e / rw;
+        if (c < ncs) A[(j0 + r) + (int64_t)(cs + c) * ld] = Xs[r * (LP_COLS + 1) + c];
+    }
+}
+
+// The deferred row exchanges of the L columns: column c (in the panel ending at e_c) receives the
+// exchanges j = max(e_c, jf) .. n-1 in order (jf: first panel whose exchanges were deferred).  Each
+// block holds LS_COLS columns' rows [jf, n) in LDS; one thread per column walks the exchanges.
+constexpr int LS_COLS = 16;
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_lu_swap_left(const DMat *__restrict__ mats, const int64_t *__restrict__ poff,
+                                                      T *__restrict__ Ab, const int32_t *__restrict__ piv, int jf) {
+    const DMat m = mats[blockIdx.y];
+    const int n = m.n;
+    const int c0 = blockIdx.x * LS_COLS;
+    if (c0 >= n || jf >= n) return;
+    T *A = Ab + m.off;
+    const int ld = m.ld;
+    const int32_t *pv = piv + poff[blockIdx.y];
+    const int rows = n - jf;
+    extern __shared__ double shs[];
+    T *Xs = reinterpret_cast<T *>(shs);                   // rows x LS_COLS, (i, c) at i * LS_COLS + c
+    const int tid = threadIdx.x;
+    staged_copy<8>(
+        rows * LS_COLS, tid, 256, [&](int e) { return A[(jf + e % rows) + (int64_t)min(c0 + e / rows, n - 1) * ld]; },
+        [&](int e, T v) { Xs[(e % rows) * LS_COLS + e / rows] = c0 + e / rows < n ? v : T(0); });
+    __syncthreads();
+    if (tid < LS_COLS && c0 + tid < n) {
+        const int c = c0 + tid;
+        const int ec = min(n, (c / LU_NB + 1) * LU_NB);
+        for (int j = max(ec, jf); j < n; ++j) {
+            const int p = pv[j];
+            if (p != j) {
+                const T x = Xs[(j - jf) * LS_COLS + tid];
+                Xs[(j - jf) * LS_COLS + tid] = Xs[(p - jf) * LS_COLS + tid];
+                Xs[(p - jf) * LS_COLS + tid] = x;
+            }
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < rows * LS_COLS; e += 256) {
+        const int i = e % rows, c = e / rows;
+        if (c0 + c < n) A[(jf + i) + (int64_t)(c0 + c) * ld] = Xs[i * LS_COLS + c];
+    }
+}
+
 template <typename T>
 int32_t lu_batched(const DMat *d_mats, const int64_t *d_poff, int nbatch, int maxn, T *A, int32_t *piv,
                    int32_t *info, bool pivot, hipStream_t s, int band) {
@@ -427,6 +612,9 @@ int32_t lu_batched(const DMat *d_mats, const int64_t *d_poff, int nbatch, int ma
     // a band of half-width `band` (band < 0: dense): column j has no entry below row j + band, and
     // with row exchanges the rows of a panel reach at most 2 band columns past their diagonal
     const bool banded = band >= 0;
+    // the left exchanges of fused panels are deferred when the deferred pass fits in LDS
+    const bool defer = pivot && (size_t)maxn * LS_COLS * sizeof(T) <= (size_t)150 * 1024;
+    int jf = -1;                        // first panel whose left exchanges are deferred
     for (int j0 = 0; j0 < maxn; j0 += LU_NB) {
         const int jend = std::min(j0 + LU_NB, maxn);
         const int mlim = banded ? std::min(maxn, jend + band) : maxn;           // panel rows end
@@ -455,12 +643,27 @@ int32_t lu_batched(const DMat *d_mats, const int64_t *d_poff, int nbatch, int ma
         else
             hipLaunchKernelGGL(k_lu_panel<T>, dim3(nbatch), dim3(256), 0, s, d_mats, d_poff, A, piv, info, j0,
                                (int)pivot);
+        const int ccols = clim - jend, crows = mlim - jend;
+        if (rows <= LP_MAXROWS) {
+            // exchanges (right of the panel), U12 and the trailing update in one launch; the
+            // exchanges of the columns on the left wait for k_lu_swap_left
+            if (defer && jf < 0) jf = j0;
+            if (pivot && !defer && j0 > 0)
+                hipLaunchKernelGGL(k_lu_laswp<T>, dim3((j0 + 255) / 256, nbatch), dim3(256), 0, s, d_mats, d_poff, A,
+                                   piv, j0, j0);     // the columns left of the panel only
+            const int nright = ccols > 0 ? (ccols + LP_COLS - 1) / LP_COLS : 0;
+            if (nright > 0) {
+                const size_t shm = (size_t)rows * (LU_NB + 1 + LP_COLS + 1) * sizeof(T);
+                hipLaunchKernelGGL(k_lu_post<T>, dim3(nright, nbatch), dim3(256), shm, s, d_mats, d_poff, A, piv, j0,
+                                   mlim, clim, (int)pivot);
+            }
+            continue;
+        }
         if (pivot) {
             int outside = maxn;
             hipLaunchKernelGGL(k_lu_laswp<T>, dim3((outside + 255) / 256, nbatch), dim3(256), 0, s, d_mats, d_poff, A,
-                               piv, j0);
+                               piv, j0, 0x7fffffff);
         }
-        const int ccols = clim - jend, crows = mlim - jend;
         if (ccols > 0) {
             hipLaunchKernelGGL(k_lu_trsm_row<T>, dim3((ccols + TRI_COLS - 1) / TRI_COLS, nbatch), dim3(TRI_COLS), 0, s,
                                d_mats, A, j0, clim);
@@ -470,6 +673,11 @@ int32_t lu_batched(const DMat *d_mats, const int64_t *d_poff, int nbatch, int ma
                                    clim);
             }
         }
+    }
+    if (defer && jf >= 0 && jf + LU_NB < maxn) {
+        const size_t shm = (size_t)(maxn - jf) * LS_COLS * sizeof(T);
+        hipLaunchKernelGGL(k_lu_swap_left<T>, dim3((maxn - LU_NB + LS_COLS - 1) / LS_COLS, nbatch), dim3(256), shm, s,
+                           d_mats, d_poff, A, piv, jf);
     }
     HKG_HIP(hipGetLastError());
     return HKG_OK;
@@ -507,7 +715,13 @@ __global__ __launch_bounds__(TRI_COLS) void k_tri_diag(const TriJob *__restrict_
     const int col = blockIdx.x * TRI_COLS + threadIdx.x;
     const bool valid = col < J.ncol;
     T *X = Xb + J.offX + (int64_t)col * J.ldX + k0;
-    for (int r = 0; r < LU_NB; ++r) xs[r][threadIdx.x] = (valid && r < nb) ? X[r] : T(0);
+    {
+        T v[LU_NB];
+#pragma unroll
+        for (int r = 0; r < LU_NB; ++r) v[r] = valid ? X[min(r, nb - 1)] : T(0);
+#pragma unroll
+        for (int r = 0; r < LU_NB; ++r) xs[r][threadIdx.x] = r < nb ? v[r] : T(0);
+    }
     __syncthreads();
     solve_block_lds<T, MODE>(Ls, xs, threadIdx.x);
     if (valid)
@@ -568,10 +782,9 @@ __global__ __launch_bounds__(256) void k_tri_band(const TriJob *__restrict__ job
     const T *Tm = Tb + J.offT;
     T *X = Xb + J.offX;
     const int tid = threadIdx.x, r = tid & 31, c = tid >> 5;
-    for (int q = tid; q < n * TB_COLS; q += 256) {
-        const int cc = q / n, i = q % n;
-        ys[i * TB_COLS + cc] = (c0 + cc < J.ncol) ? X[i + (int64_t)(c0 + cc) * J.ldX] : T(0);
-    }
+    staged_copy<8>(
+        n * TB_COLS, tid, 256, [&](int q) { return X[q % n + (int64_t)min(c0 + q / n, J.ncol - 1) * J.ldX]; },
+        [&](int q, T v) { ys[(q % n) * TB_COLS + q / n] = c0 + q / n < J.ncol ? v : T(0); });
     const bool fwd = MODE == TRI_LOWER_UNIT;
     const int nblk = (n + LU_NB - 1) / LU_NB;
     for (int bb = 0; bb < nblk; ++bb) {
@@ -584,15 +797,14 @@ __global__ __launch_bounds__(256) void k_tri_band(const TriJob *__restrict__ job
         __syncthreads();      // previous block done with Ls and with its rows of ys
         if (MODE == TRI_LOWER_UNIT_TRANS) {
             // op(T)[i][k] = T[k][i]: consecutive k are contiguous
-            for (int e = tid; e < LU_NB * w; e += 256) {
-                const int kk = e % w, rr = e / w;
-                Ls[rr * W + kk] = rr < nb ? Tm[(ka + kk) + (int64_t)(i0 + rr) * J.ldT] : T(0);
-            }
+            staged_copy<8>(
+                LU_NB * w, tid, 256, [&](int e) { return Tm[(ka + e % w) + (int64_t)(i0 + min(e / w, nb - 1)) * J.ldT]; },
+                [&](int e, T v) { Ls[(e / w) * W + e % w] = e / w < nb ? v : T(0); });
         } else {
-            for (int e = tid; e < LU_NB * w; e += 256) {
-                const int rr = e % LU_NB, kk = e / LU_NB;
-                Ls[rr * W + kk] = rr < nb ? Tm[(i0 + rr) + (int64_t)(ka + kk) * J.ldT] : T(0);
-            }
+            staged_copy<8>(
+                LU_NB * w, tid, 256,
+                [&](int e) { return Tm[(i0 + min(e % LU_NB, nb - 1)) + (int64_t)(ka + e / LU_NB) * J.ldT]; },
+                [&](int e, T v) { Ls[(e % LU_NB) * W + e / LU_NB] = e % LU_NB < nb ? v : T(0); });
         }
         __syncthreads();
         // band product with the rows already solved

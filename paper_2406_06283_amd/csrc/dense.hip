@@ -456,6 +456,25 @@ __device__ __forceinline__ void unit_lower_solve_regs(T (&x)[LU_NB], const T *__
     }
 }
 
+// op(T) x = x for one full LU_NB block held in registers, right-looking (the same operation order as
+// a wave-synchronous sweep): TRI_LOWER_UNIT forward; TRI_UPPER and TRI_LOWER_UNIT_TRANS backward
+// (the latter unit diagonal).  Entry (r, k) of op(T) at Lb[r * ldl + k].
+template <typename T, int MODE>
+__device__ __forceinline__ void block_solve_regs(T (&x)[LU_NB], const T *__restrict__ Lb, int ldl) {
+    if (MODE == TRI_LOWER_UNIT) {
+        unit_lower_solve_regs(x, Lb, ldl);
+    } else {
+#pragma unroll
+        for (int k = LU_NB - 1; k >= 0; --k) {
+            if (MODE == TRI_UPPER) x[k] = x[k] / Lb[k * ldl + k];
+            const T xk = x[k];
+#pragma unroll
+            for (int r = 0; r < k; ++r) x[r] = fma(-Lb[r * ldl + k], xk, x[r]);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+}
+
 // Everything after a panel in one launch, for panels of at most LP_MAXROWS rows (rows [j0, mlim)):
 // each block takes LP_COLS columns right of the panel (up to clim) with the panel staged in LDS,
 // exchanges their rows, solves U12 = L11^{-1} A12 and updates rows [jend, mlim) with L21 U12, all
@@ -817,9 +836,20 @@ __global__ __launch_bounds__(256) void k_tri_band(const TriJob *__restrict__ job
             }
             ys[(i0 + r) * TB_COLS + c] -= acc;
         }
-        // the diagonal block, wave-synchronously within each column
+        // the diagonal block: a full block by one thread per column in registers, the last
+        // (partial) block wave-synchronously within each column
         const int dofs = fwd ? i0 - ka : 0;     // column offset of the block in Ls
-        if (fwd) {
+        if (nb == LU_NB) {
+            __syncthreads();
+            if (tid < TB_COLS) {
+                T x[LU_NB];
+#pragma unroll
+                for (int rr = 0; rr < LU_NB; ++rr) x[rr] = ys[(i0 + rr) * TB_COLS + tid];
+                block_solve_regs<T, MODE>(x, Ls + dofs, W);
+#pragma unroll
+                for (int rr = 0; rr < LU_NB; ++rr) ys[(i0 + rr) * TB_COLS + tid] = x[rr];
+            }
+        } else if (fwd) {
             for (int k = 0; k < nb - 1; ++k) {
                 const T yk = ys[(i0 + k) * TB_COLS + c];
                 if (r > k && r < nb) ys[(i0 + r) * TB_COLS + c] -= Ls[r * W + dofs + k] * yk;

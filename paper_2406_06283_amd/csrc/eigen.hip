@@ -54,9 +54,48 @@ constexpr int SY_THREADS = 1024;
 constexpr int SY_RT = 256;          // row-pair threads of the product A0 v
 constexpr int SY_G = SY_THREADS / SY_RT;   // column groups of the product
 
-// NB: panel width; LDSVW: V and W of the panel are kept in LDS (every access of the corrections and
-// of W^T v, V^T v is then an LDS access) and copied to the global [V | W | V] at the end
-template <int NB, bool LDSVW>
+// part[g (n + 1) + r] = sum over the columns c = j + 1 + g (mod SY_G) of A0[r][c] v[c], rows j+1..n-1:
+// row pairs (16-byte loads: ld and the pair's first row are even) times SY_G column groups, eight
+// column loads in flight per thread (indices clamped into range, the surplus terms masked), summed in
+// column order
+__device__ __forceinline__ void sytrd_product_parts(const double *__restrict__ A, int ld, int n, int j,
+                                                    const double *v, double *part, int tid) {
+    const int rt = tid & (SY_RT - 1), g = tid / SY_RT;
+    const int rp0 = (j + 1) & ~1;
+    for (int r = rp0 + 2 * rt; r < n; r += 2 * SY_RT) {
+        double s0 = 0.0, s1 = 0.0;
+        for (int c0 = j + 1 + g; c0 < n; c0 += 8 * SY_G) {
+            double2 a[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                a[u] = *reinterpret_cast<const double2 *>(A + r + (int64_t)min(c0 + SY_G * u, n - 1) * ld);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const double vc = c0 + SY_G * u < n ? v[min(c0 + SY_G * u, n - 1)] : 0.0;
+                s0 = fma(a[u].x, vc, s0);
+                s1 = fma(a[u].y, vc, s1);
+            }
+        }
+        part[g * (n + 1) + r] = s0;
+        part[g * (n + 1) + r + 1] = s1;
+    }
+}
+
+// block-wide sum with a single barrier; `red` holds one slot per wave.  The slots may be written
+// again only after a later barrier that every reader of this call has passed, so callers alternate
+// between two slot sets with other barriers between their uses.
+__device__ __forceinline__ double block_sum_once(double v, double *red) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    v = wave_sum(v);
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int i = 0; i < nw; ++i) t += red[i];
+    return t;
+}
+
+// NB: panel width; V and W of the panel in the global workspace
+template <int NB>
 __global__ __launch_bounds__(SY_THREADS) void k_sytrd_panel(const SubDev *__restrict__ subs, double *__restrict__ Sq,
                                                             double *__restrict__ VWVb, double *__restrict__ dout,
                                                             double *__restrict__ eout, double *__restrict__ tout,
@@ -76,14 +115,13 @@ __global__ __launch_bounds__(SY_THREADS) void k_sytrd_panel(const SubDev *__rest
     double *part = sh + 2 * n;       // SY_G (n + 1): partial products per column group
     double *t12 = part + SY_G * (n + 1);   // 2 NB
     double *vw = t12 + 2 * NB;       // 2 NB: W[j, :], V[j, :]
-    double *red = vw + 2 * NB;       // 16
-    // V and W of the panel (column q at q n): in LDS after red, or the global workspace
-    double *V = LDSVW ? red + 16 : Vg;
+    double *red = vw + 2 * NB;       // 32
+    double *V = Vg;                  // V and W of the panel (column q at q n)
     double *W = V + (int64_t)NB * n;
     double *V2 = Vg + (int64_t)2 * NB * n;
     double dmine = 0.0, emine = 0.0, tmine = 0.0;   // column tid's d, e, tau (tid < jb)
     // zero the panel's columns of V, W (and V2 in global memory; rows not written stay zero)
-    for (int64_t q = tid; q < (int64_t)(LDSVW ? 2 : 3) * NB * n; q += SY_THREADS) V[q] = 0.0;
+    for (int64_t q = tid; q < (int64_t)3 * NB * n; q += SY_THREADS) V[q] = 0.0;
     __syncthreads();
     for (int kk = 0; kk < jb; ++kk) {
         const int j = j0 + kk;
@@ -126,7 +164,7 @@ __global__ __launch_bounds__(SY_THREADS) void k_sytrd_panel(const SubDev *__rest
             v[r] = vr;
             A[r + (int64_t)j * ld] = vr;
             V[r + (int64_t)kk * n] = vr;
-            if (!LDSVW) V2[r + (int64_t)kk * n] = vr;
+            V2[r + (int64_t)kk * n] = vr;
         }
         if (tid == kk) {            // stored after the panel (a store per column stalls its wave)
             dmine = p[j];
@@ -136,30 +174,7 @@ __global__ __launch_bounds__(SY_THREADS) void k_sytrd_panel(const SubDev *__rest
         __syncthreads();
         if (t == 0.0) continue;          // H_j = I: W column stays zero
         // 3. p = t (A0 v - V (W^T v) - W (V^T v)) on rows j+1..n-1
-        {
-            // row pairs (16-byte loads: ld and the pair's first row are even) times four column
-            // groups, eight column loads in flight per thread (indices clamped into range, the
-            // surplus terms masked), summed in column order
-            const int rt = tid & (SY_RT - 1), g = tid / SY_RT;
-            const int rp0 = (j + 1) & ~1;
-            for (int r = rp0 + 2 * rt; r < n; r += 2 * SY_RT) {
-                double s0 = 0.0, s1 = 0.0;
-                for (int c0 = j + 1 + g; c0 < n; c0 += 8 * SY_G) {
-                    double2 a[8];
-#pragma unroll
-                    for (int u = 0; u < 8; ++u)
-                        a[u] = *reinterpret_cast<const double2 *>(A + r + (int64_t)min(c0 + SY_G * u, n - 1) * ld);
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        const double vc = c0 + SY_G * u < n ? v[min(c0 + SY_G * u, n - 1)] : 0.0;
-                        s0 = fma(a[u].x, vc, s0);
-                        s1 = fma(a[u].y, vc, s1);
-                    }
-                }
-                part[g * (n + 1) + r] = s0;
-                part[g * (n + 1) + r + 1] = s1;
-            }
-        }
+        sytrd_product_parts(A, ld, n, j, v, part, tid);
         for (int q2 = wv; q2 < 2 * kk; q2 += SY_THREADS / 64) {
             const double *col = (q2 < kk) ? W + (int64_t)q2 * n : V + (int64_t)(q2 - kk) * n;
             double s = 0.0;
@@ -197,14 +212,107 @@ __global__ __launch_bounds__(SY_THREADS) void k_sytrd_panel(const SubDev *__rest
         e[j0 + tid] = emine;
         tau[j0 + tid] = tmine;
     }
-    if (LDSVW) {
-        __syncthreads();
-        for (int64_t q = tid; q < (int64_t)NB * n; q += SY_THREADS) {
-            const double x = V[q], y = W[q];
-            Vg[q] = x;
-            Vg[q + (int64_t)NB * n] = y;
-            Vg[q + (int64_t)2 * NB * n] = x;
+}
+
+
+// The panel with V and W in LDS (every access of the corrections and of W^T v, V^T v is an LDS
+// access; copied to the global [V | W | V] at the end), n <= SY_THREADS: thread t owns row j + t in
+// the column phases and keeps its values in registers, so a column takes five barriers.  A0 is not
+// modified within the panel except for the reflector written into column j while column j is
+// processed, so the next column's entry of each row is loaded one column ahead.
+template <int NB>
+__global__ __launch_bounds__(SY_THREADS) void k_sytrd_panel_lds(const SubDev *__restrict__ subs,
+                                                                double *__restrict__ Sq, double *__restrict__ VWVb,
+                                                                double *__restrict__ dout, double *__restrict__ eout,
+                                                                double *__restrict__ tout, int j0) {
+    extern __shared__ double sh[];
+    const SubDev sd = subs[blockIdx.x];
+    const int n = sd.nI;
+    double *A = Sq + sd.offM;
+    const int ld = sd.ldM;
+    double *d = dout + sd.offI, *e = eout + sd.offI, *tau = tout + sd.offI;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    if (j0 >= n - 1) return;
+    const int jb = min(NB, n - 1 - j0);
+    double *Vg = VWVb + 3 * NB * sd.offI;
+    double *v = sh;                  // n
+    double *p = sh + n;              // n: the corrected column
+    double *part = sh + 2 * n;       // SY_G (n + 1)
+    double *t12 = part + SY_G * (n + 1);   // 2 NB
+    double *red = t12 + 4 * NB;      // two sets of 16 slots
+    double *V = red + 32;            // NB x n
+    double *W = V + (int64_t)NB * n; // NB x n
+    double dmine = 0.0, emine = 0.0, tmine = 0.0;   // column tid's d, e, tau (tid < jb)
+    for (int64_t q = tid; q < (int64_t)2 * NB * n; q += SY_THREADS) V[q] = 0.0;
+    double anext = j0 + tid < n ? A[(j0 + tid) + (int64_t)j0 * ld] : 0.0;
+    __syncthreads();
+    for (int kk = 0; kk < jb; ++kk) {
+        const int j = j0 + kk;
+        const int r = j + tid;
+        const bool own = r < n;
+        // 1. corrected column j (rows j..n-1) and the squared norm of its part below j + 1
+        double s = anext;
+        anext = (r + 1 < n && kk + 1 < jb) ? A[(r + 1) + (int64_t)(j + 1) * ld] : 0.0;
+        if (own) {
+            for (int q = 0; q < kk; ++q)
+                s -= V[r + (int64_t)q * n] * W[j + (int64_t)q * n] + W[r + (int64_t)q * n] * V[j + (int64_t)q * n];
+            p[r] = s;
         }
+        const double xn2 = block_sum_once(own && r >= j + 2 ? s * s : 0.0, red);
+        // 2. reflector from x = p[j+1 .. n-1]
+        const double alpha = p[j + 1];
+        double t = 0.0, beta = alpha, scal = 0.0;
+        if (xn2 != 0.0) {
+            beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+            t = (beta - alpha) / beta;
+            scal = 1.0 / (alpha - beta);
+        }
+        const bool below = own && r >= j + 1;
+        if (below) {
+            const double vr = (r == j + 1) ? 1.0 : (xn2 != 0.0 ? s * scal : 0.0);
+            v[r] = vr;
+            A[r + (int64_t)j * ld] = vr;
+            V[r + (int64_t)kk * n] = vr;
+        }
+        if (tid == kk) {            // stored after the panel (a store per column stalls its wave)
+            dmine = p[j];
+            emine = beta;
+            tmine = t;
+        }
+        __syncthreads();
+        if (t == 0.0) continue;          // H_j = I: W column stays zero
+        // 3. A0 v in column-group parts, and t12[q] = W_q . v, t12[kk + q] = V_q . v
+        sytrd_product_parts(A, ld, n, j, v, part, tid);
+        for (int q2 = wv; q2 < 2 * kk; q2 += SY_THREADS / 64) {
+            const double *col = (q2 < kk) ? W + (int64_t)q2 * n : V + (int64_t)(q2 - kk) * n;
+            double sq = 0.0;
+            for (int rr = j + 1 + lane; rr < n; rr += 64) sq = fma(col[rr], v[rr], sq);
+            sq = wave_sum(sq);
+            if (lane == 0) t12[q2] = sq;
+        }
+        __syncthreads();
+        // 4. p = t (A0 v - V (W^T v) - W (V^T v)); w = p - (t/2)(p . v) v
+        double pr = 0.0, vr = 0.0;
+        if (below) {
+            double y = (part[r] + part[(n + 1) + r]) + (part[2 * (n + 1) + r] + part[3 * (n + 1) + r]);
+            for (int q = 0; q < kk; ++q) y -= V[r + (int64_t)q * n] * t12[q] + W[r + (int64_t)q * n] * t12[kk + q];
+            pr = t * y;
+            vr = v[r];
+        }
+        const double K = 0.5 * t * block_sum_once(pr * vr, red + 16);
+        if (below) W[r + (int64_t)kk * n] = pr - K * vr;
+        __syncthreads();
+    }
+    if (tid < jb) {
+        d[j0 + tid] = dmine;
+        e[j0 + tid] = emine;
+        tau[j0 + tid] = tmine;
+    }
+    for (int64_t q = tid; q < (int64_t)NB * n; q += SY_THREADS) {
+        const double x = V[q], y = W[q];
+        Vg[q] = x;
+        Vg[q + (int64_t)NB * n] = y;
+        Vg[q + (int64_t)2 * NB * n] = x;
     }
 }
 
@@ -236,11 +344,11 @@ __global__ void k_sytrd_last(const SubDev *__restrict__ subs, const double *__re
 int32_t tridiagonalize_blocked(const SubDev *d_sub, int nsub, int maxnI, double *Sq, double *VWV, double *d, double *e,
                                double *tau, hipStream_t s) {
     const int tiles = (maxnI + 63) / 64;
-    const size_t base = (size_t)(2 * maxnI + SY_G * (maxnI + 1) + 16);
+    const size_t base = (size_t)(2 * maxnI + SY_G * (maxnI + 1) + 32);
     const size_t shm_lds = (base + 4 * SY_NB_LDS + (size_t)2 * SY_NB_LDS * maxnI) * sizeof(double);
-    if (shm_lds <= (size_t)156 * 1024) {
+    if (shm_lds <= (size_t)156 * 1024 && maxnI <= SY_THREADS) {
         for (int j0 = 0; j0 < maxnI; j0 += SY_NB_LDS) {
-            hipLaunchKernelGGL((k_sytrd_panel<SY_NB_LDS, true>), dim3(nsub), dim3(SY_THREADS), shm_lds, s, d_sub, Sq, VWV,
+            hipLaunchKernelGGL(k_sytrd_panel_lds<SY_NB_LDS>, dim3(nsub), dim3(SY_THREADS), shm_lds, s, d_sub, Sq, VWV,
                                d, e, tau, j0);
             hipLaunchKernelGGL(k_sytrd_update<SY_NB_LDS>, dim3(tiles * tiles, nsub), dim3(256), 0, s, d_sub, Sq, VWV, j0,
                                tiles);
@@ -248,7 +356,7 @@ int32_t tridiagonalize_blocked(const SubDev *d_sub, int nsub, int maxnI, double 
     } else {
         const size_t shm = (base + 4 * SY_NB) * sizeof(double);
         for (int j0 = 0; j0 < maxnI; j0 += SY_NB) {
-            hipLaunchKernelGGL((k_sytrd_panel<SY_NB, false>), dim3(nsub), dim3(SY_THREADS), shm, s, d_sub, Sq, VWV, d, e,
+            hipLaunchKernelGGL(k_sytrd_panel<SY_NB>, dim3(nsub), dim3(SY_THREADS), shm, s, d_sub, Sq, VWV, d, e,
                                tau, j0);
             hipLaunchKernelGGL(k_sytrd_update<SY_NB>, dim3(tiles * tiles, nsub), dim3(256), 0, s, d_sub, Sq, VWV, j0,
                                tiles);

@@ -784,12 +784,13 @@ __global__ __launch_bounds__(256) void k_tri_update(const TriJob *__restrict__ j
 // the vectors in LDS: per row block, the band rows of op(T) next to it (and its diagonal block)
 // are staged in LDS, every (row, column) subtracts its band product, and the diagonal block is
 // solved wave-synchronously (lanes 0-31 and 32-63 of a wave hold one column each; a wave's LDS
-// operations complete in order).
+// operations complete in order).  TIN: the right-hand sides are the rows of Xin (a square matrix
+// with the layout of X), read as the transpose on the fly.
 constexpr int TB_COLS = 8;
 
-template <typename T, int MODE>
+template <typename T, int MODE, bool TIN>
 __global__ __launch_bounds__(256) void k_tri_band(const TriJob *__restrict__ jobs, const T *__restrict__ Tb,
-                                                  T *__restrict__ Xb, int band) {
+                                                  const T *__restrict__ Xin, T *__restrict__ Xb, int band) {
     const TriJob J = jobs[blockIdx.y];
     const int c0 = blockIdx.x * TB_COLS;
     const int n = J.n;
@@ -801,9 +802,18 @@ __global__ __launch_bounds__(256) void k_tri_band(const TriJob *__restrict__ job
     const T *Tm = Tb + J.offT;
     T *X = Xb + J.offX;
     const int tid = threadIdx.x, r = tid & 31, c = tid >> 5;
-    staged_copy<8>(
-        n * TB_COLS, tid, 256, [&](int q) { return X[q % n + (int64_t)min(c0 + q / n, J.ncol - 1) * J.ldX]; },
-        [&](int q, T v) { ys[(q % n) * TB_COLS + q / n] = c0 + q / n < J.ncol ? v : T(0); });
+    if (TIN) {
+        // right-hand side c0 + cc is row c0 + cc of Xin: eight consecutive entries per column of Xin
+        const T *Xi = Xin + J.offX;
+        staged_copy<8>(
+            n * TB_COLS, tid, 256,
+            [&](int q) { return Xi[min(c0 + q % TB_COLS, J.ncol - 1) + (int64_t)(q / TB_COLS) * J.ldX]; },
+            [&](int q, T v) { ys[q] = c0 + q % TB_COLS < J.ncol ? v : T(0); });
+    } else {
+        staged_copy<8>(
+            n * TB_COLS, tid, 256, [&](int q) { return X[q % n + (int64_t)min(c0 + q / n, J.ncol - 1) * J.ldX]; },
+            [&](int q, T v) { ys[(q % n) * TB_COLS + q / n] = c0 + q / n < J.ncol ? v : T(0); });
+    }
     const bool fwd = MODE == TRI_LOWER_UNIT;
     const int nblk = (n + LU_NB - 1) / LU_NB;
     for (int bb = 0; bb < nblk; ++bb) {
@@ -869,24 +879,32 @@ __global__ __launch_bounds__(256) void k_tri_band(const TriJob *__restrict__ job
     }
 }
 
+bool tri_band_fits(int maxn, int band, size_t elem) {
+    return band >= 0 && ((size_t)maxn * TB_COLS + (size_t)LU_NB * (band + LU_NB)) * elem <= (size_t)144 * 1024;
+}
+
 template <typename T>
 int32_t tri_solve_batched(const TriJob *d_jobs, int nbatch, int maxn, int maxcol, const T *Tm, T *X, int mode,
-                          hipStream_t s, int band) {
+                          hipStream_t s, int band, const T *Xin) {
     if (nbatch == 0 || maxn == 0 || maxcol == 0) return HKG_OK;
-    if (band >= 0) {
+    if (band >= 0 && tri_band_fits(maxn, band, sizeof(T))) {
         const size_t shm = ((size_t)maxn * TB_COLS + (size_t)LU_NB * (band + LU_NB)) * sizeof(T);
-        if (shm <= (size_t)144 * 1024) {
-            const dim3 g((maxcol + TB_COLS - 1) / TB_COLS, nbatch);
-            if (mode == TRI_LOWER_UNIT)
-                hipLaunchKernelGGL((k_tri_band<T, TRI_LOWER_UNIT>), g, dim3(256), shm, s, d_jobs, Tm, X, band);
-            else if (mode == TRI_UPPER)
-                hipLaunchKernelGGL((k_tri_band<T, TRI_UPPER>), g, dim3(256), shm, s, d_jobs, Tm, X, band);
-            else
-                hipLaunchKernelGGL((k_tri_band<T, TRI_LOWER_UNIT_TRANS>), g, dim3(256), shm, s, d_jobs, Tm, X, band);
-            HKG_HIP(hipGetLastError());
-            return HKG_OK;
+        const dim3 g((maxcol + TB_COLS - 1) / TB_COLS, nbatch);
+        if (Xin) {
+            if (mode != TRI_LOWER_UNIT) return HKG_EINVAL;
+            hipLaunchKernelGGL((k_tri_band<T, TRI_LOWER_UNIT, true>), g, dim3(256), shm, s, d_jobs, Tm, Xin, X, band);
+        } else if (mode == TRI_LOWER_UNIT) {
+            hipLaunchKernelGGL((k_tri_band<T, TRI_LOWER_UNIT, false>), g, dim3(256), shm, s, d_jobs, Tm, X, X, band);
+        } else if (mode == TRI_UPPER) {
+            hipLaunchKernelGGL((k_tri_band<T, TRI_UPPER, false>), g, dim3(256), shm, s, d_jobs, Tm, X, X, band);
+        } else {
+            hipLaunchKernelGGL((k_tri_band<T, TRI_LOWER_UNIT_TRANS, false>), g, dim3(256), shm, s, d_jobs, Tm, X, X,
+                               band);
         }
+        HKG_HIP(hipGetLastError());
+        return HKG_OK;
     }
+    if (Xin) return HKG_EINVAL;
     const int nblk = (maxn + LU_NB - 1) / LU_NB;
     const int urows = band >= 0 ? std::min(maxn, band) : maxn;      // rows of one update at most
     const int tiles_m = (urows + GT - 1) / GT, tiles_n = (maxcol + GT - 1) / GT;
@@ -915,8 +933,9 @@ int32_t tri_solve_batched(const TriJob *d_jobs, int nbatch, int maxn, int maxcol
     return HKG_OK;
 }
 template int32_t tri_solve_batched<double>(const TriJob *, int, int, int, const double *, double *, int, hipStream_t,
-                                           int);
-template int32_t tri_solve_batched<float>(const TriJob *, int, int, int, const float *, float *, int, hipStream_t, int);
+                                           int, const double *);
+template int32_t tri_solve_batched<float>(const TriJob *, int, int, int, const float *, float *, int, hipStream_t, int,
+                                          const float *);
 
 // ------------------------------------------------------------------------------------------------
 // Inverse of one packed LU (P A = L U) by recursive block triangular inversion: the LU_NB diagonal

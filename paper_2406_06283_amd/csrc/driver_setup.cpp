@@ -403,9 +403,14 @@ int32_t coarse_space(hkgeneo_ctx *c, hipStream_t s) {
     HKG_HIP(hipStreamWaitEvent(s, c->ev_join3, 0));
     HKG_TRY(tri_solve_batched<double>(dp<TriJob>(c->jobsSq), ns, c->max_nI, c->max_nI, dp<double>(c->wCII),
                                       dp<double>(c->wS), TRI_LOWER_UNIT, s, c->band_I));
-    HKG_TRY(transpose_batched<double>(dp<DMat>(c->matsSq), ns, c->max_nI, dp<double>(c->wS), dp<double>(c->wW), s));
-    HKG_TRY(tri_solve_batched<double>(dp<TriJob>(c->jobsSq), ns, c->max_nI, c->max_nI, dp<double>(c->wCII),
-                                      dp<double>(c->wW), TRI_LOWER_UNIT, s, c->band_I));
+    if (tri_band_fits(c->max_nI, c->band_I, sizeof(double))) {      // the transpose read on the fly
+        HKG_TRY(tri_solve_batched<double>(dp<TriJob>(c->jobsSq), ns, c->max_nI, c->max_nI, dp<double>(c->wCII),
+                                          dp<double>(c->wW), TRI_LOWER_UNIT, s, c->band_I, dp<double>(c->wS)));
+    } else {
+        HKG_TRY(transpose_batched<double>(dp<DMat>(c->matsSq), ns, c->max_nI, dp<double>(c->wS), dp<double>(c->wW), s));
+        HKG_TRY(tri_solve_batched<double>(dp<TriJob>(c->jobsSq), ns, c->max_nI, c->max_nI, dp<double>(c->wCII),
+                                          dp<double>(c->wW), TRI_LOWER_UNIT, s, c->band_I));
+    }
     HKG_TRY(walloc(c, &c->wT, (size_t)c->nM * sizeof(double)));
     HKG_TRY(scale_sym(dsub, ns, c->max_nI, dp<double>(c->wCII), dp<double>(c->wW), dp<double>(c->wT), s));
     // tridiagonal form and selection

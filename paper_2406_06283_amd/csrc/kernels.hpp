@@ -17,9 +17,13 @@ template <typename T>
 int32_t lu_batched(const DMat *d_mats, const int64_t *d_poff, int nbatch, int maxn, T *A, int32_t *piv,
                    int32_t *info, bool pivot, hipStream_t s, int band = -1);
 template <typename T>
-// band >= 0: op(T) has no entry farther than `band` from the diagonal
+// band >= 0: op(T) has no entry farther than `band` from the diagonal.  Xin (banded lower solves
+// with tri_band_fits only, square right-hand sides): solve for the transpose of Xin (same layout as
+// X) into X, Xin untouched
 int32_t tri_solve_batched(const TriJob *d_jobs, int nbatch, int maxn, int maxcol, const T *Tm, T *X, int mode,
-                          hipStream_t s, int band = -1);
+                          hipStream_t s, int band = -1, const T *Xin = nullptr);
+// whether the one-launch banded solve serves matrices of up to maxn rows with this half-bandwidth
+bool tri_band_fits(int maxn, int band, size_t elem);
 constexpr int LU_BLOCK = 32;    // block size of the dense LU, triangular solves and inversions
 
 // diagonal LU_BLOCK blocks of L^{-1} (unit lower) and U^{-1} of one packed LU, into Linv / Uinv

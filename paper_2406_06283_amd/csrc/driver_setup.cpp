@@ -353,7 +353,7 @@ int32_t coarse_space(hkgeneo_ctx *c, hipStream_t s) {
     HKG_TRY(walloc(c, &c->wPivC, c->nPiv * sizeof(int32_t)));
     HKG_TRY(walloc(c, &c->wInfoC, ns * sizeof(int32_t)));
     HKG_TRY(walloc(c, &c->wFlagSpd, ns * sizeof(int32_t)));
-    // C_II = L U without exchanges (positive pivots <=> SPD) on the third stream, concurrently with
+    // C_II = L U without exchanges (= L D L^T; positive pivots <=> SPD) on the third stream, concurrently with
     // the Gamma block's LU and the Schur complement; the flags are read back after the selection
     // (enqueued by a helper thread, so that this thread's launches for the Gamma block start at once)
     HKG_HIP(hipEventRecord(c->ev_fork3, s));
@@ -361,8 +361,12 @@ int32_t coarse_space(hkgeneo_ctx *c, hipStream_t s) {
     int32_t st_cii = HKG_OK;
     std::string err_cii;
     std::thread enq_cii([&]() {
-        st_cii = lu_batched<double>(dp<DMat>(c->matsSq), dp<int64_t>(c->poffSub), ns, c->max_nI, dp<double>(c->wCII),
-                                    dp<int32_t>(c->wPivC), dp<int32_t>(c->wInfoC), false, c->s3, c->band_I);
+        if (ldl_band_fits(c->max_nI, c->band_I))
+            st_cii = ldl_band(dsub, ns, c->max_nI, dp<double>(c->wCII), c->band_I, c->s3);
+        else
+            st_cii = lu_batched<double>(dp<DMat>(c->matsSq), dp<int64_t>(c->poffSub), ns, c->max_nI,
+                                        dp<double>(c->wCII), dp<int32_t>(c->wPivC), dp<int32_t>(c->wInfoC), false,
+                                        c->s3, c->band_I);
         if (st_cii == HKG_OK) st_cii = check_spd_pivots(dsub, ns, dp<double>(c->wCII), dp<int32_t>(c->wFlagSpd), c->s3);
         if (st_cii == HKG_OK && hipEventRecord(c->ev_join3, c->s3) != hipSuccess) {
             set_last_error("recording the end of the C_II factorisation");

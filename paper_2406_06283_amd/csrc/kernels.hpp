@@ -72,6 +72,10 @@ int32_t apply_pivots_rows(const SubDev *d_sub, int nsub, int maxcol, const int32
 int32_t copy_bii(const SubDev *d_sub, int nsub, int maxnI, const double *BIO, double *out, hipStream_t s);
 int32_t copy_bii_f32(const SubDev *d_sub, int nsub, int maxnI, const double *BIO, float *out, hipStream_t s);
 int32_t check_spd_pivots(const SubDev *d_sub, int nsub, const double *C, int32_t *flag, hipStream_t s);
+// C_II = L D L^T in place (packed as an LU without exchanges) when its band fits the one-launch
+// kernel (ldl_band_fits); C at offSq with ld n_I
+bool ldl_band_fits(int maxnI, int band);
+int32_t ldl_band(const SubDev *d_sub, int nsub, int maxnI, double *C, int band, hipStream_t s);
 // T = D^{-1/2} S D^{-1/2} into the padded (offM, ldM) layout
 int32_t scale_sym(const SubDev *d_sub, int nsub, int maxnI, const double *C, const double *S, double *T, hipStream_t s);
 

@@ -189,6 +189,89 @@ __global__ __launch_bounds__(256) void k_check_spd(const SubDev *__restrict__ su
     if (threadIdx.x == 0) flag[blockIdx.x] = bad;
 }
 
+// C_II = L D L^T for every subdomain (C_II of Def 2.14 restricted to the interior dofs: symmetric
+// positive definite, and banded, no entry farther than `band` from the diagonal), one workgroup per
+// subdomain with the lower band in LDS.  Column j is one step: every entry (j+t, j+s),
+// 1 <= s <= t <= band, of the trailing window takes its rank-1 term -l_t a_s (l_t = a_t / d_j) from
+// the thread that owns the pair (s, t); one barrier per step.  Written back in the packed form of an
+// LU without exchanges: unit L below the diagonal, D on it, D L^T above (only the band).
+constexpr int LDL_THREADS = 256;
+constexpr int LDL_PAIRS = 4;            // (s, t) pairs per thread: band <= 44
+
+bool ldl_band_fits(int maxnI, int band) {
+    return band >= 0 && band * (band + 1) / 2 <= LDL_THREADS * LDL_PAIRS &&
+           (size_t)2 * maxnI * (band + 1) * sizeof(double) <= (size_t)156 * 1024;
+}
+
+__global__ __launch_bounds__(LDL_THREADS) void k_ldl_band(const SubDev *__restrict__ subs, double *__restrict__ C,
+                                                          int band) {
+    extern __shared__ double shl[];
+    const SubDev sd = subs[blockIdx.x];
+    const int n = sd.nI;
+    if (n == 0) return;
+    const int w = band + 1;
+    double *Bd = shl;                          // Bd[j w + t]: current entry (j + t, j)
+    double *Lo = shl + (int64_t)n * w;         // Lo[j w] = d_j, Lo[j w + t] = L[j + t][j]
+    double *A = C + sd.offSq;                  // n x n, ld n
+    const int tid = threadIdx.x;
+    for (int e0 = tid; e0 < n * w; e0 += LDL_THREADS * 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = min(e0 + u * LDL_THREADS, n * w - 1), j = e / w, t = e % w;
+            v[u] = A[min(j + t, n - 1) + (int64_t)j * n];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + u * LDL_THREADS;
+            if (e < n * w) Bd[e] = (e / w) + (e % w) < n ? v[u] : 0.0;
+        }
+    }
+    // this thread's pairs (s, t), enumerated t = 1.., s = 1..t
+    const int npair = band * (band + 1) / 2;
+    int ps[LDL_PAIRS], pt[LDL_PAIRS];
+#pragma unroll
+    for (int u = 0; u < LDL_PAIRS; ++u) {
+        const int q = tid + u * LDL_THREADS;
+        int t = 1;
+        while (t * (t + 1) / 2 <= q) ++t;
+        pt[u] = q < npair ? t : n;          // t = n: never applied
+        ps[u] = q < npair ? q - t * (t - 1) / 2 + 1 : 1;
+    }
+    __syncthreads();
+    for (int j = 0; j < n; ++j) {
+        const double *col = Bd + (int64_t)j * w;
+        const double d = col[0];
+        const double rd = 1.0 / d;
+#pragma unroll
+        for (int u = 0; u < LDL_PAIRS; ++u) {
+            const int s = ps[u], t = pt[u];
+            if (j + t < n) Bd[(int64_t)(j + s) * w + (t - s)] -= (col[t] * rd) * col[s];
+        }
+        if (tid < w) Lo[(int64_t)j * w + tid] = tid == 0 ? d : (j + tid < n ? col[tid] * rd : 0.0);
+        __syncthreads();
+    }
+    for (int e = tid; e < n * w; e += LDL_THREADS) {
+        const int j = e / w, t = e % w;
+        if (j + t >= n) continue;
+        const double v = Lo[e];
+        if (t == 0) {
+            A[j + (int64_t)j * n] = v;
+        } else {
+            A[(j + t) + (int64_t)j * n] = v;
+            A[j + (int64_t)(j + t) * n] = Lo[(int64_t)j * w] * v;
+        }
+    }
+}
+
+int32_t ldl_band(const SubDev *d_sub, int nsub, int maxnI, double *C, int band, hipStream_t s) {
+    if (!ldl_band_fits(maxnI, band)) return HKG_EINVAL;
+    const size_t shm = (size_t)2 * maxnI * (band + 1) * sizeof(double);
+    hipLaunchKernelGGL(k_ldl_band, dim3(nsub), dim3(LDL_THREADS), shm, s, d_sub, C, band);
+    HKG_HIP(hipGetLastError());
+    return HKG_OK;
+}
+
 int32_t check_spd_pivots(const SubDev *d_sub, int nsub, const double *C, int32_t *flag, hipStream_t s) {
     hipLaunchKernelGGL(k_check_spd, dim3(nsub), dim3(256), 0, s, d_sub, C, flag);
     HKG_HIP(hipGetLastError());

@@ -391,10 +391,12 @@ int32_t coarse_space(hkgeneo_ctx *c, hipStream_t s) {
     // X = B~_GG^{-1} B_GI ; S = B_II - B_IG X
     HKG_TRY(gather_gamma_rows(dsub, ns, c->max_nI, dp<double>(c->wBIO), dp<double>(c->wGI), s));
     HKG_TRY(apply_pivots_rows<double>(dsub, ns, c->max_nI, dp<int32_t>(c->wPiv), dp<double>(c->wGI), 0, s));
+    // the Gamma block is dense: as a band of half-width n_G - 1 the solves take one launch each
+    const int bandG = tri_band_fits(c->max_nG, c->max_nG - 1, sizeof(double)) ? c->max_nG - 1 : -1;
     HKG_TRY(tri_solve_batched<double>(dp<TriJob>(c->jobsGI), ns, c->max_nG, c->max_nI, dp<double>(c->wGG),
-                                      dp<double>(c->wGI), TRI_LOWER_UNIT, s));
+                                      dp<double>(c->wGI), TRI_LOWER_UNIT, s, bandG));
     HKG_TRY(tri_solve_batched<double>(dp<TriJob>(c->jobsGI), ns, c->max_nG, c->max_nI, dp<double>(c->wGG),
-                                      dp<double>(c->wGI), TRI_UPPER, s));
+                                      dp<double>(c->wGI), TRI_UPPER, s, bandG));
     HKG_TRY(copy_bii(dsub, ns, c->max_nI, dp<double>(c->wBIO), dp<double>(c->wS), s));
     HKG_TRY(gemm_batched<double>(dp<GemmJob>(c->gjobsSchur), ns, c->max_nI, c->max_nI, dp<double>(c->wBIO),
                                  dp<double>(c->wGI), dp<double>(c->wS), -1.0, 1.0, false, false, s));

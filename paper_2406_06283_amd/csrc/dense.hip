@@ -879,7 +879,194 @@ __global__ __launch_bounds__(256) void k_tri_band(const TriJob *__restrict__ job
     }
 }
 
+// Wide banded triangular solve: TW_COLS right-hand sides per block and only a window of the solution
+// in LDS (the band rows behind the current row block and the block itself, a ring of band + LU_NB
+// rows), so the blocks are few and wide and all resident at once.  Per row block: the band of op(T)
+// and the block's right-hand-side rows are staged; every thread takes a 4-row x 2-column tile of the
+// band product (op(T) entries broadcast from LDS, two columns per 16-byte window read); threads
+// 0..TW_COLS-1 solve the diagonal block for one column each in registers; the solved rows are
+// written out by all threads, 32 consecutive rows of a column at a time.
+constexpr int TW_COLS = 64;
+
+template <typename T>
+struct vec2_of;
+template <>
+struct vec2_of<double> {
+    using type = double2;
+};
+template <>
+struct vec2_of<float> {
+    using type = float2;
+};
+
+size_t tri_bandw_lds(int band, size_t elem) {
+    return ((size_t)(band + 2 * LU_NB) * TW_COLS + (size_t)LU_NB * (band + LU_NB)) * elem;
+}
+
+template <typename T, int MODE, bool TIN>
+__global__ __launch_bounds__(256) void k_tri_bandw(const TriJob *__restrict__ jobs, const T *__restrict__ Tb,
+                                                   const T *__restrict__ Xin, T *__restrict__ Xb, int band) {
+    using T2 = typename vec2_of<T>::type;
+    const TriJob J = jobs[blockIdx.y];
+    const int c0 = blockIdx.x * TW_COLS;
+    const int n = J.n;
+    if (c0 >= J.ncol || n == 0) return;
+    const int ncb = min(TW_COLS, J.ncol - c0);
+    extern __shared__ double shw[];
+    const int WIN = band + 2 * LU_NB;              // window rows; row r sits in slot r mod WIN
+    const int W = band + LU_NB;                    // row stride of the staged band
+    T *win = reinterpret_cast<T *>(shw);           // WIN x TW_COLS, row-major
+    T *Ls = win + (int64_t)WIN * TW_COLS;          // LU_NB x W: Ls[r W + k - ka] = op(T)[i0 + r][k]
+    const T *Tm = Tb + J.offT;
+    T *X = Xb + J.offX;
+    const T *Xi = TIN ? Xin + J.offX : X;
+    const int tid = threadIdx.x;
+    const bool fwd = MODE == TRI_LOWER_UNIT;
+    const int nblk = (n + LU_NB - 1) / LU_NB;
+    const int cp = tid & 31, rg = tid >> 5;        // band-product tile: rows 4 rg.., columns 2 cp..
+    // the solved rows of a block out, 32 consecutive rows of a column at a time (the window keeps
+    // them until the next block's rows are staged: its slots are band + 2 LU_NB, so the rows staged
+    // next never land on the rows being written out)
+    auto write_out = [&](int r0, int nr) {
+        const int t0 = r0 % WIN;
+        for (int q = tid; q < LU_NB * TW_COLS; q += 256) {
+            const int rr = q % LU_NB, cc = q / LU_NB;
+            if (rr < nr && cc < ncb) {
+                int sl = t0 + rr;
+                if (sl >= WIN) sl -= WIN;
+                X[(r0 + rr) + (int64_t)(c0 + cc) * J.ldX] = win[sl * TW_COLS + cc];
+            }
+        }
+    };
+    int pi0 = 0, pnb = 0;                          // the block solved last (pnb = 0: none)
+    for (int bb = 0; bb < nblk; ++bb) {
+        const int b = fwd ? bb : nblk - 1 - bb;
+        const int i0 = b * LU_NB, nb = min(LU_NB, n - i0);
+        const int ka = fwd ? max(0, i0 - band) : i0;
+        const int kb = fwd ? i0 + nb : min(n, i0 + nb + band);
+        const int w = kb - ka;
+        const int s0 = i0 % WIN;                   // slot of row i0 (the block's rows are s0, s0+1, .. mod WIN)
+        __syncthreads();      // the previous block is solved; Ls is free
+        if (pnb > 0) write_out(pi0, pnb);
+        if (MODE == TRI_LOWER_UNIT_TRANS) {
+            staged_copy<8>(
+                LU_NB * w, tid, 256, [&](int e) { return Tm[(ka + e % w) + (int64_t)(i0 + min(e / w, nb - 1)) * J.ldT]; },
+                [&](int e, T v) { Ls[(e / w) * W + e % w] = e / w < nb ? v : T(0); });
+        } else {
+            staged_copy<8>(
+                LU_NB * w, tid, 256,
+                [&](int e) { return Tm[(i0 + min(e % LU_NB, nb - 1)) + (int64_t)(ka + e / LU_NB) * J.ldT]; },
+                [&](int e, T v) { Ls[(e % LU_NB) * W + e / LU_NB] = e % LU_NB < nb ? v : T(0); });
+        }
+        if (TIN) {            // right-hand side c is row c of Xin: consecutive columns contiguous
+            staged_copy<8>(
+                LU_NB * TW_COLS, tid, 256,
+                [&](int q) {
+                    return Xi[(c0 + min(q % TW_COLS, ncb - 1)) + (int64_t)(i0 + min(q / TW_COLS, nb - 1)) * J.ldX];
+                },
+                [&](int q, T v) {
+                    const int rr = q / TW_COLS, cc = q % TW_COLS;
+                    int sl = s0 + rr;
+                    if (sl >= WIN) sl -= WIN;
+                    if (rr < nb) win[sl * TW_COLS + cc] = cc < ncb ? v : T(0);
+                });
+        } else {              // 32 consecutive rows of a column at a time
+            staged_copy<8>(
+                LU_NB * TW_COLS, tid, 256,
+                [&](int q) {
+                    return Xi[(i0 + min(q % LU_NB, nb - 1)) + (int64_t)(c0 + min(q / LU_NB, ncb - 1)) * J.ldX];
+                },
+                [&](int q, T v) {
+                    const int rr = q % LU_NB, cc = q / LU_NB;
+                    int sl = s0 + rr;
+                    if (sl >= WIN) sl -= WIN;
+                    if (rr < nb) win[sl * TW_COLS + cc] = cc < ncb ? v : T(0);
+                });
+        }
+        __syncthreads();
+        // band product with the rows already solved (forward: [ka, i0); backward: [i0 + nb, kb))
+        {
+            const int kbeg = fwd ? ka : i0 + nb, kend = fwd ? i0 : kb;
+            T acc[4][2];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc[u][0] = acc[u][1] = T(0);
+            int sl = kbeg % WIN;
+            for (int k = kbeg; k < kend; ++k) {
+                const T2 yv = *reinterpret_cast<const T2 *>(win + sl * TW_COLS + 2 * cp);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const T l = Ls[(4 * rg + u) * W + (k - ka)];
+                    acc[u][0] = fma(l, yv.x, acc[u][0]);
+                    acc[u][1] = fma(l, yv.y, acc[u][1]);
+                }
+                if (++sl == WIN) sl = 0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int r = 4 * rg + u;
+                if (r < nb) {
+                    int slr = s0 + r;
+                    if (slr >= WIN) slr -= WIN;
+                    T2 *p = reinterpret_cast<T2 *>(win + slr * TW_COLS + 2 * cp);
+                    T2 y = *p;
+                    y.x -= acc[u][0];
+                    y.y -= acc[u][1];
+                    *p = y;
+                }
+            }
+        }
+        __syncthreads();
+        // the diagonal block, one column per thread
+        const int dofs = fwd ? i0 - ka : 0;        // column offset of the block in Ls
+        if (tid < TW_COLS) {
+            if (nb == LU_NB) {
+                T x[LU_NB];
+#pragma unroll
+                for (int rr = 0; rr < LU_NB; ++rr) {
+                    int sl = s0 + rr;
+                    if (sl >= WIN) sl -= WIN;
+                    x[rr] = win[sl * TW_COLS + tid];
+                }
+                block_solve_regs<T, MODE>(x, Ls + dofs, W);
+#pragma unroll
+                for (int rr = 0; rr < LU_NB; ++rr) {
+                    int sl = s0 + rr;
+                    if (sl >= WIN) sl -= WIN;
+                    win[sl * TW_COLS + tid] = x[rr];
+                }
+            } else {
+                auto at = [&](int r) -> T & {
+                    int sl = s0 + r;
+                    if (sl >= WIN) sl -= WIN;
+                    return win[sl * TW_COLS + tid];
+                };
+                if (fwd) {
+                    for (int k = 0; k < nb - 1; ++k) {
+                        const T yk = at(k);
+                        for (int r = k + 1; r < nb; ++r) at(r) -= Ls[r * W + dofs + k] * yk;
+                    }
+                } else {
+                    for (int k = nb - 1; k >= 0; --k) {
+                        if (MODE == TRI_UPPER) at(k) /= Ls[k * W + dofs + k];
+                        const T yk = at(k);
+                        for (int r = 0; r < k; ++r) at(r) -= Ls[r * W + dofs + k] * yk;
+                    }
+                }
+            }
+        }
+        pi0 = i0;
+        pnb = nb;
+    }
+    __syncthreads();
+    write_out(pi0, pnb);
+}
+
+static bool tri_band_fits_narrow(int maxn, int band, size_t elem) {
+    return band >= 0 && ((size_t)maxn * TB_COLS + (size_t)LU_NB * (band + LU_NB)) * elem <= (size_t)144 * 1024;
+}
+
 bool tri_band_fits(int maxn, int band, size_t elem) {
+    if (band >= 0 && tri_bandw_lds(band, elem) <= (size_t)80 * 1024) return true;
     return band >= 0 && ((size_t)maxn * TB_COLS + (size_t)LU_NB * (band + LU_NB)) * elem <= (size_t)144 * 1024;
 }
 
@@ -887,6 +1074,26 @@ template <typename T>
 int32_t tri_solve_batched(const TriJob *d_jobs, int nbatch, int maxn, int maxcol, const T *Tm, T *X, int mode,
                           hipStream_t s, int band, const T *Xin) {
     if (nbatch == 0 || maxn == 0 || maxcol == 0) return HKG_OK;
+    // wide blocks for many right-hand sides; a few (the coarse basis) keep the narrow blocks, which
+    // give more blocks per matrix
+    const bool narrow_ok = band >= 0 && !Xin && tri_band_fits_narrow(maxn, band, sizeof(T));
+    if (band >= 0 && tri_bandw_lds(band, sizeof(T)) <= (size_t)80 * 1024 && !(maxcol <= TW_COLS / 2 && narrow_ok)) {
+        const size_t shm = tri_bandw_lds(band, sizeof(T));
+        const dim3 g((maxcol + TW_COLS - 1) / TW_COLS, nbatch);
+        if (Xin) {
+            if (mode != TRI_LOWER_UNIT) return HKG_EINVAL;
+            hipLaunchKernelGGL((k_tri_bandw<T, TRI_LOWER_UNIT, true>), g, dim3(256), shm, s, d_jobs, Tm, Xin, X, band);
+        } else if (mode == TRI_LOWER_UNIT) {
+            hipLaunchKernelGGL((k_tri_bandw<T, TRI_LOWER_UNIT, false>), g, dim3(256), shm, s, d_jobs, Tm, X, X, band);
+        } else if (mode == TRI_UPPER) {
+            hipLaunchKernelGGL((k_tri_bandw<T, TRI_UPPER, false>), g, dim3(256), shm, s, d_jobs, Tm, X, X, band);
+        } else {
+            hipLaunchKernelGGL((k_tri_bandw<T, TRI_LOWER_UNIT_TRANS, false>), g, dim3(256), shm, s, d_jobs, Tm, X, X,
+                               band);
+        }
+        HKG_HIP(hipGetLastError());
+        return HKG_OK;
+    }
     if (band >= 0 && tri_band_fits(maxn, band, sizeof(T))) {
         const size_t shm = ((size_t)maxn * TB_COLS + (size_t)LU_NB * (band + LU_NB)) * sizeof(T);
         const dim3 g((maxcol + TB_COLS - 1) / TB_COLS, nbatch);

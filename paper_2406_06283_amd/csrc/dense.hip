@@ -873,9 +873,19 @@ __global__ __launch_bounds__(256) void k_tri_band(const TriJob *__restrict__ job
         }
     }
     __syncthreads();
+    // (TIN: scaled by D^{-1/2} on both sides, D the diagonal of T, into (offO, ldO))
+    T *Xo = TIN ? Xb + J.offO : X;
+    const int ldo = TIN ? J.ldO : J.ldX;
     for (int q = tid; q < n * TB_COLS; q += 256) {
         const int cc = q / n, i = q % n;
-        if (c0 + cc < J.ncol) X[i + (int64_t)(c0 + cc) * J.ldX] = ys[i * TB_COLS + cc];
+        if (c0 + cc < J.ncol) {
+            T v = ys[i * TB_COLS + cc];
+            if (TIN) {
+                const int c = c0 + cc;
+                v = v / (sqrt(Tm[i + (int64_t)i * J.ldT]) * sqrt(Tm[c + (int64_t)c * J.ldT]));
+            }
+            Xo[i + (int64_t)(c0 + cc) * ldo] = v;
+        }
     }
 }
 
@@ -927,6 +937,9 @@ __global__ __launch_bounds__(256) void k_tri_bandw(const TriJob *__restrict__ jo
     // the solved rows of a block out, 32 consecutive rows of a column at a time (the window keeps
     // them until the next block's rows are staged: its slots are band + 2 LU_NB, so the rows staged
     // next never land on the rows being written out)
+    // (TIN: scaled by D^{-1/2} on both sides, D the diagonal of T, into (offO, ldO))
+    T *Xo = TIN ? Xb + J.offO : X;
+    const int ldo = TIN ? J.ldO : J.ldX;
     auto write_out = [&](int r0, int nr) {
         const int t0 = r0 % WIN;
         for (int q = tid; q < LU_NB * TW_COLS; q += 256) {
@@ -934,7 +947,12 @@ __global__ __launch_bounds__(256) void k_tri_bandw(const TriJob *__restrict__ jo
             if (rr < nr && cc < ncb) {
                 int sl = t0 + rr;
                 if (sl >= WIN) sl -= WIN;
-                X[(r0 + rr) + (int64_t)(c0 + cc) * J.ldX] = win[sl * TW_COLS + cc];
+                T v = win[sl * TW_COLS + cc];
+                if (TIN) {
+                    const int i = r0 + rr, c = c0 + cc;
+                    v = v / (sqrt(Tm[i + (int64_t)i * J.ldT]) * sqrt(Tm[c + (int64_t)c * J.ldT]));
+                }
+                Xo[(r0 + rr) + (int64_t)(c0 + cc) * ldo] = v;
             }
         }
     };

@@ -183,7 +183,7 @@ int32_t analyze(hkgeneo_ctx *c, const hkgeneo_problem *p, hipStream_t s, int32_t
         hpl[i] = pl;
         pl += sd.nI;
         jGI[i] = {sd.offGG, sd.offGI, sd.nG, ldG, sd.nI, ldG};
-        jSq[i] = {sd.offSq, sd.offSq, sd.nI, sd.nI, sd.nI, sd.nI};
+        jSq[i] = {sd.offSq, sd.offSq, sd.nI, sd.nI, sd.nI, sd.nI, sd.offM, sd.ldM};
         hM[i] = {sd.offM, sd.nI, sd.ldM};
         jM[i] = {sd.offSq, sd.offM, sd.nI, sd.nI, sd.nI, sd.ldM};
         gS[i] = {sd.offBIO + (int64_t)sd.nI * sd.nI, sd.offGI, sd.offSq, sd.nI, sd.nI, sd.nG, sd.nI, ldG, sd.nI};
@@ -409,16 +409,18 @@ int32_t coarse_space(hkgeneo_ctx *c, hipStream_t s) {
     HKG_HIP(hipStreamWaitEvent(s, c->ev_join3, 0));
     HKG_TRY(tri_solve_batched<double>(dp<TriJob>(c->jobsSq), ns, c->max_nI, c->max_nI, dp<double>(c->wCII),
                                       dp<double>(c->wS), TRI_LOWER_UNIT, s, c->band_I));
-    if (tri_band_fits(c->max_nI, c->band_I, sizeof(double))) {      // the transpose read on the fly
+    HKG_TRY(walloc(c, &c->wT, (size_t)c->nM * sizeof(double)));
+    if (tri_band_fits(c->max_nI, c->band_I, sizeof(double))) {
+        // the transpose read on the fly, D^{-1/2} on both sides applied as the result is written
+        // into the padded layout of the tridiagonalisation
         HKG_TRY(tri_solve_batched<double>(dp<TriJob>(c->jobsSq), ns, c->max_nI, c->max_nI, dp<double>(c->wCII),
-                                          dp<double>(c->wW), TRI_LOWER_UNIT, s, c->band_I, dp<double>(c->wS)));
+                                          dp<double>(c->wT), TRI_LOWER_UNIT, s, c->band_I, dp<double>(c->wS)));
     } else {
         HKG_TRY(transpose_batched<double>(dp<DMat>(c->matsSq), ns, c->max_nI, dp<double>(c->wS), dp<double>(c->wW), s));
         HKG_TRY(tri_solve_batched<double>(dp<TriJob>(c->jobsSq), ns, c->max_nI, c->max_nI, dp<double>(c->wCII),
                                           dp<double>(c->wW), TRI_LOWER_UNIT, s, c->band_I));
+        HKG_TRY(scale_sym(dsub, ns, c->max_nI, dp<double>(c->wCII), dp<double>(c->wW), dp<double>(c->wT), s));
     }
-    HKG_TRY(walloc(c, &c->wT, (size_t)c->nM * sizeof(double)));
-    HKG_TRY(scale_sym(dsub, ns, c->max_nI, dp<double>(c->wCII), dp<double>(c->wW), dp<double>(c->wT), s));
     // tridiagonal form and selection
     HKG_TRY(walloc(c, &c->wD, c->sum_nI * sizeof(double)));
     HKG_TRY(walloc(c, &c->wE, c->sum_nI * sizeof(double)));

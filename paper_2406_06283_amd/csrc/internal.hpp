@@ -69,7 +69,8 @@ struct DMat {
     int32_t ld;
 };
 
-// triangular-solve job: triangle T (n x n at offT, ldT) and right-hand sides X (n x ncol at offX, ldX)
+// triangular-solve job: triangle T (n x n at offT, ldT) and right-hand sides X (n x ncol at offX, ldX);
+// offO, ldO: where a solve that reads its right-hand sides transposed writes its result
 struct TriJob {
     int64_t offT;
     int64_t offX;
@@ -77,6 +78,9 @@ struct TriJob {
     int32_t ldT;
     int32_t ncol;
     int32_t ldX;
+    int64_t offO = 0;
+    int32_t ldO = 0;
+    int32_t pad_ = 0;
 };
 
 // general GEMM job: C (M x N) = beta C + alpha op(A) op(B)

@@ -18,8 +18,8 @@ int32_t lu_batched(const DMat *d_mats, const int64_t *d_poff, int nbatch, int ma
                    int32_t *info, bool pivot, hipStream_t s, int band = -1);
 template <typename T>
 // band >= 0: op(T) has no entry farther than `band` from the diagonal.  Xin (banded lower solves
-// with tri_band_fits only, square right-hand sides): solve for the transpose of Xin (same layout as
-// X) into X, Xin untouched
+// with tri_band_fits only, square right-hand sides, T the packed L D L^T): Y = L^{-1} Xin^T (Xin
+// with the layout of X) written as D^{-1/2} Y D^{-1/2} into X at the jobs' (offO, ldO); Xin untouched
 int32_t tri_solve_batched(const TriJob *d_jobs, int nbatch, int maxn, int maxcol, const T *Tm, T *X, int mode,
                           hipStream_t s, int band = -1, const T *Xin = nullptr);
 // whether the one-launch banded solve serves matrices of up to maxn rows with this half-bandwidth

@@ -385,6 +385,31 @@ __device__ int sturm_count(const double *__restrict__ d, const double *__restric
     return cnt;
 }
 
+// Sturm count with the quotient e^2 / q from the hardware reciprocal estimate refined by two
+// Newton-Raphson steps (r <- r (2 - q r)); |q| >= pivmin keeps every operand finite, and the
+// refined quotient is within a few ulps, inside the rounding model of the recurrence.  Used by the
+// multisection, whose cost is the instruction count of this loop.
+__device__ __forceinline__ double quot_nr(double e2, double q) {
+    double r = __builtin_amdgcn_rcp(q);
+    r = fma(fma(-q, r, 1.0), r, r);
+    r = fma(fma(-q, r, 1.0), r, r);
+    return e2 * r;
+}
+
+__device__ int sturm_count_nr(const double *__restrict__ d, const double *__restrict__ e2, int n, double sigma,
+                              double pivmin) {
+    int cnt = 0;
+    double q = d[0] - sigma;
+    if (fabs(q) < pivmin) q = -pivmin;
+    cnt += (q < 0.0);
+    for (int i = 1; i < n; ++i) {
+        q = (d[i] - sigma) - quot_nr(e2[i - 1], q);
+        if (fabs(q) < pivmin) q = -pivmin;
+        cnt += (q < 0.0);
+    }
+    return cnt;
+}
+
 // k-th smallest eigenvalue (0-based) by bisection in (lo, hi]
 __device__ double bisect_kth(const double *d, const double *e2, int n, int k, double lo, double hi, double pivmin) {
     for (int it = 0; it < 200; ++it) {
@@ -476,13 +501,11 @@ __global__ __launch_bounds__(64) void k_select_refine(const SubDev *__restrict__
     for (int it = 0; it < 40; ++it) {
         const double sig = a + (b - a) * ((double)(lane + 1) / 65.0);
         const bool inside = sig > a && sig < b;
-        const int cnt = inside ? sturm_count(d, e2, n, sig, pivmin) : 0;
+        const int cnt = inside ? sturm_count_nr(d, e2, n, sig, pivmin) : 0;
         double na = (inside && cnt <= k) ? sig : a;
         double nb = (inside && cnt > k) ? sig : b;
-        for (int o = 32; o > 0; o >>= 1) {
-            na = fmax(na, __shfl_xor(na, o, 64));
-            nb = fmin(nb, __shfl_xor(nb, o, 64));
-        }
+        na = wave_max64(na);
+        nb = wave_min64(nb);
         if (na == a && nb == b) break;     // the bracket cannot be split further
         a = na;
         b = nb;

@@ -72,6 +72,23 @@ __device__ __forceinline__ double wave_sum64(double v) {
     return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
 }
 
+// max / min over the 64 lanes; every lane gets the result
+__device__ __forceinline__ double wave_max64(double v) {
+    v = fmax(v, dpp_f64<DPP_QUAD_XOR1>(v));
+    v = fmax(v, dpp_f64<DPP_QUAD_XOR2>(v));
+    v = fmax(v, dpp_f64<DPP_ROW_HALF_MIRROR>(v));
+    v = fmax(v, dpp_f64<DPP_ROW_MIRROR>(v));
+    return fmax(fmax(readlane_f64(v, 0), readlane_f64(v, 16)), fmax(readlane_f64(v, 32), readlane_f64(v, 48)));
+}
+
+__device__ __forceinline__ double wave_min64(double v) {
+    v = fmin(v, dpp_f64<DPP_QUAD_XOR1>(v));
+    v = fmin(v, dpp_f64<DPP_QUAD_XOR2>(v));
+    v = fmin(v, dpp_f64<DPP_ROW_HALF_MIRROR>(v));
+    v = fmin(v, dpp_f64<DPP_ROW_MIRROR>(v));
+    return fmin(fmin(readlane_f64(v, 0), readlane_f64(v, 16)), fmin(readlane_f64(v, 32), readlane_f64(v, 48)));
+}
+
 // arg-max of |value| candidates (v, idx): larger v wins, ties go to the smaller idx
 template <typename T>
 __device__ __forceinline__ void argmax_pick(T &v, int &idx, T ov, int oi) {

@@ -145,22 +145,18 @@ __global__ __launch_bounds__(256) void k_lu_panel(const DMat *__restrict__ mats,
 constexpr int PANEL_REG_ROWS = 1024;
 
 
-template <typename T, int NT>
-__global__ __launch_bounds__(NT) void k_lu_panel_reg(const DMat *__restrict__ mats, const int64_t *__restrict__ poff,
-                                                     T *__restrict__ Ab, int32_t *__restrict__ piv,
-                                                     int32_t *__restrict__ info, int j0, int pivot, int mlim) {
+// the panel factorisation of one matrix (A with n rows and leading dimension ld, pivots pv, info
+// slot *info) by a workgroup of NT threads; load(r, c) gives the panel's entry (r, j0 + c) as the
+// factorisation starts
+template <typename T, int NT, typename LOAD>
+__device__ __forceinline__ void lu_panel_reg_body(int n, T *__restrict__ A, int ld, int32_t *__restrict__ pv,
+                                                  int32_t *__restrict__ info, int j0, int pivot, int mlim, LOAD load) {
     constexpr int NW = NT / 64;
-    const DMat m = mats[blockIdx.x];
-    const int n = m.n;
     if (j0 >= n) return;
-    T *A = Ab + m.off;
-    const int ld = m.ld;
     const int nb = min(j0 + LU_NB, n) - j0;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int r = j0 + tid;
     const bool own = r < min(n, mlim);
-    // loaded once: a global load inside the column loop would stall its wave at every column
-    int32_t *pv = piv + poff[blockIdx.x];
     int bad = 0;                        // first zero (or non-finite) pivot column + 1
     int pmine = 0;                      // thread jj keeps the pivot of column jj: one store at the end
                                         // (a store per column would stall on its completion)
@@ -170,7 +166,7 @@ __global__ __launch_bounds__(NT) void k_lu_panel_reg(const DMat *__restrict__ ma
     __shared__ int widx[2][NW];
     T a[LU_NB];
 #pragma unroll
-    for (int c = 0; c < LU_NB; ++c) a[c] = (own && c < nb) ? A[r + (int64_t)(j0 + c) * ld] : T(0);
+    for (int c = 0; c < LU_NB; ++c) a[c] = (own && c < nb) ? load(r, c) : T(0);
     if (pivot) {
         T v = own ? fabs(a[0]) : T(-1);
         int idx = own ? r : 0x7fffffff;
@@ -238,7 +234,18 @@ __global__ __launch_bounds__(NT) void k_lu_panel_reg(const DMat *__restrict__ ma
             if (c < nb) A[r + (int64_t)(j0 + c) * ld] = a[c];
     }
     if (tid < nb) pv[j0 + tid] = pmine;
-    if (tid == 0 && bad && info[blockIdx.x] == 0) info[blockIdx.x] = bad;
+    if (tid == 0 && bad && *info == 0) *info = bad;
+}
+
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_lu_panel_reg(const DMat *__restrict__ mats, const int64_t *__restrict__ poff,
+                                                     T *__restrict__ Ab, int32_t *__restrict__ piv,
+                                                     int32_t *__restrict__ info, int j0, int pivot, int mlim) {
+    const DMat m = mats[blockIdx.x];
+    T *A = Ab + m.off;
+    const int ld = m.ld;
+    lu_panel_reg_body<T, NT>(m.n, A, ld, piv + poff[blockIdx.x], info + blockIdx.x, j0, pivot, mlim,
+                             [&](int r, int c) { return A[r + (int64_t)(j0 + c) * ld]; });
 }
 
 // Panel factorisation by one wave: lane l owns the physical rows j0 + l + 64 q (q < RPL), so panels
@@ -484,10 +491,14 @@ __device__ __forceinline__ void block_solve_regs(T (&x)[LU_NB], const T *__restr
 constexpr int LP_COLS = 32;
 constexpr int LP_MAXROWS = 256;
 
+// fuse: block 0 (whose strip is the next panel's columns) goes on to factor the next panel (rows
+// [jend, mlim_next)), taking the rows it has just updated from its LDS copy and those below from
+// global memory, while the other blocks update their strips.
 template <typename T>
 __global__ __launch_bounds__(256) void k_lu_post(const DMat *__restrict__ mats, const int64_t *__restrict__ poff,
-                                                 T *__restrict__ Ab, const int32_t *__restrict__ piv, int j0, int mlim,
-                                                 int clim, int pivot) {
+                                                 T *__restrict__ Ab, int32_t *__restrict__ piv, int j0, int mlim,
+                                                 int clim, int pivot, int fuse, int mlim_next,
+                                                 int32_t *__restrict__ info) {
     const DMat m = mats[blockIdx.y];
     const int n = m.n;
     if (j0 >= n) return;
@@ -505,10 +516,10 @@ __global__ __launch_bounds__(256) void k_lu_post(const DMat *__restrict__ mats, 
     T *Ps = reinterpret_cast<T *>(shp);                         // rw x (LU_NB + 1): the panel
     T *Xs = Ps + (int64_t)rw * (LU_NB + 1);                     // rw x (LP_COLS + 1): the strip
     __shared__ int lp[LU_NB];
-    staged_copy<8>(
+    staged_copy<16>(
         rw * LU_NB, tid, 256, [&](int e) { return A[(j0 + e % rw) + (int64_t)(j0 + min(e / rw, nb - 1)) * ld]; },
         [&](int e, T v) { Ps[(e % rw) * (LU_NB + 1) + e / rw] = e / rw < nb ? v : T(0); });
-    staged_copy<8>(
+    staged_copy<16>(
         rw * LP_COLS, tid, 256, [&](int e) { return A[(j0 + e % rw) + (int64_t)(cs + min(e / rw, ncs - 1)) * ld]; },
         [&](int e, T v) { Xs[(e % rw) * (LP_COLS + 1) + e / rw] = e / rw < ncs ? v : T(0); });
     if (tid < LU_NB) lp[tid] = (pivot && tid < nb) ? pv[j0 + tid] - j0 : tid;
@@ -578,6 +589,13 @@ __global__ __launch_bounds__(256) void k_lu_post(const DMat *__restrict__ mats, 
         const int r = e % rw, c = e / rw;
         if (c < ncs) A[(j0 + r) + (int64_t)(cs + c) * ld] = Xs[r * (LP_COLS + 1) + c];
     }
+    if (fuse && blockIdx.x == 0 && jend < n) {
+        __syncthreads();
+        lu_panel_reg_body<T, 256>(n, A, ld, piv + poff[blockIdx.y], info + blockIdx.y, jend, pivot, mlim_next,
+                                  [&](int r, int c) {
+                                      return r < rend ? Xs[(r - j0) * (LP_COLS + 1) + c] : A[r + (int64_t)(jend + c) * ld];
+                                  });
+    }
 }
 
 // The deferred row exchanges of the L columns: column c (in the panel ending at e_c) receives the
@@ -634,14 +652,24 @@ int32_t lu_batched(const DMat *d_mats, const int64_t *d_poff, int nbatch, int ma
     // the left exchanges of fused panels are deferred when the deferred pass fits in LDS
     const bool defer = pivot && (size_t)maxn * LS_COLS * sizeof(T) <= (size_t)150 * 1024;
     int jf = -1;                        // first panel whose left exchanges are deferred
+    bool factored = false;              // the panel at j0 was factored by the previous k_lu_post
+    // one wave for narrow panels (float: up to 64 rows, where its registers suffice)
+    const bool wide_wave = sizeof(T) == 8;
+    auto panel_rows = [&](int j) {
+        const int je = std::min(j + LU_NB, maxn);
+        return (banded ? std::min(maxn, je + band) : maxn) - j;
+    };
+    auto uses_reg256 = [&](int rows) { return rows > (wide_wave ? 192 : 64) && rows <= 256; };
     for (int j0 = 0; j0 < maxn; j0 += LU_NB) {
         const int jend = std::min(j0 + LU_NB, maxn);
         const int mlim = banded ? std::min(maxn, jend + band) : maxn;           // panel rows end
         const int clim = banded ? std::min(maxn, jend + 2 * band) : maxn;       // columns reached
         const int rows = mlim - j0;
-        // one wave for narrow panels (float: up to 64 rows, where its registers suffice)
-        const bool wide_wave = sizeof(T) == 8;
-        if (rows <= 64)
+        const bool was_factored = factored;
+        factored = false;
+        if (was_factored)
+            ;
+        else if (rows <= 64)
             hipLaunchKernelGGL((k_lu_panel_wave<T, 1>), dim3(nbatch), dim3(64), 0, s, d_mats, d_poff, A, piv, info, j0,
                                (int)pivot, mlim);
         else if (wide_wave && rows <= 128)
@@ -672,9 +700,14 @@ int32_t lu_batched(const DMat *d_mats, const int64_t *d_poff, int nbatch, int ma
                                    piv, j0, j0);     // the columns left of the panel only
             const int nright = ccols > 0 ? (ccols + LP_COLS - 1) / LP_COLS : 0;
             if (nright > 0) {
+                // block 0 factors the next panel when that panel takes the 256-thread kernel
+                const int jn = j0 + LU_NB;
+                const bool fuse = jn < maxn && uses_reg256(panel_rows(jn));
+                const int mlim_next = fuse ? jn + panel_rows(jn) : 0;
                 const size_t shm = (size_t)rows * (LU_NB + 1 + LP_COLS + 1) * sizeof(T);
                 hipLaunchKernelGGL(k_lu_post<T>, dim3(nright, nbatch), dim3(256), shm, s, d_mats, d_poff, A, piv, j0,
-                                   mlim, clim, (int)pivot);
+                                   mlim, clim, (int)pivot, (int)fuse, mlim_next, info);
+                factored = fuse;
             }
             continue;
         }

@@ -383,13 +383,13 @@ int32_t coarse_space(hkgeneo_ctx *c, hipStream_t s) {
     } join_cii{enq_cii};
     // B~_GG and its LU
     HKG_HIP(hipMemsetAsync(c->wGG.p, 0, c->wGG.bytes, s));
-    HKG_TRY(assemble_gamma(dsub, ns, c->npe, nullptr, dp<int32_t>(c->bandLoc), dp<double>(c->bandK),
+    HKG_TRY(assemble_gamma(dsub, ns, c->max_nG, c->npe, nullptr, dp<int32_t>(c->bandLoc), dp<double>(c->bandK),
                            dp<double>(c->bandM), k2, dp<double>(c->wGG), s));
     HKG_TRY(lu_batched<double>(dp<DMat>(c->matsGG), dp<int64_t>(c->poffSub), ns, c->max_nG, dp<double>(c->wGG),
                                dp<int32_t>(c->wPiv), dp<int32_t>(c->wInfo), true, s));
     std::vector<int32_t> flags;
     // X = B~_GG^{-1} B_GI ; S = B_II - B_IG X
-    HKG_TRY(gather_gamma_rows(dsub, ns, c->max_nI, dp<double>(c->wBIO), dp<double>(c->wGI), s));
+    HKG_TRY(gather_gamma_rows(dsub, ns, c->max_nI, c->max_nG, dp<double>(c->wBIO), dp<double>(c->wGI), s));
     HKG_TRY(apply_pivots_rows<double>(dsub, ns, c->max_nI, dp<int32_t>(c->wPiv), dp<double>(c->wGI), 0, s));
     // the Gamma block is dense: as a band of half-width n_G - 1 the solves take one launch each
     const int bandG = tri_band_fits(c->max_nG, c->max_nG - 1, sizeof(double)) ? c->max_nG - 1 : -1;

@@ -64,9 +64,11 @@ int32_t form_operator(const double *A, const double *S, double k2, double *B, do
 int32_t extract_blocks(const SubDev *d_sub, int nsub, int maxnI, const int32_t *rowptr, const int32_t *colidx,
                        const double *Bval, const double *Dval, const int32_t *I_idx, const int32_t *G_idx,
                        const double *winv, double *BIO, double *CII, hipStream_t s);
-int32_t assemble_gamma(const SubDev *d_sub, int nsub, int npe, const int32_t *band_elem, const int32_t *band_loc,
-                       const double *elemK, const double *elemM, double k2, double *BGG, hipStream_t s);
-int32_t gather_gamma_rows(const SubDev *d_sub, int nsub, int maxnI, const double *BIO, double *GI, hipStream_t s);
+int32_t assemble_gamma(const SubDev *d_sub, int nsub, int maxnG, int npe, const int32_t *band_elem,
+                       const int32_t *band_loc, const double *elemK, const double *elemM, double k2, double *BGG,
+                       hipStream_t s);
+int32_t gather_gamma_rows(const SubDev *d_sub, int nsub, int maxnI, int maxnG, const double *BIO, double *GI,
+                          hipStream_t s);
 template <typename T>
 int32_t apply_pivots_rows(const SubDev *d_sub, int nsub, int maxcol, const int32_t *piv, T *X, int which, hipStream_t s);
 int32_t copy_bii(const SubDev *d_sub, int nsub, int maxnI, const double *BIO, double *out, hipStream_t s);

@@ -97,17 +97,86 @@ __global__ __launch_bounds__(64) void k_assemble_gamma(const SubDev *__restrict_
     }
 }
 
-int32_t assemble_gamma(const SubDev *d_sub, int nsub, int npe, const int32_t *band_elem, const int32_t *band_loc,
-                       const double *elemK, const double *elemM, double k2, double *BGG, hipStream_t s) {
+// The same sums with the block in LDS: one wave adds the elements in the same order (a wave's LDS
+// operations complete in order, and within one element the lanes hit distinct entries), the
+// element data loaded eight elements ahead; the block is written out once.
+constexpr int AG_AHEAD = 8;
+
+__global__ __launch_bounds__(64) void k_assemble_gamma_lds(const SubDev *__restrict__ subs, int npe,
+                                                           const int32_t *__restrict__ band_loc,
+                                                           const double *__restrict__ bandK,
+                                                           const double *__restrict__ bandM, double k2,
+                                                           double *__restrict__ BGG) {
+    extern __shared__ double G[];                     // nG x nG, ld nG
+    const SubDev sd = subs[blockIdx.x];
+    const int nG = sd.nG;
+    const int t = threadIdx.x;
+    for (int e = t; e < nG * nG; e += 64) G[e] = 0.0;
+    const int npe2 = npe * npe;
+    const int a = t / npe, c = t % npe;
+    for (int b0 = sd.bandBeg; b0 < sd.bandEnd; b0 += AG_AHEAD) {
+        double v[AG_AHEAD];
+        int idx[AG_AHEAD];
+#pragma unroll
+        for (int u = 0; u < AG_AHEAD; ++u) {
+            const int b = b0 + u;
+            const bool ok = t < npe2 && b < sd.bandEnd;
+            const int la = ok ? band_loc[(int64_t)b * npe + a] : -1;
+            const int lc = ok ? band_loc[(int64_t)b * npe + c] : -1;
+            idx[u] = (la >= 0 && lc >= 0) ? la + lc * nG : -1;
+            v[u] = ok ? bandK[(int64_t)b * npe2 + t] - k2 * bandM[(int64_t)b * npe2 + t] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < AG_AHEAD; ++u)
+            if (idx[u] >= 0) G[idx[u]] += v[u];
+    }
+    for (int e = t; e < nG * nG; e += 64) BGG[sd.offGG + e] = G[e];
+}
+
+int32_t assemble_gamma(const SubDev *d_sub, int nsub, int maxnG, int npe, const int32_t *band_elem,
+                       const int32_t *band_loc, const double *elemK, const double *elemM, double k2, double *BGG,
+                       hipStream_t s) {
     (void)band_elem;
+    const size_t shm = (size_t)maxnG * maxnG * sizeof(double);
+    if (npe * npe <= 64 && shm <= (size_t)120 * 1024) {
+        hipLaunchKernelGGL(k_assemble_gamma_lds, dim3(nsub), dim3(64), shm, s, d_sub, npe, band_loc, elemK, elemM, k2,
+                           BGG);
+        HKG_HIP(hipGetLastError());
+        return HKG_OK;
+    }
     hipLaunchKernelGGL(k_assemble_gamma, dim3(nsub), dim3(64), 0, s, d_sub, npe, band_loc, elemK, elemM, k2, BGG);
     HKG_HIP(hipGetLastError());
     return HKG_OK;
 }
 
-// GI = B_GI = (B_IG)^T, nG x nI with ld nG
+// GI = B_GI = (B_IG)^T, nG x nI with ld nG: 64 columns of GI per block through an LDS tile (reads
+// along the rows of B_IG, writes along the columns of GI, both contiguous)
+constexpr int GG_TILE = 64;
+
 __global__ __launch_bounds__(256) void k_gather_gamma_rows(const SubDev *__restrict__ subs, const double *__restrict__ BIO,
                                                            double *__restrict__ GI) {
+    extern __shared__ double tile[];                  // nG x (GG_TILE + 1)
+    const SubDev sd = subs[blockIdx.y];
+    const int a0 = blockIdx.x * GG_TILE;
+    const int nI = sd.nI, nG = sd.nG;
+    if (a0 >= nI || nG == 0) return;
+    const int na = min(GG_TILE, nI - a0);
+    const int tid = threadIdx.x;
+    for (int q = tid; q < nG * GG_TILE; q += 256) {
+        const int la = q % GG_TILE, g = q / GG_TILE;
+        if (la < na) tile[g * (GG_TILE + 1) + la] = BIO[sd.offBIO + (a0 + la) + (int64_t)(nI + g) * nI];
+    }
+    __syncthreads();
+    for (int q = tid; q < nG * GG_TILE; q += 256) {
+        const int g = q % nG, la = q / nG;
+        if (la < na) GI[sd.offGI + g + (int64_t)(a0 + la) * nG] = tile[g * (GG_TILE + 1) + la];
+    }
+}
+
+// the same without the tile (Gamma blocks too tall for it)
+__global__ __launch_bounds__(256) void k_gather_gamma_rows_direct(const SubDev *__restrict__ subs,
+                                                                  const double *__restrict__ BIO,
+                                                                  double *__restrict__ GI) {
     const SubDev sd = subs[blockIdx.y];
     const int a = blockIdx.x * 256 + threadIdx.x;
     if (a >= sd.nI) return;
@@ -115,8 +184,15 @@ __global__ __launch_bounds__(256) void k_gather_gamma_rows(const SubDev *__restr
         GI[sd.offGI + g + (int64_t)a * sd.nG] = BIO[sd.offBIO + a + (int64_t)(sd.nI + g) * sd.nI];
 }
 
-int32_t gather_gamma_rows(const SubDev *d_sub, int nsub, int maxnI, const double *BIO, double *GI, hipStream_t s) {
-    hipLaunchKernelGGL(k_gather_gamma_rows, dim3((maxnI + 255) / 256, nsub), dim3(256), 0, s, d_sub, BIO, GI);
+int32_t gather_gamma_rows(const SubDev *d_sub, int nsub, int maxnI, int maxnG, const double *BIO, double *GI,
+                          hipStream_t s) {
+    const size_t shm = (size_t)std::max(maxnG, 1) * (GG_TILE + 1) * sizeof(double);
+    if (shm <= (size_t)64 * 1024)
+        hipLaunchKernelGGL(k_gather_gamma_rows, dim3((maxnI + GG_TILE - 1) / GG_TILE, nsub), dim3(256), shm, s, d_sub,
+                           BIO, GI);
+    else
+        hipLaunchKernelGGL(k_gather_gamma_rows_direct, dim3((maxnI + 255) / 256, nsub), dim3(256), 0, s, d_sub, BIO,
+                           GI);
     HKG_HIP(hipGetLastError());
     return HKG_OK;
 }

@@ -14,6 +14,7 @@
 #include <string>
 #include <thread>
 #include <cstring>
+#include <functional>
 
 #include "ctx.hpp"
 
@@ -337,7 +338,10 @@ int32_t lu_inverse(hkgeneo_ctx *c, int n, const double *LU, const int32_t *piv, 
     return gemm_batched<double>(dj + (jobs.size() - 1), 1, n, n, Uinv, tmp, out, 1.0, 0.0, false, false, s);
 }
 
-int32_t coarse_space(hkgeneo_ctx *c, hipStream_t s) {
+// start_side: forks the local-inverse pipeline to the second stream; called once the Gamma block's
+// LU is enqueued (the side pipeline is far off the critical path, and its hundred launches from a
+// second host thread would slow this thread's first ones)
+int32_t coarse_space(hkgeneo_ctx *c, hipStream_t s, const std::function<int32_t()> &start_side) {
     const int ns = c->n_sub;
     const hkgeneo_options &o = c->opt;
     const int mmax = o.max_eig_per_sub;
@@ -355,12 +359,11 @@ int32_t coarse_space(hkgeneo_ctx *c, hipStream_t s) {
     HKG_TRY(walloc(c, &c->wFlagSpd, ns * sizeof(int32_t)));
     // C_II = L U without exchanges (= L D L^T; positive pivots <=> SPD) on the third stream, concurrently with
     // the Gamma block's LU and the Schur complement; the flags are read back after the selection
-    // (enqueued by a helper thread, so that this thread's launches for the Gamma block start at once)
     HKG_HIP(hipEventRecord(c->ev_fork3, s));
     HKG_HIP(hipStreamWaitEvent(c->s3, c->ev_fork3, 0));
     int32_t st_cii = HKG_OK;
     std::string err_cii;
-    std::thread enq_cii([&]() {
+    auto enqueue_cii = [&]() {
         if (ldl_band_fits(c->max_nI, c->band_I))
             st_cii = ldl_band(dsub, ns, c->max_nI, dp<double>(c->wCII), c->band_I, c->s3);
         else
@@ -373,7 +376,13 @@ int32_t coarse_space(hkgeneo_ctx *c, hipStream_t s) {
             st_cii = HKG_EHIP;
         }
         if (st_cii != HKG_OK) err_cii = g_last_error;
-    });
+    };
+    // the one-launch L D L^T is enqueued here; the panel-chain LU (a hundred launches) by a helper
+    std::thread enq_cii;
+    if (ldl_band_fits(c->max_nI, c->band_I))
+        enqueue_cii();
+    else
+        enq_cii = std::thread(enqueue_cii);
     // joined (and its status checked) before anything waits on its event
     struct Joiner {
         std::thread &t;
@@ -387,6 +396,7 @@ int32_t coarse_space(hkgeneo_ctx *c, hipStream_t s) {
                            dp<double>(c->bandM), k2, dp<double>(c->wGG), s));
     HKG_TRY(lu_batched<double>(dp<DMat>(c->matsGG), dp<int64_t>(c->poffSub), ns, c->max_nG, dp<double>(c->wGG),
                                dp<int32_t>(c->wPiv), dp<int32_t>(c->wInfo), true, s));
+    HKG_TRY(start_side());
     std::vector<int32_t> flags;
     // X = B~_GG^{-1} B_GI ; S = B_II - B_IG X
     HKG_TRY(gather_gamma_rows(dsub, ns, c->max_nI, c->max_nG, dp<double>(c->wBIO), dp<double>(c->wGI), s));
@@ -401,7 +411,7 @@ int32_t coarse_space(hkgeneo_ctx *c, hipStream_t s) {
     HKG_TRY(gemm_batched<double>(dp<GemmJob>(c->gjobsSchur), ns, c->max_nI, c->max_nI, dp<double>(c->wBIO),
                                  dp<double>(c->wGI), dp<double>(c->wS), -1.0, 1.0, false, false, s));
     // S^ = D^{-1/2} L^{-1} S L^{-T} D^{-1/2} once C_II = L U is done
-    enq_cii.join();
+    if (enq_cii.joinable()) enq_cii.join();
     if (st_cii != HKG_OK) {
         set_last_error(err_cii);
         return st_cii;
@@ -603,20 +613,29 @@ int32_t factor(hkgeneo_ctx *c, hipStream_t s) {
                            dp<double>(c->wDk), dp<int32_t>(c->I_idx), dp<int32_t>(c->G_idx), dp<double>(c->winv),
                            dp<double>(c->wBIO), dp<double>(c->wCII), s));
     // the local inverses (reading B_II) on the second stream, the coarse space on the caller's: the
-    // two pipelines share no buffer written after this point
+    // two pipelines share no buffer written after this point.  The local pipeline is enqueued by a
+    // helper thread (about a hundred launches) while this thread enqueues the coarse space, which
+    // waits on the device several times; it is forked once coarse_space has its first launches in.
     HKG_TRY(local_buffers(c));
-    HKG_HIP(hipEventRecord(c->ev_fork, s));
-    HKG_HIP(hipStreamWaitEvent(c->s2, c->ev_fork, 0));
-    // the local pipeline is enqueued by a helper thread (about a hundred launches) while this
-    // thread enqueues the coarse space, which waits on the device several times
     int32_t st_local = HKG_OK;
     std::string err_local;
-    std::thread enq([&]() {
-        st_local = local_operators(c, c->s2);
-        if (st_local != HKG_OK) err_local = g_last_error;
-    });
-    int32_t st = c->opt.two_level ? coarse_space(c, s) : HKG_OK;
-    enq.join();
+    std::thread enq;
+    auto start_side = [&]() -> int32_t {
+        if (enq.joinable()) return HKG_OK;
+        HKG_HIP(hipEventRecord(c->ev_fork, s));
+        HKG_HIP(hipStreamWaitEvent(c->s2, c->ev_fork, 0));
+        enq = std::thread([&]() {
+            st_local = local_operators(c, c->s2);
+            if (st_local != HKG_OK) err_local = g_last_error;
+        });
+        return HKG_OK;
+    };
+    int32_t st = c->opt.two_level ? coarse_space(c, s, start_side) : HKG_OK;
+    if (!enq.joinable()) {
+        const int32_t st2 = start_side();
+        if (st == HKG_OK) st = st2;
+    }
+    if (enq.joinable()) enq.join();
     if (st == HKG_OK && st_local != HKG_OK) {
         set_last_error(err_local);
         st = st_local;

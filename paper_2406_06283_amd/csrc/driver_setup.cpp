@@ -533,7 +533,7 @@ int32_t coarse_space(hkgeneo_ctx *c, hipStream_t s, const std::function<int32_t(
     HKG_TRY(walloc(c, &c->wB0, (size_t)m0 * m0 * sizeof(double)));
     HKG_HIP(hipMemsetAsync(c->wB0.p, 0, (size_t)m0 * m0 * sizeof(double), s));
     HKG_TRY(coarse_pairs(npairs, pp, pp + npairs, pp + 2 * npairs, pp + 3 * npairs + 1,
-                         pp + 3 * npairs + 1 + CP.qi.size(), dsub, dp<double>(c->wY), dp<double>(c->Z),
+                         pp + 3 * npairs + 1 + CP.qi.size(), dsub, c->max_m, dp<double>(c->wY), dp<double>(c->Zr),
                          dp<double>(c->wB0), m0, s));
     if ((int64_t)m0 * m0 <= (int64_t)2048 * 2048) {
         // a device copy for queries (the LU below overwrites B_0); read back only when asked

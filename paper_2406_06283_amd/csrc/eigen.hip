@@ -859,11 +859,72 @@ int32_t finish_basis(const SubDev *d_sub, int nsub, const int32_t *I_idx, const 
 // coarse matrix blocks: B_0[(j, b), (i, a)] = sum over q in ovdof(D_i) and dof(D_j) of
 //   Z_j[q, b] (B Z_i)[q, a],  with (B Z_i)[q, a] = Y_i[a, q] and Y_i = Z_i^T [B_II | B_IG]  (B symmetric)
 // ------------------------------------------------------------------------------------------------
+// the shared dofs of a pair in chunks of CP_CH staged in LDS (rows of Z_j from its row-major copy,
+// columns of Y_i, both contiguous), each thread then summing its entries over the chunk in the
+// same order as the direct form below
+constexpr int CP_CH = 64;
+constexpr int CP_MMAX = 32;
+
 __global__ __launch_bounds__(256) void k_coarse_pairs(const int32_t *__restrict__ pi, const int32_t *__restrict__ pj,
                                                       const int32_t *__restrict__ ptr, const int32_t *__restrict__ qi,
                                                       const int32_t *__restrict__ qj, const SubDev *__restrict__ subs,
-                                                      const double *__restrict__ Y, const double *__restrict__ Zb,
+                                                      const double *__restrict__ Y, const double *__restrict__ Zr,
                                                       double *__restrict__ B0, int m0) {
+    __shared__ double ys[CP_CH][CP_MMAX + 1];      // ys[u][a] = Y_i[a, qi[u]]
+    __shared__ double zs[CP_CH][CP_MMAX + 1];      // zs[u][b] = Z_j[qj[u], b]
+    const int t = blockIdx.x;
+    const SubDev si = subs[pi[t]], sj = subs[pj[t]];
+    const int mi = si.m, mj = sj.m;
+    if (mi == 0 || mj == 0) return;
+    const int beg = ptr[t], end = ptr[t + 1];
+    const int tid = threadIdx.x;
+    constexpr int PER = CP_MMAX * CP_MMAX / 256;   // entries per thread
+    double acc[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) acc[k] = 0.0;
+    for (int u0 = beg; u0 < end; u0 += CP_CH) {
+        const int cnt = min(CP_CH, end - u0);
+        __syncthreads();
+        for (int e = tid; e < cnt * mi; e += 256) {
+            const int u = e / mi, a = e % mi;
+            ys[u][a] = Y[si.offY + a + (int64_t)qi[u0 + u] * mi];
+        }
+        for (int e = tid; e < cnt * mj; e += 256) {
+            const int u = e / mj, b = e % mj;
+            zs[u][b] = Zr[sj.offZ + (int64_t)qj[u0 + u] * mj + b];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int q = tid + 256 * k;
+            if (q < mi * mj) {
+                const int b = q % mj, a = q / mj;
+                double sacc = acc[k];
+                for (int u = 0; u < cnt; ++u) sacc += zs[u][b] * ys[u][a];
+                acc[k] = sacc;
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int q = tid + 256 * k;
+        if (q < mi * mj) {
+            const int b = q % mj, a = q / mj;
+            B0[(int64_t)(sj.offm + b) + (int64_t)(si.offm + a) * m0] = acc[k];
+        }
+    }
+}
+
+// direct form: every thread gathers its terms from global memory (subdomains with m > CP_MMAX)
+__global__ __launch_bounds__(256) void k_coarse_pairs_direct(const int32_t *__restrict__ pi,
+                                                             const int32_t *__restrict__ pj,
+                                                             const int32_t *__restrict__ ptr,
+                                                             const int32_t *__restrict__ qi,
+                                                             const int32_t *__restrict__ qj,
+                                                             const SubDev *__restrict__ subs,
+                                                             const double *__restrict__ Y,
+                                                             const double *__restrict__ Zr,
+                                                             double *__restrict__ B0, int m0) {
     const int t = blockIdx.x;
     const SubDev si = subs[pi[t]], sj = subs[pj[t]];
     const int mi = si.m, mj = sj.m;
@@ -873,16 +934,20 @@ __global__ __launch_bounds__(256) void k_coarse_pairs(const int32_t *__restrict_
         const int b = q % mj, a = q / mj;
         double s = 0.0;
         for (int u = beg; u < end; ++u)
-            s += Zb[sj.offZ + qj[u] + (int64_t)b * sj.nI] * Y[si.offY + a + (int64_t)qi[u] * mi];
+            s += Zr[sj.offZ + (int64_t)qj[u] * mj + b] * Y[si.offY + a + (int64_t)qi[u] * mi];
         B0[(int64_t)(sj.offm + b) + (int64_t)(si.offm + a) * m0] = s;
     }
 }
 
 int32_t coarse_pairs(int npairs, const int32_t *pi, const int32_t *pj, const int32_t *ptr, const int32_t *qi,
-                     const int32_t *qj, const SubDev *d_sub, const double *Y, const double *Z, double *B0, int m0,
-                     hipStream_t s) {
+                     const int32_t *qj, const SubDev *d_sub, int max_m, const double *Y, const double *Zr, double *B0,
+                     int m0, hipStream_t s) {
     if (npairs == 0) return HKG_OK;
-    hipLaunchKernelGGL(k_coarse_pairs, dim3(npairs), dim3(256), 0, s, pi, pj, ptr, qi, qj, d_sub, Y, Z, B0, m0);
+    if (max_m <= CP_MMAX)
+        hipLaunchKernelGGL(k_coarse_pairs, dim3(npairs), dim3(256), 0, s, pi, pj, ptr, qi, qj, d_sub, Y, Zr, B0, m0);
+    else
+        hipLaunchKernelGGL(k_coarse_pairs_direct, dim3(npairs), dim3(256), 0, s, pi, pj, ptr, qi, qj, d_sub, Y, Zr, B0,
+                           m0);
     HKG_HIP(hipGetLastError());
     return HKG_OK;
 }

@@ -96,9 +96,10 @@ int32_t back_transform_n(const SubDev *d_sub, int nsub, int maxnI, int max_m, co
 int32_t scale_rows_invsqrt_diag(const SubDev *d_sub, int nsub, const double *C, double *Z, hipStream_t s);
 int32_t finish_basis(const SubDev *d_sub, int nsub, const int32_t *I_idx, const double *winv, double *Z,
                      hipStream_t s);
+// Zr: the basis row-major (n_I x m_i at offZ); max_m: the largest m_i
 int32_t coarse_pairs(int npairs, const int32_t *pi, const int32_t *pj, const int32_t *ptr, const int32_t *qi,
-                     const int32_t *qj, const SubDev *d_sub, const double *Y, const double *Z, double *B0, int m0,
-                     hipStream_t s);
+                     const int32_t *qj, const SubDev *d_sub, int max_m, const double *Y, const double *Zr, double *B0,
+                     int m0, hipStream_t s);
 
 // ---- apply.hip: one application of the two-level preconditioner ----------------------------------
 struct ApplyPlan {

@@ -28,26 +28,63 @@ __device__ __forceinline__ void gemm_tile(int M, int N, int K, const T *__restri
 #pragma unroll
         for (int c = 0; c < 4; ++c) acc[r][c] = T(0);
 
-    for (int k0 = 0; k0 < K; k0 += GK) {
-        // stage op(A)(i0 + ii, k0 + kk) into sA[kk][ii]
-        for (int e = tid; e < GK * GT; e += 256) {
-            int ii, kk;
-            if (!ta) { ii = e % GT; kk = e / GT; } else { kk = e % GK; ii = e / GK; }
-            int gi = i0 + ii, gk = k0 + kk;
-            T v = T(0);
-            if (gi < M && gk < K) v = ta ? A[gk + (int64_t)gi * lda] : A[gi + (int64_t)gk * lda];
-            sA[kk][ii] = v;
+    // element e (< GK GT) of a k-step's A and B tiles: its LDS slot and its value; the next step's
+    // values are loaded into registers while the current step is computed
+    constexpr int PER = GK * GT / 256;
+    auto a_slot = [&](int e, int &kk, int &ii) {
+        if (!ta) {
+            ii = e % GT;
+            kk = e / GT;
+        } else {
+            kk = e % GK;
+            ii = e / GK;
         }
-        // stage op(B)(k0 + kk, j0 + jj) into sB[kk][jj]
-        for (int e = tid; e < GK * GT; e += 256) {
-            int jj, kk;
-            if (!tb) { kk = e % GK; jj = e / GK; } else { jj = e % GT; kk = e / GT; }
-            int gj = j0 + jj, gk = k0 + kk;
-            T v = T(0);
-            if (gj < N && gk < K) v = tb ? B[gj + (int64_t)gk * ldb] : B[gk + (int64_t)gj * ldb];
-            sB[kk][jj] = v;
+    };
+    auto b_slot = [&](int e, int &kk, int &jj) {
+        if (!tb) {
+            kk = e % GK;
+            jj = e / GK;
+        } else {
+            jj = e % GT;
+            kk = e / GT;
+        }
+    };
+    auto a_val = [&](int k0, int e) -> T {
+        int kk, ii;
+        a_slot(e, kk, ii);
+        const int gi = i0 + ii, gk = k0 + kk;
+        return (gi < M && gk < K) ? (ta ? A[gk + (int64_t)gi * lda] : A[gi + (int64_t)gk * lda]) : T(0);
+    };
+    auto b_val = [&](int k0, int e) -> T {
+        int kk, jj;
+        b_slot(e, kk, jj);
+        const int gj = j0 + jj, gk = k0 + kk;
+        return (gj < N && gk < K) ? (tb ? B[gj + (int64_t)gk * ldb] : B[gk + (int64_t)gj * ldb]) : T(0);
+    };
+    T ra[PER], rb[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        ra[u] = a_val(0, tid + 256 * u);
+        rb[u] = b_val(0, tid + 256 * u);
+    }
+#pragma clang loop unroll(disable)
+    for (int k0 = 0; k0 < K; k0 += GK) {
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            int kk, ii;
+            a_slot(tid + 256 * u, kk, ii);
+            sA[kk][ii] = ra[u];
+            b_slot(tid + 256 * u, kk, ii);
+            sB[kk][ii] = rb[u];
         }
         __syncthreads();
+        if (k0 + GK < K) {
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                ra[u] = a_val(k0 + GK, tid + 256 * u);
+                rb[u] = b_val(k0 + GK, tid + 256 * u);
+            }
+        }
 #pragma unroll
         for (int kk = 0; kk < GK; ++kk) {
             T a[4], b[4];

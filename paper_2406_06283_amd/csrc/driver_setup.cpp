@@ -440,7 +440,7 @@ int32_t coarse_space(hkgeneo_ctx *c, hipStream_t s, const std::function<int32_t(
                                    dp<double>(c->wE), dp<double>(c->wTau), s));
     HKG_TRY(walloc(c, &c->wM, ns * sizeof(int32_t)));
     HKG_TRY(walloc(c, &c->wLam, (size_t)ns * (mmax + 2) * sizeof(double)));
-    HKG_TRY(walloc(c, &c->wIv, (size_t)3 * ns * sizeof(double)));
+    HKG_TRY(walloc(c, &c->wIv, (size_t)5 * ns * sizeof(double)));
     HKG_TRY(select_eigs(dsub, ns, c->max_nI, dp<double>(c->wD), dp<double>(c->wE), o.eig_mode, o.tau, o.nev,
                         o.cluster_rtol, mmax, dp<int32_t>(c->wM), dp<double>(c->wLam), dp<int32_t>(c->wFlag),
                         dp<double>(c->wIv), s));

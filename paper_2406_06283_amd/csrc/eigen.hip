@@ -456,6 +456,9 @@ __device__ void stage_tridiagonal(const double *__restrict__ dg, const double *_
     *piv_out = pivmin;
 }
 
+// per subdomain: Gershgorin bounds, pivot floor, count below tau, count below 0
+constexpr int IV_SLOTS = 5;
+
 __global__ __launch_bounds__(64) void k_select_count(const SubDev *__restrict__ subs, const double *__restrict__ dbuf,
                                                      const double *__restrict__ ebuf, int mode, double tau, int nev,
                                                      int mmax, int32_t *__restrict__ m_out, int32_t *__restrict__ flag,
@@ -476,15 +479,19 @@ __global__ __launch_bounds__(64) void k_select_count(const SubDev *__restrict__ 
     if (lane == 0) {
         m_out[blockIdx.x] = m;
         flag[blockIdx.x] = m > mmax ? 1 : 0;
-        iv[3 * blockIdx.x] = lo;
-        iv[3 * blockIdx.x + 1] = hi;
-        iv[3 * blockIdx.x + 2] = pivmin;
+        iv[IV_SLOTS * blockIdx.x] = lo;
+        iv[IV_SLOTS * blockIdx.x + 1] = hi;
+        iv[IV_SLOTS * blockIdx.x + 2] = pivmin;
+        // the counts below tau (threshold mode) and below 0: eigenvalue k < count lies below that
+        // shift, which bounds its bracket from above
+        iv[IV_SLOTS * blockIdx.x + 3] = mode == HKG_EIG_THRESHOLD ? (double)c0 : 0.0;
+        iv[IV_SLOTS * blockIdx.x + 4] = (double)c1;
     }
 }
 
 // wave (subdomain, k): lambda_k in (a, b] with count(a) <= k < count(b), narrowed 65-fold per round
 __global__ __launch_bounds__(64) void k_select_refine(const SubDev *__restrict__ subs, const double *__restrict__ dbuf,
-                                                      const double *__restrict__ ebuf, int mmax,
+                                                      const double *__restrict__ ebuf, int mmax, double tau,
                                                       const int32_t *__restrict__ m_in, const int32_t *__restrict__ flag,
                                                       const double *__restrict__ iv, double *__restrict__ lam_out) {
     extern __shared__ double sh[];
@@ -495,8 +502,11 @@ __global__ __launch_bounds__(64) void k_select_refine(const SubDev *__restrict__
     double *d = sh, *e2 = sh + n;
     double lo0, hi0, pv0;
     stage_tridiagonal(dbuf + sd.offI, ebuf + sd.offI, n, d, e2, &lo0, &hi0, &pv0);
-    const double pivmin = iv[3 * sub + 2];
-    double a = iv[3 * sub], b = iv[3 * sub + 1];
+    const double pivmin = iv[IV_SLOTS * sub + 2];
+    double a = iv[IV_SLOTS * sub], b = iv[IV_SLOTS * sub + 1];
+    // count(tau) > k or count(0) > k: the bracket (a, b] may end at that shift
+    if (k < (int)iv[IV_SLOTS * sub + 3]) b = fmin(b, tau);
+    if (k < (int)iv[IV_SLOTS * sub + 4]) b = fmin(b, 0.0);
     const int lane = threadIdx.x;
     for (int it = 0; it < 40; ++it) {
         const double sig = a + (b - a) * ((double)(lane + 1) / 65.0);
@@ -532,7 +542,7 @@ __global__ __launch_bounds__(64) void k_select_close(const SubDev *__restrict__ 
     while (m > 0 && m < n && lam[m] - lam[m - 1] <= rtol * fmax(1.0, fabs(lam[m - 1]))) {
         ++m;
         if (m > mmax) break;
-        if (m < n) lam[m] = bisect_kth(d, e2, n, m, iv[3 * sub], iv[3 * sub + 1], pivmin);
+        if (m < n) lam[m] = bisect_kth(d, e2, n, m, iv[IV_SLOTS * sub], iv[IV_SLOTS * sub + 1], pivmin);
     }
     flag[sub] = (m > mmax) ? 1 : 0;
     m_io[sub] = m;
@@ -543,8 +553,8 @@ int32_t select_eigs(const SubDev *d_sub, int nsub, int maxnI, const double *d, c
                     hipStream_t s) {
     const size_t shm = (size_t)2 * maxnI * sizeof(double);
     hipLaunchKernelGGL(k_select_count, dim3(nsub), dim3(64), shm, s, d_sub, d, e, mode, tau, nev, mmax, m_out, flag, iv);
-    hipLaunchKernelGGL(k_select_refine, dim3(nsub, mmax + 1), dim3(64), shm, s, d_sub, d, e, mmax, m_out, flag, iv,
-                       lam_out);
+    hipLaunchKernelGGL(k_select_refine, dim3(nsub, mmax + 1), dim3(64), shm, s, d_sub, d, e, mmax, tau, m_out, flag,
+                       iv, lam_out);
     hipLaunchKernelGGL(k_select_close, dim3(nsub), dim3(64), shm, s, d_sub, d, e, rtol, mmax, m_out, flag, iv, lam_out);
     HKG_HIP(hipGetLastError());
     return HKG_OK;

@@ -144,3 +144,76 @@ def test_one_level_zero_overlap_rejected():
     p = pb.make_problem(8, s=2, overlap=0)
     with pytest.raises(ValueError):
         _M(p)
+
+
+# ------------------------------------------------------------------------------------------------
+# Partition-of-unity weighted one-level operator (W_D = Xi_D, Def 2.13) and the sign convention
+# ------------------------------------------------------------------------------------------------
+
+def _clean_dofs(p, subs):
+    """Dofs l such that, for every subdomain D, l is in dof(D) or is not coupled (through the sparsity
+    of B) to any dof of D.  For u supported there, R_D B u = B_D R_D u exactly for every D."""
+    B = (p.A - p.S).tocsr()
+    pat = (abs(B) + abs(p.A) + abs(p.S)).tocsr()
+    ok = np.ones(p.n_dof, bool)
+    for s in subs:
+        inD = np.zeros(p.n_dof, bool)
+        inD[s.dof] = True
+        coupled = np.asarray(pat[s.dof].sum(axis=0)).ravel() != 0
+        ok &= inD | ~coupled
+    return np.nonzero(ok)[0]
+
+
+def test_pou_one_level_reproduces_data_away_from_subdomain_boundaries():
+    # For u vanishing near every subdomain boundary, each exact local solve returns R_D u, so
+    #   sum_D E_D Xi_D B_D^{-1} R_D (B u) = sum_D E_D diag(1/mu) R_D u = u      (partition of unity),
+    # while the unweighted sum (eq. 2.22) gives mu * u.  Weights on the restriction side, mu in place
+    # of 1/mu, or multiplicities counted over ovdof all break the first identity where mu > 1.
+    p = pb.make_problem(20, k=7.0, s=2, overlap=3, coef="cells", seed=2, n_cells=5)
+    Mp = _M(p, two_level=False, prolong=schwarz.PROLONG_POU)
+    Ma = _M(p, two_level=False)
+    Q = _clean_dofs(p, Mp.subs)
+    mu = Mp.mu
+    assert np.any(mu[Q] == 2) and np.any(mu[Q] == 4)        # the weights matter on this support
+    u = np.zeros(p.n_dof)
+    u[Q] = np.random.default_rng(7).standard_normal(Q.size)
+    r = Mp.B @ u
+    np.testing.assert_allclose(Mp.apply(r), u, atol=1e-11 * np.abs(u).max())
+    np.testing.assert_allclose(Ma.apply(r), mu * u, atol=1e-11 * np.abs(u).max())
+    # the transposed (restriction-side) weighting does not reproduce u
+    wrong = np.zeros(p.n_dof)
+    for s, lu in zip(Mp.subs, Mp.local_lu):
+        wrong[s.dof] += sla.lu_solve(lu, r[s.dof] / mu[s.dof])
+    assert np.abs(wrong - u).max() > 1e-3 * np.abs(u).max()
+
+
+def test_pou_dense_operator_from_boolean_matrices():
+    # W_D = Xi_D: M^{-1} = sum_D R_D^T diag(1/mu) (R_D B R_D^T)^{-1} R_D + Z (Z^T B Z)^{-1} Z^T, with the
+    # multiplicities counted from the Boolean R_D (mu = sum_D R_D^T R_D 1).
+    p = pb.make_problem(10, k=8.0, s=3, overlap=2, coef="cells", seed=6, n_cells=5)
+    M = _M(p, eig_mode=local.EIG_FIXED, nev=3, prolong=schwarz.PROLONG_POU)
+    B = M.B.toarray()
+    Rs = [dec.restriction_matrix(s.dof, p.n_dof).toarray() for s in M.subs]
+    mu = sum(R.T @ R for R in Rs) @ np.ones(p.n_dof)
+    ref = np.zeros_like(B)
+    for R in Rs:
+        ref += R.T @ np.diag(1.0 / (R @ mu)) @ np.linalg.inv(R @ B @ R.T) @ R
+    Z = M.Z.toarray()
+    ref += Z @ np.linalg.inv(Z.T @ B @ Z) @ Z.T
+    np.testing.assert_allclose(M.dense(), ref, atol=1e-10 * np.abs(ref).max())
+
+
+def test_eigenvector_sign_convention():
+    # Every column's entry of largest magnitude is positive (the first such entry on ties), and the
+    # convention is a function of the span of each column: flipping input signs changes nothing.
+    p = pb.make_problem(12, k=9.0, s=2, overlap=2, coef="lognormal", seed=1)
+    M = _M(p, eig_mode=local.EIG_FIXED, nev=4)
+    for s in M.subs:
+        Bt, C = local.geneo_pencil(p, s, M.mu)
+        _, P = local.geneo_eigenpairs(Bt, C, s.dof.size)
+        top = P[np.argmax(np.abs(P), axis=0), np.arange(P.shape[1])]
+        assert np.all(top > 0)
+        flips = np.where(np.arange(P.shape[1]) % 2 == 0, -1.0, 1.0)
+        np.testing.assert_array_equal(local.normalise_signs(P * flips), P)
+    T = np.array([[0.5, -2.0], [-0.5, 2.0], [0.1, 0.3]])
+    np.testing.assert_array_equal(local.normalise_signs(T), np.array([[0.5, 2.0], [-0.5, -2.0], [0.1, -0.3]]))

@@ -442,9 +442,9 @@ int32_t retire(Engine *E, int slot) {
     d.info.resize(R);
     for (int r = 0; r < R; ++r) {
         const double fn = sc[8 * r + 1];
-        const double rel = fn > 0 ? rn[r] / fn : 0.0;
+        const double rel = gmres_relres(rn[r], fn);
         d.info[r].iters = it[r];
-        d.info[r].converged = rel <= P.rtol;
+        d.info[r].converged = rel <= P.rtol;     // false for NaN
         d.info[r].relres_est = fn > 0 ? sc[8 * r + 2] / fn : 0.0;
         d.info[r].relres_true = rel;
         if (!d.info[r].converged) d.status = HKG_ENOTCONV;

@@ -516,7 +516,9 @@ __global__ __launch_bounds__(BROWS) void k_b_finish(const ProbDev *__restrict__ 
         const int brk = hn <= 1e-14 * hc[m + 1];
         const int sing = d == 0.0;
         const int itn = ++P.iters[rhs];
-        sc[3] = (double)(j + 1);
+        // a singular rotated column (zero diagonal of R) is left out of the back substitution; the
+        // restart phase then retires the pair (sc[5])
+        sc[3] = (double)(sing ? j : j + 1);
         if (conv || brk || sing || j + 1 == m || itn >= P.max_iter) {
             P.active[rhs] = PS_CYCLE_END;
             sc[4] = conv ? 1.0 : 0.0;
@@ -676,7 +678,8 @@ __global__ void k_r_decide(const ProbDev *__restrict__ probs, const int32_t *__r
         P.iters[rhs] = 0;
     }
     const double fn = sc[1];
-    if (fn == 0.0 || rn <= P.rtol * fn || P.iters[rhs] >= P.max_iter) {
+    const bool sing = st == PS_CYCLE_END && sc[5] != 0.0;
+    if (fn == 0.0 || !gmres_keeps_going(rn, fn, P.rtol) || sing || P.iters[rhs] >= P.max_iter) {
         P.active[rhs] = PS_DONE;
         return;
     }

@@ -52,8 +52,6 @@ int32_t gemm_batched(const GemmJob *d_jobs, int nbatch, int maxM, int maxN, cons
 }
 template int32_t gemm_batched<double>(const GemmJob *, int, int, int, const double *, const double *, double *, double,
                                       double, bool, bool, hipStream_t);
-template int32_t gemm_batched<float>(const GemmJob *, int, int, int, const float *, const float *, float *, float,
-                                     float, bool, bool, hipStream_t);
 
 // ------------------------------------------------------------------------------------------------
 // LU with partial pivoting, right-looking blocked (panel, row swaps, U12 solve, trailing GEMM).
@@ -640,6 +638,40 @@ __global__ __launch_bounds__(256) void k_lu_swap_left(const DMat *__restrict__ m
     }
 }
 
+// Numerically singular factors: after the LU with partial pivoting, a pivot whose magnitude is at
+// most 32 n eps times the largest pivot magnitude counts as a zero pivot (the backward error of the
+// factorisation is of that order, so the matrix cannot be told from a singular one).  The first such
+// column goes to info, as an exact zero pivot does; NaN pivots are caught the same way.  One block
+// per matrix.
+template <typename T>
+__global__ __launch_bounds__(256) void k_lu_tiny_pivot(const DMat *__restrict__ mats, const T *__restrict__ Ab,
+                                                       int32_t *__restrict__ info) {
+    __shared__ double redm[4];
+    __shared__ int redi[4];
+    const DMat m = mats[blockIdx.x];
+    const T *A = Ab + m.off;
+    const int n = m.n, ld = m.ld;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double mx = 0.0;
+    for (int j = threadIdx.x; j < n; j += 256) mx = fmax(mx, fabs((double)A[j + (int64_t)j * ld]));
+    mx = wave_max64(mx);
+    if (lane == 0) redm[w] = mx;
+    __syncthreads();
+    mx = fmax(fmax(redm[0], redm[1]), fmax(redm[2], redm[3]));
+    const double eps = sizeof(T) == 8 ? 2.220446049250313e-16 : 1.1920928955078125e-07;
+    const double tiny = 32.0 * (double)n * eps * mx;
+    int first = n;
+    for (int j = threadIdx.x; j < n; j += 256)
+        if (!(fabs((double)A[j + (int64_t)j * ld]) > tiny)) first = min(first, j);
+    first = (int)wave_min64((double)first);
+    if (lane == 0) redi[w] = first;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        first = min(min(redi[0], redi[1]), min(redi[2], redi[3]));
+        if (first < n && info[blockIdx.x] == 0) info[blockIdx.x] = first + 1;
+    }
+}
+
 template <typename T>
 int32_t lu_batched(const DMat *d_mats, const int64_t *d_poff, int nbatch, int maxn, T *A, int32_t *piv,
                    int32_t *info, bool pivot, hipStream_t s, int band) {
@@ -731,13 +763,12 @@ int32_t lu_batched(const DMat *d_mats, const int64_t *d_poff, int nbatch, int ma
         hipLaunchKernelGGL(k_lu_swap_left<T>, dim3((maxn - LU_NB + LS_COLS - 1) / LS_COLS, nbatch), dim3(256), shm, s,
                            d_mats, d_poff, A, piv, jf);
     }
+    if (pivot && sizeof(T) == 8) hipLaunchKernelGGL(k_lu_tiny_pivot<T>, dim3(nbatch), dim3(256), 0, s, d_mats, (const T *)A, info);
     HKG_HIP(hipGetLastError());
     return HKG_OK;
 }
 template int32_t lu_batched<double>(const DMat *, const int64_t *, int, int, double *, int32_t *, int32_t *, bool,
                                     hipStream_t, int);
-template int32_t lu_batched<float>(const DMat *, const int64_t *, int, int, float *, int32_t *, int32_t *, bool,
-                                   hipStream_t, int);
 
 // ------------------------------------------------------------------------------------------------
 // Blocked triangular solves op(T) X = X with many right-hand sides (T n x n, X n x ncol):
@@ -1192,8 +1223,6 @@ int32_t tri_solve_batched(const TriJob *d_jobs, int nbatch, int maxn, int maxcol
 }
 template int32_t tri_solve_batched<double>(const TriJob *, int, int, int, const double *, double *, int, hipStream_t,
                                            int, const double *);
-template int32_t tri_solve_batched<float>(const TriJob *, int, int, int, const float *, float *, int, hipStream_t, int,
-                                          const float *);
 
 // ------------------------------------------------------------------------------------------------
 // Inverse of one packed LU (P A = L U) by recursive block triangular inversion: the LU_NB diagonal
@@ -1444,8 +1473,6 @@ int32_t perm_identity_batched(const DMat *d_mats, const int64_t *d_poff, int nba
 }
 template int32_t perm_identity_batched<double>(const DMat *, const int64_t *, int, int, const int32_t *, double *,
                                                hipStream_t);
-template int32_t perm_identity_batched<float>(const DMat *, const int64_t *, int, int, const int32_t *, float *,
-                                              hipStream_t);
 
 // out = in^T for square matrices with the same descriptors (separate buffers)
 template <typename T>

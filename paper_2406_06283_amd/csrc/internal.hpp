@@ -29,6 +29,18 @@ namespace hkg {
 void set_last_error(const std::string &msg);
 extern thread_local std::string g_last_error;
 
+// FGMRES stopping rule, shared by the host loop and the device kernels of both solve paths: a
+// right-hand side keeps iterating while its residual norm is finite and above rtol ||f||.  A NaN or
+// infinite residual (or ||f||) stops it; the result then reports non-convergence.
+__host__ __device__ inline bool gmres_keeps_going(double rn, double fn, double rtol) {
+    return rn > rtol * fn && rn <= 1.7976931348623157e308;   // comparisons with NaN are false
+}
+// ||f - B x|| / ||f||: 0 for a zero right-hand side, NaN when ||f|| is not finite
+__host__ __device__ inline double gmres_relres(double rn, double fn) {
+    if (fn == 0.0) return 0.0;
+    return (fn > 0.0 && fn <= 1.7976931348623157e308) ? rn / fn : __builtin_nan("");
+}
+
 // ------------------------------------------------------------------------------------------------
 // Host partitioner output (Def. 2.8, Def. 2.12, Def. 2.13, Lambda of Sec. 2.4)
 // ------------------------------------------------------------------------------------------------

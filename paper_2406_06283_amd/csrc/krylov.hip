@@ -190,7 +190,9 @@ __global__ __launch_bounds__(KB) void k_arnoldi_finish(GmresDev G, int j, double
         const int it = ++G.iters[rhs];
         if (conv || brk || sing || j + 1 == m || it >= G.max_iter) {
             G.active[rhs] = 0;
-            sc[3] = (double)(j + 1);       // columns used in this cycle
+            // columns used in this cycle; a singular rotated column (zero diagonal of R) is left
+            // out of the back substitution, and the host stops the right-hand side (sc[5])
+            sc[3] = (double)(sing ? j : j + 1);
             sc[4] = conv ? 1.0 : 0.0;
             sc[5] = sing ? 1.0 : 0.0;
         }
@@ -216,7 +218,7 @@ __global__ __launch_bounds__(KB) void k_cycle_start(GmresDev G, const double *__
     const int n = G.n, m = G.restart;
     const double beta = rnorm[rhs];
     double *sc = G.scal + (int64_t)rhs * 8;
-    const int act = want[rhs] && beta > rtol * sc[1] && beta > 0.0;
+    const int act = want[rhs] && gmres_keeps_going(beta, sc[1], rtol) && beta > 0.0;
     double *V = G.V + (int64_t)rhs * n * (m + 1);
     const double inv = beta > 0.0 ? 1.0 / beta : 0.0;
     const int row0 = blockIdx.x * ROWS_PER_BLOCK;

@@ -1,24 +1,30 @@
 """Benchmark: Helmholtz solves/s to relative residual 1e-8 on one MI355X.
 
-Default workload (h = 1/128, k = 40, 8 x 8 subdomains).  A step is one pass of the whole hot path
-for one right-hand side with its inputs resident in device memory: the numeric setup (local blocks,
-local H_k-GenEO eigenproblems, coarse space, coarse and local factors; hkgeneo_factor) followed by
-the FGMRES solve.  The host analysis (partition, index sets, uploads) runs once before the timed
-region.  Three forms are timed, each over the same steps:
+Default workload: P1 h = 1/256 (65,025 dofs), k = 80, lognormal coefficient, 16 x 16 subdomains,
+FGMRES(150) (the mixed-precision configuration).  A step is one pass of the whole hot path for one
+right-hand side with its inputs resident in device memory: the numeric setup (local blocks, local
+H_k-GenEO eigenproblems, coarse space, coarse and local factors; hkgeneo_factor) followed by the
+FGMRES solve.  The host analysis (partition, index sets, uploads) runs once before the timed
+region.  Forms, each timed over the same steps:
 
   * mixed  - float32 local inverses (formed in float64) inside float64 FGMRES, solved by the
              batched engine (hkgeneo_batch_solve: graph-captured iteration).  This is `value`.
   * fp64   - everything in float64, same batched engine.
   * plain  - everything in float64, single-problem path (hkgeneo_gmres_solve).
+  * pou    - the mixed form with the partition-of-unity weighted local prolongation (W_D = Xi_D).
 
 The mixed form's timed region runs with the engine's measurement hook on: HIP events around every
 batched local-solve launch on the engine's stream give the roofline of that kernel (the hook
 launches the iteration directly instead of replaying its graph; the unprofiled step time is
-reported beside it).  The line also carries solve-only latency percentiles (factors resident), an
-8-right-hand-side solve-only throughput, and the CPU oracle timed on a bounded sample.
+reported beside it).  `iteration_roofline` prices the whole FGMRES iteration: the method's
+algorithmic bytes per iteration times the iterations, over the solve time.  The line also carries
+solve-only latency percentiles (factors resident), an 8-right-hand-side solve-only throughput, the
+relative error of every form's solution against the float64 oracle's FGMRES solution, and the
+oracle itself timed on the host cores (one full setup + solve).
 
-Other workloads: --workload mix64 (64 independent problems in one batch, setup timed apart) and
---workload serve (Poisson request stream through the continuous-batching server).
+Other workloads: --workload p1_h128_k40_8x8 (and the other named ones), --workload mix64 (64
+independent problems in one batch, setup timed apart) and --workload serve (Poisson request stream
+through the continuous-batching server).
 
 usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME] [--cpu-sample N]
 """
@@ -51,6 +57,17 @@ def local_solve_bytes(nI: np.ndarray, m: np.ndarray, word: int, nrhs: int = 1) -
     return int(word * int((nI64 ** 2).sum()) + 8 * int((nI64 * m.astype(np.int64)).sum()) + nrhs * per_rhs)
 
 
+def iteration_bytes(n, nnz, nI, m, m0, word, j_mean):
+    """Algorithmic bytes of one FGMRES iteration for one right-hand side (every term the method needs):
+    local inverses (sum n_D^2 words), the coarse basis read twice (restriction Z^T r and prolongation
+    Z y), the dense inverse of B_0, the CSR product, the gathers and scatters of the local vectors,
+    classical Gram-Schmidt twice against the j current basis vectors, and the new z_j, v_{j+1}."""
+    nI64 = nI.astype(np.int64)
+    s = int(nI64.sum())
+    return int(word * int((nI64 ** 2).sum()) + 16 * int((nI64 * m.astype(np.int64)).sum()) + 8 * m0 * m0
+               + 12 * nnz + 20 * n + 24 * s + 8 * n + 32 * j_mean * n + 24 * n)
+
+
 def progress(msg):
     """Progress of the longer workloads on stderr (the JSON line alone goes to stdout)."""
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -72,19 +89,21 @@ def timed_steps(S, solve, steps, warmup):
         solve()
     sync()
     fac, sol, it, rel = [], [], [], []
+    u = None
     t0 = time.perf_counter()
     for _ in range(steps):
         a = time.perf_counter()
         S.factor()
         b = time.perf_counter()
-        info = solve()
+        info, u = solve()
         c = time.perf_counter()
         fac.append(1e3 * (b - a))
         sol.append(1e3 * (c - b))
         it.append(info["iters"])
         rel.append(info["relres_true"])
     sync()
-    return dict(total_s=time.perf_counter() - t0, fac_ms=fac, sol_ms=sol, iters=it, relres=rel)
+    return dict(total_s=time.perf_counter() - t0, fac_ms=fac, sol_ms=sol, iters=it, relres=rel,
+                u=u.cpu().numpy().ravel() if u is not None else None)
 
 
 def kernel_source_hash() -> str:
@@ -147,20 +166,28 @@ def run_default(args, w, p):
     # plain float64 single-problem path
     if "plain" in forms:
         S = H.Solver(p, H.options_for(w, keep_workspace=1))
-        r = timed_steps(S, lambda: S.solve(f)[1][0], args.steps, args.warmup)
+
+        def solve_plain():
+            u, info, _ = S.solve(f)
+            return info[0], u
+        r = timed_steps(S, solve_plain, args.steps, args.warmup)
         r["lat"] = latency(lambda: S.solve(f), max(args.steps, args.lat_reps))
         r["lat8"] = latency(lambda: S.solve(f8), max(1, args.lat_reps // 4))
         r["m0"] = S.stats()["m0"]
         out["plain"] = r
         S.close()
     # batched engine, float64 and mixed
-    for tag, prec in (("fp64", 64), ("mixed", 32)):
+    for tag, prec, prolong in (("fp64", 64, H.HKG_PROLONG_AS), ("mixed", 32, H.HKG_PROLONG_AS),
+                               ("pou", 32, H.HKG_PROLONG_POU)):
         if tag not in forms:
             continue
-        S = H.Solver(p, H.options_for(w, local_prec=prec, keep_workspace=1))
+        S = H.Solver(p, H.options_for(w, local_prec=prec, prolong=prolong, keep_workspace=1))
         B = H.Batch([S], [1])
         B8 = H.Batch([S], [8])
-        solve = lambda: B.solve([f])[1][0][0]
+
+        def solve():
+            (u,), (info,), _ = B.solve([f])
+            return info[0], u
         r = timed_steps(S, solve, args.steps, args.warmup)       # graph replay
         if tag == "mixed":
             B.profile(True)
@@ -243,6 +270,7 @@ def run_cpu_baseline(w, p, sample: int):
     opts = schwarz.Options(eig_mode=local.EIG_FIXED if w.eig_mode == 1 else local.EIG_THRESHOLD, nev=w.nev, tau=w.tau)
     t0 = time.perf_counter()
     iters = []
+    x = None
     for _ in range(sample):
         M = schwarz.TwoLevelSchwarz(p, opts)
         x, info = fgmres.solve(p, M, restart=w.restart)
@@ -250,7 +278,7 @@ def run_cpu_baseline(w, p, sample: int):
     dt = time.perf_counter() - t0
     return dict(value=sample / dt, unit="solves/s", cores=int(threads), kind="oracle",
                 sample=f"{sample} full solve(s) (setup + FGMRES) of {w.name} seed 0 on the host, "
-                       f"{dt:.1f} s, {iters[0]} iterations", iters=iters[0])
+                       f"{dt:.1f} s, {iters[0]} iterations", iters=iters[0], x=x)
 
 
 def summary(r, steps):
@@ -261,12 +289,34 @@ def summary(r, steps):
             "rhs8_solves_per_s": round(8e3 / np.median(r["lat8"]), 1)}
 
 
+def oracle_error(r, x):
+    """relative error of a form's last solution against the float64 oracle's FGMRES solution"""
+    if r is None or x is None or r.get("u") is None:
+        return None
+    return float(np.linalg.norm(r["u"] - x) / np.linalg.norm(x))
+
+
+def side_workload(args, name):
+    """The mixed form of another named workload (steps/s, iterations, solve-only latency)."""
+    import argparse as _ap
+    from paper_2406_06283_amd.configs import WORKLOADS
+    w = WORKLOADS[name]
+    a = _ap.Namespace(**vars(args))
+    a.forms = "mixed"
+    r = run_default(a, w, w.problem(seed=0))["mixed"]
+    out = summary(r, args.steps)
+    out["profiled_steps_per_s"] = round(args.steps / r["profiled"]["total_s"], 3)
+    out["m0"] = int(r["m0"])
+    return out
+
+
 def main_default(args):
     from paper_2406_06283_amd.configs import WORKLOADS
     w = WORKLOADS[args.workload]
     p = w.problem(seed=0)
+    progress(f"{w.name}: forms {args.forms}")
     r = run_default(args, w, p)
-    mx, f64, plain = r["mixed"], r.get("fp64"), r.get("plain")
+    mx, f64, plain, pou = r["mixed"], r.get("fp64"), r.get("plain"), r.get("pou")
     rp = mx["profiled"]
     ref = plain or f64          # float64 iteration count the mixed form must stay within 2 of
     ok = all(x <= 1e-8 for x in rp["relres"]) and (
@@ -275,6 +325,11 @@ def main_default(args):
     bpl = local_solve_bytes(mx["nI"], mx["m"], word)
     avg_s = rp["local_ms"] / max(rp["launches"], 1) / 1e3
     achieved = bpl / avg_s / 1e9
+    iters = int(np.median(mx["iters"]))
+    j_mean = (iters - 1) / 2.0 if iters <= w.restart else (w.restart - 1) / 2.0
+    ibytes = iteration_bytes(p.n_dof, p.nnz, mx["nI"], mx["m"], int(mx["m0"]), word, j_mean)
+    solve_s = pct(mx["lat"], 50) / 1e3
+    it_achieved = ibytes * iters / solve_s / 1e9
     line = {
         "metric": METRIC,
         "value": round(args.steps / rp["total_s"], 3) if ok else 0.0,
@@ -303,15 +358,35 @@ def main_default(args):
         if args.in_flight > 1 else None,
         "fp64_batched": summary(f64, args.steps) if f64 else None,
         "fp64_plain": summary(plain, args.steps) if plain else None,
+        "pou_mixed": summary(pou, args.steps) if pou else None,
         "roofline": {"kernel": "k_b_local<%d> (float32 inverses)" % rp["waves"], "bound": "hbm",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": recorded_traffic(w.name),
                      "bytes_per_launch": bpl,
                      "avg_launch_us": round(avg_s * 1e6, 3), "launches": int(rp["launches"])},
+        "iteration_roofline": {"bound": "hbm", "achieved": round(it_achieved, 1), "peak": HBM_PEAK_GBS,
+                               "unit": "GB/s", "frac": round(it_achieved / HBM_PEAK_GBS, 4),
+                               "bytes_per_iteration": ibytes, "iterations": iters, "j_mean": j_mean,
+                               "solve_only_p50_ms": round(solve_s * 1e3, 3)},
     }
+    for extra in [x for x in args.extra_workloads.split(",") if x and x != w.name]:
+        progress(f"extra workload {extra}")
+        line.setdefault("other_workloads", {})[extra] = side_workload(args, extra)
     if not args.no_cpu_baseline:
+        progress("oracle on the host cores")
         cb = run_cpu_baseline(w, p, args.cpu_sample)
         line["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+        x = cb["x"]
+        line["vs_oracle"] = {
+            "oracle_iters": cb["iters"],
+            "rel_error": {tag: oracle_error(rr, x) for tag, rr in
+                          (("mixed", mx), ("fp64_batched", f64), ("fp64_plain", plain), ("pou_mixed", pou))
+                          if rr is not None},
+            "iters": {tag: int(np.median(rr["iters"])) for tag, rr in
+                      (("mixed", mx), ("fp64_batched", f64), ("fp64_plain", plain), ("pou_mixed", pou))
+                      if rr is not None},
+            "note": "relative 2-norm error of each form's solution against the float64 oracle's FGMRES "
+                    "solution of the same problem (both stop at relative residual 1e-8)"}
     print(json.dumps(line), flush=True)
 
 
@@ -444,11 +519,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="p1_h128_k40_8x8")
+    ap.add_argument("--workload", default="p1_h256_k80_16x16")
     ap.add_argument("--cpu-sample", type=int, default=1)
     ap.add_argument("--requests", type=int, default=200)
     ap.add_argument("--lat-reps", type=int, default=20)
-    ap.add_argument("--forms", default="plain,fp64,mixed",
+    ap.add_argument("--extra-workloads", default="p1_h128_k40_8x8",
+                    help="comma-separated named workloads whose mixed form is reported beside the line")
+    ap.add_argument("--forms", default="plain,fp64,mixed,pou",
                     help="forms of the default workload to run (mixed is always run: it gives value)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="after the run, one elementwise copy of BYTES for hardware-counter calibration")

@@ -227,49 +227,45 @@ int32_t read_flags(hkgeneo_ctx *c, const DevBuf &buf, int n, std::vector<int32_t
     return HKG_OK;
 }
 
-// B_D = P L U and B_D^{-1} = U^{-1} L^{-1} P, computed in precision T into `out` (the padded layout
-// offM / ldM, nM entries).  Launches only (buffers come from local_buffers): the pivot flags are
-// copied to c->h_infoL and checked by the caller.
-template <typename T>
-int32_t local_inverses(hkgeneo_ctx *c, T *out, hipStream_t s) {
+// B_D = P L U and B_D^{-1} = U^{-1} L^{-1} P in float64 into `out` (the padded layout offM / ldM, nM
+// entries).  Launches only (buffers come from local_buffers): the pivot flags are copied to
+// c->h_infoL and checked by the caller.
+int32_t local_inverses(hkgeneo_ctx *c, double *out, hipStream_t s) {
     const int ns = c->n_sub;
     const SubDev *dsub = dp<SubDev>(c->subs_d);
-    if (sizeof(T) == 8) HKG_TRY(copy_bii(dsub, ns, c->max_nI, dp<double>(c->wBIO), (double *)c->wLU.p, s));
-    else HKG_TRY(copy_bii_f32(dsub, ns, c->max_nI, dp<double>(c->wBIO), (float *)c->wLU.p, s));
-    HKG_TRY(lu_batched<T>(dp<DMat>(c->matsSq), dp<int64_t>(c->poffLoc), ns, c->max_nI, dp<T>(c->wLU),
-                          dp<int32_t>(c->wPivL), dp<int32_t>(c->wInfoL), true, s, c->band_I));
+    HKG_TRY(copy_bii(dsub, ns, c->max_nI, dp<double>(c->wBIO), dp<double>(c->wLU), s));
+    HKG_TRY(lu_batched<double>(dp<DMat>(c->matsSq), dp<int64_t>(c->poffLoc), ns, c->max_nI, dp<double>(c->wLU),
+                               dp<int32_t>(c->wPivL), dp<int32_t>(c->wInfoL), true, s, c->band_I));
     HKG_HIP(hipMemcpyAsync(c->h_infoL, c->wInfoL.p, ns * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HKG_TRY(perm_identity_batched<T>(dp<DMat>(c->matsM), dp<int64_t>(c->poffLoc), ns, c->max_nI,
-                                     dp<int32_t>(c->wPivL), out, s));
-    HKG_TRY(tri_solve_batched<T>(dp<TriJob>(c->jobsM), ns, c->max_nI, c->max_nI, dp<T>(c->wLU), out, TRI_LOWER_UNIT,
-                                 s));
+    HKG_TRY(perm_identity_batched<double>(dp<DMat>(c->matsM), dp<int64_t>(c->poffLoc), ns, c->max_nI,
+                                          dp<int32_t>(c->wPivL), out, s));
+    HKG_TRY(tri_solve_batched<double>(dp<TriJob>(c->jobsM), ns, c->max_nI, c->max_nI, dp<double>(c->wLU), out,
+                                      TRI_LOWER_UNIT, s));
     // U of a banded LU with row exchanges has half-bandwidth 2 band (L, with the exchanges applied to
     // its earlier columns, is not banded)
-    HKG_TRY(tri_solve_batched<T>(dp<TriJob>(c->jobsM), ns, c->max_nI, c->max_nI, dp<T>(c->wLU), out, TRI_UPPER, s,
-                                 c->band_I >= 0 ? 2 * c->band_I : -1));
+    HKG_TRY(tri_solve_batched<double>(dp<TriJob>(c->jobsM), ns, c->max_nI, c->max_nI, dp<double>(c->wLU), out,
+                                      TRI_UPPER, s, c->band_I >= 0 ? 2 * c->band_I : -1));
     return HKG_OK;
 }
 
 // every buffer of the local-inverse pipeline, allocated by the calling thread
 int32_t local_buffers(hkgeneo_ctx *c) {
     const bool store32 = c->opt.local_prec == 32;
-    const bool factor32 = store32 && c->opt.local_factor_prec == 32;
     const size_t bytes = (size_t)c->nM * (store32 ? sizeof(float) : sizeof(double));
     if (c->Minv.bytes != bytes) HKG_TRY(dalloc(c, &c->Minv, bytes));
-    HKG_TRY(walloc(c, &c->wLU, c->nSq * (factor32 ? sizeof(float) : sizeof(double))));
+    HKG_TRY(walloc(c, &c->wLU, c->nSq * sizeof(double)));
     HKG_TRY(walloc(c, &c->wPivL, c->sum_nI * sizeof(int32_t)));
     HKG_TRY(walloc(c, &c->wInfoL, c->n_sub * sizeof(int32_t)));
-    if (store32 && !factor32) HKG_TRY(walloc(c, &c->wSL, c->nM * sizeof(double)));
+    if (store32) HKG_TRY(walloc(c, &c->wSL, c->nM * sizeof(double)));
     return HKG_OK;
 }
 
-// the resident local operators in the storage precision of opt.local_prec, factorised in
-// opt.local_factor_prec (a float64 inverse rounded to float32 storage, or all in float32)
+// the resident local operators in the storage precision of opt.local_prec: B_D = P L U and
+// B_D^{-1} in float64, rounded once to float32 storage for local_prec 32
 int32_t local_operators(hkgeneo_ctx *c, hipStream_t s) {
     const bool store32 = c->opt.local_prec == 32;
-    if (!store32) return local_inverses<double>(c, dp<double>(c->Minv), s);
-    if (c->opt.local_factor_prec == 32) return local_inverses<float>(c, dp<float>(c->Minv), s);
-    HKG_TRY(local_inverses<double>(c, dp<double>(c->wSL), s));
+    if (!store32) return local_inverses(c, dp<double>(c->Minv), s);
+    HKG_TRY(local_inverses(c, dp<double>(c->wSL), s));
     return cast_f64_f32(dp<double>(c->wSL), dp<float>(c->Minv), c->nM, s);
 }
 

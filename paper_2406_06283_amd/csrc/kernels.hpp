@@ -72,7 +72,6 @@ int32_t gather_gamma_rows(const SubDev *d_sub, int nsub, int maxnI, int maxnG, c
 template <typename T>
 int32_t apply_pivots_rows(const SubDev *d_sub, int nsub, int maxcol, const int32_t *piv, T *X, int which, hipStream_t s);
 int32_t copy_bii(const SubDev *d_sub, int nsub, int maxnI, const double *BIO, double *out, hipStream_t s);
-int32_t copy_bii_f32(const SubDev *d_sub, int nsub, int maxnI, const double *BIO, float *out, hipStream_t s);
 int32_t check_spd_pivots(const SubDev *d_sub, int nsub, const double *C, int32_t *flag, hipStream_t s);
 // C_II = L D L^T in place (packed as an LU without exchanges) when its band fits the one-launch
 // kernel (ldl_band_fits); C at offSq with ld n_I

@@ -243,12 +243,6 @@ int32_t copy_bii(const SubDev *d_sub, int nsub, int maxnI, const double *BIO, do
     return HKG_OK;
 }
 
-int32_t copy_bii_f32(const SubDev *d_sub, int nsub, int maxnI, const double *BIO, float *out, hipStream_t s) {
-    int blocks = std::max(1, std::min(256, (maxnI * maxnI + 255) / 256));
-    hipLaunchKernelGGL(k_copy_bii<float>, dim3(blocks, nsub), dim3(256), 0, s, d_sub, BIO, out);
-    HKG_HIP(hipGetLastError());
-    return HKG_OK;
-}
 
 // C_II = L U without row exchanges; it is SPD exactly when every pivot is positive
 __global__ __launch_bounds__(256) void k_check_spd(const SubDev *__restrict__ subs, const double *__restrict__ C,

@@ -135,24 +135,28 @@ def test_zero_rhs_and_single_subdomain():
 
 @pytest.mark.parametrize("wl", [H32_K10, H128_K40], ids=["h32_k10", "h128_k40"])
 def test_mixed_precision_reaches_fp64_residual(wl):
-    # float32 storage and application of the local inverses inside float64 FGMRES: the residual
-    # reaches 1e-8 and, with the inverse formed in float64, at the float64 iteration count (+-2).
-    # With the LU itself in float32 the residual is still reached; near resonance (h = 1/32, k = 10)
-    # it costs extra iterations, which the test records without bounding.
+    # float32 storage and application of the local inverses (formed in float64) inside float64 FGMRES:
+    # the residual reaches 1e-8 at the float64 iteration count (+-2), on the single-problem path and
+    # on the batched engine.  A float32 LU is rejected (HKG_EINVAL).
     _say(f"[fgmres] fp32 local solves, {wl.name}")
     p = wl.problem()
     f = torch.from_numpy(p.f).to(DEV)
     res = {}
-    for tag, kw in (("64", {}), ("32", dict(local_prec=32)), ("32f", dict(local_prec=32, local_factor_prec=32))):
+    for tag, kw in (("64", {}), ("32", dict(local_prec=32))):
         with H.Solver(p, H.options_for(wl, **kw)) as S:
             u, info, st = S.solve(f)
+            with H.Batch([S], [1]) as B:
+                _, binfo, bst = B.solve([f])
             torch.cuda.synchronize()
             res[tag] = (st, info[0])
+            res[tag + "b"] = (bst, binfo[0][0])
     for tag, (st, info) in res.items():
         assert st == H.HKG_OK and info["converged"] and info["relres_true"] <= 1e-8, tag
-    assert abs(res["32"][1]["iters"] - res["64"][1]["iters"]) <= 2
-    _say(f"iterations fp64 {res['64'][1]['iters']} fp32-storage {res['32'][1]['iters']} "
-         f"fp32-factor {res['32f'][1]['iters']}")
+        assert abs(info["iters"] - res["64"][1]["iters"]) <= 2, (tag, info["iters"], res["64"][1]["iters"])
+    _say("iterations " + " ".join(f"{t} {v[1]['iters']}" for t, v in res.items()))
+    with pytest.raises(H.HkgError) as e:
+        H.Solver(p, H.options_for(wl, local_prec=32, local_factor_prec=32))
+    assert e.value.status == H.HKG_EINVAL
 
 
 @pytest.mark.slow
@@ -186,3 +190,60 @@ def test_refactor_reproduces_setup_bitwise():
             z3 = S.apply(R)
             torch.cuda.synchronize()
             assert torch.equal(z1, z2) and torch.equal(z2, z3)
+
+
+# ------------------------------------------------------------------------------------------------
+# partition-of-unity weighted local prolongation, W_D = Xi_D (Def 2.13): z = sum_D E_D Xi_D B_D^{-1} R_D r
+# (+ the coarse term of eq. 2.23)
+# ------------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("name,pkw,okw", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("two_level", [0, 1])
+def test_apply_pou_matches_oracle(name, pkw, okw, two_level):
+    _say(f"[apply pou] {name} two_level={two_level}")
+    pkw = dict(pkw)
+    N = pkw.pop("N")
+    p = pb.make_problem(N, **pkw)
+    M = _oracle(p, eig_mode=local.EIG_FIXED, two_level=bool(two_level), prolong=schwarz.PROLONG_POU, **okw)
+    R = np.random.default_rng(12).standard_normal((3, p.n_dof))
+    opts = H.default_options(eig_mode=H.HKG_EIG_FIXED, two_level=two_level, prolong=H.HKG_PROLONG_POU, **okw)
+    with H.Solver(p, opts) as S:
+        Zg = _gpu_apply(S, R)
+    Zo = np.stack([M.apply(r) for r in R])
+    scale = np.abs(Zo).max()
+    assert np.abs(Zg - Zo).max() <= 1e-10 * scale, np.abs(Zg - Zo).max() / scale
+
+
+def _pou_fgmres_case(wl):
+    p = wl.problem()
+    mode = dict(eig_mode=wl.eig_mode, tau=wl.tau, nev=wl.nev)
+    M = _oracle(p, prolong=schwarz.PROLONG_POU, **mode)
+    x, oinfo = fgmres.solve(p, M, restart=wl.restart)
+    f = torch.from_numpy(p.f).to(DEV)
+    with H.Solver(p, H.options_for(wl, prolong=H.HKG_PROLONG_POU)) as S:
+        assert list(S.subdomains()[2]) == M.m and S.stats()["m0"] == M.m0
+        u, info, st = S.solve(f)
+        torch.cuda.synchronize()
+        u = u.cpu().numpy()[0]
+    with H.Solver(p, H.options_for(wl, prolong=H.HKG_PROLONG_POU, local_prec=32)) as S32, H.Batch([S32], [1]) as B:
+        (u32,), (info32,), st32 = B.solve([f])
+        torch.cuda.synchronize()
+        u32 = u32.cpu().numpy()[0]
+    assert st == H.HKG_OK and st32 == H.HKG_OK
+    fn = np.linalg.norm(p.f[0])
+    assert np.linalg.norm(p.f[0] - M.B @ u) / fn <= 1e-8 and np.linalg.norm(p.f[0] - M.B @ u32) / fn <= 1e-8
+    assert abs(info[0]["iters"] - oinfo["iters"]) <= 2, (info[0]["iters"], oinfo["iters"])
+    assert abs(info32[0]["iters"] - oinfo["iters"]) <= 2, (info32[0]["iters"], oinfo["iters"])
+    e64 = np.linalg.norm(u - x) / np.linalg.norm(x)
+    e32 = np.linalg.norm(u32 - x) / np.linalg.norm(x)
+    _say(f"[fgmres pou] {wl.name}: iterations oracle {oinfo['iters']} fp64 {info[0]['iters']} "
+         f"mixed {info32[0]['iters']}; solution vs oracle fp64 {e64:.2e} mixed {e32:.2e}")
+    assert e64 <= 1e-8
+
+
+def test_fgmres_pou_h32_k10_matches_oracle():
+    _pou_fgmres_case(H32_K10)
+
+
+@pytest.mark.slow
+def test_fgmres_pou_h128_k40_matches_oracle():
+    _pou_fgmres_case(H128_K40)

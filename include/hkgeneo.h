@@ -27,6 +27,7 @@
 #ifndef HKGENEO_H
 #define HKGENEO_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -180,6 +181,21 @@ int32_t hkgeneo_factor(hkgeneo_ctx *ctx, void *stream);
  */
 int32_t hkgeneo_apply(hkgeneo_ctx *ctx, const double *r, double *z, int32_t nrhs, int32_t ld,
                       void *stream);
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): hkgeneo_apply without any allocation.  The same kernels
+ * and result as hkgeneo_apply; the temporaries (local vectors, the coarse restriction Z^T r and the
+ * partial sums of the coarse product: 8 nrhs (sum n_I + m0 (1 + ceil(m0 / 64))) bytes, each part
+ * rounded up to 256 bytes) live in one fixed array of HKG_APPLY_NOALLOC_MAX_BYTES per GPU, which
+ * the library holds from the first call on that GPU until the process ends; nothing in it needs to
+ * start at zero.  Every call on a GPU uses that GPU's one array, so calls that overlap in time on
+ * one GPU (different streams or host threads) race: order them on one stream.
+ * Errors: as hkgeneo_apply; HKG_EINVAL also when the temporaries exceed HKG_APPLY_NOALLOC_MAX_BYTES.
+ */
+#define HKG_APPLY_NOALLOC_MAX_BYTES ((size_t)64 << 20)
+int32_t hkgeneo_apply_noalloc(hkgeneo_ctx *ctx, const double *r, double *z, int32_t nrhs, int32_t ld,
+                              void *stream);
 
 /*
  * Solve B u = f with right-preconditioned flexible GMRES(restart) and M^{-1} as preconditioner,

@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -240,6 +241,62 @@ extern "C" int32_t hkgeneo_apply(hkgeneo_ctx *c, const double *r, double *z, int
     if (!c || !r || !z || nrhs < 1 || ld < c->n_dof) return HKG_EINVAL;
     HKG_TRY(ensure_apply_ws(c, nrhs));
     return apply_once(c, make_plan(c, nrhs), r, ld, z, ld, (hipStream_t)stream);
+}
+
+// ------------------------------------------------------------------------------------------------
+// allocation-free application: the temporaries of hkgeneo_apply (local vectors, coarse restriction,
+// partial sums of the coarse product) live in one fixed device array per GPU instead of the
+// context's lazily allocated workspace
+// ------------------------------------------------------------------------------------------------
+namespace {
+constexpr size_t kScratchDoubles = HKG_APPLY_NOALLOC_MAX_BYTES / sizeof(double);
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};    // device address of `scratch` on each GPU, once looked up
+
+// the address of this GPU's copy of `scratch` (looked up once per device, with that device current;
+// the array's name in host code is not a device address)
+int32_t scratch_on_current_device(double **out) {
+    int dev = -1;
+    HKG_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_last_error("device ordinal out of range for the allocation-free scratch table");
+        return HKG_EINVAL;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        HKG_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        g_scratch_ptr[dev] = static_cast<double *>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return HKG_OK;
+}
+}  // namespace
+
+extern "C" int32_t hkgeneo_apply_noalloc(hkgeneo_ctx *c, const double *r, double *z, int32_t nrhs, int32_t ld,
+                                         void *stream) {
+    if (!c || !r || !z || nrhs < 1 || ld < c->n_dof) return HKG_EINVAL;
+    const int64_t m0 = std::max(c->m0, 1);
+    const int64_t chunks = apply_ypart_chunks((int)m0);
+    // u (sum n_I x nrhs), c (m0 x nrhs), ypart (chunks x m0 x nrhs), each at a 256-byte boundary
+    auto round = [](int64_t d) { return (d + 31) / 32 * 32; };
+    const int64_t nu = round(c->sum_nI * nrhs), nc = round(m0 * nrhs), np = round(chunks * m0 * nrhs);
+    if ((uint64_t)(nu + nc + np) > (uint64_t)kScratchDoubles) {
+        set_last_error("hkgeneo_apply_noalloc: " + std::to_string(8 * (nu + nc + np)) +
+                       " bytes of temporaries exceed HKG_APPLY_NOALLOC_MAX_BYTES");
+        return HKG_EINVAL;
+    }
+    double *base = nullptr;
+    HKG_TRY(scratch_on_current_device(&base));
+    ApplyPlan p = make_plan(c, nrhs);
+    p.u = base;
+    p.c = base + nu;
+    p.y = nullptr;
+    p.ypart = base + nu + nc;
+    return apply_two_level(p, r, ld, z, ld, (hipStream_t)stream);
 }
 
 extern "C" int32_t hkgeneo_matvec(hkgeneo_ctx *c, const double *x, double *w, int32_t nrhs, int32_t ld, void *stream) {

@@ -31,6 +31,7 @@ HKG_EIG_THRESHOLD = 0
 HKG_EIG_FIXED = 1
 HKG_PROLONG_AS = 0
 HKG_PROLONG_POU = 1
+HKG_APPLY_NOALLOC_MAX_BYTES = 64 << 20     # size of the allocation-free scratch array per GPU
 
 _i32p = POINTER(c_int32)
 _f64p = POINTER(c_double)
@@ -78,6 +79,7 @@ SIGNATURES = {
     "hkgeneo_apply": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_void_p]),
     "hkgeneo_gmres_solve": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_int32, POINTER(hkgeneo_rhs_info),
                                       c_void_p]),
+    "hkgeneo_apply_noalloc": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_void_p]),
     "hkgeneo_matvec": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_int32, c_void_p]),
     "hkgeneo_query": (c_int32, [c_void_p, POINTER(hkgeneo_stats)]),
     "hkgeneo_query_subdomains": (c_int32, [c_void_p, _i32p, _i32p, _i32p]),
@@ -258,6 +260,14 @@ class Solver:
         _check(self.lib.hkgeneo_apply(self.handle, c_void_p(r2.data_ptr()), c_void_p(z2.data_ptr()), r2.shape[0],
                                       self.n, _stream_handle(stream)), "hkgeneo_apply")
         return z2.view_as(r) if z is None else z
+
+    def apply_noalloc(self, r, z, stream=None):
+        """hkgeneo_apply_noalloc: z = M^{-1} r with the library's fixed scratch array (z preallocated)."""
+        r2 = self._as_block(r)
+        z2 = self._as_block(z)
+        _check(self.lib.hkgeneo_apply_noalloc(self.handle, c_void_p(r2.data_ptr()), c_void_p(z2.data_ptr()),
+                                              r2.shape[0], self.n, _stream_handle(stream)), "hkgeneo_apply_noalloc")
+        return z
 
     def matvec(self, x, w=None, stream=None):
         import torch

@@ -101,6 +101,7 @@ void fill_resident(ProbDev &P, const hkgeneo_ctx *c) {
     P.B0inv = dp<double>(c->B0inv);
     P.tp_ptr = dp<int32_t>(c->tp_ptr);
     P.tp_pos = dp<int32_t>(c->tp_pos);
+    P.tp_sub = dp<int32_t>(c->tp_sub);
 }
 
 constexpr int NWS = 15;
@@ -393,7 +394,7 @@ int32_t rebuild(Engine *E) {
         for (int k = 0; k < P.nsub; ++k) items.push_back({s, k});
         for (int k = 0; k < P.nblk; ++k) rblk.push_back({s, k});
         if (P.two_level)
-            for (int k = 0; k < ((P.m0 + 63) / 64) * P.nchunk; ++k) cblk.push_back({s, k});
+            for (int k = 0; k < (P.m0 + 3) / 4; ++k) cblk.push_back({s, k});
     }
     if (items.size() > 65535) {
         set_last_error("more than 65535 subdomains in the live set");

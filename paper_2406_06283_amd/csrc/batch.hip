@@ -205,79 +205,42 @@ __global__ __launch_bounds__(LS_ROWS *WAVES) void k_b_local(const ProbDev *__res
     else local_body<double, WAVES>(P, sd, r, rhs, sh);
 }
 
-// Coarse solve y = B_0^{-1} c in two launches: split-K partial products over (64-row tile, 64-column
-// chunk) blocks, then per subdomain the fixed-order sum of its rows' partials and u_D += Z_i y_i.
-constexpr int CG_ROWS = 64;
-constexpr int CG_COLS = 64;
+// Coarse solve y = B_0^{-1} c: one wave per coarse row r.  B_0 is symmetric (B_0 = Z^T B Z), so row r
+// of its inverse is read as column r of the stored column-major inverse: contiguous, coalesced.  Lane
+// l sums the columns congruent to l modulo 64 in increasing order, then a fixed butterfly: the final
+// y (no split partial sums), whatever the batch composition.  y is stored in the ypart region.
+constexpr int CG_RPB = 4;        // rows (waves) per block
 
-__global__ __launch_bounds__(256) void k_b_coarse_gemv(const ProbDev *__restrict__ probs,
-                                                       const WorkItem *__restrict__ cblk, int mode) {
-    __shared__ double cs[CG_COLS];
-    __shared__ double part[4][CG_ROWS];
+__global__ __launch_bounds__(64 * CG_RPB) void k_b_coarse_gemv(const ProbDev *__restrict__ probs,
+                                                               const WorkItem *__restrict__ cblk, int mode) {
     const WorkItem it = cblk[blockIdx.x];
     const ProbDev &P = probs[it.p];
     const int rhs = blockIdx.z;
     if (inactive(P, rhs, mode) || !P.two_level) return;
-    const int m0 = P.m0;
-    const int rt = it.s / P.nchunk, ch = it.s % P.nchunk;
-    const int col0 = ch * CG_COLS;
-    const int ncol = min(CG_COLS, m0 - col0);
-    if ((int)threadIdx.x < ncol) cs[threadIdx.x] = P.c[(int64_t)rhs * m0 + col0 + threadIdx.x];
-    __syncthreads();
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int row = rt * CG_ROWS + lane;
-    const double *B = P.B0inv + min(row, m0 - 1) + (int64_t)col0 * m0;
-    double v[CG_COLS / 4];
-#pragma unroll
-    for (int q = 0; q < CG_COLS / 4; ++q) v[q] = B[(int64_t)min(wv + 4 * q, ncol - 1) * m0];
+    const int m0 = P.m0, lane = threadIdx.x & 63;
+    const int r = it.s * CG_RPB + (threadIdx.x >> 6);
+    if (r >= m0) return;
+    const double *col = P.B0inv + (int64_t)r * m0;
+    const double *c = P.c + (int64_t)rhs * m0;
     double acc = 0.0;
+    for (int k0 = lane; k0 < m0; k0 += 64 * 8) {
+        double b[8], x[8];
 #pragma unroll
-    for (int q = 0; q < CG_COLS / 4; ++q) acc = fma(v[q], wv + 4 * q < ncol ? cs[min(wv + 4 * q, ncol - 1)] : 0.0, acc);
-    part[wv][lane] = acc;
-    __syncthreads();
-    if (wv == 0 && row < m0)
-        P.ypart[((int64_t)rhs * P.nchunk + ch) * m0 + row] = part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane];
-}
-
-constexpr int CA_ROWS = 16;     // columns of Z_i prefetched before the partial sums arrive
-
-__global__ __launch_bounds__(256) void k_b_coarse_add(const ProbDev *__restrict__ probs,
-                                                      const WorkItem *__restrict__ items, int mode) {
-    __shared__ double ys[64];
-    const WorkItem it = items[blockIdx.y];
-    const ProbDev &P = probs[it.p];
-    const int rhs = blockIdx.z;
-    if (inactive(P, rhs, mode) || !P.two_level) return;
-    const SubDev sd = P.subs[it.s];
-    const int m = sd.m;
-    if (m == 0 || (int)blockIdx.x * 256 >= sd.nI) return;
-    const int a = blockIdx.x * 256 + threadIdx.x, ac = min(a, sd.nI - 1);
-    const double *z = P.Z + sd.offZ + ac;
-    double zv[CA_ROWS];
-#pragma unroll
-    for (int k = 0; k < CA_ROWS; ++k) zv[k] = z[(int64_t)min(k, m - 1) * sd.nI];
-    if ((int)threadIdx.x < m) {
-        const double *yp = P.ypart + (int64_t)rhs * P.nchunk * P.m0 + sd.offm + threadIdx.x;
-        double s = 0.0;
-        for (int k0 = 0; k0 < P.nchunk; k0 += 4) {
-            double v[4];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) v[k] = yp[(int64_t)min(k0 + k, P.nchunk - 1) * P.m0];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) s += k0 + k < P.nchunk ? v[k] : 0.0;
+        for (int k = 0; k < 8; ++k) {
+            const int q = min(k0 + 64 * k, m0 - 1);
+            b[k] = col[q];
+            x[k] = c[q];
         }
-        ys[threadIdx.x] = s;
-    }
-    __syncthreads();
-    if (a >= sd.nI) return;
-    double t = 0.0;
 #pragma unroll
-    for (int k = 0; k < CA_ROWS; ++k) t = fma(zv[k], k < m ? ys[min(k, m - 1)] : 0.0, t);
-    for (int k = CA_ROWS; k < m; ++k) t = fma(z[(int64_t)k * sd.nI], ys[k], t);
-    P.u[(int64_t)rhs * P.sum_nI + sd.offI + a] += t;
+        for (int k = 0; k < 8; ++k) acc = fma(b[k], k0 + 64 * k < m0 ? x[k] : 0.0, acc);
+    }
+    acc = bwsum(acc);
+    if (lane == 0) P.ypart[(int64_t)rhs * m0 + r] = acc;
 }
 
-// z_l = sum over the transpose map of u (fixed order)
+// z_l = sum over the positions t of dof l in the local vectors (transpose map, fixed order) of
+// u[t] + (Z_i y_i)[a], t = (subdomain i, local index a): the coarse correction E_0 y = sum_i E_i Z_i y_i
+// folded into the same pass (Z_i read row-wise from its row-major copy).
 __global__ __launch_bounds__(BROWS) void k_b_prolong(const ProbDev *__restrict__ probs,
                                                      const WorkItem *__restrict__ rblk, int mode, int par) {
     const WorkItem it = rblk[blockIdx.x];
@@ -287,14 +250,31 @@ __global__ __launch_bounds__(BROWS) void k_b_prolong(const ProbDev *__restrict__
     const int l = it.s * BROWS + threadIdx.x;
     if (l >= P.n) return;
     const double *uu = P.u + (int64_t)rhs * P.sum_nI;
+    const double *y = P.ypart + (int64_t)rhs * P.m0;
     const int t0 = P.tp_ptr[l], t1 = P.tp_ptr[l + 1];
     double s = 0.0;
-    for (int t = t0; t < t1; t += 4) {
-        double v[4];
+    for (int t = t0; t < t1; ++t) {
+        const int pos = P.tp_pos[t];
+        double v = uu[pos];
+        if (P.two_level) {
+            const SubDev &sd = P.subs[P.tp_sub[t]];
+            const double *zr = P.Zr + sd.offZ + (int64_t)(pos - sd.offI) * sd.m;
+            const double *yi = y + sd.offm;
+            double cz = 0.0;
+            for (int b0 = 0; b0 < sd.m; b0 += 4) {
+                double zv[4], yv[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) v[k] = uu[P.tp_pos[min(t + k, t1 - 1)]];
+                for (int k = 0; k < 4; ++k) {
+                    const int b = min(b0 + k, sd.m - 1);
+                    zv[k] = zr[b];
+                    yv[k] = yi[b];
+                }
 #pragma unroll
-        for (int k = 0; k < 4; ++k) s += t + k < t1 ? v[k] : 0.0;
+                for (int k = 0; k < 4; ++k) cz = fma(zv[k], b0 + k < sd.m ? yv[k] : 0.0, cz);
+            }
+            v += cz;
+        }
+        s += v;
     }
     double *z = (mode == 0) ? P.xout + (int64_t)rhs * P.ldout : zcol(P, rhs, jget(P, rhs, par));
     z[l] = s;
@@ -319,11 +299,8 @@ int32_t batch_apply(const BatchGeom &g, const ProbDev *probs, const WorkItem *it
     }
     HKG_HIP(hipGetLastError());
     if (ev1) HKG_HIP(hipEventRecord(ev1, s));
-    if (g.any_coarse) {
-        hipLaunchKernelGGL(k_b_coarse_gemv, dim3(g.ncblk, 1, g.max_nrhs), dim3(256), 0, s, probs, cblk, mode);
-        hipLaunchKernelGGL(k_b_coarse_add, dim3((g.max_nI + 255) / 256, g.nitems, g.max_nrhs), dim3(256), 0, s, probs,
-                           items, mode);
-    }
+    if (g.any_coarse)
+        hipLaunchKernelGGL(k_b_coarse_gemv, dim3(g.ncblk, 1, g.max_nrhs), dim3(64 * CG_RPB), 0, s, probs, cblk, mode);
     hipLaunchKernelGGL(k_b_prolong, dim3(g.nrblk, 1, g.max_nrhs), dim3(BROWS), 0, s, probs, rblk, mode, par);
     HKG_HIP(hipGetLastError());
     return HKG_OK;
@@ -332,19 +309,24 @@ int32_t batch_apply(const BatchGeom &g, const ProbDev *probs, const WorkItem *it
 // ------------------------------------------------------------------------------------------------
 // Arnoldi step (CGS2) at the device-side index j = jcur
 // ------------------------------------------------------------------------------------------------
+// CGS2 kernels run CG_T = 4 BROWS threads per row block: thread t owns row r0 + (t mod BROWS) in
+// column group t / BROWS for the update w -= V h, and the 16 waves share the slots of the partial
+// sums, so that a CU keeps many independent loads of V in flight.
+constexpr int CG_T = 4 * BROWS;
+constexpr int CG_W = CG_T / 64;          // waves per block
+
 // Partial sums of one row block (BROWS rows r0 .. r0 + BROWS): slot i <= j of x_i . w, slot j + 1 of
 // w . w, written column by column (out[i * nb], the row blocks of one slot contiguous).  Wave wv takes
-// the slots congruent to wv modulo 4; lane l holds rows r0 + l + 64 q (q < 4) of w in wl[q], so a slot
-// costs 4 independent loads and one cross-lane sum.
+// the slots congruent to wv modulo CG_W; lane l holds rows r0 + l + 64 q (q < 4) of w in wl[q], so a
+// slot costs 4 independent loads and one cross-lane sum, and four slots are in flight at once.
 __device__ __forceinline__ void slot_partials(const double *__restrict__ V, int n, int r0, int j, const double wl[4],
                                               double *__restrict__ out, int nb) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    // slots i = wv + 4 (4 t + k), k < 4: four slots' loads in flight before their cross-lane sums
-    for (int i0 = wv; i0 <= j + 1; i0 += 16) {
+    for (int i0 = wv; i0 <= j + 1; i0 += 4 * CG_W) {
         double a[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const int i = i0 + 4 * k;
+            const int i = i0 + CG_W * k;
             const double *x = V + (int64_t)min(i, j) * n;
             double d = 0.0, ww = 0.0;
 #pragma unroll
@@ -357,7 +339,7 @@ __device__ __forceinline__ void slot_partials(const double *__restrict__ V, int 
         }
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const int i = i0 + 4 * k;
+            const int i = i0 + CG_W * k;
             if (i <= j + 1) {
                 const double t = bwsum(a[k]);
                 if (lane == 0) out[(int64_t)i * nb] = t;
@@ -375,8 +357,8 @@ __device__ __forceinline__ double *part_half(const ProbDev &P, int rhs, int half
 
 // w = V[:, j+1] = B Zk[:, j] for the block's rows, then the block's first-pass partials (they need
 // only these rows of w)
-__global__ __launch_bounds__(BROWS) void k_b_spmv_dots(const ProbDev *__restrict__ probs,
-                                                       const WorkItem *__restrict__ rblk, int par) {
+__global__ __launch_bounds__(CG_T) void k_b_spmv_dots(const ProbDev *__restrict__ probs,
+                                                      const WorkItem *__restrict__ rblk, int par) {
     __shared__ double wsh[BROWS];
     const WorkItem it = rblk[blockIdx.x];
     const ProbDev &P = probs[it.p];
@@ -385,13 +367,15 @@ __global__ __launch_bounds__(BROWS) void k_b_spmv_dots(const ProbDev *__restrict
     const int n = P.n, j = jget(P, rhs, par), r0 = it.s * BROWS, lane = threadIdx.x & 63;
     const double *x = zcol(P, rhs, j);
     double *V = vcol_w(P, rhs, 0);
-    const int i = r0 + threadIdx.x;
-    double s = 0.0;
-    if (i < n) {
-        s = csr_row_dot(P.rowptr, P.colidx, P.Bval, x, i);
-        V[(int64_t)(j + 1) * n + i] = s;
+    if (threadIdx.x < BROWS) {
+        const int i = r0 + threadIdx.x;
+        double s = 0.0;
+        if (i < n) {
+            s = csr_row_dot(P.rowptr, P.colidx, P.Bval, x, i);
+            V[(int64_t)(j + 1) * n + i] = s;
+        }
+        wsh[threadIdx.x] = s;
     }
-    wsh[threadIdx.x] = s;
     __syncthreads();
     double wl[4];
 #pragma unroll
@@ -399,9 +383,10 @@ __global__ __launch_bounds__(BROWS) void k_b_spmv_dots(const ProbDev *__restrict
     slot_partials(V, n, r0, j, wl, part_half(P, rhs, 0) + it.s, P.nblk);
 }
 
-// reduce the pass's partials (wave per slot, fixed order), w -= V h, next partials
-__global__ __launch_bounds__(BROWS) void k_b_update(const ProbDev *__restrict__ probs, const WorkItem *__restrict__ rblk,
-                                                    int pass, int par) {
+// reduce the pass's partials (one wave per slot, fixed order: lane-strided sums, then a butterfly),
+// w -= V h (four column groups per row, added in group order), next partials
+__global__ __launch_bounds__(CG_T) void k_b_update(const ProbDev *__restrict__ probs, const WorkItem *__restrict__ rblk,
+                                                   int pass, int par) {
     extern __shared__ double sh[];
     const WorkItem it = rblk[blockIdx.x];
     const ProbDev &P = probs[it.p];
@@ -413,19 +398,20 @@ __global__ __launch_bounds__(BROWS) void k_b_update(const ProbDev *__restrict__ 
     const double *pin = part_half(P, rhs, pass == 1 ? 0 : 1);
     double *h = sh;              // S
     double *wsh = sh + S;        // BROWS
+    double *gs = wsh + BROWS;    // 4 x BROWS column-group sums
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int i0 = wv; i0 <= j + 1; i0 += 16) {
+    for (int i0 = wv; i0 <= j + 1; i0 += 4 * CG_W) {
         double a[4] = {0.0, 0.0, 0.0, 0.0};
         for (int b = lane; b < nb; b += 64) {
             double v[4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) v[k] = pin[(int64_t)min(i0 + 4 * k, j + 1) * nb + b];
+            for (int k = 0; k < 4; ++k) v[k] = pin[(int64_t)min(i0 + CG_W * k, j + 1) * nb + b];
 #pragma unroll
             for (int k = 0; k < 4; ++k) a[k] += v[k];
         }
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const int i = i0 + 4 * k;
+            const int i = i0 + CG_W * k;
             if (i <= j + 1) {
                 const double t = bwsum(a[k]);
                 if (lane == 0) h[i] = t;
@@ -435,24 +421,30 @@ __global__ __launch_bounds__(BROWS) void k_b_update(const ProbDev *__restrict__ 
     __syncthreads();
     if (it.s == 0) {
         double *hc = P.hcol + (int64_t)rhs * S;
-        for (int i = threadIdx.x; i <= j; i += BROWS) hc[i] = (pass == 1) ? h[i] : hc[i] + h[i];
+        for (int i = threadIdx.x; i <= j; i += CG_T) hc[i] = (pass == 1) ? h[i] : hc[i] + h[i];
         if (pass == 1 && threadIdx.x == 0) hc[m + 1] = sqrt(h[j + 1]);
     }
-    const int r0 = it.s * BROWS, row = r0 + threadIdx.x;
-    double v = 0.0;
-    if (row < n) {
-        v = w[row];
-        for (int i0 = 0; i0 <= j; i0 += 4) {
-            double x[4];
+    const int r0 = it.s * BROWS, lr = threadIdx.x & (BROWS - 1), grp = threadIdx.x / BROWS;
+    const int row = min(r0 + lr, n - 1);
+    {
+        double acc = 0.0;
+        for (int i0 = grp; i0 <= j; i0 += 4 * 8) {
+            double x[8];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) x[k] = V[(int64_t)min(i0 + k, j) * n + row];
+            for (int k = 0; k < 8; ++k) x[k] = V[(int64_t)min(i0 + 4 * k, j) * n + row];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) v = fma(-x[k], i0 + k <= j ? h[min(i0 + k, j)] : 0.0, v);
+            for (int k = 0; k < 8; ++k) acc = fma(x[k], i0 + 4 * k <= j ? h[min(i0 + 4 * k, j)] : 0.0, acc);
         }
+        gs[grp * BROWS + lr] = acc;
+    }
+    __syncthreads();
+    double v = 0.0;
+    if (grp == 0 && r0 + lr < n) {
+        v = w[row] - (((gs[lr] + gs[BROWS + lr]) + gs[2 * BROWS + lr]) + gs[3 * BROWS + lr]);
         w[row] = v;
     }
     if (pass == 1) {
-        wsh[threadIdx.x] = v;
+        if (grp == 0) wsh[lr] = v;
         __syncthreads();
         double wl[4];
 #pragma unroll
@@ -460,7 +452,7 @@ __global__ __launch_bounds__(BROWS) void k_b_update(const ProbDev *__restrict__ 
         slot_partials(V, n, r0, j, wl, part_half(P, rhs, 1) + it.s, nb);
     } else {
         const double s = bwsum(v * v);
-        if (lane == 0) wsh[wv] = s;
+        if (lane == 0 && wv < 4) wsh[wv] = s;
         __syncthreads();
         if (threadIdx.x == 0) part_half(P, rhs, 0)[it.s] = wsh[0] + wsh[1] + wsh[2] + wsh[3];
     }
@@ -533,11 +525,11 @@ __global__ __launch_bounds__(BROWS) void k_b_finish(const ProbDev *__restrict__ 
 
 int32_t batch_arnoldi(const BatchGeom &g, const ProbDev *probs, const WorkItem *rblk, int par, hipStream_t s) {
     const dim3 grid(g.nrblk, 1, g.max_nrhs);
-    const size_t upd = (size_t)(g.restart + 2 + BROWS) * sizeof(double);
+    const size_t upd = (size_t)(g.restart + 2 + 5 * BROWS) * sizeof(double);
     const size_t fin = (size_t)(3 * g.restart + 2) * sizeof(double);
-    hipLaunchKernelGGL(k_b_spmv_dots, grid, dim3(BROWS), 0, s, probs, rblk, par);
-    hipLaunchKernelGGL(k_b_update, grid, dim3(BROWS), upd, s, probs, rblk, 1, par);
-    hipLaunchKernelGGL(k_b_update, grid, dim3(BROWS), upd, s, probs, rblk, 2, par);
+    hipLaunchKernelGGL(k_b_spmv_dots, grid, dim3(CG_T), 0, s, probs, rblk, par);
+    hipLaunchKernelGGL(k_b_update, grid, dim3(CG_T), upd, s, probs, rblk, 1, par);
+    hipLaunchKernelGGL(k_b_update, grid, dim3(CG_T), upd, s, probs, rblk, 2, par);
     hipLaunchKernelGGL(k_b_finish, grid, dim3(BROWS), fin, s, probs, rblk, par);
     HKG_HIP(hipGetLastError());
     return HKG_OK;

@@ -39,9 +39,9 @@ struct ProbDev {
     const double *wloc;
     const void *Minv;
     const double *Z, *Zr, *B0inv;
-    const int32_t *tp_ptr, *tp_pos;
+    const int32_t *tp_ptr, *tp_pos, *tp_sub;
     // batch workspace of this problem
-    double *u, *c, *ypart;                                   // apply
+    double *u, *c, *ypart;                                   // apply (ypart holds y = B_0^{-1} c)
     double *V, *Zk, *H, *cs, *sn, *g, *part, *hcol, *scal;   // FGMRES, per rhs strides below
     int32_t *active, *iters;                                 // per rhs
     int32_t *jcur;                                           // two per rhs (parity double buffer)
@@ -70,7 +70,7 @@ struct BatchGeom {
 // (live[t / max_nrhs], t % max_nrhs)); work lists name table indices directly.
 // mode 0: standalone application (xin -> xout); mode 1: FGMRES iteration (V[:, j] -> Zk[:, j])
 // par: parity of the iteration (which half of the double-buffered Arnoldi index it reads)
-// cblk: (problem, row tile * nchunk + column chunk) blocks of the split coarse product
+// cblk: (problem, group of 4 coarse rows) blocks of the coarse product
 int32_t batch_apply(const BatchGeom &g, const ProbDev *probs, const WorkItem *items, const WorkItem *rblk,
                     const WorkItem *cblk, int mode, int par, hipStream_t s, hipEvent_t ev0 = nullptr,
                     hipEvent_t ev1 = nullptr);

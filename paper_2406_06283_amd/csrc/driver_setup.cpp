@@ -63,7 +63,8 @@ void free_workspace(hkgeneo_ctx *c) {
     DevBuf *w[] = {&c->wDk, &c->wBIO, &c->wCII, &c->wGG, &c->wGI, &c->wS, &c->wW, &c->wPiv, &c->wInfo,
                    &c->wFlag, &c->wD, &c->wE, &c->wTau, &c->wM, &c->wLam, &c->wY, &c->wB0, &c->wLU,
                    &c->wPivL, &c->wJobsZ, &c->wGjobsY, &c->wMisc, &c->wPiv0, &c->wInv, &c->wVWV, &c->wInfoL, &c->wSL, &c->wIv,
-                   &c->wLinv, &c->wJobsInv, &c->wT, &c->wPivC, &c->wInfoC, &c->wFlagSpd};
+                   &c->wLinv, &c->wJobsInv, &c->wT, &c->wPivC, &c->wInfoC, &c->wFlagSpd, &c->wDC, &c->wDCjobs,
+                   &c->wDCpiv, &c->wDCinfo};
     for (DevBuf *b : w) drelease(c, b);
 }
 
@@ -334,9 +335,8 @@ int32_t lu_inverse(hkgeneo_ctx *c, int n, const double *LU, const int32_t *piv, 
     return gemm_batched<double>(dj + (jobs.size() - 1), 1, n, n, Uinv, tmp, out, 1.0, 0.0, false, false, s);
 }
 
-// start_side: forks the local-inverse pipeline to the second stream; called once the Gamma block's
-// LU is enqueued (the side pipeline is far off the critical path, and its hundred launches from a
-// second host thread would slow this thread's first ones)
+// start_side: forks the local-inverse pipeline to the second stream; called once the coarse blocks
+// are enqueued, so that it fills the CUs the factorisation of B_0 leaves idle
 int32_t coarse_space(hkgeneo_ctx *c, hipStream_t s, const std::function<int32_t()> &start_side) {
     const int ns = c->n_sub;
     const hkgeneo_options &o = c->opt;
@@ -392,7 +392,6 @@ int32_t coarse_space(hkgeneo_ctx *c, hipStream_t s, const std::function<int32_t(
                            dp<double>(c->bandM), k2, dp<double>(c->wGG), s));
     HKG_TRY(lu_batched<double>(dp<DMat>(c->matsGG), dp<int64_t>(c->poffSub), ns, c->max_nG, dp<double>(c->wGG),
                                dp<int32_t>(c->wPiv), dp<int32_t>(c->wInfo), true, s));
-    HKG_TRY(start_side());
     std::vector<int32_t> flags;
     // X = B~_GG^{-1} B_GI ; S = B_II - B_IG X
     HKG_TRY(gather_gamma_rows(dsub, ns, c->max_nI, c->max_nG, dp<double>(c->wBIO), dp<double>(c->wGI), s));
@@ -538,6 +537,15 @@ int32_t coarse_space(hkgeneo_ctx *c, hipStream_t s, const std::function<int32_t(
     } else {
         drelease(c, &c->B0copy);
     }
+    // the local-inverse pipeline runs beside the factorisation of B_0, whose panel chain keeps only
+    // a few CUs busy (started earlier, it would compete with the tridiagonalisation, which fills
+    // every CU)
+    HKG_TRY(start_side());
+    // B_0^{-1} by divide and conquer over the level blocks of B_0; the LU with partial pivoting of
+    // the whole matrix (below) when the structure does not allow it or a block pivot is too small
+    bool dc = false;
+    HKG_TRY(coarse_inverse_dc(c, s, &dc));
+    if (dc) return HKG_OK;
     // B_0 = P L U and B_0^{-1}
     DMat hm{0, m0, m0};
     int64_t hp0 = 0;

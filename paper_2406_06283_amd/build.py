@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhkgeneo.so")
-SOURCES = ["api.cpp", "driver_setup.cpp", "partition.cpp", "dense.hip", "setup.hip", "eigen.hip", "apply.hip", "krylov.hip",
+SOURCES = ["api.cpp", "driver_setup.cpp", "coarse_dc.cpp", "partition.cpp", "dense.hip", "setup.hip", "eigen.hip", "apply.hip", "krylov.hip",
            "batch.cpp", "batch.hip"]
 
 HIP_FLAGS = [

@@ -32,7 +32,8 @@ struct hkgeneo_ctx {
     int band_I = -1;                      // half-bandwidth of B[I, I] and C_II (-1: treated as dense)
     // factorisation workspace (kept between calls when opt.keep_workspace, freed otherwise)
     hkg::DevBuf wDk, wBIO, wCII, wGG, wGI, wS, wW, wPiv, wInfo, wFlag, wD, wE, wTau, wM, wLam, wY, wB0, wLU, wPivL,
-        wJobsZ, wGjobsY, wMisc, wPiv0, wInv, wVWV, wInfoL, wSL, wIv, wLinv, wJobsInv, wT, wPivC, wInfoC, wFlagSpd;
+        wJobsZ, wGjobsY, wMisc, wPiv0, wInv, wVWV, wInfoL, wSL, wIv, wLinv, wJobsInv, wT, wPivC, wInfoC, wFlagSpd,
+        wDC, wDCjobs, wDCpiv, wDCinfo;
     // the local-inverse pipeline of the factorisation runs on a second stream beside the coarse-space
     // pipeline; its pivot flags come back through pinned host memory
     hipStream_t s2 = nullptr;
@@ -74,6 +75,9 @@ T *dp(const DevBuf &b) {
 
 int32_t analyze(hkgeneo_ctx *c, const hkgeneo_problem *p, hipStream_t s, int32_t *bad);
 int32_t factor(hkgeneo_ctx *c, hipStream_t s);
+// B_0^{-1} into c->B0inv from the assembled c->wB0 by divide and conquer over its level blocks;
+// *done = false when the structure does not allow it or a block needs pivoting across blocks
+int32_t coarse_inverse_dc(hkgeneo_ctx *c, hipStream_t s, bool *done);
 void free_workspace(hkgeneo_ctx *c);
 
 }  // namespace hkg

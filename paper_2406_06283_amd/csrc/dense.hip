@@ -1474,6 +1474,44 @@ int32_t perm_identity_batched(const DMat *d_mats, const int64_t *d_poff, int nba
 template int32_t perm_identity_batched<double>(const DMat *, const int64_t *, int, int, const int32_t *, double *,
                                                hipStream_t);
 
+// X = I for every matrix of the list (grid-stride over the n x n entries of the block's matrix)
+__global__ __launch_bounds__(256) void k_identity(const DMat *__restrict__ mats, double *__restrict__ Xb) {
+    const DMat m = mats[blockIdx.y];
+    const int64_t total = (int64_t)m.n * m.n;
+    for (int64_t e = blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+        const int r = (int)(e % m.n), c = (int)(e / m.n);
+        Xb[m.off + r + (int64_t)c * m.ld] = r == c ? 1.0 : 0.0;
+    }
+}
+
+int32_t identity_batched(const DMat *d_mats, int nbatch, int maxn, double *X, hipStream_t s) {
+    if (nbatch == 0 || maxn == 0) return HKG_OK;
+    const int64_t total = (int64_t)maxn * maxn;
+    const int blocks = (int)std::min<int64_t>(256, (total + 255) / 256);
+    hipLaunchKernelGGL(k_identity, dim3(blocks, nbatch), dim3(256), 0, s, d_mats, X);
+    HKG_HIP(hipGetLastError());
+    return HKG_OK;
+}
+
+__global__ __launch_bounds__(256) void k_copy_blocks(const CopyJob *__restrict__ jobs, const double *__restrict__ src,
+                                                     double *__restrict__ dst) {
+    const CopyJob J = jobs[blockIdx.y];
+    const int64_t total = (int64_t)J.rows * J.cols;
+    for (int64_t e = blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+        const int r = (int)(e % J.rows), c = (int)(e / J.rows);
+        dst[J.offD + r + (int64_t)c * J.ldD] = src[J.offS + r + (int64_t)c * J.ldS];
+    }
+}
+
+int32_t copy_blocks_batched(const CopyJob *d_jobs, int nbatch, int64_t max_elems, const double *src, double *dst,
+                            hipStream_t s) {
+    if (nbatch == 0 || max_elems == 0) return HKG_OK;
+    const int blocks = (int)std::min<int64_t>(512, (max_elems + 255) / 256);
+    hipLaunchKernelGGL(k_copy_blocks, dim3(blocks, nbatch), dim3(256), 0, s, d_jobs, src, dst);
+    HKG_HIP(hipGetLastError());
+    return HKG_OK;
+}
+
 // out = in^T for square matrices with the same descriptors (separate buffers)
 template <typename T>
 __global__ __launch_bounds__(256) void k_transpose(const DMat *__restrict__ mats, const T *__restrict__ in,

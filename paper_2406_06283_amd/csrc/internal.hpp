@@ -95,6 +95,12 @@ struct TriJob {
     int32_t pad_ = 0;
 };
 
+// rectangular block copy: dst (rows x cols at offD, ldD) = src (rows x cols at offS, ldS)
+struct CopyJob {
+    int64_t offS, offD;
+    int32_t rows, cols, ldS, ldD;
+};
+
 // general GEMM job: C (M x N) = beta C + alpha op(A) op(B)
 struct GemmJob {
     int64_t offA, offB, offC;

@@ -42,6 +42,11 @@ int32_t perm_identity_batched(const DMat *d_mats, const int64_t *d_poff, int nba
 template <typename T>
 int32_t transpose_batched(const DMat *d_mats, int nbatch, int maxn, const T *in, T *out, hipStream_t s);
 int32_t cast_f64_f32(const double *in, float *out, int64_t n, hipStream_t s);
+// X = I for every matrix of the list
+int32_t identity_batched(const DMat *d_mats, int nbatch, int maxn, double *X, hipStream_t s);
+// one rectangular block copy per job (src and dst must not overlap)
+int32_t copy_blocks_batched(const CopyJob *d_jobs, int nbatch, int64_t max_elems, const double *src, double *dst,
+                            hipStream_t s);
 
 // ---- setup.hip: local blocks of every subdomain ---------------------------------------------------
 struct SubDev {             // per-subdomain device descriptors

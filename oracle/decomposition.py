@@ -1,4 +1,5 @@
-"""Overlapping decomposition: Def 2.8, Def 2.12, Def 2.13 and Lambda (Sec. 2.3-2.4).
+"""Overlapping decomposition: Def 2.8, Def 2.12, Def 2.13, Lambda (Sec. 2.3-2.4) and the nested
+first-level subdomains of Sec. 2.3.
 
 Test infrastructure only (see the package docstring).
 
@@ -42,6 +43,20 @@ class Subdomain:
     ovdof: np.ndarray   # concatenation [dof, gamma] -- the local ordering used everywhere
 
 
+def subdomain(problem, E: sp.csr_matrix, interior: np.ndarray, in_D: np.ndarray) -> Subdomain:
+    """Index sets of the subdomain with element mask in_D (Def 2.12)."""
+    # ovdof(D): supp(phi_l) meets D  <=>  l is a vertex of an element of D
+    verts_in = np.asarray(E[in_D].sum(axis=0)).ravel() > 0
+    # dof(D): supp(phi_l) inside closure(D)  <=>  every element around l is in D
+    outside = np.asarray(E[~in_D].sum(axis=0)).ravel() > 0
+    ov_v = np.nonzero(verts_in & interior)[0]
+    in_v = np.nonzero(verts_in & interior & ~outside)[0]
+    dof = np.sort(problem.vert_dof[in_v])
+    ovd = np.sort(problem.vert_dof[ov_v])
+    gamma = np.setdiff1d(ovd, dof)
+    return Subdomain(elems=in_D, dof=dof, gamma=gamma, ovdof=np.concatenate([dof, gamma]))
+
+
 def decompose(problem) -> list[Subdomain]:
     """Overlapping subdomains from the element partition, Def 2.8 applied `overlap[i]` times."""
     E = incidence(problem)
@@ -51,17 +66,32 @@ def decompose(problem) -> list[Subdomain]:
         in_D = problem.elem_part == i
         for _ in range(int(problem.overlap[i])):
             in_D = extend_one_layer(in_D, E, interior)
-        # ovdof(D): supp(phi_l) meets D  <=>  l is a vertex of an element of D
-        verts_in = np.asarray(E[in_D].sum(axis=0)).ravel() > 0
-        # dof(D): supp(phi_l) inside closure(D)  <=>  every element around l is in D
-        outside = np.asarray(E[~in_D].sum(axis=0)).ravel() > 0
-        ov_v = np.nonzero(verts_in & interior)[0]
-        in_v = np.nonzero(verts_in & interior & ~outside)[0]
-        dof = np.sort(problem.vert_dof[in_v])
-        ovd = np.sort(problem.vert_dof[ov_v])
-        gamma = np.setdiff1d(ovd, dof)
-        subs.append(Subdomain(elems=in_D, dof=dof, gamma=gamma, ovdof=np.concatenate([dof, gamma])))
+        subs.append(subdomain(problem, E, interior, in_D))
     return subs
+
+
+def nested_fine(problem, coarse: list[Subdomain]) -> list[tuple[int, Subdomain]]:
+    """The first-level (fine) subdomains of the nested decomposition (Sec. 2.3), as (coarse index, sub).
+
+    Reading of the construction (the paper partitions the overlapping coarse subdomain and expands
+    the pieces "again" while requiring their union to be the coarse subdomain): the elements of each
+    overlapping coarse subdomain are split into Q_i pieces by the fine element partition
+    (``problem.fine_part``); each piece is expanded by ``problem.fine_overlap`` layers of Def 2.8
+    restricted to the coarse subdomain's elements, so the union of the pieces of Omega_i^c is
+    Omega_i^c.  Pieces are ordered by coarse subdomain, then by fine block id.
+    """
+    E = incidence(problem)
+    interior = problem.vert_dof >= 0
+    out = []
+    for ci, cs in enumerate(coarse):
+        for fid in np.unique(problem.fine_part[cs.elems]):
+            in_F = cs.elems & (problem.fine_part == fid)
+            for _ in range(int(problem.fine_overlap)):
+                in_F = extend_one_layer(in_F, E, interior) & cs.elems
+            sub = subdomain(problem, E, interior, in_F)
+            if sub.dof.size:            # a sliver without interior dofs has no local problem
+                out.append((ci, sub))
+    return out
 
 
 def multiplicity(subs: list[Subdomain], n_dof: int) -> np.ndarray:

@@ -6,7 +6,8 @@ Test infrastructure only (see the package docstring).
   M^{-1}_{AS,2} = E_0 B_0^{-1} R_0 + M^{-1}_{AS,1},   B_0 = R_0 B E_0              (eq. 2.23)
 
 W_D = I is the paper's additive Schwarz; W_D = X_D (the 1/mu weights of Def 2.13) is the
-partition-of-unity weighted variant, kept as an option.  The coarse space V_0 is spanned by the
+partition-of-unity weighted variant, kept as an option.  The coarse space is H_k-GenEO (Def 2.14,
+2.15) or, as an option, Delta-GenEO (the same construction on the nearby SPD problem, k = 0).  The coarse space V_0 is spanned by the
 columns of Z = [E_i X_i P_i] (Def 2.15); reading R_0 as the transpose of Z on nodal residual
 vectors (the l2 form of the L2 adjoint, as for R_D = E_D^T), B_0 = Z^T B Z.
 """
@@ -23,6 +24,9 @@ from . import local
 PROLONG_AS = 0
 PROLONG_POU = 1
 
+COARSE_HK = 0        # H_k-GenEO: the local eigenproblem of Def 2.14 (indefinite B~, D~ of (.,.)_{1,k})
+COARSE_DELTA = 1     # Delta-GenEO: the same eigenproblem built from the nearby SPD problem (k = 0)
+
 
 @dataclasses.dataclass
 class Options:
@@ -32,6 +36,7 @@ class Options:
     cluster_rtol: float = 1e-8
     prolong: int = PROLONG_AS
     two_level: bool = True
+    coarse_op: int = COARSE_HK
 
 
 def system_matrix(problem) -> sp.csr_matrix:
@@ -53,19 +58,31 @@ class TwoLevelSchwarz:
         n = problem.n_dof
         self.n = n
         self.B = system_matrix(problem)
-        self.subs = dec.decompose(problem)
-        self.mu = dec.multiplicity(self.subs, n)
+        self.subs = dec.decompose(problem)              # the coarse subdomains Omega_i^c
+        self.mu = dec.multiplicity(self.subs, n)        # their multiplicities (Xi of Def 2.13, 2.15)
         if np.any(self.mu == 0):
             raise ValueError("a degree of freedom is internal to no subdomain (overlap too small)")
-        self.Lambda = dec.overlap_count(self.subs)
+        # the subdomains of the local solves (eq. 2.22): Omega_{i,j}^f of the nested decomposition
+        # (Sec. 2.3) when the problem carries a fine partition, else the coarse subdomains (Q_i = 1)
+        if getattr(problem, "fine_part", None) is not None:
+            nested = dec.nested_fine(problem, self.subs)
+            self.fine_owner = [ci for ci, _ in nested]
+            self.fine = [sub for _, sub in nested]
+        else:
+            self.fine_owner = list(range(len(self.subs)))
+            self.fine = self.subs
+        self.mu_fine = dec.multiplicity(self.fine, n)
+        if np.any(self.mu_fine == 0):
+            raise ValueError("a degree of freedom is internal to no fine subdomain")
+        self.Lambda = dec.overlap_count(self.fine)       # Lambda counts the Omega_{i,j}^f (Sec. 2.4)
         Bd = self.B.tocsc()
         # local Dirichlet factors, eq. 2.22 (partial pivoting: B_D is indefinite in general)
         self.local_lu = []
-        for s in self.subs:
+        for s in self.fine:
             BD = Bd[s.dof][:, s.dof].toarray()
             self.local_lu.append(sla.lu_factor(BD, check_finite=True))
         self.weights = [np.ones(s.dof.shape[0]) if self.opts.prolong == PROLONG_AS
-                        else 1.0 / self.mu[s.dof] for s in self.subs]
+                        else 1.0 / self.mu_fine[s.dof] for s in self.fine]
         self.eigvals, self.m = [], []
         self.Z_local = []
         if self.opts.two_level:
@@ -76,9 +93,13 @@ class TwoLevelSchwarz:
         o = self.opts
         cols_r, cols_c, cols_v = [], [], []
         off = 0
+        # Delta-GenEO (Sec. 1, the comparison method): the paper does not write its eigenproblem;
+        # reading: Def 2.14 for the nearby SPD problem, i.e. B~ and D~ both the Neumann matrix of
+        # a(.,.) (k = 0).  The coarse matrix B_0 = Z^T B Z keeps the indefinite B.
+        eig_problem = dataclasses.replace(self.problem, k=0.0) if o.coarse_op == COARSE_DELTA else self.problem
         for s in self.subs:
             nI = s.dof.shape[0]
-            Bt, C = local.geneo_pencil(self.problem, s, self.mu)
+            Bt, C = local.geneo_pencil(eig_problem, s, self.mu)
             lam, P = local.geneo_eigenpairs(Bt, C, nI)
             m = local.select_count(lam, o.eig_mode, o.tau, o.nev, o.cluster_rtol)
             Zi = (1.0 / self.mu[s.dof])[:, None] * P[:, :m]          # X_I p_l, Gamma dropped by Xi
@@ -97,7 +118,7 @@ class TwoLevelSchwarz:
     # --- application -------------------------------------------------------------------------
     def apply_one_level(self, r):
         z = np.zeros_like(r)
-        for s, lu, w in zip(self.subs, self.local_lu, self.weights):
+        for s, lu, w in zip(self.fine, self.local_lu, self.weights):
             z[s.dof] += w * sla.lu_solve(lu, r[s.dof])
         return z
 

@@ -63,6 +63,10 @@ class Problem:
     coef: np.ndarray        # (n_elem,) float64 value of a(x) per element
     sub_grid: tuple = ()
     seed: int = 0
+    # nested decomposition (optional): a finer non-overlapping element partition and the layers by
+    # which each of its pieces inside an overlapping coarse subdomain is expanded again
+    fine_part: np.ndarray | None = None     # (n_elem,) int32 fine block ids, or None
+    fine_overlap: int = 0
 
     @property
     def n_vert(self) -> int:
@@ -284,7 +288,7 @@ def block_partition(cell: np.ndarray, N: int, s) -> tuple[np.ndarray, int, tuple
 
 def make_problem(N: int, *, dim: int = 2, elem_type: int = P1, k: float = 0.0, s=1, overlap=1,
                  coef: str = "const", seed: int = 0, rhs: str = "one", nrhs: int = 1,
-                 n_cells: int = 16, name: str = "") -> Problem:
+                 n_cells: int = 16, name: str = "", fine=None, fine_overlap: int = 1) -> Problem:
     if elem_type == P1:
         assert dim == 2, "P1 is generated on 2D triangle meshes"
         coords, elem_vert, vert_dof, cell = mesh_p1_2d(N)
@@ -307,6 +311,7 @@ def make_problem(N: int, *, dim: int = 2, elem_type: int = P1, k: float = 0.0, s
     n_dof = int((vert_dof >= 0).sum())
     row_ptr, col_idx, A_val, S_val = assemble_csr(elem_vert, vert_dof, K, M, n_dof)
     elem_part, n_sub, sub_grid = block_partition(cell, N, s)
+    fine_part = None if fine is None else block_partition(cell, N, fine)[0]
     if np.isscalar(overlap):
         ov = np.full(n_sub, int(overlap), dtype=np.int32)
     else:
@@ -331,4 +336,5 @@ def make_problem(N: int, *, dim: int = 2, elem_type: int = P1, k: float = 0.0, s
                    vert_dof=vert_dof, elem_K=np.ascontiguousarray(K), elem_M=np.ascontiguousarray(M),
                    row_ptr=row_ptr, col_idx=col_idx, A_val=A_val, S_val=S_val,
                    elem_part=elem_part, n_sub=n_sub, overlap=ov, k=float(k), f=f, coef=a,
-                   sub_grid=sub_grid, seed=seed)
+                   sub_grid=sub_grid, seed=seed, fine_part=fine_part,
+                   fine_overlap=int(fine_overlap) if fine is not None else 0)

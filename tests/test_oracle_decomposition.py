@@ -110,3 +110,51 @@ def test_gamma_is_ovdof_minus_dof():
         for g in s.gamma:
             nb = A.indices[A.indptr[g]:A.indptr[g + 1]]
             assert np.intersect1d(nb, s.dof).size > 0
+
+
+# ------------------------------------------------------------------------------------------------
+# nested decomposition (Sec. 2.3): fine subdomains inside each overlapping coarse subdomain
+# ------------------------------------------------------------------------------------------------
+
+def test_nested_fine_subdomains_hand_counted_q1():
+    # Q1 on the unit square, 4 x 4 cells, one coarse subdomain (the whole square), fine blocks of
+    # 2 x 2 cells expanded by one layer: each piece grows to 3 x 3 cells, so cell (x, y) lies in
+    # (2 if x in {1, 2} else 1) * (2 if y in {1, 2} else 1) fine subdomains and Lambda = 4.
+    p = pb.make_problem(4, dim=2, elem_type=pb.Q1, s=1, overlap=1, fine=2, fine_overlap=1)
+    coarse = dec.decompose(p)
+    fine = dec.nested_fine(p, coarse)
+    assert len(fine) == 4 and all(ci == 0 for ci, _ in fine)
+    cnt = np.zeros(p.n_elem, dtype=int)
+    for _, s in fine:
+        assert s.elems.sum() == 9
+        cnt += s.elems
+    cells = np.rint(p.coords[p.elem_vert].mean(axis=1) * 4 - 0.5).astype(int)     # cell (x, y) of each element
+    want = np.where(np.isin(cells[:, 0], [1, 2]), 2, 1) * np.where(np.isin(cells[:, 1], [1, 2]), 2, 1)
+    np.testing.assert_array_equal(cnt, want)
+    assert dec.overlap_count([s for _, s in fine]) == 4
+    # each piece's dofs: the interior vertices of its 3 x 3 cells that no outside cell touches (2 x 2)
+    assert all(s.dof.size == 4 for _, s in fine)
+
+
+def test_nested_pieces_cover_each_coarse_subdomain():
+    # with at least one layer of fine overlap inside Omega_i^c, every dof of Omega_i^c is internal to one
+    # of its pieces, and no piece reaches outside Omega_i^c (the expansion is restricted to it)
+    p = pb.make_problem(24, k=5.0, s=3, overlap=2, fine=6, fine_overlap=1)
+    coarse = dec.decompose(p)
+    fine = dec.nested_fine(p, coarse)
+    for ci, cs in enumerate(coarse):
+        mine = [s for c, s in fine if c == ci]
+        assert len(mine) > 1
+        assert all(not np.any(s.elems & ~cs.elems) for s in mine)
+        np.testing.assert_array_equal(np.unique(np.concatenate([s.dof for s in mine])), cs.dof)
+
+
+def test_single_fine_block_reproduces_the_coarse_decomposition():
+    # Q_i = 1 (one fine block covering the domain): every Omega_i^f is Omega_i^c itself
+    p = pb.make_problem(16, k=6.0, s=2, overlap=2, coef="cells", seed=1, n_cells=4, fine=1, fine_overlap=1)
+    coarse = dec.decompose(p)
+    fine = dec.nested_fine(p, coarse)
+    assert [c for c, _ in fine] == list(range(p.n_sub))
+    for (c, f), s in zip(fine, coarse):
+        np.testing.assert_array_equal(f.elems, s.elems)
+        np.testing.assert_array_equal(f.dof, s.dof)

@@ -57,6 +57,10 @@ extern "C" {
 /* local prolongation weights */
 #define HKG_PROLONG_AS 0           /* W_D = I, additive Schwarz of eq. (2.22)                       */
 #define HKG_PROLONG_POU 1          /* W_D = diag(1/mu) on dof(D) (Def. 2.13)                        */
+#define HKG_COARSE_HK 0            /* H_k-GenEO coarse space (Def. 2.14, 2.15)                      */
+#define HKG_COARSE_DELTA 1         /* Delta-GenEO: the same on the nearby SPD problem (k = 0)       */
+#define HKG_KRYLOV_RIGHT 0         /* right-preconditioned flexible GMRES, Euclidean inner product  */
+#define HKG_KRYLOV_LEFT_DK 1       /* GMRES on eq. (2.24) in the D_k inner product (Theorem 3.1)    */
 
 typedef struct hkgeneo_ctx hkgeneo_ctx;
 
@@ -71,6 +75,16 @@ typedef struct hkgeneo_ctx hkgeneo_ctx;
  *   elem_part [n_elem]       non-overlapping partition, ids in [0, n_sub)
  *   overlap [n_sub]          element layers added to each block (>= 1)
  *   k                        wavenumber (>= 0)
+ *   fine_part [n_elem]       NULL, or a finer non-overlapping element partition (ids >= 0) for the
+ *                            nested decomposition of Sec. 2.3: the elements of each overlapping coarse
+ *                            subdomain are split by it into Q_i pieces (ordered by id), each expanded
+ *                            by fine_overlap layers of Def. 2.8 restricted to the coarse subdomain (so
+ *                            the pieces cover it); the local solves of eq. (2.22) run on these fine
+ *                            subdomains, the coarse space (Def. 2.14, 2.15) on the coarse ones.
+ *                            Pieces without an interior dof are dropped.  hkgeneo_gmres_solve and
+ *                            hkgeneo_apply only (the batched engine, the server and
+ *                            hkgeneo_apply_noalloc reject nested contexts with HKG_EINVAL).
+ *   fine_overlap             layers of that expansion (>= 0; used when fine_part is set)
  */
 typedef struct {
     int32_t dim;
@@ -91,6 +105,8 @@ typedef struct {
     int32_t n_sub;
     const int32_t *overlap;
     double k;
+    const int32_t *fine_part;
+    int32_t fine_overlap;
 } hkgeneo_problem;
 
 /*
@@ -114,6 +130,19 @@ typedef struct {
  *   keep_workspace       0 (default): free the factorisation workspace (dense local blocks, Schur
  *                        complements, eigen work arrays) when setup/factor returns; 1: keep it for
  *                        the next hkgeneo_factor (no allocation on refactorisation)
+ *   krylov               HKG_KRYLOV_RIGHT (default): right-preconditioned flexible GMRES in the
+ *                        Euclidean inner product, stopping at ||f - B u|| <= rtol ||f||;
+ *                        HKG_KRYLOV_LEFT_DK: GMRES(restart) on the left-preconditioned system
+ *                        M^{-1} B u = M^{-1} f (eq. 2.24) in the inner product <x, y>_{D_k} = y^T D_k x,
+ *                        D_k = A + k^2 S (Prop 2.11): the setting of Theorem 3.1.  It stops at
+ *                        ||M^{-1}(f - B u)||_{D_k} <= rtol ||M^{-1} f||_{D_k}; one more sparse product
+ *                        (with D_k) per iteration.  hkgeneo_gmres_solve only (the batched engine and
+ *                        the server reject such contexts with HKG_EINVAL).
+ *   coarse_op            HKG_COARSE_HK (default): the H_k-GenEO eigenproblem of Def. 2.14 (indefinite
+ *                        B~, D~ the Gram matrix of (.,.)_{1,k}); HKG_COARSE_DELTA: Delta-GenEO, the
+ *                        comparison coarse space of Sec. 1, read as the same eigenproblem built from
+ *                        the nearby SPD problem (k = 0: B~ and D~ both the Neumann matrix of a(.,.));
+ *                        the local solves and B_0 = Z^T B Z keep the indefinite B either way.
  */
 typedef struct {
     int32_t eig_mode;
@@ -129,6 +158,8 @@ typedef struct {
     double rtol;
     int32_t keep_workspace;
     int32_t local_factor_prec;
+    int32_t krylov;
+    int32_t coarse_op;
 } hkgeneo_options;
 
 /* per right-hand side outcome of hkgeneo_gmres_solve (host array of nrhs entries) */
@@ -198,9 +229,13 @@ int32_t hkgeneo_apply_noalloc(hkgeneo_ctx *ctx, const double *r, double *z, int3
                               void *stream);
 
 /*
- * Solve B u = f with right-preconditioned flexible GMRES(restart) and M^{-1} as preconditioner,
- * starting from u = 0, independently for each of the nrhs columns.  f, u are device arrays
- * n_dof x nrhs (ld >= n_dof); `info` is a host array of nrhs entries (may be NULL).  Synchronous.
+ * Solve B u = f (Sec. 1: GMRES on the preconditioned system, analysed by the Elman theory of
+ * Theorem 3.1) with M^{-1} = M^{-1}_{AS,2} of eq. (2.23) as preconditioner, starting from u = 0,
+ * independently for each of the nrhs columns: right-preconditioned flexible GMRES(restart) in the
+ * Euclidean inner product, or (options.krylov = HKG_KRYLOV_LEFT_DK) GMRES(restart) on eq. (2.24) in
+ * the D_k inner product.  f, u are device arrays n_dof x nrhs (ld >= n_dof); `info` is a host array
+ * of nrhs entries (may be NULL): iterations, convergence by the variant's own criterion, its
+ * recurrence estimate, and the Euclidean true residual ||f - B u|| / ||f||.  Synchronous.
  * Returns HKG_OK if every column converged, HKG_ENOTCONV otherwise (u holds the last iterate).
  */
 int32_t hkgeneo_gmres_solve(hkgeneo_ctx *ctx, const double *f, double *u, int32_t nrhs, int32_t ld,
@@ -331,6 +366,15 @@ int32_t hkgeneo_query(const hkgeneo_ctx *ctx, hkgeneo_stats *out);
  * nI = |dof(D_i)|, nG = |Gamma_i|, m = selected eigenvectors m_i.
  */
 int32_t hkgeneo_query_subdomains(const hkgeneo_ctx *ctx, int32_t *nI, int32_t *nG, int32_t *m);
+
+/*
+ * First-level subdomains of a nested context (Sec. 2.3): their number, and per subdomain (arrays of
+ * that length, each may be NULL) |dof(Omega_{i,j}^f)| and the coarse subdomain i that owns it;
+ * *lambda_fine: Lambda of Sec. 2.4 counted over them.  A context without nesting reports its
+ * coarse subdomains (each its own owner).  Call first with nI = owner = NULL to get the count.
+ */
+int32_t hkgeneo_query_fine(const hkgeneo_ctx *ctx, int32_t *n_fine, int32_t *nI, int32_t *owner,
+                           int32_t *lambda_fine);
 
 /*
  * Index sets of subdomain `sub` into host arrays: dof ids of dof(D) ascending (nI entries) and of

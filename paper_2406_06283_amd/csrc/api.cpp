@@ -17,7 +17,9 @@ thread_local std::string g_last_error;
 void set_last_error(const std::string &msg) { g_last_error = msg; }
 
 // declared in krylov.hip
-int32_t gmres_arnoldi_step(const GmresDev &G, int j, double rtol, hipStream_t s);
+int32_t gmres_arnoldi_step(const GmresDev &G, int j, double rtol, hipStream_t s, const int32_t *rowptr = nullptr,
+                           const int32_t *colidx = nullptr, const double *Aval = nullptr, const double *Sval = nullptr,
+                           double k2 = 0.0);
 int32_t gmres_cycle_start(const GmresDev &G, const double *rnorm, double rtol, const int32_t *want, hipStream_t s);
 int32_t gmres_cycle_update(const GmresDev &G, double *x, int ldx, hipStream_t s);
 int gmres_rows_per_block();
@@ -40,6 +42,8 @@ extern "C" void hkgeneo_default_options(hkgeneo_options *o) {
     o->rtol = 1e-8;
     o->keep_workspace = 0;
     o->local_factor_prec = 64;
+    o->krylov = HKG_KRYLOV_RIGHT;
+    o->coarse_op = HKG_COARSE_HK;
 }
 
 extern "C" const char *hkgeneo_strerror(int32_t st) {
@@ -60,13 +64,15 @@ extern "C" const char *hkgeneo_last_error(void) { return hkg::g_last_error.c_str
 
 extern "C" void hkgeneo_destroy(hkgeneo_ctx *c) {
     if (!c) return;
+    if (c->fine) hkgeneo_destroy(c->fine);
+    c->fine = nullptr;
     DevBuf *bufs[] = {&c->rowptr, &c->colidx, &c->Aval,    &c->Sval,   &c->I_idx,   &c->G_idx,      &c->winv,
                       &c->wloc,   &c->tp_ptr, &c->tp_pos,  &c->tp_sub, &c->subs_d, &c->bandK,   &c->bandM,      &c->bandLoc,
                       &c->pairs,  &c->matsGG, &c->matsSq,  &c->poffSub, &c->jobsGI, &c->jobsSq,     &c->gjobsSchur,
                       &c->matsLoc, &c->poffLoc, &c->jobsLoc, &c->matsM, &c->jobsM, &c->Bval, &c->Minv,    &c->Z, &c->Zr,  &c->B0inv, &c->B0copy,
                       &c->u,      &c->c,      &c->y,       &c->ypart, &c->itersd,       &c->V,      &c->Zk,      &c->H,          &c->cs,
                       &c->sn,     &c->g,      &c->part,    &c->hcol,   &c->scal,    &c->active,     &c->want,
-                      &c->rnorm,  &c->npart,  &c->fnorm};
+                      &c->rnorm,  &c->npart,  &c->fnorm, &c->DV};
     if (c->s2) (void)hipStreamSynchronize(c->s2);
     if (c->s3) (void)hipStreamSynchronize(c->s3);
     for (DevBuf *b : bufs) drelease(c, b);
@@ -103,6 +109,11 @@ int32_t check_problem(const hkgeneo_problem *p, const hkgeneo_options *o) {
     }
     for (int s = 0; s < p->n_sub; ++s)
         if (p->overlap[s] < 1) return HKG_EINVAL;
+    if (p->fine_part) {
+        if (p->fine_overlap < 0) return HKG_EINVAL;
+        for (int e = 0; e < p->n_elem; ++e)
+            if (p->fine_part[e] < 0) return HKG_EINVAL;
+    }
     if (!(o->eig_mode == HKG_EIG_FIXED || o->eig_mode == HKG_EIG_THRESHOLD)) return HKG_EINVAL;
     if (o->nev < 0 || o->max_eig_per_sub < 1 || o->max_eig_per_sub > 64 || !(o->cluster_rtol >= 0.0))
         return HKG_EINVAL;
@@ -112,6 +123,8 @@ int32_t check_problem(const hkgeneo_problem *p, const hkgeneo_options *o) {
     // operators are always formed in float64 and rounded once
     if (o->local_factor_prec != 64) return HKG_EINVAL;
     if (!(o->prolong == HKG_PROLONG_AS || o->prolong == HKG_PROLONG_POU)) return HKG_EINVAL;
+    if (!(o->krylov == HKG_KRYLOV_RIGHT || o->krylov == HKG_KRYLOV_LEFT_DK)) return HKG_EINVAL;
+    if (!(o->coarse_op == HKG_COARSE_HK || o->coarse_op == HKG_COARSE_DELTA)) return HKG_EINVAL;
     if (o->restart < 1 || o->max_iter < 1 || !(o->rtol > 0.0)) return HKG_EINVAL;
     return HKG_OK;
 }
@@ -138,9 +151,31 @@ extern "C" int32_t hkgeneo_setup(const hkgeneo_problem *p, const hkgeneo_options
     c->k = p->k;
     c->dim = p->dim;
     int32_t bad = -1;
+    c->coarse_only = p->fine_part != nullptr;
     st = analyze(c, p, s, &bad);
     if (st == HKG_EINVAL && g_last_error.empty())
         set_last_error("partition: invalid element/vertex data or a dof internal to no subdomain");
+    if (st == HKG_OK && p->fine_part) {
+        // nested decomposition (Sec. 2.3): the first-level subdomains inside the coarse ones, in a
+        // one-level context of their own that holds the local inverses
+        std::vector<std::vector<int32_t>> sets;
+        st = build_nested_sets(p, c->P, p->fine_overlap, &sets, &c->fine_owner);
+        if (st == HKG_OK) {
+            hkgeneo_ctx *f = new hkgeneo_ctx();
+            f->opt = *o;
+            f->opt.two_level = 0;
+            f->n_dof = p->n_dof;
+            f->nnz = p->nnz;
+            f->k = p->k;
+            f->dim = p->dim;
+            c->fine = f;
+            st = analyze(f, p, s, &bad, &sets);
+            if (st == HKG_EINVAL && g_last_error.empty())
+                set_last_error("nested partition: a dof internal to no first-level subdomain");
+            if (st == HKG_OK) st = factor(f, s);
+            if (st == HKG_OK && !f->opt.keep_workspace) free_workspace(f);
+        }
+    }
     if (st == HKG_OK) st = factor(c, s);
     if (st != HKG_OK) {
         (void)hipStreamSynchronize(s);
@@ -151,7 +186,7 @@ extern "C" int32_t hkgeneo_setup(const hkgeneo_problem *p, const hkgeneo_options
     const auto t1 = std::chrono::steady_clock::now();
     c->stats.n_dof = c->n_dof;
     c->stats.n_sub = c->n_sub;
-    c->stats.lambda_overlap = c->P.lambda_overlap;
+    c->stats.lambda_overlap = c->fine ? c->fine->P.lambda_overlap : c->P.lambda_overlap;
     c->stats.m0 = c->m0;
     c->stats.sum_nI = (int32_t)c->sum_nI;
     c->stats.max_nI = c->max_nI;
@@ -167,7 +202,13 @@ extern "C" int32_t hkgeneo_factor(hkgeneo_ctx *c, void *stream) {
     g_last_error.clear();
     const auto t0 = std::chrono::steady_clock::now();
     hipStream_t s = (hipStream_t)stream;
-    int32_t st = factor(c, s);
+    int32_t st = HKG_OK;
+    if (c->fine) {
+        st = factor(c->fine, s);
+        if (!c->fine->opt.keep_workspace) free_workspace(c->fine);
+        c->fine->ws_nrhs = 0;
+    }
+    if (st == HKG_OK) st = factor(c, s);
     if (!c->opt.keep_workspace) free_workspace(c);
     c->ws_nrhs = 0;                       // the coarse dimension may have changed
     if (st != HKG_OK) return st;
@@ -237,10 +278,41 @@ static int32_t apply_once(hkgeneo_ctx *c, const ApplyPlan &plan, const double *r
     return apply_two_level(p, r, ldr, z, ldz, s);
 }
 
+// z = M^{-1} r.  For a nested decomposition (Sec. 2.3) the first-level solves come from the fine
+// context, then the coarse correction of this (coarse-only) context is added: the same sum
+// sum_{i,j} E_{i,j}^f (B_{i,j}^f)^{-1} R_{i,j}^f r + E_0 B_0^{-1} R_0 r of eqs. (2.22), (2.23).
+struct Precond {
+    ApplyPlan plan, fine;
+};
+
+static int32_t precond_plan(hkgeneo_ctx *c, int nrhs, const int32_t *active, Precond *P) {
+    HKG_TRY(ensure_apply_ws(c, nrhs));
+    P->plan = make_plan(c, nrhs);
+    P->plan.active = active;
+    if (c->fine) {
+        HKG_TRY(ensure_apply_ws(c->fine, nrhs));
+        P->fine = make_plan(c->fine, nrhs);
+        P->fine.active = active;
+        P->plan.Minv = nullptr;          // the coarse correction alone ...
+        P->plan.accumulate = 1;          // ... added to the first-level solves
+    }
+    return HKG_OK;
+}
+
+static int32_t precond_apply(hkgeneo_ctx *c, const Precond &P, const double *r, int ldr, double *z, int ldz,
+                             hipStream_t s) {
+    if (c->fine) {
+        HKG_TRY(apply_two_level(P.fine, r, ldr, z, ldz, s));
+        return apply_two_level(P.plan, r, ldr, z, ldz, s);
+    }
+    return apply_once(c, P.plan, r, ldr, z, ldz, s);
+}
+
 extern "C" int32_t hkgeneo_apply(hkgeneo_ctx *c, const double *r, double *z, int32_t nrhs, int32_t ld, void *stream) {
     if (!c || !r || !z || nrhs < 1 || ld < c->n_dof) return HKG_EINVAL;
-    HKG_TRY(ensure_apply_ws(c, nrhs));
-    return apply_once(c, make_plan(c, nrhs), r, ld, z, ld, (hipStream_t)stream);
+    Precond P;
+    HKG_TRY(precond_plan(c, nrhs, nullptr, &P));
+    return precond_apply(c, P, r, ld, z, ld, (hipStream_t)stream);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -279,6 +351,10 @@ int32_t scratch_on_current_device(double **out) {
 extern "C" int32_t hkgeneo_apply_noalloc(hkgeneo_ctx *c, const double *r, double *z, int32_t nrhs, int32_t ld,
                                          void *stream) {
     if (!c || !r || !z || nrhs < 1 || ld < c->n_dof) return HKG_EINVAL;
+    if (c->fine) {
+        set_last_error("hkgeneo_apply_noalloc: nested contexts use hkgeneo_apply");
+        return HKG_EINVAL;
+    }
     const int64_t m0 = std::max(c->m0, 1);
     const int64_t chunks = apply_ypart_chunks((int)m0);
     // u (sum n_I x nrhs), c (m0 x nrhs), ypart (chunks x m0 x nrhs), each at a 256-byte boundary
@@ -349,9 +425,141 @@ static int32_t ensure_gmres_ws(hkgeneo_ctx *c, int nrhs) {
     return HKG_OK;
 }
 
+// GMRES(restart) on the left-preconditioned system M^{-1} B u = M^{-1} f (eq. 2.24) in the D_k inner
+// product (Theorem 3.1): r = M^{-1}(f - B x), beta = ||r||_{D_k}; Arnoldi vectors w = M^{-1} B v_j
+// orthogonalised by CGS2 against D_k V (kept beside V); x += V y at the cycle end.  Stops when
+// ||M^{-1}(f - B x)||_{D_k} <= rtol ||M^{-1} f||_{D_k}; info also carries the Euclidean true residual.
+static int32_t gmres_solve_dk(hkgeneo_ctx *c, const double *f, double *u, int nrhs, int ld, hkgeneo_rhs_info *info,
+                              hipStream_t s) {
+    HKG_TRY(ensure_apply_ws(c, nrhs));
+    HKG_TRY(ensure_gmres_ws(c, nrhs));
+    const int n = c->n_dof, m = c->opt.restart;
+    const int nblk = (n + gmres_rows_per_block() - 1) / gmres_rows_per_block();
+    if (c->DV.bytes != c->V.bytes) HKG_TRY(dalloc(c, &c->DV, c->V.bytes));
+    GmresDev G{};
+    G.n = n;
+    G.nrhs = nrhs;
+    G.restart = m;
+    G.nblk = nblk;
+    G.V = dp<double>(c->V);
+    G.Zk = dp<double>(c->Zk);
+    G.H = dp<double>(c->H);
+    G.cs = dp<double>(c->cs);
+    G.sn = dp<double>(c->sn);
+    G.g = dp<double>(c->g);
+    G.part = dp<double>(c->part);
+    G.hcol = dp<double>(c->hcol);
+    G.scal = dp<double>(c->scal);
+    G.active = dp<int32_t>(c->active);
+    G.iters = dp<int32_t>(c->itersd);
+    G.max_iter = c->opt.max_iter;
+    G.DV = dp<double>(c->DV);
+    G.VD = G.DV;
+    G.dk = 1;
+    const int32_t *rp = dp<int32_t>(c->rowptr), *ci = dp<int32_t>(c->colidx);
+    const double *Av = dp<double>(c->Aval), *Sv = dp<double>(c->Sval), *Bv = dp<double>(c->Bval);
+    const double k2 = c->k * c->k;
+    Precond plan, plan0;
+    HKG_TRY(precond_plan(c, nrhs, G.active, &plan));                   // the iteration: columns in their cycle
+    HKG_TRY(precond_plan(c, nrhs, dp<int32_t>(c->want), &plan0));      // the cycle start: columns that iterate
+    const int ldV = n * (m + 1), ldZ = n * m;
+    const double rtol = c->opt.rtol;
+    for (int r = 0; r < nrhs; ++r) HKG_HIP(hipMemsetAsync(u + (size_t)r * ld, 0, n * sizeof(double), s));
+    HKG_HIP(hipMemsetAsync(c->V.p, 0, c->V.bytes, s));
+    HKG_HIP(hipMemsetAsync(c->DV.p, 0, c->DV.bytes, s));
+    HKG_HIP(hipMemsetAsync(c->Zk.p, 0, c->Zk.bytes, s));
+    HKG_HIP(hipMemsetAsync(c->scal.p, 0, c->scal.bytes, s));
+    HKG_HIP(hipMemsetAsync(c->itersd.p, 0, c->itersd.bytes, s));
+    HKG_TRY(vec_norms(n, nrhs, f, ld, dp<double>(c->fnorm), dp<double>(c->npart), nblk, s));
+    std::vector<double> fe(nrhs), rn(nrhs), ref(nrhs, 0.0), sc((size_t)8 * nrhs);
+    HKG_HIP(hipMemcpyAsync(fe.data(), c->fnorm.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+    HKG_HIP(hipStreamSynchronize(s));
+    std::vector<int32_t> want(nrhs, 1), act(nrhs, 0), iters(nrhs, 0);
+    std::vector<double> est(nrhs, 0.0);
+    for (int r = 0; r < nrhs; ++r)
+        if (!(fe[r] > 0.0)) want[r] = 0;         // zero (u = 0) or non-finite right-hand side
+    bool first = true;
+    const int check = c->prof ? 1 : 4;
+    while (true) {
+        HKG_HIP(hipMemcpyAsync(c->want.p, want.data(), nrhs * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        // r = M^{-1}(f - B x) into V[:, 0] (f - B x staged in Zk[:, 0]), beta = ||r||_{D_k}
+        HKG_TRY(spmv(n, nrhs, rp, ci, Bv, u, ld, G.Zk, ldZ, f, ld, s));
+        HKG_TRY(precond_apply(c, plan0, G.Zk, ldZ, G.V, ldV, s));
+        HKG_TRY(gmres_dk_norm(G, -1, rp, ci, Av, Sv, k2, s));
+        HKG_TRY(gmres_dk_reduce(G, dp<double>(c->rnorm), s));
+        HKG_HIP(hipMemcpyAsync(rn.data(), c->rnorm.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+        HKG_HIP(hipMemcpyAsync(iters.data(), c->itersd.p, nrhs * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HKG_HIP(hipStreamSynchronize(s));
+        if (first) {
+            // the reference norm ||M^{-1} f||_{D_k} (x = 0 on the first pass)
+            for (int r = 0; r < nrhs; ++r) {
+                ref[r] = want[r] ? rn[r] : 0.0;
+                sc[8 * r + 1] = ref[r];
+                HKG_HIP(hipMemcpyAsync(dp<double>(c->scal) + 8 * r + 1, &ref[r], sizeof(double), hipMemcpyHostToDevice,
+                                       s));
+            }
+            HKG_HIP(hipStreamSynchronize(s));
+            first = false;
+        }
+        bool any = false;
+        for (int r = 0; r < nrhs; ++r) {
+            if (!want[r]) continue;
+            est[r] = ref[r] > 0 ? rn[r] / ref[r] : 0.0;
+            if (!gmres_keeps_going(rn[r], ref[r], rtol) || iters[r] >= c->opt.max_iter) {
+                want[r] = 0;
+                continue;
+            }
+            any = true;
+        }
+        if (!any) break;
+        HKG_HIP(hipMemcpyAsync(c->want.p, want.data(), nrhs * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        HKG_TRY(gmres_cycle_start(G, dp<double>(c->rnorm), rtol, dp<int32_t>(c->want), s));
+        for (int j = 0; j < m; ++j) {
+            // w = M^{-1} B v_j into V[:, j+1] (B v_j staged in Zk[:, j])
+            HKG_TRY(spmv(n, nrhs, rp, ci, Bv, G.V + (size_t)j * n, ldV, G.Zk + (size_t)j * n, ldZ, nullptr, 0, s,
+                         G.active));
+            HKG_TRY(precond_apply(c, plan, G.Zk + (size_t)j * n, ldZ, G.V + (size_t)(j + 1) * n, ldV, s));
+            HKG_TRY(gmres_arnoldi_step(G, j, rtol, s, rp, ci, Av, Sv, k2));
+            if ((j + 1) % check == 0 || j + 1 == m) {
+                HKG_HIP(hipMemcpyAsync(act.data(), c->active.p, nrhs * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+                HKG_HIP(hipStreamSynchronize(s));
+                bool still = false;
+                for (int r = 0; r < nrhs; ++r) still = still || act[r];
+                if (!still) break;
+            }
+        }
+        HKG_HIP(hipMemcpyAsync(sc.data(), c->scal.p, sc.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        HKG_HIP(hipStreamSynchronize(s));
+        for (int r = 0; r < nrhs; ++r)
+            if (want[r] && sc[8 * r + 5] != 0.0) want[r] = 0;    // singular Hessenberg column
+        HKG_TRY(gmres_cycle_update(G, u, ld, s));
+    }
+    // Euclidean true residuals
+    HKG_TRY(spmv(n, nrhs, rp, ci, Bv, u, ld, G.V, ldV, f, ld, s));
+    HKG_TRY(vec_norms(n, nrhs, G.V, ldV, dp<double>(c->rnorm), dp<double>(c->npart), nblk, s));
+    std::vector<double> rt(nrhs);
+    HKG_HIP(hipMemcpyAsync(rt.data(), c->rnorm.p, nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+    HKG_HIP(hipMemcpyAsync(iters.data(), c->itersd.p, nrhs * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HKG_HIP(hipStreamSynchronize(s));
+    int32_t status = HKG_OK;
+    for (int r = 0; r < nrhs; ++r) {
+        const bool zero = fe[r] == 0.0;
+        const int ok = zero || (est[r] <= rtol && std::isfinite(rt[r]));      // false for NaN
+        if (!ok) status = HKG_ENOTCONV;
+        if (info) {
+            info[r].iters = iters[r];
+            info[r].converged = ok;
+            info[r].relres_est = zero ? 0.0 : est[r];
+            info[r].relres_true = gmres_relres(rt[r], fe[r]);
+        }
+    }
+    return status;
+}
+
 extern "C" int32_t hkgeneo_gmres_solve(hkgeneo_ctx *c, const double *f, double *u, int32_t nrhs, int32_t ld,
                                        hkgeneo_rhs_info *info, void *stream) {
     if (!c || !f || !u || nrhs < 1 || ld < c->n_dof) return HKG_EINVAL;
+    if (c->opt.krylov == HKG_KRYLOV_LEFT_DK) return gmres_solve_dk(c, f, u, nrhs, ld, info, (hipStream_t)stream);
     hipStream_t s = (hipStream_t)stream;
     HKG_TRY(ensure_apply_ws(c, nrhs));
     HKG_TRY(ensure_gmres_ws(c, nrhs));
@@ -374,8 +582,9 @@ extern "C" int32_t hkgeneo_gmres_solve(hkgeneo_ctx *c, const double *f, double *
     G.active = dp<int32_t>(c->active);
     G.iters = dp<int32_t>(c->itersd);
     G.max_iter = c->opt.max_iter;
-    ApplyPlan plan = make_plan(c, nrhs);
-    plan.active = G.active;
+    G.VD = G.V;
+    Precond plan;
+    HKG_TRY(precond_plan(c, nrhs, G.active, &plan));
     const int ldV = n * (m + 1), ldZ = n * m;
     const double rtol = c->opt.rtol;
     // x = 0, ||f||
@@ -418,7 +627,7 @@ extern "C" int32_t hkgeneo_gmres_solve(hkgeneo_ctx *c, const double *f, double *
         HKG_HIP(hipMemcpyAsync(c->want.p, want.data(), nrhs * sizeof(int32_t), hipMemcpyHostToDevice, s));
         HKG_TRY(gmres_cycle_start(G, dp<double>(c->rnorm), rtol, dp<int32_t>(c->want), s));
         for (int j = 0; j < m; ++j) {
-            HKG_TRY(apply_once(c, plan, G.V + (size_t)j * n, ldV, G.Zk + (size_t)j * n, ldZ, s));
+            HKG_TRY(precond_apply(c, plan, G.V + (size_t)j * n, ldV, G.Zk + (size_t)j * n, ldZ, s));
             HKG_TRY(spmv(n, nrhs, dp<int32_t>(c->rowptr), dp<int32_t>(c->colidx), dp<double>(c->Bval),
                          G.Zk + (size_t)j * n, ldZ, G.V + (size_t)(j + 1) * n, ldV, nullptr, 0, s, G.active));
             HKG_TRY(gmres_arnoldi_step(G, j, rtol, s));
@@ -467,7 +676,7 @@ extern "C" int32_t hkgeneo_gmres_solve(hkgeneo_ctx *c, const double *f, double *
 extern "C" int32_t hkgeneo_query(const hkgeneo_ctx *c, hkgeneo_stats *out) {
     if (!c || !out) return HKG_EINVAL;
     *out = c->stats;
-    out->device_bytes = c->device_bytes;
+    out->device_bytes = c->device_bytes + (c->fine ? c->fine->device_bytes : 0);
     return HKG_OK;
 }
 
@@ -477,6 +686,19 @@ extern "C" int32_t hkgeneo_query_subdomains(const hkgeneo_ctx *c, int32_t *nI, i
         if (nI) nI[i] = c->subs[i].nI;
         if (nG) nG[i] = c->subs[i].nG;
         if (m) m[i] = c->subs[i].m;
+    }
+    return HKG_OK;
+}
+
+extern "C" int32_t hkgeneo_query_fine(const hkgeneo_ctx *c, int32_t *n_fine, int32_t *nI, int32_t *owner,
+                                      int32_t *lambda_fine) {
+    if (!c) return HKG_EINVAL;
+    const hkgeneo_ctx *f = c->fine ? c->fine : c;
+    if (n_fine) *n_fine = f->n_sub;
+    if (lambda_fine) *lambda_fine = f->P.lambda_overlap;
+    for (int i = 0; i < f->n_sub; ++i) {
+        if (nI) nI[i] = f->subs[i].nI;
+        if (owner) owner[i] = c->fine ? c->fine_owner[i] : i;
     }
     return HKG_OK;
 }

@@ -44,6 +44,13 @@ __global__ __launch_bounds__(LS_ROWS * LS_WAVES) void k_local_solve(const SubDev
     const int tiles = (n + LS_ROWS - 1) / LS_ROWS;
     const bool restrict_tile = (int)blockIdx.x == tiles;
     if ((int)blockIdx.x > tiles || (restrict_tile && (sd.m == 0 || c == nullptr))) return;
+    if (!restrict_tile && Minv == nullptr) {
+        // coarse correction alone (the first-level solves of a nested decomposition run elsewhere):
+        // the local vectors start at zero and receive Z_i y_i
+        const int row = blockIdx.x * LS_ROWS + threadIdx.x;
+        if (threadIdx.x < LS_ROWS && row < n) u[(int64_t)rhs * ldu + sd.offI + row] = 0.0;
+        return;
+    }
     double *xd = sh;                                  // r_D in double
     T *xt = reinterpret_cast<T *>(sh + n);            // r_D in T (aliases nothing when T = double)
     double *part = sh + n + (n * sizeof(T) + 7) / 8;
@@ -149,11 +156,11 @@ __global__ __launch_bounds__(256) void k_coarse_add(const SubDev *__restrict__ s
     u[(int64_t)rhs * ldu + sd.offI + a] += s;
 }
 
-// z_l = sum over the transpose map of u (fixed order)
+// z_l = sum over the transpose map of u (fixed order); accumulate: z_l += that sum
 __global__ __launch_bounds__(256) void k_prolong(int n, const int32_t *__restrict__ tp_ptr,
                                                  const int32_t *__restrict__ tp_pos, const double *__restrict__ u,
                                                  int64_t ldu, double *__restrict__ z, int ldz,
-                                                 const int32_t *__restrict__ active) {
+                                                 const int32_t *__restrict__ active, int accumulate) {
     const int rhs = blockIdx.y;
     if (active && !active[rhs]) return;
     const int l = blockIdx.x * 256 + threadIdx.x;
@@ -161,7 +168,8 @@ __global__ __launch_bounds__(256) void k_prolong(int n, const int32_t *__restric
     const double *uu = u + (int64_t)rhs * ldu;
     double s = 0.0;
     for (int t = tp_ptr[l]; t < tp_ptr[l + 1]; ++t) s += uu[tp_pos[t]];
-    z[(int64_t)rhs * ldz + l] = s;
+    double *zz = z + (int64_t)rhs * ldz + l;
+    *zz = accumulate ? *zz + s : s;
 }
 
 int32_t apply_two_level(const ApplyPlan &p, const double *r, int ldr, double *z, int ldz, hipStream_t s) {
@@ -191,7 +199,7 @@ int32_t apply_two_level(const ApplyPlan &p, const double *r, int ldr, double *z,
         HKG_HIP(hipGetLastError());
     }
     hipLaunchKernelGGL(k_prolong, dim3((p.n_dof + 255) / 256, p.nrhs), dim3(256), 0, s, p.n_dof, p.tp_ptr, p.tp_pos,
-                       p.u, ldu, z, ldz, p.active);
+                       p.u, ldu, z, ldz, p.active, p.accumulate);
     HKG_HIP(hipGetLastError());
     return HKG_OK;
 }

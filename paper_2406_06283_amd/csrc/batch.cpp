@@ -632,8 +632,10 @@ extern "C" int32_t hkgeneo_batch_create(hkgeneo_ctx *const *ctxs, const int32_t 
     *out = nullptr;
     int maxR = 0;
     for (int p = 0; p < nprob; ++p) {
-        if (!ctxs[p] || nrhs[p] < 1 || nrhs[p] > 65535 || ctxs[p]->opt.restart != ctxs[0]->opt.restart) {
-            set_last_error("batch: every problem needs a context, 1..65535 right-hand sides and the same restart");
+        if (!ctxs[p] || nrhs[p] < 1 || nrhs[p] > 65535 || ctxs[p]->opt.restart != ctxs[0]->opt.restart ||
+            ctxs[p]->opt.krylov != HKG_KRYLOV_RIGHT || ctxs[p]->fine) {
+            set_last_error("batch: every problem needs a context (flexible GMRES), 1..65535 right-hand sides and "
+                           "the same restart");
             return HKG_EINVAL;
         }
         maxR = std::max(maxR, (int)nrhs[p]);
@@ -716,7 +718,7 @@ extern "C" int32_t hkgeneo_server_create(int64_t workspace_budget, int32_t max_r
 
 extern "C" int32_t hkgeneo_server_submit(hkgeneo_server *s, hkgeneo_ctx *ctx, const double *f, double *u,
                                          int32_t nrhs, int32_t ld, int64_t tag, void *stream) {
-    if (!s) return HKG_EINVAL;
+    if (!s || !ctx || ctx->opt.krylov != HKG_KRYLOV_RIGHT || ctx->fine) return HKG_EINVAL;
     return submit(s, ctx, f, u, nrhs, ld, tag, (hipStream_t)stream);
 }
 

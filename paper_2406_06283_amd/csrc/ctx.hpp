@@ -33,7 +33,7 @@ struct hkgeneo_ctx {
     // factorisation workspace (kept between calls when opt.keep_workspace, freed otherwise)
     hkg::DevBuf wDk, wBIO, wCII, wGG, wGI, wS, wW, wPiv, wInfo, wFlag, wD, wE, wTau, wM, wLam, wY, wB0, wLU, wPivL,
         wJobsZ, wGjobsY, wMisc, wPiv0, wInv, wVWV, wInfoL, wSL, wIv, wLinv, wJobsInv, wT, wPivC, wInfoC, wFlagSpd,
-        wDC, wDCjobs, wDCpiv, wDCinfo;
+        wDC, wDCjobs, wDCpiv, wDCinfo, wAIO;
     // the local-inverse pipeline of the factorisation runs on a second stream beside the coarse-space
     // pipeline; its pivot flags come back through pinned host memory
     hipStream_t s2 = nullptr;
@@ -48,12 +48,19 @@ struct hkgeneo_ctx {
     int ws_nrhs = 0;
     // gmres workspace
     hkg::DevBuf V, Zk, H, cs, sn, g, part, hcol, scal, active, want, rnorm, npart, fnorm, itersd;
+    hkg::DevBuf DV;                       // D_k V of the D_k-inner-product variant
     int gm_nrhs = 0;
     // measurement hook: events around the local-solve kernel
     bool prof = false;
     std::vector<hipEvent_t> ev;
     size_t ev_used = 0;
     hkgeneo_stats stats{};
+    // nested decomposition (Sec. 2.3): this context holds the coarse subdomains and the coarse space
+    // only (coarse_only: no local inverses), `fine` the first-level subdomains and their local
+    // inverses (a one-level context), fine_owner the coarse subdomain of each
+    hkgeneo_ctx *fine = nullptr;
+    bool coarse_only = false;
+    std::vector<int32_t> fine_owner;
 };
 
 namespace hkg {
@@ -73,7 +80,8 @@ T *dp(const DevBuf &b) {
     return reinterpret_cast<T *>(b.p);
 }
 
-int32_t analyze(hkgeneo_ctx *c, const hkgeneo_problem *p, hipStream_t s, int32_t *bad);
+int32_t analyze(hkgeneo_ctx *c, const hkgeneo_problem *p, hipStream_t s, int32_t *bad,
+                const std::vector<std::vector<int32_t>> *sets = nullptr);
 int32_t factor(hkgeneo_ctx *c, hipStream_t s);
 // B_0^{-1} into c->B0inv from the assembled c->wB0 by divide and conquer over its level blocks;
 // *done = false when the structure does not allow it or a block needs pivoting across blocks

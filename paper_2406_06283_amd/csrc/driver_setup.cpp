@@ -64,15 +64,17 @@ void free_workspace(hkgeneo_ctx *c) {
                    &c->wFlag, &c->wD, &c->wE, &c->wTau, &c->wM, &c->wLam, &c->wY, &c->wB0, &c->wLU,
                    &c->wPivL, &c->wJobsZ, &c->wGjobsY, &c->wMisc, &c->wPiv0, &c->wInv, &c->wVWV, &c->wInfoL, &c->wSL, &c->wIv,
                    &c->wLinv, &c->wJobsInv, &c->wT, &c->wPivC, &c->wInfoC, &c->wFlagSpd, &c->wDC, &c->wDCjobs,
-                   &c->wDCpiv, &c->wDCinfo};
+                   &c->wDCpiv, &c->wDCinfo, &c->wAIO};
     for (DevBuf *b : w) drelease(c, b);
 }
 
 // ------------------------------------------------------------------------------------------------
 // analysis: partition, layout, resident inputs, descriptors that depend on the partition only
 // ------------------------------------------------------------------------------------------------
-int32_t analyze(hkgeneo_ctx *c, const hkgeneo_problem *p, hipStream_t s, int32_t *bad) {
-    HKG_TRY(build_partition(p, &c->P, bad));
+int32_t analyze(hkgeneo_ctx *c, const hkgeneo_problem *p, hipStream_t s, int32_t *bad,
+                const std::vector<std::vector<int32_t>> *sets) {
+    HKG_TRY(build_partition(p, &c->P, bad, sets));
+    c->n_sub = c->P.n_sub;
     c->npe = c->P.npe;
     const Partition &P = c->P;
     const int ns = c->n_sub;
@@ -342,7 +344,9 @@ int32_t coarse_space(hkgeneo_ctx *c, hipStream_t s, const std::function<int32_t(
     const hkgeneo_options &o = c->opt;
     const int mmax = o.max_eig_per_sub;
     const SubDev *dsub = dp<SubDev>(c->subs_d);
-    const double k2 = c->k * c->k;
+    const bool delta = o.coarse_op == HKG_COARSE_DELTA;
+    const double k2 = delta ? 0.0 : c->k * c->k;          // wavenumber of the local eigenproblem
+    double *eigIO = delta ? dp<double>(c->wAIO) : dp<double>(c->wBIO);   // its [.._II | .._IG] blocks
     HKG_TRY(walloc(c, &c->wGG, std::max<int64_t>(c->nGG, 1) * sizeof(double)));
     HKG_TRY(walloc(c, &c->wGI, std::max<int64_t>(c->nGI, 1) * sizeof(double)));
     HKG_TRY(walloc(c, &c->wS, c->nSq * sizeof(double)));
@@ -394,7 +398,7 @@ int32_t coarse_space(hkgeneo_ctx *c, hipStream_t s, const std::function<int32_t(
                                dp<int32_t>(c->wPiv), dp<int32_t>(c->wInfo), true, s));
     std::vector<int32_t> flags;
     // X = B~_GG^{-1} B_GI ; S = B_II - B_IG X
-    HKG_TRY(gather_gamma_rows(dsub, ns, c->max_nI, c->max_nG, dp<double>(c->wBIO), dp<double>(c->wGI), s));
+    HKG_TRY(gather_gamma_rows(dsub, ns, c->max_nI, c->max_nG, eigIO, dp<double>(c->wGI), s));
     HKG_TRY(apply_pivots_rows<double>(dsub, ns, c->max_nI, dp<int32_t>(c->wPiv), dp<double>(c->wGI), 0, s));
     // the Gamma block is dense: as a band of half-width n_G - 1 the solves take one launch each
     const int bandG = tri_band_fits(c->max_nG, c->max_nG - 1, sizeof(double)) ? c->max_nG - 1 : -1;
@@ -402,8 +406,8 @@ int32_t coarse_space(hkgeneo_ctx *c, hipStream_t s, const std::function<int32_t(
                                       dp<double>(c->wGI), TRI_LOWER_UNIT, s, bandG));
     HKG_TRY(tri_solve_batched<double>(dp<TriJob>(c->jobsGI), ns, c->max_nG, c->max_nI, dp<double>(c->wGG),
                                       dp<double>(c->wGI), TRI_UPPER, s, bandG));
-    HKG_TRY(copy_bii(dsub, ns, c->max_nI, dp<double>(c->wBIO), dp<double>(c->wS), s));
-    HKG_TRY(gemm_batched<double>(dp<GemmJob>(c->gjobsSchur), ns, c->max_nI, c->max_nI, dp<double>(c->wBIO),
+    HKG_TRY(copy_bii(dsub, ns, c->max_nI, eigIO, dp<double>(c->wS), s));
+    HKG_TRY(gemm_batched<double>(dp<GemmJob>(c->gjobsSchur), ns, c->max_nI, c->max_nI, eigIO,
                                  dp<double>(c->wGI), dp<double>(c->wS), -1.0, 1.0, false, false, s));
     // S^ = D^{-1/2} L^{-1} S L^{-T} D^{-1/2} once C_II = L U is done
     if (enq_cii.joinable()) enq_cii.join();
@@ -613,19 +617,32 @@ int32_t factor(hkgeneo_ctx *c, hipStream_t s) {
     HKG_TRY(walloc(c, &c->wCII, c->nSq * sizeof(double)));
     HKG_HIP(hipMemsetAsync(c->wBIO.p, 0, c->nBIO * sizeof(double), s));
     HKG_HIP(hipMemsetAsync(c->wCII.p, 0, c->nSq * sizeof(double), s));
+    // [B_II | B_IG] and C_II = X D_k[I, I] X; for Delta-GenEO the eigenproblem is that of the nearby SPD
+    // problem (k = 0): C_II = X A[I, I] X and [A_II | A_IG] beside [B_II | B_IG] (the local solves and
+    // the coarse matrix keep B)
+    const bool delta = c->opt.coarse_op == HKG_COARSE_DELTA;
     HKG_TRY(extract_blocks(dsub, ns, c->max_nI, dp<int32_t>(c->rowptr), dp<int32_t>(c->colidx), dp<double>(c->Bval),
-                           dp<double>(c->wDk), dp<int32_t>(c->I_idx), dp<int32_t>(c->G_idx), dp<double>(c->winv),
-                           dp<double>(c->wBIO), dp<double>(c->wCII), s));
+                           delta ? dp<double>(c->Aval) : dp<double>(c->wDk), dp<int32_t>(c->I_idx), dp<int32_t>(c->G_idx),
+                           dp<double>(c->winv), dp<double>(c->wBIO), dp<double>(c->wCII), s));
+    if (delta) {
+        HKG_TRY(walloc(c, &c->wAIO, c->nBIO * sizeof(double)));
+        HKG_HIP(hipMemsetAsync(c->wAIO.p, 0, c->nBIO * sizeof(double), s));
+        HKG_TRY(extract_blocks(dsub, ns, c->max_nI, dp<int32_t>(c->rowptr), dp<int32_t>(c->colidx), dp<double>(c->Aval),
+                               dp<double>(c->Aval), dp<int32_t>(c->I_idx), dp<int32_t>(c->G_idx), dp<double>(c->winv),
+                               dp<double>(c->wAIO), dp<double>(c->wCII), s));
+    }
     // the local inverses (reading B_II) on the second stream, the coarse space on the caller's: the
     // two pipelines share no buffer written after this point.  The local pipeline is enqueued by a
     // helper thread (about a hundred launches) while this thread enqueues the coarse space, which
     // waits on the device several times; it is forked once coarse_space has its first launches in.
-    HKG_TRY(local_buffers(c));
+    // (a coarse-only context of a nested decomposition has no local inverses: its first-level
+    // subdomains live in a context of their own)
+    if (!c->coarse_only) HKG_TRY(local_buffers(c));
     int32_t st_local = HKG_OK;
     std::string err_local;
     std::thread enq;
     auto start_side = [&]() -> int32_t {
-        if (enq.joinable()) return HKG_OK;
+        if (enq.joinable() || c->coarse_only) return HKG_OK;
         HKG_HIP(hipEventRecord(c->ev_fork, s));
         HKG_HIP(hipStreamWaitEvent(c->s2, c->ev_fork, 0));
         enq = std::thread([&]() {
@@ -654,7 +671,7 @@ int32_t factor(hkgeneo_ctx *c, hipStream_t s) {
         set_last_error("joining the side streams of the factorisation");
         return HKG_EHIP;
     }
-    for (int i = 0; i < ns; ++i)
+    for (int i = 0; i < ns && !c->coarse_only; ++i)
         if (c->h_infoL[i]) {
             set_last_error("zero pivot in the local Dirichlet matrix of subdomain " + std::to_string(i));
             return HKG_ESINGULAR_LOCAL;

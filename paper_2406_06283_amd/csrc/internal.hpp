@@ -54,9 +54,17 @@ struct Partition {
     std::vector<int32_t> tp_ptr, tp_pos;
     // elements of D carrying at least one Gamma dof, with the Gamma-local index of each vertex
     std::vector<int32_t> band_ptr, band_elem, band_loc;   // band_loc: npe entries per band element
+    std::vector<int32_t> el_ptr, el_list;  // the (overlapping) element set of each subdomain, ascending
 };
 
-int32_t build_partition(const hkgeneo_problem *p, Partition *out, int *bad_sub);
+// sets == nullptr: subdomains from p->elem_part expanded by p->overlap layers (Def. 2.8); otherwise
+// the given element sets as they are
+int32_t build_partition(const hkgeneo_problem *p, Partition *out, int *bad_sub,
+                        const std::vector<std::vector<int32_t>> *sets = nullptr);
+// element sets of the first-level subdomains of the nested decomposition (Sec. 2.3) inside the
+// coarse subdomains of Pc, and the coarse subdomain owning each
+int32_t build_nested_sets(const hkgeneo_problem *p, const Partition &Pc, int layers,
+                          std::vector<std::vector<int32_t>> *sets, std::vector<int32_t> *owner);
 
 // Pairs (i, j) with ovdof(D_i) and dof(D_j) intersecting: the nonzero blocks of B_0 = Z^T B Z.
 struct CoarsePairs {

@@ -122,6 +122,8 @@ struct ApplyPlan {
     int64_t sum_nI;
     const int32_t *active = nullptr;           // optional per-rhs flags (FGMRES): skip inactive columns
     hipEvent_t ev0 = nullptr, ev1 = nullptr;   // optional: recorded around the local-solve kernel
+    int accumulate = 0;                        // z += M^{-1} r instead of z = M^{-1} r
+    // Minv == nullptr: the coarse correction alone (a coarse-only context of a nested decomposition)
 };
 int32_t apply_two_level(const ApplyPlan &p, const double *r, int ldr, double *z, int ldz, hipStream_t s);
 int apply_ypart_chunks(int m0);
@@ -144,7 +146,18 @@ struct GmresDev {
     int32_t *active;    // per rhs
     int32_t *iters;     // per rhs: preconditioner applications so far
     int max_iter;
+    // inner product of the Arnoldi process: the dot products read the columns of VD (V itself for
+    // the Euclidean product; D_k V, stored in DV, for the D_k inner product, dk = 1)
+    const double *VD = nullptr;
+    double *DV = nullptr;
+    int dk = 0;
 };
+// D_k-inner-product Arnoldi: DV[:, j+1] = D_k w for w = V[:, j+1] (j = -1: the cycle's first vector)
+// with D_k = A + k2 S from the two CSR value arrays, and the partial sums of w . D_k w in the slot
+// the Euclidean norm partials use; gmres_dk_reduce: out[rhs] = sqrt of their fixed-order sum
+int32_t gmres_dk_norm(const GmresDev &G, int j, const int32_t *rowptr, const int32_t *colidx, const double *Aval,
+                      const double *Sval, double k2, hipStream_t s);
+int32_t gmres_dk_reduce(const GmresDev &G, double *out, hipStream_t s);
 int32_t gmres_norm_init(const GmresDev &G, const double *r, int ldr, hipStream_t s);
 int32_t gmres_arnoldi_step(const GmresDev &G, int j, hipStream_t s);
 int32_t gmres_finish_cycle(const GmresDev &G, const int32_t *jd, double *x, int ldx, hipStream_t s);

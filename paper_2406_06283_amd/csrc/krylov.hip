@@ -85,7 +85,7 @@ __global__ __launch_bounds__(KB) void k_cgs_dots(GmresDev G, int j) {
     const double *V = G.V + (int64_t)rhs * n * (G.restart + 1);
     const double *w = V + (int64_t)(j + 1) * n;
     double *part = G.part + ((int64_t)rhs * 2 * G.nblk + blockIdx.x) * S;
-    block_dots(V, n, j + 1, w, blockIdx.x * ROWS_PER_BLOCK, part, red);
+    block_dots(G.VD + (int64_t)rhs * n * (G.restart + 1), n, j + 1, w, blockIdx.x * ROWS_PER_BLOCK, part, red);
 }
 
 // reduce pass-p partial sums (fixed order), w -= V h; pass 1 then forms the pass-2 dot products,
@@ -132,7 +132,7 @@ __global__ __launch_bounds__(KB) void k_cgs_update(GmresDev G, int j, int pass) 
     __syncthreads();
     double *pout = G.part + ((int64_t)rhs * 2 * nb + (pass == 1 ? nb : 0)) * S + (int64_t)blockIdx.x * S;
     if (pass == 1) {
-        block_dots(V, n, j + 1, w, row0, pout, red);
+        block_dots(G.VD + (int64_t)rhs * n * (G.restart + 1), n, j + 1, w, row0, pout, red);
     } else {
         double s = 0.0;
 #pragma unroll
@@ -161,10 +161,21 @@ __global__ __launch_bounds__(KB) void k_arnoldi_finish(GmresDev G, int j, double
 #pragma unroll
     for (int k = 0; k < KR; ++k) {
         int r = row0 + threadIdx.x + k * KB;
-        if (r < n) w[r] *= inv;
+        if (r < n) {
+            w[r] *= inv;
+            if (G.dk) G.DV[(int64_t)rhs * n * (m + 1) + (int64_t)(j + 1) * n + r] *= inv;
+        }
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         const double *hc = G.hcol + (int64_t)rhs * (m + 2);
+        // ||w|| before the orthogonalisation: measured for the Euclidean product; in the D_k product
+        // the norm of its D_k-orthogonal decomposition (the h_i of this column and the new norm)
+        double w0 = hc[m + 1];
+        if (G.dk) {
+            double q = hn * hn;
+            for (int i = 0; i <= j; ++i) q = fma(hc[i], hc[i], q);
+            w0 = sqrt(q);
+        }
         double *H = G.H + (int64_t)rhs * (m + 1) * m + (int64_t)j * (m + 1);
         double *cs = G.cs + (int64_t)rhs * m, *sn = G.sn + (int64_t)rhs * m, *g = G.g + (int64_t)rhs * (m + 1);
         double *sc = G.scal + (int64_t)rhs * 8;
@@ -185,7 +196,7 @@ __global__ __launch_bounds__(KB) void k_arnoldi_finish(GmresDev G, int j, double
         g[j] = c * g[j];
         sc[2] = fabs(g[j + 1]);
         const int conv = fabs(g[j + 1]) <= tol_abs_scale * sc[1];
-        const int brk = hn <= 1e-14 * hc[m + 1];
+        const int brk = hn <= 1e-14 * w0;
         const int sing = d == 0.0;
         const int it = ++G.iters[rhs];
         if (conv || brk || sing || j + 1 == m || it >= G.max_iter) {
@@ -199,12 +210,17 @@ __global__ __launch_bounds__(KB) void k_arnoldi_finish(GmresDev G, int j, double
     }
 }
 
-int32_t gmres_arnoldi_step(const GmresDev &G, int j, double rtol, hipStream_t s) {
+__global__ void k_dk_norm(GmresDev G, int j, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
+                          const double *__restrict__ Aval, const double *__restrict__ Sval, double k2);
+
+int32_t gmres_arnoldi_step(const GmresDev &G, int j, double rtol, hipStream_t s, const int32_t *rowptr,
+                           const int32_t *colidx, const double *Aval, const double *Sval, double k2) {
     const dim3 grid(G.nblk, G.nrhs);
     const size_t red_bytes = (size_t)4 * (G.restart + 2) * sizeof(double);
     hipLaunchKernelGGL(k_cgs_dots, grid, dim3(KB), red_bytes, s, G, j);
     hipLaunchKernelGGL(k_cgs_update, grid, dim3(KB), red_bytes + (G.restart + 2) * sizeof(double), s, G, j, 1);
     hipLaunchKernelGGL(k_cgs_update, grid, dim3(KB), red_bytes + (G.restart + 2) * sizeof(double), s, G, j, 2);
+    if (G.dk) hipLaunchKernelGGL(k_dk_norm, grid, dim3(KB), 0, s, G, j, rowptr, colidx, Aval, Sval, k2);
     hipLaunchKernelGGL(k_arnoldi_finish, grid, dim3(KB), 0, s, G, j, rtol);
     HKG_HIP(hipGetLastError());
     return HKG_OK;
@@ -225,7 +241,10 @@ __global__ __launch_bounds__(KB) void k_cycle_start(GmresDev G, const double *__
 #pragma unroll
     for (int k = 0; k < KR; ++k) {
         int r = row0 + threadIdx.x + k * KB;
-        if (r < n) V[r] *= inv;
+        if (r < n) {
+            V[r] *= inv;
+            if (G.dk && want[rhs]) G.DV[(int64_t)rhs * n * (m + 1) + r] *= inv;
+        }
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         double *g = G.g + (int64_t)rhs * (m + 1);
@@ -246,9 +265,10 @@ int32_t gmres_cycle_start(const GmresDev &G, const double *rnorm, double rtol, c
     return HKG_OK;
 }
 
-// y = R^{-1} g on the jd x jd rotated Hessenberg (one thread per rhs), then x += Zk y
+// y = R^{-1} g on the jd x jd rotated Hessenberg (one thread per rhs), then x += X y with X the
+// preconditioned directions Zk (flexible, right preconditioning) or the basis V (left preconditioning)
 __global__ __launch_bounds__(KB) void k_cycle_update(GmresDev G, double *__restrict__ x, int ldx,
-                                                     double *__restrict__ ybuf) {
+                                                     const double *__restrict__ Xb, int64_t xstride) {
     extern __shared__ double y[];
     const int rhs = blockIdx.y;
     const int n = G.n, m = G.restart;
@@ -264,7 +284,7 @@ __global__ __launch_bounds__(KB) void k_cycle_update(GmresDev G, double *__restr
         }
     }
     __syncthreads();
-    const double *Zk = G.Zk + (int64_t)rhs * n * m;
+    const double *Zk = Xb + (int64_t)rhs * xstride;
     const int row0 = blockIdx.x * ROWS_PER_BLOCK;
 #pragma unroll
     for (int k = 0; k < KR; ++k) {
@@ -275,12 +295,63 @@ __global__ __launch_bounds__(KB) void k_cycle_update(GmresDev G, double *__restr
             x[(int64_t)rhs * ldx + r] = s;
         }
     }
-    (void)ybuf;
 }
 
 int32_t gmres_cycle_update(const GmresDev &G, double *x, int ldx, hipStream_t s) {
+    const double *X = G.dk ? G.V : G.Zk;
+    const int64_t stride = (int64_t)G.n * (G.dk ? G.restart + 1 : G.restart);
     hipLaunchKernelGGL(k_cycle_update, dim3(G.nblk, G.nrhs), dim3(KB), (size_t)(G.restart + 1) * sizeof(double), s, G, x,
-                       ldx, (double *)nullptr);
+                       ldx, X, stride);
+    HKG_HIP(hipGetLastError());
+    return HKG_OK;
+}
+
+// D_k w for w = V[:, j+1] (D_k = A + k2 S, one thread per row, nonzeros in index order) into
+// DV[:, j+1], and the block's partial sum of w . D_k w (slot 0 of the pass-2 partials)
+__global__ __launch_bounds__(KB) void k_dk_norm(GmresDev G, int j, const int32_t *__restrict__ rowptr,
+                                                const int32_t *__restrict__ colidx, const double *__restrict__ Aval,
+                                                const double *__restrict__ Sval, double k2) {
+    __shared__ double red[KB / 64];
+    const int rhs = blockIdx.y;
+    if (j >= 0 && !G.active[rhs]) return;
+    const int n = G.n, m = G.restart, S = m + 2;
+    const double *w = G.V + (int64_t)rhs * n * (m + 1) + (int64_t)(j + 1) * n;
+    double *dw = G.DV + (int64_t)rhs * n * (m + 1) + (int64_t)(j + 1) * n;
+    const int i = blockIdx.x * ROWS_PER_BLOCK + threadIdx.x;
+    double s = 0.0;
+    if (i < n) {
+        double d = 0.0;
+        for (int t = rowptr[i]; t < rowptr[i + 1]; ++t) d = fma(fma(k2, Sval[t], Aval[t]), w[colidx[t]], d);
+        dw[i] = d;
+        s = w[i] * d;
+    }
+    s = wsum(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        G.part[((int64_t)rhs * 2 * G.nblk + blockIdx.x) * S] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ void k_dk_reduce(GmresDev G, double *__restrict__ out) {
+    const int rhs = blockIdx.x;
+    if (threadIdx.x == 0) {
+        const int S = G.restart + 2;
+        const double *pin = G.part + (int64_t)rhs * 2 * G.nblk * S;
+        double s = 0.0;
+        for (int b = 0; b < G.nblk; ++b) s += pin[(int64_t)b * S];
+        out[rhs] = sqrt(fmax(s, 0.0));
+    }
+}
+
+int32_t gmres_dk_norm(const GmresDev &G, int j, const int32_t *rowptr, const int32_t *colidx, const double *Aval,
+                      const double *Sval, double k2, hipStream_t s) {
+    hipLaunchKernelGGL(k_dk_norm, dim3(G.nblk, G.nrhs), dim3(KB), 0, s, G, j, rowptr, colidx, Aval, Sval, k2);
+    HKG_HIP(hipGetLastError());
+    return HKG_OK;
+}
+
+int32_t gmres_dk_reduce(const GmresDev &G, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_dk_reduce, dim3(G.nrhs), dim3(64), 0, s, G, out);
     HKG_HIP(hipGetLastError());
     return HKG_OK;
 }

@@ -17,8 +17,9 @@
 
 namespace hkg {
 
-int32_t build_partition(const hkgeneo_problem *p, Partition *out, int *bad_sub) {
-    const int ne = p->n_elem, nv = p->n_vert, nd = p->n_dof, ns = p->n_sub;
+int32_t build_partition(const hkgeneo_problem *p, Partition *out, int *bad_sub,
+                        const std::vector<std::vector<int32_t>> *sets) {
+    const int ne = p->n_elem, nv = p->n_vert, nd = p->n_dof, ns = sets ? (int)sets->size() : p->n_sub;
     const int npe = (p->dim == 2) ? (p->elem_type == HKG_P1 ? 3 : 4) : (p->elem_type == HKG_P1 ? 4 : 8);
     Partition &P = *out;
     P = Partition();
@@ -44,13 +45,22 @@ int32_t build_partition(const hkgeneo_problem *p, Partition *out, int *bad_sub) 
     for (int v = 0; v < nv; ++v)
         if (p->vert_dof[v] < -1 || p->vert_dof[v] >= nd) return HKG_EINVAL;
 
-    // elements of each block of the non-overlapping partition
+    // elements of each block of the non-overlapping partition (or the given element sets, which are
+    // taken as they are: no layers added)
     std::vector<std::vector<int32_t>> block(ns);
-    for (int e = 0; e < ne; ++e) {
-        int s = p->elem_part[e];
-        if (s < 0 || s >= ns) return HKG_EINVAL;
-        block[s].push_back(e);
+    if (sets) {
+        block = *sets;
+        for (auto &b : block)
+            for (int e : b)
+                if (e < 0 || e >= ne) return HKG_EINVAL;
+    } else {
+        for (int e = 0; e < ne; ++e) {
+            int s = p->elem_part[e];
+            if (s < 0 || s >= ns) return HKG_EINVAL;
+            block[s].push_back(e);
+        }
     }
+    P.el_ptr.assign(ns + 1, 0);
 
     std::vector<uint8_t> inD(ne, 0);
     std::vector<int32_t> vmark(nv, -1);         // stamp per vertex
@@ -65,10 +75,11 @@ int32_t build_partition(const hkgeneo_problem *p, Partition *out, int *bad_sub) 
     int stamp = 0;
 
     for (int s = 0; s < ns; ++s) {
-        if (p->overlap[s] < 0) return HKG_EINVAL;
+        const int layers = sets ? 0 : p->overlap[s];
+        if (layers < 0) return HKG_EINVAL;
         std::vector<int32_t> elems = block[s];
         for (int e : elems) inD[e] = 1;
-        for (int layer = 0; layer < p->overlap[s]; ++layer) {
+        for (int layer = 0; layer < layers; ++layer) {
             // interior vertices of the current elements: their basis functions meet D'
             ++stamp;
             std::vector<int32_t> verts;
@@ -114,6 +125,12 @@ int32_t build_partition(const hkgeneo_problem *p, Partition *out, int *bad_sub) 
         std::sort(dofs.begin(), dofs.end());
         std::sort(gam.begin(), gam.end());
         if (dofs.empty()) { *bad_sub = s; return HKG_EINVAL; }
+        {
+            std::vector<int32_t> sorted(elems);
+            std::sort(sorted.begin(), sorted.end());
+            P.el_list.insert(P.el_list.end(), sorted.begin(), sorted.end());
+            P.el_ptr[s + 1] = (int32_t)P.el_list.size();
+        }
         P.nI[s] = (int32_t)dofs.size();
         P.nG[s] = (int32_t)gam.size();
         P.offI[s + 1] = P.offI[s] + P.nI[s];
@@ -157,6 +174,89 @@ int32_t build_partition(const hkgeneo_problem *p, Partition *out, int *bad_sub) 
             }
     }
     return HKG_OK;
+}
+
+// First-level subdomains of the nested decomposition (Sec. 2.3): the elements of each overlapping
+// coarse subdomain are split by the fine element partition into pieces, ordered by fine block id,
+// and each piece is expanded by `layers` layers of Def. 2.8 restricted to the coarse subdomain, so
+// that the pieces of a coarse subdomain cover it.  Pieces without an interior dof are dropped.
+int32_t build_nested_sets(const hkgeneo_problem *p, const Partition &Pc, int layers,
+                          std::vector<std::vector<int32_t>> *sets, std::vector<int32_t> *owner) {
+    const int ne = p->n_elem, nv = p->n_vert;
+    const int npe = Pc.npe;
+    std::vector<int32_t> v_ptr(nv + 1, 0), v_el((size_t)ne * npe);
+    for (int e = 0; e < ne; ++e)
+        for (int a = 0; a < npe; ++a) v_ptr[p->elem_vert[(size_t)e * npe + a] + 1]++;
+    for (int v = 0; v < nv; ++v) v_ptr[v + 1] += v_ptr[v];
+    {
+        std::vector<int32_t> fill(v_ptr.begin(), v_ptr.end() - 1);
+        for (int e = 0; e < ne; ++e)
+            for (int a = 0; a < npe; ++a) v_el[fill[p->elem_vert[(size_t)e * npe + a]]++] = e;
+    }
+    sets->clear();
+    owner->clear();
+    std::vector<uint8_t> inC(ne, 0), inF(ne, 0);
+    std::vector<int32_t> vmark(nv, -1);
+    int stamp = 0;
+    for (int i = 0; i < Pc.n_sub; ++i) {
+        const int32_t *ce = Pc.el_list.data() + Pc.el_ptr[i];
+        const int nce = Pc.el_ptr[i + 1] - Pc.el_ptr[i];
+        for (int q = 0; q < nce; ++q) inC[ce[q]] = 1;
+        std::vector<int32_t> ids;
+        for (int q = 0; q < nce; ++q) {
+            const int f = p->fine_part[ce[q]];
+            if (f < 0) return HKG_EINVAL;
+            ids.push_back(f);
+        }
+        std::sort(ids.begin(), ids.end());
+        ids.erase(std::unique(ids.begin(), ids.end()), ids.end());
+        for (int fid : ids) {
+            std::vector<int32_t> elems;
+            for (int q = 0; q < nce; ++q)
+                if (p->fine_part[ce[q]] == fid) elems.push_back(ce[q]);
+            for (int e : elems) inF[e] = 1;
+            for (int layer = 0; layer < layers; ++layer) {
+                ++stamp;
+                std::vector<int32_t> verts;
+                for (int e : elems)
+                    for (int a = 0; a < npe; ++a) {
+                        const int v = p->elem_vert[(size_t)e * npe + a];
+                        if (p->vert_dof[v] >= 0 && vmark[v] != stamp) {
+                            vmark[v] = stamp;
+                            verts.push_back(v);
+                        }
+                    }
+                for (int v : verts)
+                    for (int t = v_ptr[v]; t < v_ptr[v + 1]; ++t) {
+                        const int e = v_el[t];
+                        if (inC[e] && !inF[e]) {
+                            inF[e] = 1;
+                            elems.push_back(e);
+                        }
+                    }
+            }
+            // keep the piece if some interior vertex has all its elements in it
+            bool has_dof = false;
+            for (int e : elems) {
+                for (int a = 0; a < npe && !has_dof; ++a) {
+                    const int v = p->elem_vert[(size_t)e * npe + a];
+                    if (p->vert_dof[v] < 0) continue;
+                    bool inside = true;
+                    for (int t = v_ptr[v]; t < v_ptr[v + 1]; ++t)
+                        if (!inF[v_el[t]]) { inside = false; break; }
+                    has_dof = inside;
+                }
+                if (has_dof) break;
+            }
+            for (int e : elems) inF[e] = 0;
+            if (!has_dof) continue;
+            std::sort(elems.begin(), elems.end());
+            sets->push_back(std::move(elems));
+            owner->push_back(i);
+        }
+        for (int q = 0; q < nce; ++q) inC[ce[q]] = 0;
+    }
+    return sets->empty() ? HKG_EINVAL : HKG_OK;
 }
 
 void build_coarse_pairs(const Partition &P, CoarsePairs *out) {

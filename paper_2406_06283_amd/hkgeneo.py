@@ -31,6 +31,10 @@ HKG_EIG_THRESHOLD = 0
 HKG_EIG_FIXED = 1
 HKG_PROLONG_AS = 0
 HKG_PROLONG_POU = 1
+HKG_COARSE_HK = 0
+HKG_COARSE_DELTA = 1
+HKG_KRYLOV_RIGHT = 0
+HKG_KRYLOV_LEFT_DK = 1
 HKG_APPLY_NOALLOC_MAX_BYTES = 64 << 20     # size of the allocation-free scratch array per GPU
 
 _i32p = POINTER(c_int32)
@@ -42,14 +46,15 @@ class hkgeneo_problem(ctypes.Structure):
                 ("n_dof", c_int32), ("nnz", c_int32), ("elem_vert", _i32p), ("vert_dof", _i32p),
                 ("elem_K", _f64p), ("elem_M", _f64p), ("row_ptr", _i32p), ("col_idx", _i32p),
                 ("A_val", _f64p), ("S_val", _f64p), ("elem_part", _i32p), ("n_sub", c_int32),
-                ("overlap", _i32p), ("k", c_double)]
+                ("overlap", _i32p), ("k", c_double), ("fine_part", _i32p), ("fine_overlap", c_int32)]
 
 
 class hkgeneo_options(ctypes.Structure):
     _fields_ = [("eig_mode", c_int32), ("tau", c_double), ("nev", c_int32), ("cluster_rtol", c_double),
                 ("max_eig_per_sub", c_int32), ("local_prec", c_int32), ("prolong", c_int32),
                 ("two_level", c_int32), ("restart", c_int32), ("max_iter", c_int32), ("rtol", c_double),
-                ("keep_workspace", c_int32), ("local_factor_prec", c_int32)]
+                ("keep_workspace", c_int32), ("local_factor_prec", c_int32), ("krylov", c_int32),
+                ("coarse_op", c_int32)]
 
 
 class hkgeneo_rhs_info(ctypes.Structure):
@@ -84,6 +89,7 @@ SIGNATURES = {
     "hkgeneo_query": (c_int32, [c_void_p, POINTER(hkgeneo_stats)]),
     "hkgeneo_query_subdomains": (c_int32, [c_void_p, _i32p, _i32p, _i32p]),
     "hkgeneo_query_index_sets": (c_int32, [c_void_p, c_int32, _i32p, _i32p, _i32p]),
+    "hkgeneo_query_fine": (c_int32, [c_void_p, _i32p, _i32p, _i32p, _i32p]),
     "hkgeneo_query_eigen": (c_int32, [c_void_p, c_int32, _f64p, c_int32, _f64p]),
     "hkgeneo_query_coarse_matrix": (c_int32, [c_void_p, _f64p]),
     "hkgeneo_partition": (c_int32, [POINTER(hkgeneo_problem), _i32p, _i32p, _i32p, _i32p, _i32p, _i32p]),
@@ -173,6 +179,9 @@ class _ProblemView:
             elem_part=np.ascontiguousarray(p.elem_part, dtype=np.int32),
             overlap=np.ascontiguousarray(p.overlap, dtype=np.int32),
         )
+        fine = getattr(p, "fine_part", None)
+        if fine is not None:
+            self.keep["fine_part"] = np.ascontiguousarray(fine, dtype=np.int32)
         k = self.keep
         self.c = hkgeneo_problem(
             dim=p.dim, elem_type=p.elem_type, n_vert=p.n_vert, n_elem=p.n_elem, n_dof=p.n_dof, nnz=p.nnz,
@@ -181,7 +190,9 @@ class _ProblemView:
             row_ptr=_ptr(k["row_ptr"], c_int32), col_idx=_ptr(k["col_idx"], c_int32),
             A_val=_ptr(k["A_val"], c_double), S_val=_ptr(k["S_val"], c_double),
             elem_part=_ptr(k["elem_part"], c_int32), n_sub=p.n_sub, overlap=_ptr(k["overlap"], c_int32),
-            k=float(p.k))
+            k=float(p.k),
+            fine_part=_ptr(k["fine_part"], c_int32) if "fine_part" in k else None,
+            fine_overlap=int(getattr(p, "fine_overlap", 0)))
 
 
 def partition(problem):
@@ -303,6 +314,18 @@ class Solver:
         _check(self.lib.hkgeneo_query_subdomains(self.handle, _ptr(nI, c_int32), _ptr(nG, c_int32), _ptr(m, c_int32)),
                "hkgeneo_query_subdomains")
         return nI, nG, m
+
+    def fine(self):
+        """(owner coarse subdomain per fine subdomain, |dof| per fine subdomain, Lambda over them)."""
+        n = c_int32()
+        lam = c_int32()
+        _check(self.lib.hkgeneo_query_fine(self.handle, ctypes.byref(n), None, None, ctypes.byref(lam)),
+               "hkgeneo_query_fine")
+        nI = np.zeros(n.value, np.int32)
+        own = np.zeros(n.value, np.int32)
+        _check(self.lib.hkgeneo_query_fine(self.handle, ctypes.byref(n), _ptr(nI, c_int32), _ptr(own, c_int32),
+                                           ctypes.byref(lam)), "hkgeneo_query_fine")
+        return own, nI, lam.value
 
     def index_sets(self, sub):
         nI, nG, _ = self.subdomains()

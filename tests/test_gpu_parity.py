@@ -247,3 +247,99 @@ def test_fgmres_pou_h32_k10_matches_oracle():
 @pytest.mark.slow
 def test_fgmres_pou_h128_k40_matches_oracle():
     _pou_fgmres_case(H128_K40)
+
+
+# ------------------------------------------------------------------------------------------------
+# GMRES on the left-preconditioned system (eq. 2.24) in the D_k inner product (Theorem 3.1)
+# ------------------------------------------------------------------------------------------------
+DK_CASES = [
+    ("h32_k10", None),
+    ("p1_n24_s3_lognormal", dict(N=24, k=9.0, s=3, overlap=2, coef="lognormal", seed=2, rhs="normal", nrhs=2)),
+    ("q1_3d_n8_s2", dict(N=8, dim=3, elem_type=pb.Q1, k=4.0, s=2, overlap=1, coef="cells", seed=1, n_cells=3)),
+]
+
+
+@pytest.mark.parametrize("name,pkw", DK_CASES, ids=[c[0] for c in DK_CASES])
+def test_gmres_left_dk_matches_oracle(name, pkw):
+    _say(f"[gmres D_k] {name}")
+    if pkw is None:
+        p, nev, restart = H32_K10.problem(), 10, 50
+    else:
+        pkw = dict(pkw)
+        N = pkw.pop("N")
+        p, nev, restart = pb.make_problem(N, **pkw), 4, 30
+    M = _oracle(p, eig_mode=local.EIG_FIXED, nev=nev)
+    f = torch.from_numpy(np.ascontiguousarray(p.f)).to(DEV)
+    opts = H.default_options(eig_mode=H.HKG_EIG_FIXED, nev=nev, restart=restart, krylov=H.HKG_KRYLOV_LEFT_DK)
+    with H.Solver(p, opts) as S:
+        u, info, st = S.solve(f)
+        torch.cuda.synchronize()
+        u = u.cpu().numpy()
+        with pytest.raises(H.HkgError) as e:       # the batched engine runs flexible GMRES only
+            H.Batch([S], [p.f.shape[0]])
+        assert e.value.status == H.HKG_EINVAL
+    with H.Solver(p, H.default_options(eig_mode=H.HKG_EIG_FIXED, nev=nev, restart=restart, local_prec=32,
+                                       krylov=H.HKG_KRYLOV_LEFT_DK)) as S32:
+        u32, info32, st32 = S32.solve(f)
+        torch.cuda.synchronize()
+    assert st == H.HKG_OK and st32 == H.HKG_OK
+    for r in range(p.f.shape[0]):
+        x, oinfo = fgmres.solve_left_dk(p, M, f=p.f[r], restart=restart)
+        assert oinfo["converged"] and info[r]["converged"] and info32[r]["converged"]
+        assert abs(info[r]["iters"] - oinfo["iters"]) <= 2, (r, info[r]["iters"], oinfo["iters"])
+        # float32 local inverses make M^{-1} linear only to float32 rounding; GMRES on the left-preconditioned
+        # system (not flexible) still reaches the bar, with more iterations near resonance (h = 1/32, k = 10:
+        # 57 against 26), so only convergence is required of it
+        assert info32[r]["relres_est"] <= 1e-8
+        err = np.linalg.norm(u[r] - x) / np.linalg.norm(x)
+        _say(f"  rhs {r}: iterations oracle {oinfo['iters']} gpu {info[r]['iters']} mixed {info32[r]['iters']}; "
+             f"solution vs oracle {err:.2e}; true residual {info[r]['relres_true']:.2e} "
+             f"(oracle {oinfo['relres_true']:.2e})")
+        assert err <= 1e-8
+        assert abs(info[r]["relres_true"] - oinfo["relres_true"]) <= 1e-3 * oinfo["relres_true"] + 1e-14
+
+
+# ------------------------------------------------------------------------------------------------
+# Delta-GenEO coarse space (the eigenproblem of the nearby SPD problem, k = 0; B_0 keeps B)
+# ------------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("name,pkw,okw", CASES, ids=[c[0] for c in CASES])
+def test_apply_delta_geneo_matches_oracle(name, pkw, okw):
+    _say(f"[apply delta] {name}")
+    pkw = dict(pkw)
+    N = pkw.pop("N")
+    p = pb.make_problem(N, **pkw)
+    M = _oracle(p, eig_mode=local.EIG_FIXED, coarse_op=schwarz.COARSE_DELTA, **okw)
+    R = np.random.default_rng(13).standard_normal((2, p.n_dof))
+    with H.Solver(p, H.default_options(eig_mode=H.HKG_EIG_FIXED, coarse_op=H.HKG_COARSE_DELTA, **okw)) as S:
+        assert S.stats()["m0"] == M.m0 and list(S.subdomains()[2]) == M.m
+        for i in (0, p.n_sub - 1):
+            lam, _ = S.eigen(i)
+            assert np.abs(lam - M.eigvals[i][:lam.size]).max() <= 1e-10 * np.abs(M.eigvals[i]).max()
+        Zg = _gpu_apply(S, R)
+    Zo = np.stack([M.apply(r) for r in R])
+    scale = np.abs(Zo).max()
+    assert np.abs(Zg - Zo).max() <= 1e-10 * scale, np.abs(Zg - Zo).max() / scale
+
+
+@pytest.mark.parametrize("wl", [H32_K10, H128_K40], ids=["h32_k10", "h128_k40"])
+def test_fgmres_delta_geneo_matches_oracle(wl):
+    _say(f"[fgmres delta] {wl.name}")
+    p = wl.problem()
+    mode = dict(eig_mode=wl.eig_mode, tau=wl.tau, nev=wl.nev)
+    M = _oracle(p, coarse_op=schwarz.COARSE_DELTA, **mode)
+    x, oinfo = fgmres.solve(p, M, restart=wl.restart)
+    f = torch.from_numpy(p.f).to(DEV)
+    with H.Solver(p, H.options_for(wl, coarse_op=H.HKG_COARSE_DELTA, local_prec=32)) as S, H.Batch([S], [1]) as B:
+        assert list(S.subdomains()[2]) == M.m and S.stats()["m0"] == M.m0
+        (u,), (info,), st = B.solve([f])
+        torch.cuda.synchronize()
+        u = u.cpu().numpy()[0]
+    assert st == H.HKG_OK and info[0]["converged"]
+    assert abs(info[0]["iters"] - oinfo["iters"]) <= 2, (info[0]["iters"], oinfo["iters"])
+    assert np.linalg.norm(p.f[0] - M.B @ u) / np.linalg.norm(p.f[0]) <= 1e-8
+    err = np.linalg.norm(u - x) / np.linalg.norm(x)
+    hk = _oracle(p, **mode)
+    _, hinfo = fgmres.solve(p, hk, restart=wl.restart)
+    _say(f"  iterations: Delta-GenEO oracle {oinfo['iters']} gpu {info[0]['iters']} (H_k-GenEO oracle "
+         f"{hinfo['iters']}); m0 {M.m0} (H_k {hk.m0}); solution vs oracle {err:.2e}")
+    assert err <= 1e-8

@@ -67,7 +67,7 @@ def _setup_status(p, **opt):
     return lib.hkgeneo_setup(ctypes.byref(pv.c), ctypes.byref(o), None, ctypes.byref(h)), h
 
 
-@pytest.mark.parametrize("bad", ["overlap0", "negative_k", "local_prec", "factor32", "restart", "bad_part",
+@pytest.mark.parametrize("bad", ["overlap0", "negative_k", "local_prec", "factor32", "krylov", "coarse_op", "restart", "bad_part",
                                  "unsorted_csr"])
 def test_setup_validates_before_device_work(bad):
     p = pb.make_problem(8, k=3.0, s=2, overlap=1)
@@ -81,6 +81,10 @@ def test_setup_validates_before_device_work(bad):
     elif bad == "factor32":          # the float32 LU is not offered
         opt["local_prec"] = 32
         opt["local_factor_prec"] = 32
+    elif bad == "krylov":
+        opt["krylov"] = 2
+    elif bad == "coarse_op":
+        opt["coarse_op"] = 7
     elif bad == "restart":
         opt["restart"] = 0
     elif bad == "bad_part":

@@ -296,6 +296,50 @@ def oracle_error(r, x):
     return float(np.linalg.norm(r["u"] - x) / np.linalg.norm(x))
 
 
+def run_next_rows(args, w):
+    """The widened rows on the default workload, single-problem path, float64 local inverses:
+    the nested decomposition (fine element blocks of half the coarse width, one fine overlap layer),
+    GMRES on the left-preconditioned system in the D_k inner product, and the Delta-GenEO coarse
+    space.  Per row: steps/s of (factor + solve), iterations, true residual, solve-only p50."""
+    import torch
+    from paper_2406_06283_amd import hkgeneo as H
+    dev = torch.device("cuda:0")
+    fine = 2 * w.s
+    rows = {
+        "nested": (w.problem(seed=0, fine=fine, fine_overlap=1), {},
+                   f"nested decomposition: coarse {w.s}^{w.dim} subdomains (eigenproblems, B_0), fine pieces cut "
+                   f"by {fine}^{w.dim} element blocks inside each and grown by 1 layer (local solves)"),
+        "dk_gmres": (None, dict(krylov=H.HKG_KRYLOV_LEFT_DK),
+                     "GMRES on M^-1 B u = M^-1 f in the D_k inner product, stopped on the preconditioned D_k norm"),
+        "delta_geneo": (None, dict(coarse_op=H.HKG_COARSE_DELTA),
+                        "Delta-GenEO coarse space (k = 0 eigenproblem, same tau), B_0 at the actual k"),
+    }
+    out = {}
+    for name, (prob, kw, what) in rows.items():
+        progress(f"next row {name}")
+        p = prob if prob is not None else w.problem(seed=0)
+        f = torch.from_numpy(p.f).to(dev)
+        S = H.Solver(p, H.options_for(w, keep_workspace=1, **kw))
+
+        def solve():
+            u, info, _ = S.solve(f)
+            return info[0], u
+        r = timed_steps(S, solve, args.steps, args.warmup)
+        r["lat"] = latency(lambda: S.solve(f), max(args.steps, args.lat_reps // 2))
+        st = S.stats()
+        own, nI, lam = S.fine()
+        _, info, _ = S.solve(f)
+        out[name] = {"what": what, "steps_per_s": round(args.steps / r["total_s"], 3),
+                     "factor_ms_p50": round(pct(r["fac_ms"], 50), 3), "solve_ms_p50": round(pct(r["sol_ms"], 50), 3),
+                     "solve_only_p50_ms": round(pct(r["lat"], 50), 3), "iters": int(np.median(r["iters"])),
+                     "relres_true_max": max(r["relres"]), "relres_est": info[0]["relres_est"],
+                     "converged": bool(info[0]["converged"]), "m0": int(st["m0"]),
+                     "local_subdomains": int(len(nI)), "mean_local_dofs": round(float(np.mean(nI)), 1),
+                     "lambda": int(lam), "device_mb": round(st["device_bytes"] / 2 ** 20, 1)}
+        S.close()
+    return out
+
+
 def side_workload(args, name):
     """The mixed form of another named workload (steps/s, iterations, solve-only latency)."""
     import argparse as _ap
@@ -369,6 +413,8 @@ def main_default(args):
                                "bytes_per_iteration": ibytes, "iterations": iters, "j_mean": j_mean,
                                "solve_only_p50_ms": round(solve_s * 1e3, 3)},
     }
+    if not args.no_next_rows:
+        line["next_rows"] = run_next_rows(args, w)
     for extra in [x for x in args.extra_workloads.split(",") if x and x != w.name]:
         progress(f"extra workload {extra}")
         line.setdefault("other_workloads", {})[extra] = side_workload(args, extra)
@@ -473,9 +519,10 @@ def main_serve(args):
     def make_solver(key, stream):
         return H.Solver(problems[key], H.default_options(**serve_options(key)), stream=stream)
 
-    def estimate(key):
-        o = serve_options(key)
-        return serve.footprint_estimate(problems[key], o["local_prec"], max(o["nev"], 12))
+    cap = H.default_options().max_eig_per_sub
+
+    def estimate(key):      # an upper bound: no subdomain keeps more than max_eig_per_sub vectors
+        return serve.footprint_estimate(problems[key], serve_options(key)["local_prec"], cap)
 
     from paper_2406_06283_amd.configs import MIX_RESTART
     kw = dict(ctx_budget=96 << 30, workspace_budget=48 << 30, max_requests=64, max_nrhs=8, restart=MIX_RESTART)
@@ -523,6 +570,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1)
     ap.add_argument("--requests", type=int, default=200)
     ap.add_argument("--lat-reps", type=int, default=20)
+    ap.add_argument("--no-next-rows", action="store_true",
+                    help="skip the nested / D_k GMRES / Delta-GenEO rows of the default workload")
     ap.add_argument("--extra-workloads", default="p1_h128_k40_8x8",
                     help="comma-separated named workloads whose mixed form is reported beside the line")
     ap.add_argument("--forms", default="plain,fp64,mixed,pou",

@@ -182,6 +182,7 @@ typedef struct {
     int32_t bad_sub;          /* -1 for a context that was set up (failures return no context)  */
     int64_t device_bytes;     /* device memory held by the context                             */
     double setup_ms;          /* wall time of hkgeneo_setup                                    */
+    int64_t peak_device_bytes; /* high-water mark of device_bytes, setup/factor workspace included */
 } hkgeneo_stats;
 
 /* Fill `opt` with the defaults documented above. */

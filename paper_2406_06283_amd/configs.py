@@ -45,10 +45,11 @@ class Workload:
     description: str
     restart: int = 50
 
-    def problem(self, seed: int = 0, nrhs: int | None = None) -> pb.Problem:
+    def problem(self, seed: int = 0, nrhs: int | None = None, fine=None, fine_overlap: int = 1) -> pb.Problem:
         return pb.make_problem(self.N, dim=self.dim, elem_type=self.elem_type, k=self.k, s=self.s,
                                overlap=self.overlap, coef=self.coef, seed=seed, rhs=self.rhs,
-                               nrhs=self.nrhs if nrhs is None else nrhs, name=self.name)
+                               nrhs=self.nrhs if nrhs is None else nrhs, name=self.name, fine=fine,
+                               fine_overlap=fine_overlap)
 
 
 H32_K10 = Workload(

@@ -677,6 +677,7 @@ extern "C" int32_t hkgeneo_query(const hkgeneo_ctx *c, hkgeneo_stats *out) {
     if (!c || !out) return HKG_EINVAL;
     *out = c->stats;
     out->device_bytes = c->device_bytes + (c->fine ? c->fine->device_bytes : 0);
+    out->peak_device_bytes = c->peak_device_bytes + (c->fine ? c->fine->peak_device_bytes : 0);
     return HKG_OK;
 }
 

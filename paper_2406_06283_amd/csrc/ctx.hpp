@@ -20,6 +20,7 @@ struct hkgeneo_ctx {
     std::vector<int32_t> m_host;
     std::vector<double> lam_host;         // n_sub x (max_eig_per_sub + 2)
     int64_t device_bytes = 0;
+    int64_t peak_device_bytes = 0;       // high-water mark of device_bytes (setup workspace included)
 
     // resident inputs and static descriptors (analysis phase)
     hkg::DevBuf rowptr, colidx, Aval, Sval, I_idx, G_idx, winv, wloc, tp_ptr, tp_pos, tp_sub, subs_d;

@@ -32,6 +32,7 @@ int32_t dalloc(hkgeneo_ctx *c, DevBuf *b, size_t bytes) {
     }
     b->bytes = bytes;
     c->device_bytes += (int64_t)bytes;
+    c->peak_device_bytes = std::max(c->peak_device_bytes, c->device_bytes);
     return HKG_OK;
 }
 

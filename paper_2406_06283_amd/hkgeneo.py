@@ -64,7 +64,7 @@ class hkgeneo_rhs_info(ctypes.Structure):
 class hkgeneo_stats(ctypes.Structure):
     _fields_ = [("n_dof", c_int32), ("n_sub", c_int32), ("lambda_overlap", c_int32), ("m0", c_int32),
                 ("sum_nI", c_int32), ("max_nI", c_int32), ("max_nG", c_int32), ("bad_sub", c_int32),
-                ("device_bytes", c_int64), ("setup_ms", c_double)]
+                ("device_bytes", c_int64), ("setup_ms", c_double), ("peak_device_bytes", c_int64)]
 
 
 class hkgeneo_server_stats(ctypes.Structure):

@@ -48,14 +48,18 @@ def test_serve_loop_results_equal_alone():
     def make_solver(key, stream):
         return H.Solver(problems[key], H.default_options(**OPTS), stream=stream)
 
+    cap = H.default_options(**OPTS).max_eig_per_sub
+
     def estimate(key):
-        return serve.footprint_estimate(problems[key], 32, 4)
+        return serve.footprint_estimate(problems[key], 32, cap)
 
     cache = serve.ContextCache(8 << 30)
     try:
         done, summ = serve.run_stream(reqs, make_solver, estimate, ctx_budget=8 << 30, workspace_budget=1 << 30,
                                       max_requests=4, max_nrhs=8, cache=cache)
         assert summ["converged"] and summ["setups"] == 3 and summ["misses"] >= 3 and summ["hits"] >= 1
+        # the reservation made at dispatch bounds every context's peak device bytes
+        assert summ["reservation_overshoots"] == 0 and summ["over_budget_inserts"] == 0
         for r in done:
             assert all(i["relres_true"] <= 1e-8 for i in r.info)
             S = cache.acquire(r.key)

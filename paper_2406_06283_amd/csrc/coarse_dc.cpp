@@ -5,14 +5,16 @@
 // subdomains into consecutive runs of w gives level blocks such that B_0 couples each level block
 // only with its two neighbours: B_0 is block tridiagonal in them.  Its inverse is then built without
 // a factorisation of the whole matrix:
-//   * leaves: the inverse of every diagonal block (batched LU with partial pivoting inside the block,
-//     then the two triangular solves against P I);
+//   * leaves: the inverse of every diagonal block (batched Gauss-Jordan with partial pivoting inside
+//     the block, one launch; blocks beyond its size limit take an LU with partial pivoting and the two
+//     triangular solves against P I);
 //   * merges, level by level, of two adjacent ranges A (rows a, last level block l) and D (rows d,
 //     first level block f), coupled only by U = B_0[l, f] and L = B_0[f, l]:
 //       Q = L (A^-1)_ll U,   S = D - E_f Q E_f^T  (Schur complement of A),
 //       S^-1 = D^-1 + D^-1 E_f (I - Q G)^-1 Q E_f^T D^-1,   G = (D^-1)_ff,
 //       [A^-1 + X S_ff Y,  -X S^-1_(f,:) ;  -S^-1_(:,f) Y,  S^-1],  X = A^-1 E_l U,  Y = L E_l^T A^-1,
-//     where the only inverse formed is that of the small matrix I - Q G (LU with partial pivoting).
+//     where the only inverse formed is that of the small matrix I - Q G (Gauss-Jordan or LU with
+//     partial pivoting, as for the leaves).
 // Every step is a batched launch over the merges of a level, so the serial chain is
 // log2(#level blocks) small factorisations instead of one panel per 32 columns of B_0.  Pivoting
 // stays inside the blocks: when any of the small factorisations meets a pivot that counts as zero,
@@ -78,7 +80,7 @@ int32_t coarse_inverse_dc(hkgeneo_ctx *c, hipStream_t s, bool *done) {
     std::vector<DMat> leafLU(K), leafX(K);
     std::vector<int64_t> leafPoff(K);
     std::vector<TriJob> leafTri(K);
-    std::vector<CopyJob> leafCopy(K);
+    std::vector<CopyJob> leafCopy(K), leafGJ(K);
     int64_t arenaLeaf = 0, pivLeaf = 0;
     for (int k = 0; k < K; ++k) {
         const int n = (int)(b1v[k] - b0v[k]);
@@ -88,6 +90,7 @@ int32_t coarse_inverse_dc(hkgeneo_ctx *c, hipStream_t s, bool *done) {
         leafPoff[k] = pivLeaf;
         leafTri[k] = {arenaLeaf, d, n, n, n, (int32_t)m0};
         leafCopy[k] = {d, arenaLeaf, n, n, (int32_t)m0, n};
+        leafGJ[k] = {d, d, n, n, (int32_t)m0, (int32_t)m0};
         arenaLeaf += (int64_t)n * n;
         pivLeaf += n;
     }
@@ -96,7 +99,7 @@ int32_t coarse_inverse_dc(hkgeneo_ctx *c, hipStream_t s, bool *done) {
         int nm = 0, maxf = 0, maxa = 0, maxd = 0, maxl = 0;
         int64_t maxcopy = 0;
         size_t gTq, gQ, gW, gK, gPK, gUpd, gXa, gYa, gXaS, gAD, gDA, gAA;   // GemmJob sections
-        size_t mW, mWinv, poff, tri, cp;                                   // DMat, poff, TriJob, CopyJob
+        size_t mW, mWinv, poff, tri, cp, gj;                               // DMat, poff, TriJob, CopyJob
     };
     std::vector<Level> levels;
     std::vector<Range> ranges(K);
@@ -109,7 +112,7 @@ int32_t coarse_inverse_dc(hkgeneo_ctx *c, hipStream_t s, bool *done) {
         std::vector<DMat> mW, mWinv;
         std::vector<int64_t> poff;
         std::vector<TriJob> tri;
-        std::vector<CopyJob> cp;
+        std::vector<CopyJob> cp, gj;
         std::vector<Range> next;
         int64_t off = 0, poffv = 0;
         for (size_t q = 0; q + 1 < ranges.size(); q += 2) {
@@ -132,6 +135,7 @@ int32_t coarse_inverse_dc(hkgeneo_ctx *c, hipStream_t s, bool *done) {
             poff.push_back(poffv);
             poffv += nf;
             tri.push_back({w, winv, nf, nf, nf, nf});
+            gj.push_back({w, winv, nf, nf, nf, nf});
             jK.push_back({winv, qq, kk, nf, nf, nf, nf, nf, nf});                       // K = W^-1 Q
             cp.push_back({d0 + f0 * m0, pm, nd, nf, ld, nd});                           // D^-1 E_f
             cp.push_back({f0 + d0 * m0, rm, nf, nd, ld, nf});                           // E_f^T D^-1
@@ -169,6 +173,7 @@ int32_t coarse_inverse_dc(hkgeneo_ctx *c, hipStream_t s, bool *done) {
         L.poff = blob.add(poff);
         L.tri = blob.add(tri);
         L.cp = blob.add(cp);
+        L.gj = blob.add(gj);
         arenaMerge = std::max(arenaMerge, off);
         pivMerge = std::max<int64_t>(pivMerge, poffv);
         nflags += L.nm;
@@ -176,7 +181,7 @@ int32_t coarse_inverse_dc(hkgeneo_ctx *c, hipStream_t s, bool *done) {
         ranges.swap(next);
     }
     const size_t sLeafLU = blob.add(leafLU), sLeafX = blob.add(leafX), sLeafPoff = blob.add(leafPoff),
-                 sLeafTri = blob.add(leafTri), sLeafCopy = blob.add(leafCopy);
+                 sLeafTri = blob.add(leafTri), sLeafCopy = blob.add(leafCopy), sLeafGJ = blob.add(leafGJ);
     // every block every job touches lies inside its buffer (checked here, before any launch)
     const int64_t arena = std::max(arenaLeaf, arenaMerge), nX = m0 * m0;
     auto inside = [](int64_t off, int64_t rows, int64_t cols, int64_t ld, int64_t size) {
@@ -208,6 +213,10 @@ int32_t coarse_inverse_dc(hkgeneo_ctx *c, hipStream_t s, bool *done) {
             for (int t = 0; t < 2 * L.nm; ++t)
                 ok = ok && inside(cj[t].offS, cj[t].rows, cj[t].cols, cj[t].ldS, nX) &&
                      inside(cj[t].offD, cj[t].rows, cj[t].cols, cj[t].ldD, arena);
+            const auto *gjj = reinterpret_cast<const CopyJob *>(blob.bytes.data() + L.gj);
+            for (int t = 0; t < L.nm; ++t)
+                ok = ok && inside(gjj[t].offS, gjj[t].rows, gjj[t].cols, gjj[t].ldS, arena) &&
+                     inside(gjj[t].offD, gjj[t].rows, gjj[t].cols, gjj[t].ldD, arena);
         }
         if (!ok) {
             set_last_error("coarse divide and conquer: a block lies outside its buffer");
@@ -229,14 +238,19 @@ int32_t coarse_inverse_dc(hkgeneo_ctx *c, hipStream_t s, bool *done) {
     int32_t *piv = dp<int32_t>(c->wDCpiv), *info = dp<int32_t>(c->wDCinfo);
 
     // ---- leaves: X[b, b] = B_0[b, b]^-1 ----------------------------------------------------------
-    HKG_TRY(copy_blocks_batched(reinterpret_cast<const CopyJob *>(jb + sLeafCopy), K, (int64_t)maxb * maxb, B0, ar, s));
-    HKG_TRY(lu_batched<double>(reinterpret_cast<const DMat *>(jb + sLeafLU), reinterpret_cast<const int64_t *>(jb + sLeafPoff),
-                               K, maxb, ar, piv, info, true, s));
-    HKG_TRY(perm_identity_batched<double>(reinterpret_cast<const DMat *>(jb + sLeafX),
-                                          reinterpret_cast<const int64_t *>(jb + sLeafPoff), K, maxb, piv, X, s));
-    const TriJob *lt = reinterpret_cast<const TriJob *>(jb + sLeafTri);
-    HKG_TRY(tri_solve_batched<double>(lt, K, maxb, maxb, ar, X, TRI_LOWER_UNIT, s));
-    HKG_TRY(tri_solve_batched<double>(lt, K, maxb, maxb, ar, X, TRI_UPPER, s));
+    if (maxb <= inv_gj_max_n()) {
+        HKG_TRY(inv_gj_batched(reinterpret_cast<const CopyJob *>(jb + sLeafGJ), K, maxb, B0, X, info, s));
+    } else {
+        HKG_TRY(copy_blocks_batched(reinterpret_cast<const CopyJob *>(jb + sLeafCopy), K, (int64_t)maxb * maxb, B0, ar,
+                                    s));
+        HKG_TRY(lu_batched<double>(reinterpret_cast<const DMat *>(jb + sLeafLU),
+                                   reinterpret_cast<const int64_t *>(jb + sLeafPoff), K, maxb, ar, piv, info, true, s));
+        HKG_TRY(perm_identity_batched<double>(reinterpret_cast<const DMat *>(jb + sLeafX),
+                                              reinterpret_cast<const int64_t *>(jb + sLeafPoff), K, maxb, piv, X, s));
+        const TriJob *lt = reinterpret_cast<const TriJob *>(jb + sLeafTri);
+        HKG_TRY(tri_solve_batched<double>(lt, K, maxb, maxb, ar, X, TRI_LOWER_UNIT, s));
+        HKG_TRY(tri_solve_batched<double>(lt, K, maxb, maxb, ar, X, TRI_UPPER, s));
+    }
 
     // ---- merges ------------------------------------------------------------------------------------
     int flag0 = K;
@@ -249,10 +263,14 @@ int32_t coarse_inverse_dc(hkgeneo_ctx *c, hipStream_t s, bool *done) {
         HKG_TRY(gemm_batched<double>(J(L.gQ), nm, f, f, ar, B0, ar, 1.0, 0.0, false, false, s));
         HKG_TRY(identity_batched(mW, nm, f, ar, s));
         HKG_TRY(gemm_batched<double>(J(L.gW), nm, f, f, ar, X, ar, -1.0, 1.0, false, false, s));
-        HKG_TRY(lu_batched<double>(mW, po, nm, f, ar, piv, info + flag0, true, s));
-        HKG_TRY(perm_identity_batched<double>(reinterpret_cast<const DMat *>(jb + L.mWinv), po, nm, f, piv, ar, s));
-        HKG_TRY(tri_solve_batched<double>(tj, nm, f, f, ar, ar, TRI_LOWER_UNIT, s));
-        HKG_TRY(tri_solve_batched<double>(tj, nm, f, f, ar, ar, TRI_UPPER, s));
+        if (f <= inv_gj_max_n()) {
+            HKG_TRY(inv_gj_batched(reinterpret_cast<const CopyJob *>(jb + L.gj), nm, f, ar, ar, info + flag0, s));
+        } else {
+            HKG_TRY(lu_batched<double>(mW, po, nm, f, ar, piv, info + flag0, true, s));
+            HKG_TRY(perm_identity_batched<double>(reinterpret_cast<const DMat *>(jb + L.mWinv), po, nm, f, piv, ar, s));
+            HKG_TRY(tri_solve_batched<double>(tj, nm, f, f, ar, ar, TRI_LOWER_UNIT, s));
+            HKG_TRY(tri_solve_batched<double>(tj, nm, f, f, ar, ar, TRI_UPPER, s));
+        }
         HKG_TRY(gemm_batched<double>(J(L.gK), nm, f, f, ar, ar, ar, 1.0, 0.0, false, false, s));
         HKG_TRY(copy_blocks_batched(reinterpret_cast<const CopyJob *>(jb + L.cp), 2 * nm, L.maxcopy, X, ar, s));
         HKG_TRY(gemm_batched<double>(J(L.gPK), nm, L.maxd, f, ar, ar, ar, 1.0, 0.0, false, false, s));

@@ -5,6 +5,8 @@
 // blockIdx.y as the batch index, so a launch covers matrices of different sizes; work past a
 // matrix's own size returns early.  Matrices are column-major.  T is double or float; the float
 // instantiations accumulate in float (the mixed-precision local factors).
+#include <cfloat>
+
 #include "internal.hpp"
 #include "kernels.hpp"
 #include "tile.hpp"
@@ -1552,6 +1554,170 @@ int32_t cast_f64_f32(const double *in, float *out, int64_t n, hipStream_t s) {
     if (n == 0) return HKG_OK;
     int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
     hipLaunchKernelGGL(k_cast_f64_f32, dim3(blocks), dim3(256), 0, s, in, out, n);
+    HKG_HIP(hipGetLastError());
+    return HKG_OK;
+}
+
+// ------------------------------------------------------------------------------------------------
+// Batched inverse of small dense matrices by Gauss-Jordan elimination with partial pivoting, one
+// workgroup per matrix and the whole matrix in registers: thread (r, g) holds row r, columns
+// g, g + 4, g + 8, ... (CPT <= 64 of them; R a multiple of 64, so g is the same across a wave), and
+// the 4 x R threads cover n <= min(R, 4 CPT).
+// Step k picks the pivot row p among the rows not yet pivoted (largest |a_ik|, found by every wave
+// from the column staged in LDS, DPP arg-max, lowest index on ties), stages row p divided by the
+// pivot (with 1/pivot in column k), and updates every other row i: a_i -= a_ik * row_p after
+// a_ik := 0.  Rows are never exchanged: physical row p_k holds logical row k, and the final store
+// unscrambles (A^{-1})[k, p_j] = a[p_k, j].  The pivots are those of an LU with partial pivoting;
+// info = 1 when one of them is at most 32 n eps times the largest (or any is not finite).
+// Column slots rotate: the four columns of slot s sit in a[0] while their four steps run, then
+// the slots move down by one, so the pivot column is a fixed register (no run-time indexing of the
+// register array, one copy of the step code).  Two barriers per step, the column and pivot-row
+// buffers double-buffered.  A step is a latency chain (barrier, LDS round trips, arg-max, staging,
+// FMAs): about 3 us at n = 200, against the dozens of launches of a blocked LU and its inverse.
+// Job: CopyJob {offS in, offD out, rows = cols = n, ldS, ldD}.
+// ------------------------------------------------------------------------------------------------
+template <int CPT, int R>
+__global__ __launch_bounds__(4 * R) void k_inv_gj(const CopyJob *__restrict__ jobs, const double *__restrict__ in,
+                                                  double *__restrict__ out, int32_t *__restrict__ info) {
+    static_assert(R % 64 == 0, "a wave holds one column group");
+    constexpr int G = 4;
+    __shared__ double colv[2][R];
+    __shared__ double cola[2][R];
+    __shared__ double prow[2][G * CPT];
+    __shared__ int32_t pk[R], kof[R];
+    const CopyJob J = jobs[blockIdx.x];
+    const int n = J.rows;
+    const int t = threadIdx.x, r = t % R, g = t / R, lane = t & 63;
+    if (n <= 0) {
+        if (t == 0) info[blockIdx.x] = 0;
+        return;
+    }
+    for (int i = t; i < R; i += G * R) {
+        pk[i] = 0;
+        kof[i] = 0;
+    }
+    const bool live = r < n;
+    const int rc = min(r, n - 1);
+    double a[CPT];
+    const double *src = in + J.offS + rc;
+#pragma unroll
+    for (int q0 = 0; q0 < CPT; q0 += 4) {
+#pragma unroll
+        for (int u = 0; u < 4 && q0 + u < CPT; ++u) {
+            const int j = G * (q0 + u) + g;
+            double v = src[(int64_t)min(j, n - 1) * J.ldS];
+            asm volatile("" : "+v"(v));     // keep the (in-range) load unconditional: no branch per load
+            a[q0 + u] = (live && j < n) ? v : 0.0;
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    bool used = false, finite = true;
+    double pmax = 0.0, pmin = INFINITY;
+    const int nslot = (n + G - 1) / G;
+#pragma unroll 1
+    for (int sl = 0; sl < nslot; ++sl) {
+        const int gend = min(G, n - G * sl);
+#pragma unroll 1
+        for (int gk = 0; gk < gend; ++gk) {
+            const int k = G * sl + gk;
+            const int b = k & 1;
+            if (g == gk) {
+                colv[b][r] = a[0];
+                cola[b][r] = (live && !used) ? fabs(a[0]) : -1.0;
+            }
+            __syncthreads();
+            double best = -2.0;
+            int bi = 0;
+#pragma unroll
+            for (int i0 = 0; i0 < R; i0 += 64) {
+                const double x = cola[b][i0 + lane];
+                if (x > best) {
+                    best = x;
+                    bi = i0 + lane;
+                }
+            }
+            argmax_wave64(best, bi);
+            // no admissible row (a column of NaNs): flagged; p is then some row < R, and the final
+            // store clamps every index into the matrix
+            const int p = __builtin_amdgcn_readfirstlane(bi);
+            const double piv = colv[b][p];
+            const double apiv = fabs(piv);
+            finite = finite && best >= 0.0 && (apiv <= DBL_MAX);
+            pmax = fmax(pmax, apiv);
+            pmin = fmin(pmin, apiv);
+            const bool isp = (r == p);
+            if (isp) {
+                used = true;
+                const double inv = 1.0 / piv;
+#pragma unroll
+                for (int q0 = 0; q0 < CPT; q0 += 4) {
+#pragma unroll
+                    for (int u = 0; u < 4 && q0 + u < CPT; ++u) prow[b][g * CPT + q0 + u] = a[q0 + u] * inv;
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                if (g == gk) prow[b][g * CPT] = inv;
+                if (g == 0) {
+                    pk[k] = p;
+                    kof[p] = k;
+                }
+            }
+            __syncthreads();
+            // every row: a_ik := 0, then a_i -= a_ik * row_p; the pivot row then takes row_p.
+            // Staged entries are read 4 at a time: a fence per chunk keeps the scheduler from
+            // hoisting every LDS read, each of which costs a register pair.
+            const double f = colv[b][r];
+            if (g == gk) a[0] = 0.0;
+#pragma unroll
+            for (int q0 = 0; q0 < CPT; q0 += 4) {
+                double pv[4];
+#pragma unroll
+                for (int u = 0; u < 4 && q0 + u < CPT; ++u) pv[u] = prow[b][g * CPT + q0 + u];
+#pragma unroll
+                for (int u = 0; u < 4 && q0 + u < CPT; ++u) a[q0 + u] = fma(-f, pv[u], a[q0 + u]);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            if (isp) {
+#pragma unroll
+                for (int q = 0; q < CPT; ++q) a[q] = prow[b][g * CPT + q];
+            }
+        }
+        const double a0 = a[0];
+#pragma unroll
+        for (int q = 0; q + 1 < CPT; ++q) a[q] = a[q + 1];
+        a[CPT - 1] = a0;
+    }
+    __syncthreads();
+    // slot q now holds the columns of original slot (q + nslot) mod CPT
+    if (live) {
+        double *dst = out + J.offD + min(max(kof[r], 0), n - 1);
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) {
+            const int j = G * ((q + nslot) % CPT) + g;
+            if (j < n) dst[(int64_t)min(max(pk[j], 0), n - 1) * J.ldD] = a[q];
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    if (t == 0) {
+        const double tiny = 32.0 * (double)n * 2.220446049250313e-16 * pmax;
+        info[blockIdx.x] = (finite && pmin > tiny) ? 0 : 1;
+    }
+}
+
+int inv_gj_max_n() { return 208; }
+
+int32_t inv_gj_batched(const CopyJob *d_jobs, int nbatch, int maxn, const double *in, double *out, int32_t *info,
+                       hipStream_t s) {
+    if (nbatch == 0 || maxn == 0) return HKG_OK;
+    if (maxn <= 64)
+        hipLaunchKernelGGL((k_inv_gj<16, 64>), dim3(nbatch), dim3(256), 0, s, d_jobs, in, out, info);
+    else if (maxn <= 128)
+        hipLaunchKernelGGL((k_inv_gj<32, 128>), dim3(nbatch), dim3(512), 0, s, d_jobs, in, out, info);
+    else if (maxn <= 192)
+        hipLaunchKernelGGL((k_inv_gj<48, 192>), dim3(nbatch), dim3(768), 0, s, d_jobs, in, out, info);
+    else if (maxn <= 208)
+        hipLaunchKernelGGL((k_inv_gj<52, 256>), dim3(nbatch), dim3(1024), 0, s, d_jobs, in, out, info);
+    else
+        return HKG_EINVAL;
     HKG_HIP(hipGetLastError());
     return HKG_OK;
 }

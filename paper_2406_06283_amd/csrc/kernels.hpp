@@ -44,6 +44,12 @@ int32_t transpose_batched(const DMat *d_mats, int nbatch, int maxn, const T *in,
 int32_t cast_f64_f32(const double *in, float *out, int64_t n, hipStream_t s);
 // X = I for every matrix of the list
 int32_t identity_batched(const DMat *d_mats, int nbatch, int maxn, double *X, hipStream_t s);
+// Batched inverse by Gauss-Jordan with partial pivoting (one workgroup per matrix, the
+// matrix in registers): out block = in block^{-1} for n <= inv_gj_max_n(); info[b] = 1 when a pivot
+// is at most 32 n eps times the largest one or not finite.  Jobs: CopyJob {offS, offD, n, n, ldS, ldD}.
+int inv_gj_max_n();
+int32_t inv_gj_batched(const CopyJob *d_jobs, int nbatch, int maxn, const double *in, double *out, int32_t *info,
+                       hipStream_t s);
 // one rectangular block copy per job (src and dst must not overlap)
 int32_t copy_blocks_batched(const CopyJob *d_jobs, int nbatch, int64_t max_elems, const double *src, double *dst,
                             hipStream_t s);

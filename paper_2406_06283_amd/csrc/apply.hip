@@ -223,4 +223,23 @@ int32_t transpose_basis(const SubDev *d_sub, int nsub, const double *Z, double *
     return HKG_OK;
 }
 
+__global__ __launch_bounds__(256) void k_tp_coarse(const SubDev *__restrict__ subs, const int32_t *__restrict__ tp_pos,
+                                                   const int32_t *__restrict__ tp_sub, int64_t ntp,
+                                                   TpCoarse *__restrict__ out) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= ntp) return;
+    const SubDev &sd = subs[tp_sub[t]];
+    // a subdomain without coarse vectors points at entry 0 (read, then masked, by the prolongation)
+    if (sd.m > 0) out[t] = {sd.offZ + (int64_t)(tp_pos[t] - sd.offI) * sd.m, sd.offm, sd.m};
+    else out[t] = {0, 0, 0};
+}
+
+int32_t tp_coarse(const SubDev *d_sub, const int32_t *tp_pos, const int32_t *tp_sub, int64_t ntp, TpCoarse *out,
+                  hipStream_t s) {
+    if (ntp == 0) return HKG_OK;
+    hipLaunchKernelGGL(k_tp_coarse, dim3((unsigned)((ntp + 255) / 256)), dim3(256), 0, s, d_sub, tp_pos, tp_sub, ntp, out);
+    HKG_HIP(hipGetLastError());
+    return HKG_OK;
+}
+
 }  // namespace hkg

@@ -101,7 +101,7 @@ void fill_resident(ProbDev &P, const hkgeneo_ctx *c) {
     P.B0inv = dp<double>(c->B0inv);
     P.tp_ptr = dp<int32_t>(c->tp_ptr);
     P.tp_pos = dp<int32_t>(c->tp_pos);
-    P.tp_sub = dp<int32_t>(c->tp_sub);
+    P.tpc = dp<TpCoarse>(c->tpZ);
 }
 
 constexpr int NWS = 15;

@@ -9,6 +9,7 @@
 // so a problem solved alone or in a mix gives bitwise the same iterates.
 #include "batch.hpp"
 #include "internal.hpp"
+#include "wave.hpp"
 
 namespace hkg {
 
@@ -240,44 +241,47 @@ __global__ __launch_bounds__(64 * CG_RPB) void k_b_coarse_gemv(const ProbDev *__
 
 // z_l = sum over the positions t of dof l in the local vectors (transpose map, fixed order) of
 // u[t] + (Z_i y_i)[a], t = (subdomain i, local index a): the coarse correction E_0 y = sum_i E_i Z_i y_i
-// folded into the same pass (Z_i read row-wise from its row-major copy).
-__global__ __launch_bounds__(BROWS) void k_b_prolong(const ProbDev *__restrict__ probs,
-                                                     const WorkItem *__restrict__ rblk, int mode, int par) {
+// folded into the same pass.  Four lanes per dof: lane q takes the positions t0 + q, t0 + q + 4, ...
+// (each carries its row of Z_i in the row-major copy and its slice of y; Z and y entries are loaded
+// eight at a time), and the quad's sums are added in lane order, which for up to four positions is
+// the sequential order over t.  (One lane per dof left a chain of dependent memory round trips per
+// thread at four waves per CU.)
+__global__ __launch_bounds__(4 * BROWS) void k_b_prolong(const ProbDev *__restrict__ probs,
+                                                         const WorkItem *__restrict__ rblk, int mode, int par) {
     const WorkItem it = rblk[blockIdx.x];
     const ProbDev &P = probs[it.p];
     const int rhs = blockIdx.z;
     if (inactive(P, rhs, mode)) return;
-    const int l = it.s * BROWS + threadIdx.x;
-    if (l >= P.n) return;
+    const int q = threadIdx.x & 3;
+    const int l = it.s * BROWS + (threadIdx.x >> 2);
+    if (l >= P.n) return;                  // whole quads leave together
     const double *uu = P.u + (int64_t)rhs * P.sum_nI;
     const double *y = P.ypart + (int64_t)rhs * P.m0;
-    const int t0 = P.tp_ptr[l], t1 = P.tp_ptr[l + 1];
-    double s = 0.0;
-    for (int t = t0; t < t1; ++t) {
-        const int pos = P.tp_pos[t];
-        double v = uu[pos];
+    const int t1 = P.tp_ptr[l + 1];
+    double v = 0.0;
+    for (int t = P.tp_ptr[l] + q; t < t1; t += 4) {
+        double c = 0.0;
         if (P.two_level) {
-            const SubDev &sd = P.subs[P.tp_sub[t]];
-            const double *zr = P.Zr + sd.offZ + (int64_t)(pos - sd.offI) * sd.m;
-            const double *yi = y + sd.offm;
-            double cz = 0.0;
-            for (int b0 = 0; b0 < sd.m; b0 += 4) {
-                double zv[4], yv[4];
+            const TpCoarse d = P.tpc[t];
+            for (int b0 = 0; b0 < d.m; b0 += 8) {
+                double zv[8], yv[8];
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const int b = min(b0 + k, sd.m - 1);
-                    zv[k] = zr[b];
-                    yv[k] = yi[b];
+                for (int k = 0; k < 8; ++k) {
+                    const int kk = min(b0 + k, d.m - 1);
+                    zv[k] = P.Zr[d.zoff + kk];
+                    yv[k] = y[d.yoff + kk];
                 }
 #pragma unroll
-                for (int k = 0; k < 4; ++k) cz = fma(zv[k], b0 + k < sd.m ? yv[k] : 0.0, cz);
+                for (int k = 0; k < 8; ++k) c = fma(zv[k], b0 + k < d.m ? yv[k] : 0.0, c);
             }
-            v += cz;
         }
-        s += v;
+        v += uu[P.tp_pos[t]] + c;
     }
-    double *z = (mode == 0) ? P.xout + (int64_t)rhs * P.ldout : zcol(P, rhs, jget(P, rhs, par));
-    z[l] = s;
+    const double s = ((dpp_f64<0x00>(v) + dpp_f64<0x55>(v)) + dpp_f64<0xAA>(v)) + dpp_f64<0xFF>(v);
+    if (q == 0) {
+        double *z = (mode == 0) ? P.xout + (int64_t)rhs * P.ldout : zcol(P, rhs, jget(P, rhs, par));
+        z[l] = s;
+    }
 }
 
 int32_t batch_apply(const BatchGeom &g, const ProbDev *probs, const WorkItem *items, const WorkItem *rblk,
@@ -301,7 +305,7 @@ int32_t batch_apply(const BatchGeom &g, const ProbDev *probs, const WorkItem *it
     if (ev1) HKG_HIP(hipEventRecord(ev1, s));
     if (g.any_coarse)
         hipLaunchKernelGGL(k_b_coarse_gemv, dim3(g.ncblk, 1, g.max_nrhs), dim3(64 * CG_RPB), 0, s, probs, cblk, mode);
-    hipLaunchKernelGGL(k_b_prolong, dim3(g.nrblk, 1, g.max_nrhs), dim3(BROWS), 0, s, probs, rblk, mode, par);
+    hipLaunchKernelGGL(k_b_prolong, dim3(g.nrblk, 1, g.max_nrhs), dim3(4 * BROWS), 0, s, probs, rblk, mode, par);
     HKG_HIP(hipGetLastError());
     return HKG_OK;
 }

@@ -39,7 +39,8 @@ struct ProbDev {
     const double *wloc;
     const void *Minv;
     const double *Z, *Zr, *B0inv;
-    const int32_t *tp_ptr, *tp_pos, *tp_sub;
+    const int32_t *tp_ptr, *tp_pos;
+    const TpCoarse *tpc;                 // coarse term per transpose-map position (two-level only)
     // batch workspace of this problem
     double *u, *c, *ypart;                                   // apply (ypart holds y = B_0^{-1} c)
     double *V, *Zk, *H, *cs, *sn, *g, *part, *hcol, *scal;   // FGMRES, per rhs strides below

@@ -28,6 +28,7 @@ struct hkgeneo_ctx {
     hkg::DevBuf matsGG, matsSq, poffSub, jobsGI, jobsSq, gjobsSchur, matsLoc, poffLoc, jobsLoc, matsM, jobsM;
     // numeric results (factorisation phase)
     hkg::DevBuf Bval, Minv, Z, Zr, B0inv;
+    hkg::DevBuf tpZ;                      // per transpose-map position: its row of Z_i and slice of y
     hkg::DevBuf B0copy;                   // B_0 kept on the device for queries when m0 <= 2048
     int b0_band = -1;                     // half-bandwidth of B_0 used by its LU (-1: dense)
     int band_I = -1;                      // half-bandwidth of B[I, I] and C_II (-1: treated as dense)

@@ -520,6 +520,9 @@ int32_t coarse_space(hkgeneo_ctx *c, hipStream_t s, const std::function<int32_t(
         HKG_TRY(finish_basis(dsub, ns, dp<int32_t>(c->I_idx), dp<double>(c->winv), dp<double>(c->Z), s));
         if (c->Zr.bytes != (size_t)offZ * sizeof(double)) HKG_TRY(dalloc(c, &c->Zr, offZ * sizeof(double)));
         HKG_TRY(transpose_basis(dsub, ns, dp<double>(c->Z), dp<double>(c->Zr), s));
+        const int64_t ntp = (int64_t)c->P.tp_pos.size();
+        if (c->tpZ.bytes != (size_t)ntp * sizeof(TpCoarse)) HKG_TRY(dalloc(c, &c->tpZ, ntp * sizeof(TpCoarse)));
+        HKG_TRY(tp_coarse(dsub, dp<int32_t>(c->tp_pos), dp<int32_t>(c->tp_sub), ntp, dp<TpCoarse>(c->tpZ), s));
         // Y_i = Z_i^T [B_II | B_IG]
         HKG_TRY(walloc(c, &c->wY, std::max<int64_t>(offY, 1) * sizeof(double)));
         HKG_TRY(gemm_batched<double>(dp<GemmJob>(c->wGjobsY), ns, c->max_m, maxN, dp<double>(c->Z), dp<double>(c->wBIO),

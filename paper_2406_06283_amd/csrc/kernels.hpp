@@ -135,6 +135,15 @@ int32_t apply_two_level(const ApplyPlan &p, const double *r, int ldr, double *z,
 int apply_ypart_chunks(int m0);
 int32_t transpose_basis(const SubDev *d_sub, int nsub, const double *Z, double *Zr, hipStream_t s);
 
+// coarse term of one position t of the transpose map (dof l in subdomain i at local index a): row a
+// of Z_i in the row-major copy (zoff, m entries) and the slice y_i of the coarse vector (yoff)
+struct TpCoarse {
+    int64_t zoff;
+    int32_t yoff, m;
+};
+int32_t tp_coarse(const SubDev *d_sub, const int32_t *tp_pos, const int32_t *tp_sub, int64_t ntp, TpCoarse *out,
+                  hipStream_t s);
+
 // ---- krylov.hip ------------------------------------------------------------------------------------
 int32_t spmv(int n, int nrhs, const int32_t *rowptr, const int32_t *colidx, const double *val, const double *x,
              int ldx, double *y, int ldy, const double *f, int ldf, hipStream_t s, const int32_t *active = nullptr);

@@ -16,11 +16,8 @@ namespace hkg {
 constexpr int LS_ROWS = 64;
 constexpr int NPART = 16;        // partial sums per local-solve row (a multiple of every wave count)
 
-__device__ __forceinline__ double bwsum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
+// sum over the 64 lanes of a wave (DPP moves within 16-lane rows, then the four row sums in order)
+__device__ __forceinline__ double bwsum(double v) { return wave_sum64(v); }
 
 // Loads in the loops below are never guarded by a wave-uniform branch: a branch around a load makes the
 // wave wait for it before the next one issues.  Indices are clamped into range instead and only the
@@ -208,8 +205,9 @@ __global__ __launch_bounds__(LS_ROWS *WAVES) void k_b_local(const ProbDev *__res
 
 // Coarse solve y = B_0^{-1} c: one wave per coarse row r.  B_0 is symmetric (B_0 = Z^T B Z), so row r
 // of its inverse is read as column r of the stored column-major inverse: contiguous, coalesced.  Lane
-// l sums the columns congruent to l modulo 64 in increasing order, then a fixed butterfly: the final
-// y (no split partial sums), whatever the batch composition.  y is stored in the ypart region.
+// l sums the columns congruent to l modulo 64 in increasing order (eight loads in flight; sixteen
+// measured slower), then a fixed-order wave reduction: the final y (no split partial sums), whatever
+// the batch composition.  y is stored in the ypart region.
 constexpr int CG_RPB = 4;        // rows (waves) per block
 
 __global__ __launch_bounds__(64 * CG_RPB) void k_b_coarse_gemv(const ProbDev *__restrict__ probs,

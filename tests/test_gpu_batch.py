@@ -168,3 +168,45 @@ def test_batch_restarted_cycles_match_oracle(restart):
         assert np.linalg.norm(U[r] - Us[r]) / np.linalg.norm(Us[r]) <= 1e-8
     if restart == 8:
         assert min(i["iters"] for i in info) > 2 * restart
+
+
+def test_batch_of_24_uneven_problems_matches_oracle():
+    # the batched-mix generator at small sizes: h in {1/24, ..., 1/48}, k = 0.3/h, 2x2 to 6x6 blocks
+    # with overlaps drawn per subdomain from {1, 2, 3}, both coefficient fields, 1-4 right-hand sides
+    # (67 in all), threshold selection; float32 local inverses in every other problem
+    from paper_2406_06283_amd.configs import batch_mix, mix_options
+    mix = batch_mix(24, seed0=1000, n_choices=(24, 32, 40, 48), s_range=(2, 6), nrhs_range=(1, 4), max_block=None)
+    probs = [m.problem() for m in mix]
+    solvers = [H.Solver(p, H.default_options(**mix_options(m, local_prec=32 if q % 2 == 0 else 64)))
+               for q, (m, p) in enumerate(zip(mix, probs))]
+    try:
+        fs = [_rhs(p) for p in probs]
+        _say(f"[batch] 24 problems, {sum(p.f.shape[0] for p in probs)} right-hand sides")
+        with H.Batch(solvers, [p.f.shape[0] for p in probs]) as B:
+            um, im, st = B.solve(fs)
+            torch.cuda.synchronize()
+            um = [u.cpu().numpy() for u in um]
+        assert st == H.HKG_OK
+        for q in (0, 11, 23):
+            with H.Batch([solvers[q]], [probs[q].f.shape[0]]) as B1:
+                (ua,), (ia,), _ = B1.solve([fs[q]])
+                torch.cuda.synchronize()
+            assert np.array_equal(ua.cpu().numpy(), um[q]), mix[q].name
+            assert [i["iters"] for i in ia] == [i["iters"] for i in im[q]], mix[q].name
+        worst = 0.0
+        for q, (m, p, S) in enumerate(zip(mix, probs, solvers)):
+            M = schwarz.TwoLevelSchwarz(p, schwarz.Options(eig_mode=local.EIG_THRESHOLD, tau=m.tau))
+            assert S.stats()["m0"] == M.m0 and list(S.subdomains()[2]) == M.m, m.name
+            for r in range(p.f.shape[0]):
+                x, oinfo = fgmres.solve(p, M, f=p.f[r], restart=200)
+                rel = np.linalg.norm(p.f[r] - M.B @ um[q][r]) / np.linalg.norm(p.f[r])
+                assert im[q][r]["converged"] and rel <= 1e-8, (m.name, r, rel)
+                assert abs(im[q][r]["iters"] - oinfo["iters"]) <= 2, (m.name, r, im[q][r]["iters"], oinfo["iters"])
+                err = np.linalg.norm(um[q][r] - x) / np.linalg.norm(x)
+                if q % 2 == 1:          # float64 local inverses: the same iterates up to rounding
+                    assert err <= 1e-8, (m.name, r, err)
+                worst = max(worst, err)
+        _say(f"[batch] every right-hand side within the bars; largest solution difference {worst:.1e}")
+    finally:
+        for S in solvers:
+            S.close()

@@ -37,6 +37,7 @@ def test_serve_loop_results_equal_alone():
     problems = {k: _problem(k) for k in KEYS}
     rng = np.random.default_rng(5)
     arrivals = np.cumsum(rng.exponential(0.004, size=14))
+    arrivals[10:] += 1.0        # the last four arrive once every setup has ended: cache hits
     reqs = []
     for q, t in enumerate(arrivals):
         key = "abc"[q % 3] if q < 6 else "abc"[int(rng.integers(0, 3))]

@@ -519,10 +519,9 @@ def main_serve(args):
     def make_solver(key, stream):
         return H.Solver(problems[key], H.default_options(**serve_options(key)), stream=stream)
 
-    cap = H.default_options().max_eig_per_sub
-
     def estimate(key):      # an upper bound: no subdomain keeps more than max_eig_per_sub vectors
-        return serve.footprint_estimate(problems[key], serve_options(key)["local_prec"], cap)
+        o = serve_options(key)
+        return serve.footprint_estimate(problems[key], o["local_prec"], o["max_eig_per_sub"])
 
     from paper_2406_06283_amd.configs import MIX_RESTART
     kw = dict(ctx_budget=96 << 30, workspace_budget=48 << 30, max_requests=64, max_nrhs=8, restart=MIX_RESTART)

@@ -170,10 +170,12 @@ def serve_problem(key: tuple) -> pb.Problem:
 
 def serve_options(key: tuple) -> dict:
     """Options of a serving key: float32 local solves; threshold selection (tau = 0.85) in 2D, ten
-    eigenvectors per subdomain in 3D; FGMRES(MIX_RESTART) (the stream includes h = 1/256, k = 76.8)."""
+    eigenvectors per subdomain in 3D; FGMRES(MIX_RESTART) (the stream includes h = 1/256, k = 76.8).
+    At most 32 eigenvectors per subdomain (the stream's keys keep at most 25): the cap bounds the
+    coarse terms of the footprint the server reserves before a setup."""
     if key[0] == "p1":
-        return dict(eig_mode=EIG_THRESHOLD, tau=0.85, nev=0, local_prec=32, restart=MIX_RESTART)
-    return dict(eig_mode=EIG_FIXED, nev=10, local_prec=32, restart=MIX_RESTART)
+        return dict(eig_mode=EIG_THRESHOLD, tau=0.85, nev=0, local_prec=32, restart=MIX_RESTART, max_eig_per_sub=32)
+    return dict(eig_mode=EIG_FIXED, nev=10, local_prec=32, restart=MIX_RESTART, max_eig_per_sub=32)
 
 
 def serve_stream(n_requests: int, rate: float, seed: int = 0, frac_3d: float = 0.25, n_seeds: int = 16,

@@ -137,12 +137,15 @@ class SetupAdmission:
     """Admission of setups by HBM footprint: keys missing from the cache queue up in arrival order,
     and the head is dispatched (``dispatch(key)``) only once the cache can reserve ``estimate(key)``
     bytes for it, evicting idle contexts if needed.  Keys stay queued in order while the head does not
-    fit (no overtaking, so a large setup is not starved by small ones)."""
+    fit (no overtaking, so a large setup is not starved by small ones).  At most ``max_in_flight``
+    setups are dispatched at a time: the worker runs them one after the other anyway, and a longer
+    queue would only hold reservations (upper bounds) that evict resident contexts."""
 
-    def __init__(self, cache: ContextCache, estimate, dispatch):
+    def __init__(self, cache: ContextCache, estimate, dispatch, max_in_flight: int = 2):
         self.cache = cache
         self.estimate = estimate
         self.dispatch = dispatch
+        self.max_in_flight = int(max_in_flight)
         self.blocked: collections.deque = collections.deque()
         self.in_setup: set = set()
 
@@ -152,7 +155,7 @@ class SetupAdmission:
 
     def pump(self) -> int:
         n = 0
-        while self.blocked:
+        while self.blocked and len(self.in_setup) < self.max_in_flight:
             key = self.blocked[0]
             need = int(self.estimate(key))
             if need > self.cache.budget:

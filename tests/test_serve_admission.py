@@ -102,3 +102,14 @@ def test_cached_key_is_not_set_up_again():
     adm.finished("a", FakeSolver(10))
     adm.request("a")
     assert adm.pump() == 0 and sent == ["a"]
+
+
+def test_admission_keeps_at_most_max_in_flight_setups():
+    c = serve.ContextCache(1000)
+    sent = []
+    adm = serve.SetupAdmission(c, lambda k: 10, sent.append, max_in_flight=2)
+    for k in "abcd":
+        adm.request(k)
+    assert adm.pump() == 2 and sent == ["a", "b"] and c.bytes == 20
+    adm.finished("a", FakeSolver(5))
+    assert adm.pump() == 1 and sent == ["a", "b", "c"]

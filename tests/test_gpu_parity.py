@@ -343,3 +343,28 @@ def test_fgmres_delta_geneo_matches_oracle(wl):
     _say(f"  iterations: Delta-GenEO oracle {oinfo['iters']} gpu {info[0]['iters']} (H_k-GenEO oracle "
          f"{hinfo['iters']}); m0 {M.m0} (H_k {hk.m0}); solution vs oracle {err:.2e}")
     assert err <= 1e-8
+
+
+@pytest.mark.parametrize("nev", [24, 32])
+def test_coarse_inverse_paths_match_oracle(nev):
+    # 6x6 subdomains couple at most 7 apart in index, so the divide-and-conquer inverse of B_0 works on
+    # level blocks of 7 subdomains: 168 coarse rows with nev = 24 (the one-launch Gauss-Jordan
+    # inverse), 224 with nev = 32 (past its size limit: batched LU and triangular solves)
+    p = pb.make_problem(48, k=12.0, s=6, overlap=2, coef="cells", seed=11, n_cells=6, rhs="normal", nrhs=2)
+    _say(f"[coarse inverse] 6x6 subdomains, nev={nev}: level blocks of {7 * nev} rows")
+    M = _oracle(p, eig_mode=local.EIG_FIXED, nev=nev)
+    R = np.random.default_rng(31).standard_normal((2, p.n_dof))
+    with H.Solver(p, H.default_options(eig_mode=H.HKG_EIG_FIXED, nev=nev)) as S:
+        assert S.stats()["m0"] == M.m0 == 36 * nev
+        Zg = _gpu_apply(S, R)
+        u, info, st = S.solve(torch.from_numpy(np.ascontiguousarray(p.f)).to(DEV))
+        torch.cuda.synchronize()
+        u = u.cpu().numpy()
+    Zo = np.stack([M.apply(r) for r in R])
+    scale = np.abs(Zo).max()
+    assert np.abs(Zg - Zo).max() <= 1e-10 * scale, np.abs(Zg - Zo).max() / scale
+    assert st == H.HKG_OK
+    for r in range(2):
+        x, oinfo = fgmres.solve(p, M, f=p.f[r])
+        assert info[r]["converged"] and abs(info[r]["iters"] - oinfo["iters"]) <= 2, (info[r]["iters"], oinfo["iters"])
+        assert np.linalg.norm(u[r] - x) / np.linalg.norm(x) <= 1e-8

@@ -33,6 +33,7 @@ struct hkgeneo_ctx {
     int b0_band = -1;                     // half-bandwidth of B_0 used by its LU (-1: dense)
     int band_I = -1;                      // half-bandwidth of B[I, I] and C_II (-1: treated as dense)
     // factorisation workspace (kept between calls when opt.keep_workspace, freed otherwise)
+    hkg::DevBuf wGGi, wGI2, jobsGGinv, gjobsGX;   // Gamma block inverse, gathered rows, their job lists
     hkg::DevBuf wDk, wBIO, wCII, wGG, wGI, wS, wW, wPiv, wInfo, wFlag, wD, wE, wTau, wM, wLam, wY, wB0, wLU, wPivL,
         wJobsZ, wGjobsY, wMisc, wPiv0, wInv, wVWV, wInfoL, wSL, wIv, wLinv, wJobsInv, wT, wPivC, wInfoC, wFlagSpd,
         wDC, wDCjobs, wDCpiv, wDCinfo, wAIO;

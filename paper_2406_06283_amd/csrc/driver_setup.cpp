@@ -61,7 +61,7 @@ int32_t upload_bytes(hkgeneo_ctx *c, DevBuf *b, const void *host, size_t bytes, 
 }
 
 void free_workspace(hkgeneo_ctx *c) {
-    DevBuf *w[] = {&c->wDk, &c->wBIO, &c->wCII, &c->wGG, &c->wGI, &c->wS, &c->wW, &c->wPiv, &c->wInfo,
+    DevBuf *w[] = {&c->wGGi, &c->wGI2, &c->wDk, &c->wBIO, &c->wCII, &c->wGG, &c->wGI, &c->wS, &c->wW, &c->wPiv, &c->wInfo,
                    &c->wFlag, &c->wD, &c->wE, &c->wTau, &c->wM, &c->wLam, &c->wY, &c->wB0, &c->wLU,
                    &c->wPivL, &c->wJobsZ, &c->wGjobsY, &c->wMisc, &c->wPiv0, &c->wInv, &c->wVWV, &c->wInfoL, &c->wSL, &c->wIv,
                    &c->wLinv, &c->wJobsInv, &c->wT, &c->wPivC, &c->wInfoC, &c->wFlagSpd, &c->wDC, &c->wDCjobs,
@@ -177,7 +177,8 @@ int32_t analyze(hkgeneo_ctx *c, const hkgeneo_problem *p, hipStream_t s, int32_t
     std::vector<int64_t> hpo(ns), hpl(ns);
     std::vector<TriJob> jGI(ns), jSq(ns), jM(ns);
     std::vector<DMat> hM(ns);
-    std::vector<GemmJob> gS(ns);
+    std::vector<GemmJob> gS(ns), gX(ns);
+    std::vector<CopyJob> jGinv(ns);
     int64_t pl = 0;
     for (int i = 0; i < ns; ++i) {
         const SubDev &sd = c->subs[i];
@@ -192,6 +193,8 @@ int32_t analyze(hkgeneo_ctx *c, const hkgeneo_problem *p, hipStream_t s, int32_t
         hM[i] = {sd.offM, sd.nI, sd.ldM};
         jM[i] = {sd.offSq, sd.offM, sd.nI, sd.nI, sd.nI, sd.ldM};
         gS[i] = {sd.offBIO + (int64_t)sd.nI * sd.nI, sd.offGI, sd.offSq, sd.nI, sd.nI, sd.nG, sd.nI, ldG, sd.nI};
+        jGinv[i] = {sd.offGG, sd.offGG, sd.nG, sd.nG, ldG, ldG};
+        gX[i] = {sd.offGG, sd.offGI, sd.offGI, sd.nG, sd.nI, sd.nG, ldG, ldG, ldG};
     }
     HKG_TRY(upload(c, &c->matsGG, hGG.data(), ns, s));
     HKG_TRY(upload(c, &c->matsSq, hSq.data(), ns, s));
@@ -202,6 +205,8 @@ int32_t analyze(hkgeneo_ctx *c, const hkgeneo_problem *p, hipStream_t s, int32_t
     HKG_TRY(upload(c, &c->matsM, hM.data(), ns, s));
     HKG_TRY(upload(c, &c->jobsM, jM.data(), ns, s));
     HKG_TRY(upload(c, &c->gjobsSchur, gS.data(), ns, s));
+    HKG_TRY(upload(c, &c->jobsGGinv, jGinv.data(), ns, s));
+    HKG_TRY(upload(c, &c->gjobsGX, gX.data(), ns, s));
 
     // neighbouring pairs of the coarse matrix
     build_coarse_pairs(P, &c->CP);
@@ -395,18 +400,30 @@ int32_t coarse_space(hkgeneo_ctx *c, hipStream_t s, const std::function<int32_t(
     HKG_HIP(hipMemsetAsync(c->wGG.p, 0, c->wGG.bytes, s));
     HKG_TRY(assemble_gamma(dsub, ns, c->max_nG, c->npe, nullptr, dp<int32_t>(c->bandLoc), dp<double>(c->bandK),
                            dp<double>(c->bandM), k2, dp<double>(c->wGG), s));
-    HKG_TRY(lu_batched<double>(dp<DMat>(c->matsGG), dp<int64_t>(c->poffSub), ns, c->max_nG, dp<double>(c->wGG),
-                               dp<int32_t>(c->wPiv), dp<int32_t>(c->wInfo), true, s));
     std::vector<int32_t> flags;
     // X = B~_GG^{-1} B_GI ; S = B_II - B_IG X
-    HKG_TRY(gather_gamma_rows(dsub, ns, c->max_nI, c->max_nG, eigIO, dp<double>(c->wGI), s));
-    HKG_TRY(apply_pivots_rows<double>(dsub, ns, c->max_nI, dp<int32_t>(c->wPiv), dp<double>(c->wGI), 0, s));
-    // the Gamma block is dense: as a band of half-width n_G - 1 the solves take one launch each
-    const int bandG = tri_band_fits(c->max_nG, c->max_nG - 1, sizeof(double)) ? c->max_nG - 1 : -1;
-    HKG_TRY(tri_solve_batched<double>(dp<TriJob>(c->jobsGI), ns, c->max_nG, c->max_nI, dp<double>(c->wGG),
-                                      dp<double>(c->wGI), TRI_LOWER_UNIT, s, bandG));
-    HKG_TRY(tri_solve_batched<double>(dp<TriJob>(c->jobsGI), ns, c->max_nG, c->max_nI, dp<double>(c->wGG),
-                                      dp<double>(c->wGI), TRI_UPPER, s, bandG));
+    if (c->max_nG <= inv_gj_max_n()) {
+        // small Gamma blocks: their inverses in one Gauss-Jordan launch (partial pivoting; the flags
+        // mean what the LU's do), then X by one batched GEMM with the gathered rows
+        HKG_TRY(walloc(c, &c->wGGi, std::max<int64_t>(c->nGG, 1) * sizeof(double)));
+        HKG_TRY(walloc(c, &c->wGI2, std::max<int64_t>(c->nGI, 1) * sizeof(double)));
+        HKG_TRY(inv_gj_batched(dp<CopyJob>(c->jobsGGinv), ns, c->max_nG, dp<double>(c->wGG), dp<double>(c->wGGi),
+                               dp<int32_t>(c->wInfo), s));
+        HKG_TRY(gather_gamma_rows(dsub, ns, c->max_nI, c->max_nG, eigIO, dp<double>(c->wGI2), s));
+        HKG_TRY(gemm_batched<double>(dp<GemmJob>(c->gjobsGX), ns, c->max_nG, c->max_nI, dp<double>(c->wGGi),
+                                     dp<double>(c->wGI2), dp<double>(c->wGI), 1.0, 0.0, false, false, s));
+    } else {
+        HKG_TRY(lu_batched<double>(dp<DMat>(c->matsGG), dp<int64_t>(c->poffSub), ns, c->max_nG, dp<double>(c->wGG),
+                                   dp<int32_t>(c->wPiv), dp<int32_t>(c->wInfo), true, s));
+        HKG_TRY(gather_gamma_rows(dsub, ns, c->max_nI, c->max_nG, eigIO, dp<double>(c->wGI), s));
+        HKG_TRY(apply_pivots_rows<double>(dsub, ns, c->max_nI, dp<int32_t>(c->wPiv), dp<double>(c->wGI), 0, s));
+        // the Gamma block is dense: as a band of half-width n_G - 1 the solves take one launch each
+        const int bandG = tri_band_fits(c->max_nG, c->max_nG - 1, sizeof(double)) ? c->max_nG - 1 : -1;
+        HKG_TRY(tri_solve_batched<double>(dp<TriJob>(c->jobsGI), ns, c->max_nG, c->max_nI, dp<double>(c->wGG),
+                                          dp<double>(c->wGI), TRI_LOWER_UNIT, s, bandG));
+        HKG_TRY(tri_solve_batched<double>(dp<TriJob>(c->jobsGI), ns, c->max_nG, c->max_nI, dp<double>(c->wGG),
+                                          dp<double>(c->wGI), TRI_UPPER, s, bandG));
+    }
     HKG_TRY(copy_bii(dsub, ns, c->max_nI, eigIO, dp<double>(c->wS), s));
     HKG_TRY(gemm_batched<double>(dp<GemmJob>(c->gjobsSchur), ns, c->max_nI, c->max_nI, eigIO,
                                  dp<double>(c->wGI), dp<double>(c->wS), -1.0, 1.0, false, false, s));

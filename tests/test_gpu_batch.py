@@ -71,8 +71,27 @@ def test_batch_of_one_matches_oracle():
     assert np.linalg.norm(u - x) / np.linalg.norm(x) <= 1e-8
 
 
+_INPUTS = ("elem_vert", "vert_dof", "elem_K", "elem_M", "row_ptr", "col_idx", "A_val", "S_val", "elem_part", "overlap",
+           "f")
+
+
+def _snapshot(p):
+    return {k: np.array(getattr(p, k), copy=True) for k in _INPUTS}
+
+
+def _assert_inputs_unchanged(p, snap, name):
+    # the library reads its host inputs and never writes them
+    for k, v in snap.items():
+        now = np.asarray(getattr(p, k))
+        if not np.array_equal(now, v):
+            bad = np.flatnonzero(now.ravel() != v.ravel())
+            raise AssertionError(f"{name}: host input {k} changed at {bad.size} entries, first {bad[:8].tolist()}: "
+                                 f"{v.ravel()[bad[:4]].tolist()} -> {now.ravel()[bad[:4]].tolist()}")
+
+
 def test_batch_mix_equals_alone_and_matches_oracle():
     probs = [_make(c[1]) for c in MIX]
+    snaps = [_snapshot(p) for p in probs]
     okws = [c[2] for c in MIX]
     solvers = _solvers(probs, okws)
     try:
@@ -92,6 +111,7 @@ def test_batch_mix_equals_alone_and_matches_oracle():
             assert [i["iters"] for i in ia] == [i["iters"] for i in im[q]], name
             # against the oracle, column by column
             p = probs[q]
+            _assert_inputs_unchanged(p, snaps[q], name)
             o = dict(okw)
             two = bool(o.pop("two_level", 1))
             o.pop("local_prec", None)

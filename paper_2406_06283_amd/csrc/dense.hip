@@ -43,12 +43,45 @@ __global__ __launch_bounds__(256) void k_gemm_batched(const GemmJob *__restrict_
 }
 
 template <typename T>
+__global__ __launch_bounds__(256) void k_gemm_batched32(const GemmJob *__restrict__ jobs, const T *__restrict__ Ab,
+                                                        const T *__restrict__ Bb, T *__restrict__ Cb, T alpha, T beta,
+                                                        int ta, int tb, int tiles_m_max) {
+    const GemmJob J = jobs[blockIdx.y];
+    const int tm = blockIdx.x % tiles_m_max, tn = blockIdx.x / tiles_m_max;
+    if (tm * GT2 >= J.M || tn * GT2 >= J.N || J.K <= 0) {
+        if (J.K <= 0 && tm * GT2 < J.M && tn * GT2 < J.N) {
+            // an empty sum: C = beta C
+            const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+            for (int c = 0; c < 2; ++c)
+                for (int r = 0; r < 2; ++r) {
+                    const int gi = tm * GT2 + tx + 16 * r, gj = tn * GT2 + ty + 16 * c;
+                    if (gi < J.M && gj < J.N) {
+                        T *p = Cb + J.offC + gi + (int64_t)gj * J.ldc;
+                        *p = beta == T(0) ? T(0) : beta * *p;
+                    }
+                }
+        }
+        return;
+    }
+    gemm_tile32<T>(J.M, J.N, J.K, Ab + J.offA, J.lda, ta, Bb + J.offB, J.ldb, tb, Cb + J.offC, J.ldc, alpha, beta, tm,
+                   tn);
+}
+
+template <typename T>
 int32_t gemm_batched(const GemmJob *d_jobs, int nbatch, int maxM, int maxN, const T *A, const T *B, T *C, T alpha,
                      T beta, bool ta, bool tb, hipStream_t s) {
     if (nbatch == 0 || maxM == 0 || maxN == 0) return HKG_OK;
     int tmm = (maxM + GT - 1) / GT, tnm = (maxN + GT - 1) / GT;
-    dim3 grid(tmm * tnm, nbatch);
-    hipLaunchKernelGGL(k_gemm_batched<T>, grid, dim3(256), 0, s, d_jobs, A, B, C, alpha, beta, (int)ta, (int)tb, tmm);
+    if ((int64_t)tmm * tnm * nbatch < 256) {
+        // too few 64 x 64 tiles to fill the CUs: 32 x 32 tiles (same sums, same bits)
+        const int t2m = (maxM + GT2 - 1) / GT2, t2n = (maxN + GT2 - 1) / GT2;
+        hipLaunchKernelGGL(k_gemm_batched32<T>, dim3(t2m * t2n, nbatch), dim3(256), 0, s, d_jobs, A, B, C, alpha, beta,
+                           (int)ta, (int)tb, t2m);
+    } else {
+        dim3 grid(tmm * tnm, nbatch);
+        hipLaunchKernelGGL(k_gemm_batched<T>, grid, dim3(256), 0, s, d_jobs, A, B, C, alpha, beta, (int)ta, (int)tb,
+                           tmm);
+    }
     HKG_HIP(hipGetLastError());
     return HKG_OK;
 }

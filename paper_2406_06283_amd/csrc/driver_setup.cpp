@@ -407,6 +407,8 @@ int32_t coarse_space(hkgeneo_ctx *c, hipStream_t s, const std::function<int32_t(
         // mean what the LU's do), then X by one batched GEMM with the gathered rows
         HKG_TRY(walloc(c, &c->wGGi, std::max<int64_t>(c->nGG, 1) * sizeof(double)));
         HKG_TRY(walloc(c, &c->wGI2, std::max<int64_t>(c->nGI, 1) * sizeof(double)));
+        // (no launch when every Gamma block is empty: the flags start at zero)
+        HKG_HIP(hipMemsetAsync(c->wInfo.p, 0, ns * sizeof(int32_t), s));
         HKG_TRY(inv_gj_batched(dp<CopyJob>(c->jobsGGinv), ns, c->max_nG, dp<double>(c->wGG), dp<double>(c->wGGi),
                                dp<int32_t>(c->wInfo), s));
         HKG_TRY(gather_gamma_rows(dsub, ns, c->max_nI, c->max_nG, eigIO, dp<double>(c->wGI2), s));

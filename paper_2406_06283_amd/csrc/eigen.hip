@@ -741,9 +741,10 @@ int32_t tridiag_vectors_n(const SubDev *d_sub, int nsub, int64_t max_nm, const d
 
 // ------------------------------------------------------------------------------------------------
 // 4. back-transformation y <- Q y with Q = H_0 H_1 ... H_{n-2} (reflectors applied last-first), one
-//    wave per eigenvector with the vector staged in LDS.  Reflector j - 1 is loaded into registers
-//    while reflector j is applied, so each step costs a dot product and an update, not a memory
-//    round trip.  NB = ceil(n / 64) registers per lane hold a reflector.
+//    wave per eigenvector with the vector staged in LDS.  The reflectors are read three steps ahead
+//    into a queue of registers (a step is a dot product, a wave sum and an update, shorter than a
+//    memory round trip, so one step of look-ahead left every step waiting on its loads).
+//    NB = ceil(n / 64) registers per lane hold a reflector.
 // ------------------------------------------------------------------------------------------------
 template <int NB>
 __global__ __launch_bounds__(64) void k_back_transform(const SubDev *__restrict__ subs, const double *__restrict__ Sq,
@@ -763,41 +764,49 @@ __global__ __launch_bounds__(64) void k_back_transform(const SubDev *__restrict_
         for (int i = lane; i < n; i += 64) z[i] = zs[i];
         return;
     }
-    // reflector j: v = A[j+1 .. n-1, j]; entry i of it (i < L = n - j - 1) in lane i % 64, slot i / 64
-    double vc[NB], vn[NB];
+    // reflector j: v = A[j+1 .. n-1, j]; entry i of it (i < L = n - j - 1) in lane i % 64, slot i / 64.
+    // Indices below 0 are clamped to reflector 0 (loaded, never applied).
+    double v0[NB], v1[NB], v2[NB];
     auto load = [&](int j, double *dst) {
+        j = max(j, 0);
         const int L = n - j - 1;
         const double *v = A + (j + 1) + (int64_t)j * ld;
 #pragma unroll
         for (int q = 0; q < NB; ++q) dst[q] = v[min(lane + 64 * q, L - 1)];
     };
-    load(n - 2, vc);
-    double tc = tau[n - 2];
+    load(n - 2, v0);
+    load(n - 3, v1);
+    load(n - 4, v2);
+    double t0 = tau[n - 2], t1 = tau[max(n - 3, 0)], t2 = tau[max(n - 4, 0)];
     for (int j = n - 2; j >= 0; --j) {
-        double tn = 0.0;
-        if (j > 0) {
-            load(j - 1, vn);
-            tn = tau[j - 1];
-        }
-        if (tc != 0.0) {
+        double v3[NB];
+        load(j - 3, v3);
+        const double t3 = tau[max(j - 3, 0)];
+        if (t0 != 0.0) {
             const int L = n - j - 1;
             double s = 0.0;
 #pragma unroll
             for (int q = 0; q < NB; ++q) {
                 const int i = lane + 64 * q;
-                if (i < L) s = fma(vc[q], zs[j + 1 + i], s);
+                if (i < L) s = fma(v0[q], zs[j + 1 + i], s);
             }
-            s = tc * wave_sum(s);
+            s = t0 * wave_sum(s);
 #pragma unroll
             for (int q = 0; q < NB; ++q) {
                 const int i = lane + 64 * q;
-                if (i < L) zs[j + 1 + i] -= s * vc[q];
+                if (i < L) zs[j + 1 + i] -= s * v0[q];
             }
         }
         __syncthreads();
 #pragma unroll
-        for (int q = 0; q < NB; ++q) vc[q] = vn[q];
-        tc = tn;
+        for (int q = 0; q < NB; ++q) {
+            v0[q] = v1[q];
+            v1[q] = v2[q];
+            v2[q] = v3[q];
+        }
+        t0 = t1;
+        t1 = t2;
+        t2 = t3;
     }
     for (int i = lane; i < n; i += 64) z[i] = zs[i];
 }

@@ -37,8 +37,8 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
 
 // ------------------------------------------------------------------------------------------------
 // 1. Blocked Householder tridiagonalisation of the symmetric nI x nI matrix T of each subdomain,
-//    stored at offM with the padded leading dimension ldM (both triangles kept up to date; every
-//    column starts on a 256-byte boundary).  Reflector j is stored in column j below the diagonal
+//    stored at offM with the padded leading dimension ldM (every column starts on a 256-byte
+//    boundary; with V and W in LDS only the lower triangle is kept up to date, otherwise both).  Reflector j is stored in column j below the diagonal
 //    (its first entry, 1, explicitly), with tau[j]; d and e receive the diagonal and sub-diagonal.
 //    Within a panel of SY_NB columns starting at j0 the
 //     trailing matrix A0 is left as it was at the panel start; with V (reflectors) and W (their
@@ -215,9 +215,121 @@ __global__ __launch_bounds__(SY_THREADS) void k_sytrd_panel(const SubDev *__rest
 }
 
 
+// The product A0 v of the panel with V and W in LDS, from the lower triangle of A0 only (the update
+// after such a panel keeps only the lower triangle current).  Rows are cut into blocks of SYM_RB
+// (a wave covers one block, two rows per lane, 16-byte loads) and columns into chunks of SYM_CH.
+// An entry (r, c) with c < r adds A0[r][c] v[c] to row r (summed in the lane) and A0[r][c] v[r] to
+// row c (summed over the wave's 64 lanes); a diagonal entry adds to its row only.  v is zero outside
+// rows j+1 .. n-1, so entries outside the trailing block add nothing; entries above the diagonal,
+// and the row past n that a 16-byte load reads when n is odd, are masked by selects.
+//
+// The active row blocks share the 16 waves in proportion to their active chunk counts (one wave at
+// least, the remainder to the last block); the waves of a block take its chunks in turn.  Outputs:
+// rowpart[w][0 .. SYM_RB) the row sums of wave w, colpart[b npad + c] the column sums of row block b,
+// share[2 b], share[2 b + 1] the first wave of block b and the number of its waves with chunks.
+constexpr int SYM_RB = 128;
+constexpr int SYM_CH = 8;
+constexpr int SYM_CPB = SYM_RB / SYM_CH;
+constexpr int SYM_NW = SY_THREADS / 64;
+
+// sum of p's and q's values over the two 32-lane halves: the lower half gets p's sums, the upper q's
+__device__ __forceinline__ double fold32(double p, double q) {
+    const long long pb = __double_as_longlong(p), qb = __double_as_longlong(q);
+    const auto lo = __builtin_amdgcn_permlane32_swap((int)pb, (int)qb, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap((int)(pb >> 32), (int)(qb >> 32), false, false);
+    const double p2 = __longlong_as_double(((long long)(int)hi[0] << 32) | (unsigned int)lo[0]);
+    const double q2 = __longlong_as_double(((long long)(int)hi[1] << 32) | (unsigned int)lo[1]);
+    return p2 + q2;
+}
+
+// the same over pairs of 16-lane rows (0, 1) and (2, 3): rows 0 and 2 get p's sums, rows 1 and 3 q's
+__device__ __forceinline__ double fold16(double p, double q) {
+    const long long pb = __double_as_longlong(p), qb = __double_as_longlong(q);
+    const auto lo = __builtin_amdgcn_permlane16_swap((int)pb, (int)qb, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap((int)(pb >> 32), (int)(qb >> 32), false, false);
+    const double p2 = __longlong_as_double(((long long)(int)hi[0] << 32) | (unsigned int)lo[0]);
+    const double q2 = __longlong_as_double(((long long)(int)hi[1] << 32) | (unsigned int)lo[1]);
+    return p2 + q2;
+}
+
+// x[u] summed over the 64 lanes; lane l returns the sum of x[l >> 3]
+__device__ __forceinline__ double wave_sum_cols8(double x[SYM_CH], int lane) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) x[k] = fold32(x[k], x[k + 4]);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) x[k] = fold16(x[k], x[k + 2]);
+    const bool up = lane & 8;          // partner lane 15 - l of the row has the other value of bit 3
+    const double snd = up ? x[0] : x[1];
+    double s = (up ? x[1] : x[0]) + dpp_f64<DPP_ROW_MIRROR>(snd);
+    s += dpp_f64<DPP_QUAD_XOR1>(s);
+    s += dpp_f64<DPP_QUAD_XOR2>(s);
+    s += dpp_f64<DPP_ROW_HALF_MIRROR>(s);
+    return s;
+}
+
+__device__ __forceinline__ void sytrd_product_sym(const double *__restrict__ A, int ld, int n, int npad, int j,
+                                                  const double *v, double *rowpart, double *colpart, int *share,
+                                                  int tid) {
+    const int lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int nblk = npad / SYM_RB, bmin = (j + 1) / SYM_RB, nb = nblk - bmin;
+    const int cmin = (j + 1) / SYM_CH, clast = (n - 1) / SYM_CH;
+    int K = 0;
+    for (int q = bmin; q < nblk; ++q) K += min(SYM_CPB * q + SYM_CPB - 1, clast) - cmin + 1;
+    const float scale = (float)(SYM_NW - nb) / (float)K;
+    int B = bmin, i = 0, wb = 1, acc = 0;
+    for (int q = bmin; q < nblk; ++q) {
+        const int kq = min(SYM_CPB * q + SYM_CPB - 1, clast) - cmin + 1;
+        const int wq = (q == nblk - 1) ? SYM_NW - acc : 1 + (int)(scale * (float)kq);
+        if (w >= acc && w < acc + wq) {
+            B = q;
+            i = w - acc;
+            wb = min(wq, kq);
+            if (i == 0 && lane == 0) {
+                share[2 * q] = acc;
+                share[2 * q + 1] = wb;
+            }
+        }
+        acc += wq;
+    }
+    if (i >= wb) return;
+    const int r0 = SYM_RB * B + 2 * lane, r1 = r0 + 1;
+    const bool rin = r0 < n && r1 > j;
+    const double2 vr = *reinterpret_cast<const double2 *>(v + r0);
+    double s0 = 0.0, s1 = 0.0;
+    const int cmax = min(SYM_CPB * B + SYM_CPB - 1, clast);
+    for (int C = cmin + i; C <= cmax; C += wb) {
+        const int c0 = C * SYM_CH;
+        const bool need = rin && r1 >= c0;
+        double2 a[SYM_CH];
+#pragma unroll
+        for (int u = 0; u < SYM_CH; ++u) a[u] = make_double2(0.0, 0.0);
+        if (need) {
+#pragma unroll
+            for (int u = 0; u < SYM_CH; ++u)
+                a[u] = *reinterpret_cast<const double2 *>(A + r0 + (int64_t)min(c0 + u, n - 1) * ld);
+        }
+        double x[SYM_CH];
+#pragma unroll
+        for (int u = 0; u < SYM_CH; ++u) {
+            const int c = c0 + u;
+            const double vc = v[c];
+            const double a0 = c <= r0 ? a[u].x : 0.0;
+            const double a1 = (c <= r1 && r1 < n) ? a[u].y : 0.0;
+            s0 = fma(a0, vc, s0);
+            s1 = fma(a1, vc, s1);
+            x[u] = fma(c < r0 ? a0 : 0.0, vr.x, (c < r1 ? a1 : 0.0) * vr.y);
+        }
+        const double cs = wave_sum_cols8(x, lane);
+        if ((lane & 7) == 0) colpart[B * npad + c0 + (lane >> 3)] = cs;
+    }
+    *reinterpret_cast<double2 *>(rowpart + w * SYM_RB + 2 * lane) = make_double2(s0, s1);
+}
+
 // The panel with V and W in LDS (every access of the corrections and of W^T v, V^T v is an LDS
 // access; copied to the global [V | W | V] at the end), n <= SY_THREADS: thread t owns row j + t in
-// the column phases and keeps its values in registers, so a column takes five barriers.  A0 is not
+// the column phases and keeps its values in registers, so a column takes five barriers; the product
+// A0 v reads the lower triangle only (sytrd_product_sym).  A0 is not
 // modified within the panel except for the reflector written into column j while column j is
 // processed, so the next column's entry of each row is loaded one column ahead.
 template <int NB>
@@ -235,15 +347,19 @@ __global__ __launch_bounds__(SY_THREADS) void k_sytrd_panel_lds(const SubDev *__
     if (j0 >= n - 1) return;
     const int jb = min(NB, n - 1 - j0);
     double *Vg = VWVb + 3 * NB * sd.offI;
-    double *v = sh;                  // n
-    double *p = sh + n;              // n: the corrected column
-    double *part = sh + 2 * n;       // SY_G (n + 1)
-    double *t12 = part + SY_G * (n + 1);   // 2 NB
+    const int npad = (n + SYM_RB - 1) / SYM_RB * SYM_RB;
+    double *v = sh;                  // npad: the reflector on rows j+1 .. n-1, zero elsewhere
+    double *p = sh + npad;           // n: the corrected column
+    double *rowpart = p + npad;      // SYM_NW x SYM_RB
+    double *colpart = rowpart + SYM_NW * SYM_RB;   // (npad / SYM_RB) x npad
+    int *share = reinterpret_cast<int *>(colpart + (npad / SYM_RB) * npad);   // 16 ints
+    double *t12 = colpart + (npad / SYM_RB) * npad + 8;   // 2 NB
     double *red = t12 + 4 * NB;      // two sets of 16 slots
     double *V = red + 32;            // NB x n
     double *W = V + (int64_t)NB * n; // NB x n
     double dmine = 0.0, emine = 0.0, tmine = 0.0;   // column tid's d, e, tau (tid < jb)
     for (int64_t q = tid; q < (int64_t)2 * NB * n; q += SY_THREADS) V[q] = 0.0;
+    for (int q = tid; q < npad; q += SY_THREADS) v[q] = 0.0;
     double anext = j0 + tid < n ? A[(j0 + tid) + (int64_t)j0 * ld] : 0.0;
     __syncthreads();
     for (int kk = 0; kk < jb; ++kk) {
@@ -273,6 +389,8 @@ __global__ __launch_bounds__(SY_THREADS) void k_sytrd_panel_lds(const SubDev *__
             v[r] = vr;
             A[r + (int64_t)j * ld] = vr;
             V[r + (int64_t)kk * n] = vr;
+        } else if (tid == 0) {
+            v[j] = 0.0;                  // row j leaves the trailing block
         }
         if (tid == kk) {            // stored after the panel (a store per column stalls its wave)
             dmine = p[j];
@@ -282,7 +400,7 @@ __global__ __launch_bounds__(SY_THREADS) void k_sytrd_panel_lds(const SubDev *__
         __syncthreads();
         if (t == 0.0) continue;          // H_j = I: W column stays zero
         // 3. A0 v in column-group parts, and t12[q] = W_q . v, t12[kk + q] = V_q . v
-        sytrd_product_parts(A, ld, n, j, v, part, tid);
+        sytrd_product_sym(A, ld, n, npad, j, v, rowpart, colpart, share, tid);
         for (int q2 = wv; q2 < 2 * kk; q2 += SY_THREADS / 64) {
             const double *col = (q2 < kk) ? W + (int64_t)q2 * n : V + (int64_t)(q2 - kk) * n;
             double sq = 0.0;
@@ -294,7 +412,10 @@ __global__ __launch_bounds__(SY_THREADS) void k_sytrd_panel_lds(const SubDev *__
         // 4. p = t (A0 v - V (W^T v) - W (V^T v)); w = p - (t/2)(p . v) v
         double pr = 0.0, vr = 0.0;
         if (below) {
-            double y = (part[r] + part[(n + 1) + r]) + (part[2 * (n + 1) + r] + part[3 * (n + 1) + r]);
+            const int b = r / SYM_RB, w0 = share[2 * b], nw = share[2 * b + 1];
+            double y = 0.0;
+            for (int q = 0; q < nw; ++q) y += rowpart[(w0 + q) * SYM_RB + (r & (SYM_RB - 1))];
+            for (int q = b; q < npad / SYM_RB; ++q) y += colpart[q * npad + r];
             for (int q = 0; q < kk; ++q) y -= V[r + (int64_t)q * n] * t12[q] + W[r + (int64_t)q * n] * t12[kk + q];
             pr = t * y;
             vr = v[r];
@@ -335,6 +456,30 @@ __global__ __launch_bounds__(256) void k_sytrd_update(const SubDev *__restrict__
                       -1.0, 1.0, tm, tn);
 }
 
+// the same update on the lower 64 x 64 tiles only (tile index t = tm (tm + 1) / 2 + tn, tn <= tm), for
+// the panel that reads the lower triangle only
+template <int NB>
+__global__ __launch_bounds__(256) void k_sytrd_update_lower(const SubDev *__restrict__ subs, double *__restrict__ Sq,
+                                                            const double *__restrict__ VWVb, int j0) {
+    const SubDev sd = subs[blockIdx.y];
+    const int n = sd.nI;
+    if (j0 >= n - 1) return;
+    const int jb = min(NB, n - 1 - j0);
+    const int j1 = j0 + jb;
+    const int L1 = n - j1;
+    const int t = blockIdx.x;
+    int tm = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+    while ((tm + 1) * (tm + 2) / 2 <= t) ++tm;
+    while (tm * (tm + 1) / 2 > t) --tm;
+    const int tn = t - tm * (tm + 1) / 2;
+    if (tm * 64 >= L1) return;
+    const double *V = VWVb + 3 * NB * sd.offI;
+    double *A = Sq + sd.offM;
+    const int ld = sd.ldM;
+    gemm_tile<double>(L1, L1, 2 * NB, V + j1, n, false, V + (int64_t)NB * n + j1, n, true, A + j1 + (int64_t)j1 * ld, ld,
+                      -1.0, 1.0, tm, tn);
+}
+
 // the last diagonal entry, after the final trailing update
 __global__ void k_sytrd_last(const SubDev *__restrict__ subs, const double *__restrict__ Sq, double *__restrict__ dout) {
     const SubDev sd = subs[blockIdx.x];
@@ -345,13 +490,15 @@ int32_t tridiagonalize_blocked(const SubDev *d_sub, int nsub, int maxnI, double 
                                double *tau, hipStream_t s) {
     const int tiles = (maxnI + 63) / 64;
     const size_t base = (size_t)(2 * maxnI + SY_G * (maxnI + 1) + 32);
-    const size_t shm_lds = (base + 4 * SY_NB_LDS + (size_t)2 * SY_NB_LDS * maxnI) * sizeof(double);
+    const size_t npad = (size_t)(maxnI + SYM_RB - 1) / SYM_RB * SYM_RB;
+    const size_t shm_lds = (2 * npad + SYM_NW * SYM_RB + (npad / SYM_RB) * npad + 8 + 4 * SY_NB_LDS + 32 +
+                            (size_t)2 * SY_NB_LDS * maxnI) * sizeof(double);
     if (shm_lds <= (size_t)156 * 1024 && maxnI <= SY_THREADS) {
         for (int j0 = 0; j0 < maxnI; j0 += SY_NB_LDS) {
             hipLaunchKernelGGL(k_sytrd_panel_lds<SY_NB_LDS>, dim3(nsub), dim3(SY_THREADS), shm_lds, s, d_sub, Sq, VWV,
                                d, e, tau, j0);
-            hipLaunchKernelGGL(k_sytrd_update<SY_NB_LDS>, dim3(tiles * tiles, nsub), dim3(256), 0, s, d_sub, Sq, VWV, j0,
-                               tiles);
+            hipLaunchKernelGGL(k_sytrd_update_lower<SY_NB_LDS>, dim3(tiles * (tiles + 1) / 2, nsub), dim3(256), 0, s,
+                               d_sub, Sq, VWV, j0);
         }
     } else {
         const size_t shm = (base + 4 * SY_NB) * sizeof(double);

@@ -355,9 +355,9 @@ __global__ __launch_bounds__(SY_THREADS) void k_sytrd_panel_lds(const SubDev *__
     int *share = reinterpret_cast<int *>(colpart + (npad / SYM_RB) * npad);   // 16 ints
     double *t12 = colpart + (npad / SYM_RB) * npad + 8;   // 2 NB
     double *red = t12 + 4 * NB;      // two sets of 16 slots
-    double *V = red + 32;            // NB x n
+    double *det = red + 32;          // 3 NB: d, e, tau of the panel's columns
+    double *V = det + 3 * NB;        // NB x n
     double *W = V + (int64_t)NB * n; // NB x n
-    double dmine = 0.0, emine = 0.0, tmine = 0.0;   // column tid's d, e, tau (tid < jb)
     for (int64_t q = tid; q < (int64_t)2 * NB * n; q += SY_THREADS) V[q] = 0.0;
     for (int q = tid; q < npad; q += SY_THREADS) v[q] = 0.0;
     double anext = j0 + tid < n ? A[(j0 + tid) + (int64_t)j0 * ld] : 0.0;
@@ -392,10 +392,10 @@ __global__ __launch_bounds__(SY_THREADS) void k_sytrd_panel_lds(const SubDev *__
         } else if (tid == 0) {
             v[j] = 0.0;                  // row j leaves the trailing block
         }
-        if (tid == kk) {            // stored after the panel (a store per column stalls its wave)
-            dmine = p[j];
-            emine = beta;
-            tmine = t;
+        if (tid == 0) {              // stored after the panel (a global store per column stalls its wave)
+            det[kk] = p[j];
+            det[NB + kk] = beta;
+            det[2 * NB + kk] = t;
         }
         __syncthreads();
         if (t == 0.0) continue;          // H_j = I: W column stays zero
@@ -424,10 +424,11 @@ __global__ __launch_bounds__(SY_THREADS) void k_sytrd_panel_lds(const SubDev *__
         if (below) W[r + (int64_t)kk * n] = pr - K * vr;
         __syncthreads();
     }
+    __syncthreads();
     if (tid < jb) {
-        d[j0 + tid] = dmine;
-        e[j0 + tid] = emine;
-        tau[j0 + tid] = tmine;
+        d[j0 + tid] = det[tid];
+        e[j0 + tid] = det[NB + tid];
+        tau[j0 + tid] = det[2 * NB + tid];
     }
     for (int64_t q = tid; q < (int64_t)NB * n; q += SY_THREADS) {
         const double x = V[q], y = W[q];
@@ -457,10 +458,15 @@ __global__ __launch_bounds__(256) void k_sytrd_update(const SubDev *__restrict__
 }
 
 // the same update on the lower 64 x 64 tiles only (tile index t = tm (tm + 1) / 2 + tn, tn <= tm), for
-// the panel that reads the lower triangle only
+// the panel that reads the lower triangle only.  K = 2 NB is short, so a block stages the whole
+// 64 x K slices of [V W] and [W V] in LDS at once and loads its 64 x 64 tile of A in the same round
+// of loads: one barrier, then K FMAs per output (k in increasing order), then A - acc is stored.
 template <int NB>
 __global__ __launch_bounds__(256) void k_sytrd_update_lower(const SubDev *__restrict__ subs, double *__restrict__ Sq,
                                                             const double *__restrict__ VWVb, int j0) {
+    constexpr int K = 2 * NB;
+    __shared__ double sA[K][GT + 1];
+    __shared__ double sB[K][GT + 1];
     const SubDev sd = subs[blockIdx.y];
     const int n = sd.nI;
     if (j0 >= n - 1) return;
@@ -472,12 +478,176 @@ __global__ __launch_bounds__(256) void k_sytrd_update_lower(const SubDev *__rest
     while ((tm + 1) * (tm + 2) / 2 <= t) ++tm;
     while (tm * (tm + 1) / 2 > t) --tm;
     const int tn = t - tm * (tm + 1) / 2;
-    if (tm * 64 >= L1) return;
-    const double *V = VWVb + 3 * NB * sd.offI;
+    if (tm * GT >= L1) return;
+    const double *VW = VWVb + 3 * NB * sd.offI + j1;          // [V W], column q at q n
+    const double *WV = VWVb + 3 * NB * sd.offI + (int64_t)NB * n + j1;   // [W V]
+    double *A = Sq + sd.offM + j1 + (int64_t)j1 * sd.ldM;
+    const int ld = sd.ldM;
+    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    const int i0 = tm * GT, c0 = tn * GT;
+    // the tile of A (rows i0 + tx + 16 r, columns c0 + ty + 16 c) and the two K-slices, all in flight
+    double cv[4][4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int gi = i0 + tx + 16 * r, gj = c0 + ty + 16 * c;
+            cv[r][c] = (gi < L1 && gj < L1) ? A[gi + (int64_t)gj * ld] : 0.0;
+        }
+    double ra[K * GT / 256], rb[K * GT / 256];
+#pragma unroll
+    for (int u = 0; u < K * GT / 256; ++u) {
+        const int e = tid + 256 * u, ii = e % GT, kk = e / GT;
+        ra[u] = i0 + ii < L1 ? VW[(i0 + ii) + (int64_t)kk * n] : 0.0;
+        rb[u] = c0 + ii < L1 ? WV[(c0 + ii) + (int64_t)kk * n] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < K * GT / 256; ++u) {
+        const int e = tid + 256 * u, ii = e % GT, kk = e / GT;
+        sA[kk][ii] = ra[u];
+        sB[kk][ii] = rb[u];
+    }
+    __syncthreads();
+    double acc[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
+#pragma unroll 8
+    for (int kk = 0; kk < K; ++kk) {
+        double a[4], b[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) a[r] = sA[kk][tx + 16 * r];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) b[c] = sB[kk][ty + 16 * c];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[r][c] = fma(a[r], b[c], acc[r][c]);
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int gi = i0 + tx + 16 * r, gj = c0 + ty + 16 * c;
+            if (gi < L1 && gj < L1) A[gi + (int64_t)gj * ld] = cv[r][c] - acc[r][c];
+        }
+}
+
+// The trailing block of at most SY_TAIL rows.  Once the blocked panels have reduced the columns
+// before J, the lower triangle of A[J:, J:] is copied into LDS (packed by rows: entry (r, c), c <= r,
+// at r (r + 1) / 2 + c) and its columns are reduced there one at a time, each reflector's two-sided
+// update A -= v w^T + w v^T applied at once.  Four threads (a quad) share row r, taking the columns
+// c = q (mod 4), eight LDS reads in flight.  Per column: the squared norm of the column below the
+// subdiagonal (block sum), the reflector (stored in its column of A in global memory, as the panels
+// store theirs, with d, e, tau), p = tau A v from the lower triangle (row r's entries for c <= r,
+// column r's for c > r; the quad's sums added by DPP moves), K = tau/2 p.v (block sum), w = p - K v,
+// and the update of row r.  The last diagonal entry is written back to A for the final step.
+constexpr int SY_TAIL = 192;
+constexpr int SY_TAIL_THREADS = 4 * SY_TAIL;
+
+__global__ __launch_bounds__(SY_TAIL_THREADS) void k_sytrd_tail(const SubDev *__restrict__ subs, double *__restrict__ Sq,
+                                                                double *__restrict__ dout, double *__restrict__ eout,
+                                                                double *__restrict__ tout, int J) {
+    extern __shared__ double sh[];
+    const SubDev sd = subs[blockIdx.x];
+    const int n = sd.nI, m = n - J;
+    if (m < 2) return;
     double *A = Sq + sd.offM;
     const int ld = sd.ldM;
-    gemm_tile<double>(L1, L1, 2 * NB, V + j1, n, false, V + (int64_t)NB * n + j1, n, true, A + j1 + (int64_t)j1 * ld, ld,
-                      -1.0, 1.0, tm, tn);
+    double *d = dout + sd.offI + J, *e = eout + sd.offI + J, *tau = tout + sd.offI + J;
+    double *L = sh;                          // m (m + 1) / 2
+    double *v = L + m * (m + 1) / 2;         // m
+    double *w = v + m;                       // m
+    double *red = w + m;                     // two sets of 16 slots
+    const int r = threadIdx.x >> 2, q = threadIdx.x & 3;
+    const bool own = r < m;
+    const int Tr = r * (r + 1) / 2;
+    const double *Aj = A + J + (int64_t)J * ld;
+    if (own) {
+        for (int c0 = q; c0 <= r; c0 += 32) {
+            double x[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) x[u] = Aj[r + (int64_t)min(c0 + 4 * u, r) * ld];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (c0 + 4 * u <= r) L[Tr + c0 + 4 * u] = x[u];
+        }
+    }
+    __syncthreads();
+    for (int jj = 0; jj < m - 1; ++jj) {
+        const bool below = own && r > jj;
+        const double x = below ? L[Tr + jj] : 0.0;
+        const double xn2 = block_sum_once(q == 0 && below && r >= jj + 2 ? x * x : 0.0, red);
+        const double alpha = L[(jj + 1) * (jj + 2) / 2 + jj];
+        double t = 0.0, beta = alpha, scal = 0.0;
+        if (xn2 != 0.0) {
+            beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+            t = (beta - alpha) / beta;
+            scal = 1.0 / (alpha - beta);
+        }
+        double vr = 0.0;
+        if (below) {
+            vr = (r == jj + 1) ? 1.0 : (xn2 != 0.0 ? x * scal : 0.0);
+            if (q == 0) {
+                v[r] = vr;
+                A[(J + r) + (int64_t)(J + jj) * ld] = vr;
+            }
+        }
+        if (threadIdx.x == 0) {
+            d[jj] = L[jj * (jj + 1) / 2 + jj];
+            e[jj] = beta;
+            tau[jj] = t;
+        }
+        __syncthreads();
+        if (t == 0.0) continue;          // H = I: nothing to update
+        double y0 = 0.0, y1 = 0.0;
+        if (below) {
+            for (int c0 = jj + 1 + q; c0 < m; c0 += 32) {
+                double a[8], vc[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int c = min(c0 + 4 * u, m - 1);
+                    a[u] = L[c <= r ? Tr + c : c * (c + 1) / 2 + r];
+                    vc[u] = v[c];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) vc[u] = c0 + 4 * u < m ? vc[u] : 0.0;
+#pragma unroll
+                for (int u = 0; u < 8; u += 2) {
+                    y0 = fma(a[u], vc[u], y0);
+                    y1 = fma(a[u + 1], vc[u + 1], y1);
+                }
+            }
+        }
+        double y = y0 + y1;
+        y += dpp_f64<DPP_QUAD_XOR1>(y);
+        y += dpp_f64<DPP_QUAD_XOR2>(y);
+        const double pr = t * y;
+        const double K = 0.5 * t * block_sum_once(q == 0 ? pr * vr : 0.0, red + 16);
+        const double wr = pr - K * vr;
+        if (below && q == 0) w[r] = wr;
+        __syncthreads();
+        if (below) {
+            for (int c0 = jj + 1 + q; c0 <= r; c0 += 32) {
+                double a[8], wc[8], vc[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int c = min(c0 + 4 * u, r);
+                    a[u] = L[Tr + c];
+                    wc[u] = w[c];
+                    vc[u] = v[c];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int c = c0 + 4 * u;
+                    if (c <= r) L[Tr + c] = a[u] - (vr * wc[u] + wr * vc[u]);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) A[(n - 1) + (int64_t)(n - 1) * ld] = L[(m - 1) * m / 2 + (m - 1)];
 }
 
 // the last diagonal entry, after the final trailing update
@@ -492,9 +662,13 @@ int32_t tridiagonalize_blocked(const SubDev *d_sub, int nsub, int maxnI, double 
     const size_t base = (size_t)(2 * maxnI + SY_G * (maxnI + 1) + 32);
     const size_t npad = (size_t)(maxnI + SYM_RB - 1) / SYM_RB * SYM_RB;
     const size_t shm_lds = (2 * npad + SYM_NW * SYM_RB + (npad / SYM_RB) * npad + 8 + 4 * SY_NB_LDS + 32 +
-                            (size_t)2 * SY_NB_LDS * maxnI) * sizeof(double);
-    if (shm_lds <= (size_t)156 * 1024 && maxnI <= SY_THREADS) {
-        for (int j0 = 0; j0 < maxnI; j0 += SY_NB_LDS) {
+                            3 * SY_NB_LDS + (size_t)2 * SY_NB_LDS * maxnI) * sizeof(double);
+    // the columns from J on (at most SY_TAIL rows left) are reduced in LDS by k_sytrd_tail
+    const bool lds_panels = shm_lds <= (size_t)156 * 1024 && maxnI <= SY_THREADS;
+    const int nb = lds_panels ? SY_NB_LDS : SY_NB;
+    const int J = maxnI > SY_TAIL ? (maxnI - SY_TAIL + nb - 1) / nb * nb : 0;
+    if (lds_panels) {
+        for (int j0 = 0; j0 < J; j0 += SY_NB_LDS) {
             hipLaunchKernelGGL(k_sytrd_panel_lds<SY_NB_LDS>, dim3(nsub), dim3(SY_THREADS), shm_lds, s, d_sub, Sq, VWV,
                                d, e, tau, j0);
             hipLaunchKernelGGL(k_sytrd_update_lower<SY_NB_LDS>, dim3(tiles * (tiles + 1) / 2, nsub), dim3(256), 0, s,
@@ -502,13 +676,17 @@ int32_t tridiagonalize_blocked(const SubDev *d_sub, int nsub, int maxnI, double 
         }
     } else {
         const size_t shm = (base + 4 * SY_NB) * sizeof(double);
-        for (int j0 = 0; j0 < maxnI; j0 += SY_NB) {
+        for (int j0 = 0; j0 < J; j0 += SY_NB) {
             hipLaunchKernelGGL(k_sytrd_panel<SY_NB>, dim3(nsub), dim3(SY_THREADS), shm, s, d_sub, Sq, VWV, d, e,
                                tau, j0);
             hipLaunchKernelGGL(k_sytrd_update<SY_NB>, dim3(tiles * tiles, nsub), dim3(256), 0, s, d_sub, Sq, VWV, j0,
                                tiles);
         }
     }
+    const size_t mt = (size_t)std::min(maxnI - J, SY_TAIL);
+    const size_t shm_tail = (mt * (mt + 1) / 2 + 2 * mt + 32) * sizeof(double);
+    if (mt >= 2)
+        hipLaunchKernelGGL(k_sytrd_tail, dim3(nsub), dim3(SY_TAIL_THREADS), shm_tail, s, d_sub, Sq, d, e, tau, J);
     hipLaunchKernelGGL(k_sytrd_last, dim3(nsub), dim3(64), 0, s, d_sub, Sq, d);
     HKG_HIP(hipGetLastError());
     return HKG_OK;

@@ -83,6 +83,8 @@ extern "C" void hkgeneo_destroy(hkgeneo_ctx *c) {
     if (c->h_infoL) (void)hipHostFree(c->h_infoL);
     if (c->ev_fork3) (void)hipEventDestroy(c->ev_fork3);
     if (c->ev_join3) (void)hipEventDestroy(c->ev_join3);
+    for (hipEvent_t e : c->ev_dc)
+        if (e) (void)hipEventDestroy(e);
     if (c->s2) (void)hipStreamDestroy(c->s2);
     if (c->s3) (void)hipStreamDestroy(c->s3);
     delete c;

@@ -253,12 +253,25 @@ int32_t coarse_inverse_dc(hkgeneo_ctx *c, hipStream_t s, bool *done) {
     }
 
     // ---- merges ------------------------------------------------------------------------------------
+    // Per level, the side stream computes X = A^-1 E_l U, Y = L E_l^T A^-1 and the copies of D^-1 E_f,
+    // E_f^T D^-1 beside the chain that ends in the small inverse (they read only blocks that stay as
+    // they are until S^-1 is formed), and later the two off-diagonal blocks beside X S_ff and the new
+    // A block.  Every buffer region written on one stream is read on the other only after an event.
+    hipStream_t s3 = c->s3;
+    for (hipEvent_t &ev : c->ev_dc)
+        if (!ev) HKG_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
     int flag0 = K;
     for (const Level &L : levels) {
         const int nm = L.nm, f = L.maxf;
         const DMat *mW = reinterpret_cast<const DMat *>(jb + L.mW);
         const int64_t *po = reinterpret_cast<const int64_t *>(jb + L.poff);
         const TriJob *tj = reinterpret_cast<const TriJob *>(jb + L.tri);
+        HKG_HIP(hipEventRecord(c->ev_dc[0], s));
+        HKG_HIP(hipStreamWaitEvent(s3, c->ev_dc[0], 0));
+        HKG_TRY(gemm_batched<double>(J(L.gXa), nm, L.maxa, f, X, B0, ar, 1.0, 0.0, false, false, s3));
+        HKG_TRY(gemm_batched<double>(J(L.gYa), nm, f, L.maxa, B0, X, ar, 1.0, 0.0, false, false, s3));
+        HKG_TRY(copy_blocks_batched(reinterpret_cast<const CopyJob *>(jb + L.cp), 2 * nm, L.maxcopy, X, ar, s3));
+        HKG_HIP(hipEventRecord(c->ev_dc[1], s3));
         HKG_TRY(gemm_batched<double>(J(L.gTq), nm, f, L.maxl, B0, X, ar, 1.0, 0.0, false, false, s));
         HKG_TRY(gemm_batched<double>(J(L.gQ), nm, f, f, ar, B0, ar, 1.0, 0.0, false, false, s));
         HKG_TRY(identity_batched(mW, nm, f, ar, s));
@@ -272,15 +285,17 @@ int32_t coarse_inverse_dc(hkgeneo_ctx *c, hipStream_t s, bool *done) {
             HKG_TRY(tri_solve_batched<double>(tj, nm, f, f, ar, ar, TRI_UPPER, s));
         }
         HKG_TRY(gemm_batched<double>(J(L.gK), nm, f, f, ar, ar, ar, 1.0, 0.0, false, false, s));
-        HKG_TRY(copy_blocks_batched(reinterpret_cast<const CopyJob *>(jb + L.cp), 2 * nm, L.maxcopy, X, ar, s));
+        HKG_HIP(hipStreamWaitEvent(s, c->ev_dc[1], 0));
         HKG_TRY(gemm_batched<double>(J(L.gPK), nm, L.maxd, f, ar, ar, ar, 1.0, 0.0, false, false, s));
         HKG_TRY(gemm_batched<double>(J(L.gUpd), nm, L.maxd, L.maxd, ar, ar, X, 1.0, 1.0, false, false, s));
-        HKG_TRY(gemm_batched<double>(J(L.gXa), nm, L.maxa, f, X, B0, ar, 1.0, 0.0, false, false, s));
-        HKG_TRY(gemm_batched<double>(J(L.gYa), nm, f, L.maxa, B0, X, ar, 1.0, 0.0, false, false, s));
+        HKG_HIP(hipEventRecord(c->ev_dc[2], s));
+        HKG_HIP(hipStreamWaitEvent(s3, c->ev_dc[2], 0));
+        HKG_TRY(gemm_batched<double>(J(L.gAD), nm, L.maxa, L.maxd, ar, X, X, -1.0, 0.0, false, false, s3));
+        HKG_TRY(gemm_batched<double>(J(L.gDA), nm, L.maxd, L.maxa, X, ar, X, -1.0, 0.0, false, false, s3));
+        HKG_HIP(hipEventRecord(c->ev_dc[3], s3));
         HKG_TRY(gemm_batched<double>(J(L.gXaS), nm, L.maxa, f, ar, X, ar, 1.0, 0.0, false, false, s));
-        HKG_TRY(gemm_batched<double>(J(L.gAD), nm, L.maxa, L.maxd, ar, X, X, -1.0, 0.0, false, false, s));
-        HKG_TRY(gemm_batched<double>(J(L.gDA), nm, L.maxd, L.maxa, X, ar, X, -1.0, 0.0, false, false, s));
         HKG_TRY(gemm_batched<double>(J(L.gAA), nm, L.maxa, L.maxa, ar, ar, X, 1.0, 1.0, false, false, s));
+        HKG_HIP(hipStreamWaitEvent(s, c->ev_dc[3], 0));
         flag0 += nm;
     }
     std::vector<int32_t> flags(nflags);

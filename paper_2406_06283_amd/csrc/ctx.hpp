@@ -44,6 +44,8 @@ struct hkgeneo_ctx {
     // a third stream factors C_II while the Gamma block and the Schur complement are formed
     hipStream_t s3 = nullptr;
     hipEvent_t ev_fork3 = nullptr, ev_join3 = nullptr;
+    // the divide-and-conquer inverse of B_0 runs part of each merge level on s3
+    hipEvent_t ev_dc[4] = {nullptr, nullptr, nullptr, nullptr};
     int32_t *h_infoL = nullptr;
     int h_infoL_n = 0;
     // apply workspace

@@ -68,7 +68,7 @@ extern "C" void hkgeneo_destroy(hkgeneo_ctx *c) {
     c->fine = nullptr;
     DevBuf *bufs[] = {&c->rowptr, &c->colidx, &c->Aval,    &c->Sval,   &c->I_idx,   &c->G_idx,      &c->winv,
                       &c->wloc,   &c->tp_ptr, &c->tp_pos,  &c->tp_sub, &c->subs_d, &c->bandK,   &c->bandM,      &c->bandLoc,
-                      &c->pairs,  &c->matsGG, &c->matsSq,  &c->poffSub, &c->jobsGI, &c->jobsSq,     &c->gjobsSchur,
+                      &c->pairs,  &c->matsGG, &c->matsSq,  &c->poffSub, &c->jobsGI, &c->jobsSq, &c->jobsSqM, &c->gjobsSchur,
                       &c->matsLoc, &c->poffLoc, &c->jobsLoc, &c->matsM, &c->jobsM, &c->jobsGGinv, &c->gjobsGX, &c->Bval, &c->Minv,    &c->Z, &c->Zr,  &c->tpZ, &c->B0inv, &c->B0copy,
                       &c->u,      &c->c,      &c->y,       &c->ypart, &c->itersd,       &c->V,      &c->Zk,      &c->H,          &c->cs,
                       &c->sn,     &c->g,      &c->part,    &c->hcol,   &c->scal,    &c->active,     &c->want,

@@ -25,7 +25,7 @@ struct hkgeneo_ctx {
     // resident inputs and static descriptors (analysis phase)
     hkg::DevBuf rowptr, colidx, Aval, Sval, I_idx, G_idx, winv, wloc, tp_ptr, tp_pos, tp_sub, subs_d;
     hkg::DevBuf bandK, bandM, bandLoc, pairs;
-    hkg::DevBuf matsGG, matsSq, poffSub, jobsGI, jobsSq, gjobsSchur, matsLoc, poffLoc, jobsLoc, matsM, jobsM;
+    hkg::DevBuf matsGG, matsSq, poffSub, jobsGI, jobsSq, jobsSqM, gjobsSchur, matsLoc, poffLoc, jobsLoc, matsM, jobsM;
     // numeric results (factorisation phase)
     hkg::DevBuf Bval, Minv, Z, Zr, B0inv;
     hkg::DevBuf tpZ;                      // per transpose-map position: its row of Z_i and slice of y

@@ -1260,6 +1260,141 @@ template int32_t tri_solve_batched<double>(const TriJob *, int, int, int, const 
                                            int, const double *);
 
 // ------------------------------------------------------------------------------------------------
+// L^{-1} applied to many right-hand sides, L the unit lower factor of a packed L D L^T with
+// half-bandwidth band <= BW: one thread per right-hand side and no barrier after the staging.  Thread
+// c keeps the last BW entries of its solution in registers (entry k in slot k mod BW, a compile-time
+// index in the loop unrolled BW times), reads its right-hand side one block of BW entries ahead and
+// writes its solution a block at a time.  Right-hand side c is row c of the input at the jobs'
+// (offX, ldX) (consecutive threads read consecutive entries) or, with IN_COLS, its column c (a
+// thread reads consecutive entries, two at a time); solution c is written as row c of the output at
+// (offO, ldO) (consecutive threads write consecutive entries), with SCALE as D^{-1/2} Y D^{-1/2}.
+// Row k of the band of L (L[k][k-1-i], i < BW, zero outside the band) and D^{-1/2} are staged in LDS.
+// ------------------------------------------------------------------------------------------------
+constexpr int TLW_THREADS = 256;
+
+template <int BW, bool SCALE, bool IN_COLS>
+__global__ __launch_bounds__(TLW_THREADS) void k_tri_lower_window(const TriJob *__restrict__ jobs,
+                                                                  const double *__restrict__ Tb,
+                                                                  const double *__restrict__ Xin,
+                                                                  double *__restrict__ Xout, int band) {
+    extern __shared__ double shl[];
+    const TriJob J = jobs[blockIdx.y];
+    const int n = J.n;
+    if ((int)blockIdx.x * TLW_THREADS >= J.ncol || n == 0) return;
+    const int tid = threadIdx.x, c = blockIdx.x * TLW_THREADS + tid;
+    double *Lb = shl;                            // n x BW
+    double *dsc = Lb + (int64_t)n * BW;          // n
+    const double *Tm = Tb + J.offT;
+    staged_copy<8>(
+        n * BW, tid, TLW_THREADS,
+        [&](int e) {
+            const int k = e / BW, i = e % BW, col = max(k - 1 - i, 0);
+            return Tm[k + (int64_t)col * J.ldT];
+        },
+        [&](int e, double v) {
+            const int k = e / BW, i = e % BW;
+            Lb[e] = (i < band && k - 1 - i >= 0) ? v : 0.0;
+        });
+    if (SCALE)
+        for (int k = tid; k < n; k += TLW_THREADS) dsc[k] = 1.0 / sqrt(Tm[k + (int64_t)k * J.ldT]);
+    __syncthreads();
+    if (c >= J.ncol) return;
+    const int64_t ldx = J.ldX, ldo = J.ldO;
+    const double *xin = IN_COLS ? Xin + J.offX + (int64_t)c * ldx : Xin + J.offX + c;
+    double *out = Xout + J.offO + c;             // entry k at out[k ldO]
+    const double sc = SCALE ? dsc[min(c, n - 1)] : 1.0;
+    const int klast = IN_COLS ? (n - 1) & ~1 : n - 1;   // pairs (k, k + 1) stay inside the padded column
+    auto load_block = [&](int k0, double *b) {
+        if (IN_COLS) {
+#pragma unroll
+            for (int u = 0; u < BW; u += 2) {
+                const double2 v = *reinterpret_cast<const double2 *>(xin + min(k0 + u, klast));
+                b[u] = v.x;
+                b[u + 1] = v.y;
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < BW; ++u) b[u] = xin[(int64_t)min(k0 + u, klast) * ldx];
+        }
+    };
+    double win[BW], Lc[BW], b[BW];
+#pragma unroll
+    for (int u = 0; u < BW; ++u) {
+        win[u] = 0.0;
+        Lc[u] = Lb[u];
+    }
+    load_block(0, b);
+    for (int k0 = 0; k0 < n; k0 += BW) {
+#pragma unroll
+        for (int u = 0; u < BW; ++u) {
+            // the next row of the band is read while this one is used
+            const double *Ln = Lb + (int64_t)min(k0 + u + 1, n - 1) * BW;
+            double Lx[BW];
+#pragma unroll
+            for (int i = 0; i < BW; ++i) Lx[i] = Ln[i];
+            double s0 = b[u], s1 = 0.0;
+#pragma unroll
+            for (int i = BW - 1; i >= 1; --i) {
+                const double xv = win[(u - 1 - i + 2 * BW) % BW];
+                if (i & 1) s1 = fma(-Lc[i], xv, s1);
+                else s0 = fma(-Lc[i], xv, s0);
+            }
+            double x = fma(-Lc[0], win[(u - 1 + BW) % BW], s0 + s1);
+            asm volatile("" : "+v"(x) : : "memory");    // no band row read before the step ends
+            win[u] = x;
+#pragma unroll
+            for (int i = 0; i < BW; ++i) Lc[i] = Lx[i];
+        }
+        // the next block's right-hand side is read before this block's solution is written, so that
+        // waiting for the reads does not wait for the writes
+        load_block(k0 + BW, b);
+#pragma unroll
+        for (int u = 0; u < BW; ++u) {
+            const int k = k0 + u;
+            if (k < n) out[k * ldo] = SCALE ? win[u] * dsc[k] * sc : win[u];
+        }
+    }
+}
+
+static int tlw_width(int band) {
+    if (band < 0) return 0;
+    for (int bw : {16, 24, 32})
+        if (band <= bw) return bw;
+    return 0;
+}
+
+static size_t tlw_lds(int maxn, int bw) { return (size_t)maxn * (bw + 1) * sizeof(double); }
+
+bool tri_lower_window_fits(int maxn, int band) {
+    const int bw = tlw_width(band);
+    return bw > 0 && tlw_lds(maxn, bw) <= (size_t)156 * 1024;
+}
+
+int32_t tri_lower_window_batched(const TriJob *d_jobs, int nbatch, int maxn, int maxcol, const double *Tm,
+                                 const double *Xin, bool in_cols, double *Xout, bool scale, int band,
+                                 hipStream_t s) {
+    if (nbatch == 0 || maxn == 0 || maxcol == 0) return HKG_OK;
+    if (!tri_lower_window_fits(maxn, band)) return HKG_EINVAL;
+    const int bw = tlw_width(band);
+    const size_t shm = tlw_lds(maxn, bw);
+    const dim3 g((maxcol + TLW_THREADS - 1) / TLW_THREADS, nbatch);
+#define HKG_TLW(BW)                                                                                                    \
+    if (bw == BW) {                                                                                                    \
+        if (scale && in_cols) hipLaunchKernelGGL((k_tri_lower_window<BW, true, true>), g, dim3(TLW_THREADS), shm, s,  \
+                                                 d_jobs, Tm, Xin, Xout, band);                                         \
+        else if (!scale && !in_cols) hipLaunchKernelGGL((k_tri_lower_window<BW, false, false>), g, dim3(TLW_THREADS),  \
+                                                        shm, s, d_jobs, Tm, Xin, Xout, band);                          \
+        else return HKG_EINVAL;                                                                                        \
+    }
+    HKG_TLW(16)
+    HKG_TLW(24)
+    HKG_TLW(32)
+#undef HKG_TLW
+    HKG_HIP(hipGetLastError());
+    return HKG_OK;
+}
+
+// ------------------------------------------------------------------------------------------------
 // Inverse of one packed LU (P A = L U) by recursive block triangular inversion: the LU_NB diagonal
 // blocks of L (unit lower) and U are inverted here; the driver then joins neighbouring blocks level
 // by level with GEMMs ([[A, 0], [C, D]]^{-1} has off-diagonal block -D^{-1} C A^{-1}), forms

@@ -175,7 +175,7 @@ int32_t analyze(hkgeneo_ctx *c, const hkgeneo_problem *p, hipStream_t s, int32_t
     // descriptors for the batched dense kernels
     std::vector<DMat> hGG(ns), hSq(ns);
     std::vector<int64_t> hpo(ns), hpl(ns);
-    std::vector<TriJob> jGI(ns), jSq(ns), jM(ns);
+    std::vector<TriJob> jGI(ns), jSq(ns), jSqM(ns), jM(ns);
     std::vector<DMat> hM(ns);
     std::vector<GemmJob> gS(ns), gX(ns);
     std::vector<CopyJob> jGinv(ns);
@@ -190,6 +190,7 @@ int32_t analyze(hkgeneo_ctx *c, const hkgeneo_problem *p, hipStream_t s, int32_t
         pl += sd.nI;
         jGI[i] = {sd.offGG, sd.offGI, sd.nG, ldG, sd.nI, ldG};
         jSq[i] = {sd.offSq, sd.offSq, sd.nI, sd.nI, sd.nI, sd.nI, sd.offM, sd.ldM};
+        jSqM[i] = {sd.offSq, sd.offM, sd.nI, sd.nI, sd.nI, sd.ldM, sd.offM, sd.ldM};
         hM[i] = {sd.offM, sd.nI, sd.ldM};
         jM[i] = {sd.offSq, sd.offM, sd.nI, sd.nI, sd.nI, sd.ldM};
         gS[i] = {sd.offBIO + (int64_t)sd.nI * sd.nI, sd.offGI, sd.offSq, sd.nI, sd.nI, sd.nG, sd.nI, ldG, sd.nI};
@@ -202,6 +203,7 @@ int32_t analyze(hkgeneo_ctx *c, const hkgeneo_problem *p, hipStream_t s, int32_t
     HKG_TRY(upload(c, &c->poffLoc, hpl.data(), ns, s));
     HKG_TRY(upload(c, &c->jobsGI, jGI.data(), ns, s));
     HKG_TRY(upload(c, &c->jobsSq, jSq.data(), ns, s));
+    HKG_TRY(upload(c, &c->jobsSqM, jSqM.data(), ns, s));
     HKG_TRY(upload(c, &c->matsM, hM.data(), ns, s));
     HKG_TRY(upload(c, &c->jobsM, jM.data(), ns, s));
     HKG_TRY(upload(c, &c->gjobsSchur, gS.data(), ns, s));
@@ -356,7 +358,7 @@ int32_t coarse_space(hkgeneo_ctx *c, hipStream_t s, const std::function<int32_t(
     HKG_TRY(walloc(c, &c->wGG, std::max<int64_t>(c->nGG, 1) * sizeof(double)));
     HKG_TRY(walloc(c, &c->wGI, std::max<int64_t>(c->nGI, 1) * sizeof(double)));
     HKG_TRY(walloc(c, &c->wS, c->nSq * sizeof(double)));
-    HKG_TRY(walloc(c, &c->wW, c->nSq * sizeof(double)));
+    HKG_TRY(walloc(c, &c->wW, (size_t)std::max(c->nSq, c->nM) * sizeof(double)));
     HKG_TRY(walloc(c, &c->wPiv, c->nPiv * sizeof(int32_t)));
     HKG_TRY(walloc(c, &c->wInfo, ns * sizeof(int32_t)));
     HKG_TRY(walloc(c, &c->wFlag, ns * sizeof(int32_t)));
@@ -436,19 +438,31 @@ int32_t coarse_space(hkgeneo_ctx *c, hipStream_t s, const std::function<int32_t(
         return st_cii;
     }
     HKG_HIP(hipStreamWaitEvent(s, c->ev_join3, 0));
-    HKG_TRY(tri_solve_batched<double>(dp<TriJob>(c->jobsSq), ns, c->max_nI, c->max_nI, dp<double>(c->wCII),
-                                      dp<double>(c->wS), TRI_LOWER_UNIT, s, c->band_I));
-    HKG_TRY(walloc(c, &c->wT, (size_t)c->nM * sizeof(double)));
-    if (tri_band_fits(c->max_nI, c->band_I, sizeof(double))) {
-        // the transpose read on the fly, D^{-1/2} on both sides applied as the result is written
-        // into the padded layout of the tridiagonalisation
-        HKG_TRY(tri_solve_batched<double>(dp<TriJob>(c->jobsSq), ns, c->max_nI, c->max_nI, dp<double>(c->wCII),
-                                          dp<double>(c->wT), TRI_LOWER_UNIT, s, c->band_I, dp<double>(c->wS)));
+    if (tri_lower_window_fits(c->max_nI, c->band_I)) {
+        // X = L^{-1} S, right-hand side j read as row j of S (S is symmetric), written as X^T into wW
+        // in the padded layout; then D^{-1/2} L^{-1} X^T D^{-1/2} (right-hand side j: row j of X, the
+        // column j of wW) into the padded layout of the tridiagonalisation.  One thread per
+        // right-hand side, the band of L in LDS, every global access coalesced or a thread's own run.
+        HKG_TRY(walloc(c, &c->wT, (size_t)c->nM * sizeof(double)));
+        HKG_TRY(tri_lower_window_batched(dp<TriJob>(c->jobsSq), ns, c->max_nI, c->max_nI, dp<double>(c->wCII),
+                                         dp<double>(c->wS), false, dp<double>(c->wW), false, c->band_I, s));
+        HKG_TRY(tri_lower_window_batched(dp<TriJob>(c->jobsSqM), ns, c->max_nI, c->max_nI, dp<double>(c->wCII),
+                                         dp<double>(c->wW), true, dp<double>(c->wT), true, c->band_I, s));
     } else {
-        HKG_TRY(transpose_batched<double>(dp<DMat>(c->matsSq), ns, c->max_nI, dp<double>(c->wS), dp<double>(c->wW), s));
         HKG_TRY(tri_solve_batched<double>(dp<TriJob>(c->jobsSq), ns, c->max_nI, c->max_nI, dp<double>(c->wCII),
-                                          dp<double>(c->wW), TRI_LOWER_UNIT, s, c->band_I));
-        HKG_TRY(scale_sym(dsub, ns, c->max_nI, dp<double>(c->wCII), dp<double>(c->wW), dp<double>(c->wT), s));
+                                          dp<double>(c->wS), TRI_LOWER_UNIT, s, c->band_I));
+        HKG_TRY(walloc(c, &c->wT, (size_t)c->nM * sizeof(double)));
+        if (tri_band_fits(c->max_nI, c->band_I, sizeof(double))) {
+            // the transpose read on the fly, D^{-1/2} on both sides applied as the result is written
+            // into the padded layout of the tridiagonalisation
+            HKG_TRY(tri_solve_batched<double>(dp<TriJob>(c->jobsSq), ns, c->max_nI, c->max_nI, dp<double>(c->wCII),
+                                              dp<double>(c->wT), TRI_LOWER_UNIT, s, c->band_I, dp<double>(c->wS)));
+        } else {
+            HKG_TRY(transpose_batched<double>(dp<DMat>(c->matsSq), ns, c->max_nI, dp<double>(c->wS), dp<double>(c->wW), s));
+            HKG_TRY(tri_solve_batched<double>(dp<TriJob>(c->jobsSq), ns, c->max_nI, c->max_nI, dp<double>(c->wCII),
+                                              dp<double>(c->wW), TRI_LOWER_UNIT, s, c->band_I));
+            HKG_TRY(scale_sym(dsub, ns, c->max_nI, dp<double>(c->wCII), dp<double>(c->wW), dp<double>(c->wT), s));
+        }
     }
     // tridiagonal form and selection
     HKG_TRY(walloc(c, &c->wD, c->sum_nI * sizeof(double)));

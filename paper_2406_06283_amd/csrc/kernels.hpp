@@ -24,6 +24,14 @@ int32_t tri_solve_batched(const TriJob *d_jobs, int nbatch, int maxn, int maxcol
                           hipStream_t s, int band = -1, const T *Xin = nullptr);
 // whether the one-launch banded solve serves matrices of up to maxn rows with this half-bandwidth
 bool tri_band_fits(int maxn, int band, size_t elem);
+// Y = L^{-1} R for square right-hand sides, L the unit lower factor of the packed L D L^T Tm with
+// half-bandwidth band: right-hand side c is row c of Xin at the jobs' (offX, ldX) (in_cols: its
+// column c, with offX and ldX even); solution c is written as row c of Xout at (offO, ldO), with
+// `scale` as D^{-1/2} Y D^{-1/2}.  Two combinations: (in rows, no scale), (in columns, scale).
+bool tri_lower_window_fits(int maxn, int band);
+int32_t tri_lower_window_batched(const TriJob *d_jobs, int nbatch, int maxn, int maxcol, const double *Tm,
+                                 const double *Xin, bool in_cols, double *Xout, bool scale, int band,
+                                 hipStream_t s);
 constexpr int LU_BLOCK = 32;    // block size of the dense LU, triangular solves and inversions
 
 // diagonal LU_BLOCK blocks of L^{-1} (unit lower) and U^{-1} of one packed LU, into Linv / Uinv

@@ -1136,9 +1136,115 @@ __global__ __launch_bounds__(64) void k_back_transform(const SubDev *__restrict_
     for (int i = lane; i < n; i += 64) z[i] = zs[i];
 }
 
+// The same with one workgroup per subdomain: the subdomain's eigenvectors stay in registers (wave w
+// holds eigenvectors w, w + BT_WAVES, ...; lane l rows l + 64 k), and the reflectors are staged in
+// LDS a panel of BT_PB at a time (reflector q of a panel in row q, zero outside rows j+1 .. n-1), the
+// next panel's loads in flight while the current panel is applied: one global round trip per panel
+// instead of one per reflector.  E = eigenvectors per wave at most; n <= 64 NB.
+constexpr int BT_PB = 8;
+constexpr int BT_WAVES = 16;
+
+template <int NB, int E>
+__global__ __launch_bounds__(64 * BT_WAVES) void k_back_transform_panel(const SubDev *__restrict__ subs,
+                                                                        const double *__restrict__ Sq,
+                                                                        const double *__restrict__ taub,
+                                                                        double *__restrict__ Zb) {
+    constexpr int NP = 64 * NB;                    // panel row stride
+    constexpr int NT = 64 * BT_WAVES;
+    constexpr int PER = BT_PB * NP / NT;           // panel entries staged per thread
+    __shared__ double pv[2][BT_PB * NP];
+    __shared__ double pt[2][BT_PB];
+    const SubDev sd = subs[blockIdx.x];
+    const int n = sd.nI, m = sd.m;
+    if (m == 0 || n < 2) return;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const double *A = Sq + sd.offM;
+    const int ld = sd.ldM;
+    const double *tau = taub + sd.offI;
+    double *Z = Zb + sd.offZ;
+    double z[E][NB];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int c = w + BT_WAVES * e;
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            const int r = lane + 64 * k;
+            z[e][k] = (c < m && r < n) ? Z[(int64_t)c * n + r] : 0.0;
+        }
+    }
+    // panel p: reflectors j = n - 2 - p BT_PB - q, q < BT_PB (the order of application)
+    const int npanel = (n - 1 + BT_PB - 1) / BT_PB;
+    double reg[PER], treg = 0.0;
+    auto load_panel = [&](int p) {
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int e = tid + NT * u, q = e / NP, r = e % NP, j = n - 2 - p * BT_PB - q;
+            const bool ok = j >= 0 && r > j && r < n;
+            reg[u] = ok ? A[r + (int64_t)max(j, 0) * ld] : 0.0;
+        }
+        if (tid < BT_PB) {
+            const int j = n - 2 - p * BT_PB - tid;
+            treg = j >= 0 ? tau[j] : 0.0;
+        }
+    };
+    auto store_panel = [&](int b) {
+#pragma unroll
+        for (int u = 0; u < PER; ++u) pv[b][tid + NT * u] = reg[u];
+        if (tid < BT_PB) pt[b][tid] = treg;
+    };
+    load_panel(0);
+    store_panel(0);
+    __syncthreads();
+    for (int p = 0; p < npanel; ++p) {
+        const int b = p & 1;
+        if (p + 1 < npanel) load_panel(p + 1);
+        for (int q = 0; q < BT_PB; ++q) {
+            const double t = pt[b][q];
+            if (t == 0.0) continue;        // H = I (also the slots past reflector 0)
+            double v[NB];
+#pragma unroll
+            for (int k = 0; k < NB; ++k) v[k] = pv[b][q * NP + lane + 64 * k];
+            double sdot[E];
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                double a = 0.0;
+#pragma unroll
+                for (int k = 0; k < NB; ++k) a = fma(v[k], z[e][k], a);
+                sdot[e] = wave_sum(a);
+            }
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const double f = t * sdot[e];
+#pragma unroll
+                for (int k = 0; k < NB; ++k) z[e][k] = fma(-f, v[k], z[e][k]);
+            }
+        }
+        if (p + 1 < npanel) store_panel(b ^ 1);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int c = w + BT_WAVES * e;
+        if (c < m)
+#pragma unroll
+            for (int k = 0; k < NB; ++k) {
+                const int r = lane + 64 * k;
+                if (r < n) Z[(int64_t)c * n + r] = z[e][k];
+            }
+    }
+}
+
 int32_t back_transform_n(const SubDev *d_sub, int nsub, int maxnI, int max_m, const double *Sq, const double *tau,
                          double *Z, hipStream_t s) {
     if (max_m == 0) return HKG_OK;
+    if (maxnI <= 8 * 64 && max_m <= 4 * BT_WAVES) {
+        const dim3 g(nsub), t(64 * BT_WAVES);
+        if (max_m <= BT_WAVES) hipLaunchKernelGGL((k_back_transform_panel<8, 1>), g, t, 0, s, d_sub, Sq, tau, Z);
+        else if (max_m <= 2 * BT_WAVES) hipLaunchKernelGGL((k_back_transform_panel<8, 2>), g, t, 0, s, d_sub, Sq, tau, Z);
+        else hipLaunchKernelGGL((k_back_transform_panel<8, 4>), g, t, 0, s, d_sub, Sq, tau, Z);
+        HKG_HIP(hipGetLastError());
+        return HKG_OK;
+    }
     const size_t shm = (size_t)maxnI * sizeof(double);
     if (maxnI <= 8 * 64)
         hipLaunchKernelGGL(k_back_transform<8>, dim3(nsub, max_m), dim3(64), shm, s, d_sub, Sq, tau, Z);

@@ -748,8 +748,10 @@ __device__ double bisect_kth(const double *d, const double *e2, int n, int k, do
 
 // Selection runs in three launches.  (1) One wave per subdomain: Gershgorin interval, pivot floor of
 // the Sturm recurrence and m from the counts at tau (or nev) and at 0.  (2) One wave per (subdomain,
-// eigenvalue k <= m): the k-th smallest eigenvalue by multisection, the 64 lanes testing 64 interior
-// shifts of the current bracket at once.  (3) One wave per subdomain: the cluster at the cut is
+// eigenvalue k <= m, four to a wave): the k-th smallest eigenvalue by multisection, the 16 lanes
+// of a row testing 16 interior shifts of its bracket at once (the Sturm counts are the cost: 16
+// shifts give 4.1 bits per round for 16 counts, 64 gave 6 bits for 64).  (3) One wave per
+// subdomain: the cluster at the cut is
 // closed (Def. 2.15 keeps lambda_{m+1} away from lambda_m), extending m by serial bisection when
 // needed.
 
@@ -814,16 +816,34 @@ __global__ __launch_bounds__(64) void k_select_count(const SubDev *__restrict__ 
     }
 }
 
-// wave (subdomain, k): lambda_k in (a, b] with count(a) <= k < count(b), narrowed 65-fold per round
+// wave (subdomain, four eigenvalues): 16-lane row r of the wave takes eigenvalue k = 4 y + r, with
+// lambda_k in (a, b] and count(a) <= k < count(b), and narrows the bracket 17-fold per round (16
+// interior shifts, one per lane; the row's new bracket by DPP max / min inside the row)
+__device__ __forceinline__ double row_max16(double v) {
+    v = fmax(v, dpp_f64<DPP_QUAD_XOR1>(v));
+    v = fmax(v, dpp_f64<DPP_QUAD_XOR2>(v));
+    v = fmax(v, dpp_f64<DPP_ROW_HALF_MIRROR>(v));
+    return fmax(v, dpp_f64<DPP_ROW_MIRROR>(v));
+}
+
+__device__ __forceinline__ double row_min16(double v) {
+    v = fmin(v, dpp_f64<DPP_QUAD_XOR1>(v));
+    v = fmin(v, dpp_f64<DPP_QUAD_XOR2>(v));
+    v = fmin(v, dpp_f64<DPP_ROW_HALF_MIRROR>(v));
+    return fmin(v, dpp_f64<DPP_ROW_MIRROR>(v));
+}
+
 __global__ __launch_bounds__(64) void k_select_refine(const SubDev *__restrict__ subs, const double *__restrict__ dbuf,
                                                       const double *__restrict__ ebuf, int mmax, double tau,
                                                       const int32_t *__restrict__ m_in, const int32_t *__restrict__ flag,
                                                       const double *__restrict__ iv, double *__restrict__ lam_out) {
     extern __shared__ double sh[];
-    const int sub = blockIdx.x, k = blockIdx.y;
+    const int sub = blockIdx.x, lane = threadIdx.x, t = lane & 15;
+    const int k = 4 * blockIdx.y + (lane >> 4);
     const SubDev sd = subs[sub];
     const int n = sd.nI;
-    if (flag[sub] || k >= min(n, m_in[sub] + 1)) return;
+    const int kend = min(n, m_in[sub] + 1);
+    if (flag[sub] || 4 * (int)blockIdx.y >= kend) return;
     double *d = sh, *e2 = sh + n;
     double lo0, hi0, pv0;
     stage_tridiagonal(dbuf + sd.offI, ebuf + sd.offI, n, d, e2, &lo0, &hi0, &pv0);
@@ -832,20 +852,19 @@ __global__ __launch_bounds__(64) void k_select_refine(const SubDev *__restrict__
     // count(tau) > k or count(0) > k: the bracket (a, b] may end at that shift
     if (k < (int)iv[IV_SLOTS * sub + 3]) b = fmin(b, tau);
     if (k < (int)iv[IV_SLOTS * sub + 4]) b = fmin(b, 0.0);
-    const int lane = threadIdx.x;
-    for (int it = 0; it < 40; ++it) {
-        const double sig = a + (b - a) * ((double)(lane + 1) / 65.0);
-        const bool inside = sig > a && sig < b;
-        const int cnt = inside ? sturm_count_nr(d, e2, n, sig, pivmin) : 0;
-        double na = (inside && cnt <= k) ? sig : a;
-        double nb = (inside && cnt > k) ? sig : b;
-        na = wave_max64(na);
-        nb = wave_min64(nb);
-        if (na == a && nb == b) break;     // the bracket cannot be split further
+    bool done = k >= kend;               // rows past the last eigenvalue take part without a result
+    for (int it = 0; it < 80; ++it) {
+        const double sig = a + (b - a) * ((double)(t + 1) / 17.0);
+        const bool inside = !done && sig > a && sig < b;
+        const int cnt = sturm_count_nr(d, e2, n, sig, pivmin);
+        const double na = row_max16((inside && cnt <= k) ? sig : a);
+        const double nb = row_min16((inside && cnt > k) ? sig : b);
+        if (na == a && nb == b) done = true;     // the bracket cannot be split further
         a = na;
         b = nb;
+        if (__all(done)) break;
     }
-    if (lane == 0) lam_out[(int64_t)sub * (mmax + 2) + k] = 0.5 * (a + b);
+    if (t == 0 && k < kend) lam_out[(int64_t)sub * (mmax + 2) + k] = 0.5 * (a + b);
 }
 
 // close a cluster at the cut: lambda_{m+1} - lambda_m <= rtol max(1, |lambda_m|) moves the cut up
@@ -878,7 +897,7 @@ int32_t select_eigs(const SubDev *d_sub, int nsub, int maxnI, const double *d, c
                     hipStream_t s) {
     const size_t shm = (size_t)2 * maxnI * sizeof(double);
     hipLaunchKernelGGL(k_select_count, dim3(nsub), dim3(64), shm, s, d_sub, d, e, mode, tau, nev, mmax, m_out, flag, iv);
-    hipLaunchKernelGGL(k_select_refine, dim3(nsub, mmax + 1), dim3(64), shm, s, d_sub, d, e, mmax, tau, m_out, flag,
+    hipLaunchKernelGGL(k_select_refine, dim3(nsub, (mmax + 1 + 3) / 4), dim3(64), shm, s, d_sub, d, e, mmax, tau, m_out, flag,
                        iv, lam_out);
     hipLaunchKernelGGL(k_select_close, dim3(nsub), dim3(64), shm, s, d_sub, d, e, rtol, mmax, m_out, flag, iv, lam_out);
     HKG_HIP(hipGetLastError());

@@ -748,9 +748,9 @@ __device__ double bisect_kth(const double *d, const double *e2, int n, int k, do
 
 // Selection runs in three launches.  (1) One wave per subdomain: Gershgorin interval, pivot floor of
 // the Sturm recurrence and m from the counts at tau (or nev) and at 0.  (2) One wave per (subdomain,
-// eigenvalue k <= m, four to a wave): the k-th smallest eigenvalue by multisection, the 16 lanes
-// of a row testing 16 interior shifts of its bracket at once (the Sturm counts are the cost: 16
-// shifts give 4.1 bits per round for 16 counts, 64 gave 6 bits for 64).  (3) One wave per
+// eigenvalue k <= m, eight to a wave): the k-th smallest eigenvalue by multisection, the 8 lanes
+// of a group testing 8 interior shifts of its bracket at once (the Sturm counts are the cost: 8
+// shifts give 3.2 bits per round for 8 counts, 64 gave 6 bits for 64).  (3) One wave per
 // subdomain: the cluster at the cut is
 // closed (Def. 2.15 keeps lambda_{m+1} away from lambda_m), extending m by serial bisection when
 // needed.
@@ -816,21 +816,19 @@ __global__ __launch_bounds__(64) void k_select_count(const SubDev *__restrict__ 
     }
 }
 
-// wave (subdomain, four eigenvalues): 16-lane row r of the wave takes eigenvalue k = 4 y + r, with
-// lambda_k in (a, b] and count(a) <= k < count(b), and narrows the bracket 17-fold per round (16
-// interior shifts, one per lane; the row's new bracket by DPP max / min inside the row)
-__device__ __forceinline__ double row_max16(double v) {
+// wave (subdomain, eight eigenvalues): 8-lane group r of the wave takes eigenvalue k = 8 y + r, with
+// lambda_k in (a, b] and count(a) <= k < count(b), and narrows the bracket 9-fold per round (8
+// interior shifts, one per lane; the group's new bracket by DPP max / min inside the group)
+__device__ __forceinline__ double group_max8(double v) {
     v = fmax(v, dpp_f64<DPP_QUAD_XOR1>(v));
     v = fmax(v, dpp_f64<DPP_QUAD_XOR2>(v));
-    v = fmax(v, dpp_f64<DPP_ROW_HALF_MIRROR>(v));
-    return fmax(v, dpp_f64<DPP_ROW_MIRROR>(v));
+    return fmax(v, dpp_f64<DPP_ROW_HALF_MIRROR>(v));
 }
 
-__device__ __forceinline__ double row_min16(double v) {
+__device__ __forceinline__ double group_min8(double v) {
     v = fmin(v, dpp_f64<DPP_QUAD_XOR1>(v));
     v = fmin(v, dpp_f64<DPP_QUAD_XOR2>(v));
-    v = fmin(v, dpp_f64<DPP_ROW_HALF_MIRROR>(v));
-    return fmin(v, dpp_f64<DPP_ROW_MIRROR>(v));
+    return fmin(v, dpp_f64<DPP_ROW_HALF_MIRROR>(v));
 }
 
 __global__ __launch_bounds__(64) void k_select_refine(const SubDev *__restrict__ subs, const double *__restrict__ dbuf,
@@ -838,12 +836,12 @@ __global__ __launch_bounds__(64) void k_select_refine(const SubDev *__restrict__
                                                       const int32_t *__restrict__ m_in, const int32_t *__restrict__ flag,
                                                       const double *__restrict__ iv, double *__restrict__ lam_out) {
     extern __shared__ double sh[];
-    const int sub = blockIdx.x, lane = threadIdx.x, t = lane & 15;
-    const int k = 4 * blockIdx.y + (lane >> 4);
+    const int sub = blockIdx.x, lane = threadIdx.x, t = lane & 7;
+    const int k = 8 * blockIdx.y + (lane >> 3);
     const SubDev sd = subs[sub];
     const int n = sd.nI;
     const int kend = min(n, m_in[sub] + 1);
-    if (flag[sub] || 4 * (int)blockIdx.y >= kend) return;
+    if (flag[sub] || 8 * (int)blockIdx.y >= kend) return;
     double *d = sh, *e2 = sh + n;
     double lo0, hi0, pv0;
     stage_tridiagonal(dbuf + sd.offI, ebuf + sd.offI, n, d, e2, &lo0, &hi0, &pv0);
@@ -853,12 +851,12 @@ __global__ __launch_bounds__(64) void k_select_refine(const SubDev *__restrict__
     if (k < (int)iv[IV_SLOTS * sub + 3]) b = fmin(b, tau);
     if (k < (int)iv[IV_SLOTS * sub + 4]) b = fmin(b, 0.0);
     bool done = k >= kend;               // rows past the last eigenvalue take part without a result
-    for (int it = 0; it < 80; ++it) {
-        const double sig = a + (b - a) * ((double)(t + 1) / 17.0);
+    for (int it = 0; it < 120; ++it) {
+        const double sig = a + (b - a) * ((double)(t + 1) / 9.0);
         const bool inside = !done && sig > a && sig < b;
         const int cnt = sturm_count_nr(d, e2, n, sig, pivmin);
-        const double na = row_max16((inside && cnt <= k) ? sig : a);
-        const double nb = row_min16((inside && cnt > k) ? sig : b);
+        const double na = group_max8((inside && cnt <= k) ? sig : a);
+        const double nb = group_min8((inside && cnt > k) ? sig : b);
         if (na == a && nb == b) done = true;     // the bracket cannot be split further
         a = na;
         b = nb;
@@ -897,7 +895,7 @@ int32_t select_eigs(const SubDev *d_sub, int nsub, int maxnI, const double *d, c
                     hipStream_t s) {
     const size_t shm = (size_t)2 * maxnI * sizeof(double);
     hipLaunchKernelGGL(k_select_count, dim3(nsub), dim3(64), shm, s, d_sub, d, e, mode, tau, nev, mmax, m_out, flag, iv);
-    hipLaunchKernelGGL(k_select_refine, dim3(nsub, (mmax + 1 + 3) / 4), dim3(64), shm, s, d_sub, d, e, mmax, tau, m_out, flag,
+    hipLaunchKernelGGL(k_select_refine, dim3(nsub, (mmax + 1 + 7) / 8), dim3(64), shm, s, d_sub, d, e, mmax, tau, m_out, flag,
                        iv, lam_out);
     hipLaunchKernelGGL(k_select_close, dim3(nsub), dim3(64), shm, s, d_sub, d, e, rtol, mmax, m_out, flag, iv, lam_out);
     HKG_HIP(hipGetLastError());

@@ -530,7 +530,7 @@ int32_t coarse_space(hkgeneo_ctx *c, hipStream_t s, const std::function<int32_t(
     HKG_TRY(walloc(c, &c->wInv, (size_t)offZ * (5 * sizeof(double) + 1)));
     int64_t max_nm = 0;
     for (int i = 0; i < ns; ++i) max_nm = std::max(max_nm, (int64_t)c->subs[i].nI * c->subs[i].m);
-    HKG_TRY(tridiag_vectors_n(dsub, ns, max_nm, dp<double>(c->wD), dp<double>(c->wE), dp<double>(c->wLam), mmax,
+    HKG_TRY(tridiag_vectors_n(dsub, ns, c->max_nI, max_nm, dp<double>(c->wD), dp<double>(c->wE), dp<double>(c->wLam), mmax,
                               dp<double>(c->Z), dp<double>(c->wInv),
                               reinterpret_cast<unsigned char *>(dp<double>(c->wInv) + 5 * offZ), s));
     HKG_TRY(back_transform_n(dsub, ns, c->max_nI, c->max_m, dp<double>(c->wT), dp<double>(c->wTau), dp<double>(c->Z),

@@ -924,7 +924,8 @@ __device__ __forceinline__ double start_value(int i, int k) {
 // waits on memory once per IU rows
 constexpr int IU = 16;
 
-template <bool LDSB>
+// NBI: rows per lane of a vector held in registers during the orthogonalisation (n <= 64 NBI)
+template <bool LDSB, int NBI>
 __global__ __launch_bounds__(64) void k_inverse_iteration(const SubDev *__restrict__ subs, const double *__restrict__ dbuf,
                                                           const double *__restrict__ ebuf, const double *__restrict__ lam_all,
                                                           int mmax, double *__restrict__ Zb, double *__restrict__ scratch,
@@ -941,6 +942,7 @@ __global__ __launch_bounds__(64) void k_inverse_iteration(const SubDev *__restri
     double *__restrict__ du2 = du + nm;
     double *__restrict__ fac = du2 + nm;
     double *__restrict__ b = LDSB ? sb : fac + nm;
+    __shared__ double scl[64];            // per vector: the scale of the last substitution
     const unsigned char *__restrict__ swp = swp_all + sd.offZ;
     unsigned char *__restrict__ swpw = swp_all + sd.offZ;
     double *Z = Zb + sd.offZ;
@@ -1040,25 +1042,43 @@ __global__ __launch_bounds__(64) void k_inverse_iteration(const SubDev *__restri
                     }
                 }
             }
-            const double inv = mx > 0.0 ? 1.0 / mx : 1.0;
-            for (int i = 0; i < n; ++i) b[(int64_t)i * m + k] *= inv;
+            scl[k] = mx > 0.0 ? 1.0 / mx : 1.0;      // applied as the vector is loaded below
         }
         __syncthreads();
-        // modified Gram-Schmidt inside clusters, then normalisation (the whole wave per vector)
+        // modified Gram-Schmidt inside clusters, then normalisation: the whole wave per vector, the
+        // vector in registers (row lane + 64 j in slot j) from its scaled load to its store
         for (int k = 0; k < m; ++k) {
+            const double sk = scl[k];
+            double bk[NBI];
+#pragma unroll
+            for (int j = 0; j < NBI; ++j) {
+                const int i = lane + 64 * j;
+                bk[j] = i < n ? b[(int64_t)i * m + k] * sk : 0.0;
+            }
             for (int q = 0; q < k; ++q) {
                 if (fabs(lam[q] - lam[k]) > orth_tol) continue;
-                double s = 0.0;
-                for (int i = lane; i < n; i += 64) s += b[(int64_t)i * m + q] * b[(int64_t)i * m + k];
+                double bq[NBI], s = 0.0;
+#pragma unroll
+                for (int j = 0; j < NBI; ++j) {
+                    const int i = lane + 64 * j;
+                    bq[j] = i < n ? b[(int64_t)i * m + q] : 0.0;
+                }
+#pragma unroll
+                for (int j = 0; j < NBI; ++j) s += bq[j] * bk[j];
                 s = wave_sum(s);
-                for (int i = lane; i < n; i += 64) b[(int64_t)i * m + k] -= s * b[(int64_t)i * m + q];
-                __syncthreads();
+#pragma unroll
+                for (int j = 0; j < NBI; ++j) bk[j] -= s * bq[j];
             }
             double s = 0.0;
-            for (int i = lane; i < n; i += 64) s += b[(int64_t)i * m + k] * b[(int64_t)i * m + k];
+#pragma unroll
+            for (int j = 0; j < NBI; ++j) s += bk[j] * bk[j];
             s = wave_sum(s);
             const double inv = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
-            for (int i = lane; i < n; i += 64) b[(int64_t)i * m + k] *= inv;
+#pragma unroll
+            for (int j = 0; j < NBI; ++j) {
+                const int i = lane + 64 * j;
+                if (i < n) b[(int64_t)i * m + k] = bk[j] * inv;
+            }
             __syncthreads();
         }
     }
@@ -1068,15 +1088,26 @@ __global__ __launch_bounds__(64) void k_inverse_iteration(const SubDev *__restri
 
 constexpr size_t II_LDS_MAX = 150 * 1024;
 
-int32_t tridiag_vectors_n(const SubDev *d_sub, int nsub, int64_t max_nm, const double *d, const double *e,
+int32_t tridiag_vectors_n(const SubDev *d_sub, int nsub, int maxnI, int64_t max_nm, const double *d, const double *e,
                           const double *lam, int mmax, double *Z, double *scratch, unsigned char *swp, hipStream_t s) {
+    if (maxnI > 24 * 64) {
+        set_last_error("inverse iteration supports at most 1536 unknowns per subdomain");
+        return HKG_EINVAL;
+    }
     const size_t shm = (size_t)max_nm * sizeof(double);
-    if (shm <= II_LDS_MAX)
-        hipLaunchKernelGGL(k_inverse_iteration<true>, dim3(nsub), dim3(64), shm, s, d_sub, d, e, lam, mmax, Z, scratch,
-                           swp);
+    const bool lds = shm <= II_LDS_MAX, narrow = maxnI <= 8 * 64;
+    if (lds && narrow)
+        hipLaunchKernelGGL((k_inverse_iteration<true, 8>), dim3(nsub), dim3(64), shm, s, d_sub, d, e, lam, mmax, Z,
+                           scratch, swp);
+    else if (lds)
+        hipLaunchKernelGGL((k_inverse_iteration<true, 24>), dim3(nsub), dim3(64), shm, s, d_sub, d, e, lam, mmax, Z,
+                           scratch, swp);
+    else if (narrow)
+        hipLaunchKernelGGL((k_inverse_iteration<false, 8>), dim3(nsub), dim3(64), 0, s, d_sub, d, e, lam, mmax, Z,
+                           scratch, swp);
     else
-        hipLaunchKernelGGL(k_inverse_iteration<false>, dim3(nsub), dim3(64), 0, s, d_sub, d, e, lam, mmax, Z, scratch,
-                           swp);
+        hipLaunchKernelGGL((k_inverse_iteration<false, 24>), dim3(nsub), dim3(64), 0, s, d_sub, d, e, lam, mmax, Z,
+                           scratch, swp);
     HKG_HIP(hipGetLastError());
     return HKG_OK;
 }

@@ -107,7 +107,7 @@ int32_t select_eigs(const SubDev *d_sub, int nsub, int maxnI, const double *d, c
                     hipStream_t s);
 // inverse iteration for the selected eigenvectors of T (one wave per subdomain); max_nm = the
 // largest n_I m_i (the iterates are staged in LDS when they fit)
-int32_t tridiag_vectors_n(const SubDev *d_sub, int nsub, int64_t max_nm, const double *d, const double *e,
+int32_t tridiag_vectors_n(const SubDev *d_sub, int nsub, int maxnI, int64_t max_nm, const double *d, const double *e,
                           const double *lam, int mmax, double *Z, double *scratch, unsigned char *swp, hipStream_t s);
 int32_t back_transform_n(const SubDev *d_sub, int nsub, int maxnI, int max_m, const double *Sq, const double *tau,
                          double *Z, hipStream_t s);

@@ -81,6 +81,8 @@ extern "C" void hkgeneo_destroy(hkgeneo_ctx *c) {
     if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
     if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     if (c->h_infoL) (void)hipHostFree(c->h_infoL);
+    if (c->h_stage) (void)hipHostFree(c->h_stage);
+    if (c->h_read) (void)hipHostFree(c->h_read);
     if (c->ev_fork3) (void)hipEventDestroy(c->ev_fork3);
     if (c->ev_join3) (void)hipEventDestroy(c->ev_join3);
     for (hipEvent_t e : c->ev_dc)

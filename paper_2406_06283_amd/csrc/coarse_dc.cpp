@@ -225,7 +225,7 @@ int32_t coarse_inverse_dc(hkgeneo_ctx *c, hipStream_t s, bool *done) {
     }
 
     // ---- device buffers ----------------------------------------------------------------------------
-    HKG_TRY(upload_bytes(c, &c->wDCjobs, blob.bytes.data(), blob.bytes.size(), s, true));
+    HKG_TRY(upload_staged(c, &c->wDCjobs, blob.bytes.data(), blob.bytes.size(), s));
     HKG_TRY(walloc(c, &c->wDC, (size_t)arena * sizeof(double)));
     HKG_TRY(walloc(c, &c->wDCpiv, (size_t)std::max(pivLeaf, pivMerge) * sizeof(int32_t)));
     HKG_TRY(walloc(c, &c->wDCinfo, (size_t)nflags * sizeof(int32_t)));

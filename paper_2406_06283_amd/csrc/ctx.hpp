@@ -48,6 +48,13 @@ struct hkgeneo_ctx {
     hipEvent_t ev_dc[4] = {nullptr, nullptr, nullptr, nullptr};
     int32_t *h_infoL = nullptr;
     int h_infoL_n = 0;
+    // pinned staging for the job lists uploaded during a factorisation (reset at its start, after
+    // the previous factorisation's final wait), so that those uploads need no wait
+    uint8_t *h_stage = nullptr;
+    size_t h_stage_cap = 0, h_stage_used = 0;
+    // pinned readback of the eigenvalue counts, eigenvalues and flags of the coarse space
+    uint8_t *h_read = nullptr;
+    size_t h_read_cap = 0;
     // apply workspace
     hkg::DevBuf u, c, y, ypart;
     int ws_nrhs = 0;
@@ -74,6 +81,8 @@ int32_t dalloc(hkgeneo_ctx *c, DevBuf *b, size_t bytes);           // fresh allo
 int32_t walloc(hkgeneo_ctx *c, DevBuf *b, size_t bytes);           // reuse if large enough
 void drelease(hkgeneo_ctx *c, DevBuf *b);
 int32_t upload_bytes(hkgeneo_ctx *c, DevBuf *b, const void *host, size_t bytes, hipStream_t s, bool reuse);
+// the same through the pinned staging area of the context: returns without waiting for the copy
+int32_t upload_staged(hkgeneo_ctx *c, DevBuf *b, const void *host, size_t bytes, hipStream_t s);
 
 template <typename T>
 int32_t upload(hkgeneo_ctx *c, DevBuf *b, const T *host, size_t count, hipStream_t s, bool reuse = false) {

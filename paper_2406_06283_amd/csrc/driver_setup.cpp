@@ -60,6 +60,28 @@ int32_t upload_bytes(hkgeneo_ctx *c, DevBuf *b, const void *host, size_t bytes, 
     return HKG_OK;
 }
 
+int32_t upload_staged(hkgeneo_ctx *c, DevBuf *b, const void *host, size_t bytes, hipStream_t s) {
+    HKG_TRY(walloc(c, b, bytes));
+    if (!bytes) return HKG_OK;
+    const size_t at = (c->h_stage_used + 255) / 256 * 256;
+    if (at + bytes > c->h_stage_cap) {
+        // a larger area: the copies from the old one finish first
+        HKG_HIP(hipStreamSynchronize(s));
+        if (c->h_stage) HKG_HIP(hipHostFree(c->h_stage));
+        c->h_stage = nullptr;
+        c->h_stage_cap = 0;
+        c->h_stage_used = 0;
+        const size_t cap = std::max<size_t>((size_t)1 << 20, 2 * bytes);
+        HKG_HIP(hipHostMalloc((void **)&c->h_stage, cap));
+        c->h_stage_cap = cap;
+        return upload_staged(c, b, host, bytes, s);
+    }
+    std::memcpy(c->h_stage + at, host, bytes);
+    HKG_HIP(hipMemcpyAsync(b->p, c->h_stage + at, bytes, hipMemcpyHostToDevice, s));
+    c->h_stage_used = at + bytes;
+    return HKG_OK;
+}
+
 void free_workspace(hkgeneo_ctx *c) {
     DevBuf *w[] = {&c->wGGi, &c->wGI2, &c->wDk, &c->wBIO, &c->wCII, &c->wGG, &c->wGI, &c->wS, &c->wW, &c->wPiv, &c->wInfo,
                    &c->wFlag, &c->wD, &c->wE, &c->wTau, &c->wM, &c->wLam, &c->wY, &c->wB0, &c->wLU,
@@ -477,25 +499,39 @@ int32_t coarse_space(hkgeneo_ctx *c, hipStream_t s, const std::function<int32_t(
     HKG_TRY(select_eigs(dsub, ns, c->max_nI, dp<double>(c->wD), dp<double>(c->wE), o.eig_mode, o.tau, o.nev,
                         o.cluster_rtol, mmax, dp<int32_t>(c->wM), dp<double>(c->wLam), dp<int32_t>(c->wFlag),
                         dp<double>(c->wIv), s));
-    c->m_host.assign(ns, 0);
-    c->lam_host.assign((size_t)ns * (mmax + 2), 0.0);
-    HKG_HIP(hipMemcpyAsync(c->m_host.data(), c->wM.p, ns * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HKG_HIP(hipMemcpyAsync(c->lam_host.data(), c->wLam.p, c->lam_host.size() * sizeof(double), hipMemcpyDeviceToHost,
-                           s));
-    // the checks deferred to this point, in the order the quantities were computed
-    HKG_TRY(read_flags(c, c->wInfo, ns, &flags, s));
+    // the counts, the eigenvalues and the three flag arrays come back together through pinned memory
+    // (one wait); the checks deferred to this point follow in the order the quantities were computed
+    const size_t nlam = (size_t)ns * (mmax + 2), rb_ints = 4 * (size_t)ns, rb_at = (rb_ints * 4 + 255) / 256 * 256;
+    const size_t rb_bytes = rb_at + nlam * sizeof(double);
+    if (c->h_read_cap < rb_bytes) {
+        if (c->h_read) HKG_HIP(hipHostFree(c->h_read));
+        c->h_read = nullptr;
+        c->h_read_cap = 0;
+        HKG_HIP(hipHostMalloc((void **)&c->h_read, rb_bytes));
+        c->h_read_cap = rb_bytes;
+    }
+    int32_t *rb = reinterpret_cast<int32_t *>(c->h_read);
+    double *rb_lam = reinterpret_cast<double *>(c->h_read + rb_at);
+    HKG_HIP(hipMemcpyAsync(rb, c->wM.p, ns * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HKG_HIP(hipMemcpyAsync(rb + ns, c->wInfo.p, ns * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HKG_HIP(hipMemcpyAsync(rb + 2 * ns, c->wFlagSpd.p, ns * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HKG_HIP(hipMemcpyAsync(rb + 3 * ns, c->wFlag.p, ns * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HKG_HIP(hipMemcpyAsync(rb_lam, c->wLam.p, nlam * sizeof(double), hipMemcpyDeviceToHost, s));
+    HKG_HIP(hipStreamSynchronize(s));
+    c->m_host.assign(rb, rb + ns);
+    c->lam_host.assign(rb_lam, rb_lam + nlam);
+    const std::vector<int32_t> fGamma(rb + ns, rb + 2 * ns), fSpd(rb + 2 * ns, rb + 3 * ns);
+    flags.assign(rb + 3 * ns, rb + 4 * ns);
     for (int i = 0; i < ns; ++i)
-        if (flags[i]) {
+        if (fGamma[i]) {
             set_last_error("the Gamma block of the local Neumann matrix is singular in subdomain " + std::to_string(i));
             return HKG_EEIG;
         }
-    HKG_TRY(read_flags(c, c->wFlagSpd, ns, &flags, s));
     for (int i = 0; i < ns; ++i)
-        if (flags[i]) {
+        if (fSpd[i]) {
             set_last_error("C_II is not positive definite in subdomain " + std::to_string(i));
             return HKG_EEIG;
         }
-    HKG_TRY(read_flags(c, c->wFlag, ns, &flags, s));
     for (int i = 0; i < ns; ++i)
         if (flags[i]) {
             set_last_error("subdomain " + std::to_string(i) + " needs " + std::to_string(c->m_host[i]) +
@@ -522,8 +558,8 @@ int32_t coarse_space(hkgeneo_ctx *c, hipStream_t s, const std::function<int32_t(
         set_last_error("coarse dimension " + std::to_string(c->m0) + " exceeds the supported 7000");
         return HKG_EINVAL;
     }
+    // (c->subs stays as it is until the next analysis: no wait for the copy)
     HKG_HIP(hipMemcpyAsync(c->subs_d.p, c->subs.data(), ns * sizeof(SubDev), hipMemcpyHostToDevice, s));
-    HKG_HIP(hipStreamSynchronize(s));
     if (c->m0 == 0) return HKG_OK;
     // eigenvectors -> coarse basis Z_i = X_I P_i
     if (c->Z.bytes != (size_t)offZ * sizeof(double)) HKG_TRY(dalloc(c, &c->Z, offZ * sizeof(double)));
@@ -546,8 +582,8 @@ int32_t coarse_space(hkgeneo_ctx *c, hipStream_t s, const std::function<int32_t(
             hg[i] = {sd.offZ, sd.offBIO, sd.offY, sd.m, sd.nI + sd.nG, sd.nI, sd.nI, sd.nI, std::max(sd.m, 1)};
             maxN = std::max(maxN, sd.nI + sd.nG);
         }
-        HKG_TRY(upload(c, &c->wJobsZ, hj.data(), ns, s, true));
-        HKG_TRY(upload(c, &c->wGjobsY, hg.data(), ns, s, true));
+        HKG_TRY(upload_staged(c, &c->wJobsZ, hj.data(), ns * sizeof(TriJob), s));
+        HKG_TRY(upload_staged(c, &c->wGjobsY, hg.data(), ns * sizeof(GemmJob), s));
         HKG_TRY(tri_solve_batched<double>(dp<TriJob>(c->wJobsZ), ns, c->max_nI, c->max_m, dp<double>(c->wCII),
                                           dp<double>(c->Z), TRI_LOWER_UNIT_TRANS, s, c->band_I));
         HKG_TRY(finish_basis(dsub, ns, dp<int32_t>(c->I_idx), dp<double>(c->winv), dp<double>(c->Z), s));
@@ -629,6 +665,7 @@ int32_t coarse_space(hkgeneo_ctx *c, hipStream_t s, const std::function<int32_t(
 int32_t factor(hkgeneo_ctx *c, hipStream_t s) {
     const int ns = c->n_sub;
     const SubDev *dsub = dp<SubDev>(c->subs_d);
+    c->h_stage_used = 0;             // the previous factorisation ended with a wait on its streams
     if (!c->s2) {
         HKG_HIP(hipStreamCreateWithFlags(&c->s2, hipStreamNonBlocking));
         HKG_HIP(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));

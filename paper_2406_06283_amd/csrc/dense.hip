@@ -1332,14 +1332,11 @@ __global__ __launch_bounds__(TLW_THREADS) void k_tri_lower_window(const TriJob *
             double Lx[BW];
 #pragma unroll
             for (int i = 0; i < BW; ++i) Lx[i] = Ln[i];
-            double s0 = b[u], s1 = 0.0;
+            // four partial sums: a chain of dependent double FMAs is long-latency
+            double acc[4] = {b[u], 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int i = BW - 1; i >= 1; --i) {
-                const double xv = win[(u - 1 - i + 2 * BW) % BW];
-                if (i & 1) s1 = fma(-Lc[i], xv, s1);
-                else s0 = fma(-Lc[i], xv, s0);
-            }
-            double x = fma(-Lc[0], win[(u - 1 + BW) % BW], s0 + s1);
+            for (int i = BW - 1; i >= 1; --i) acc[i & 3] = fma(-Lc[i], win[(u - 1 - i + 2 * BW) % BW], acc[i & 3]);
+            double x = fma(-Lc[0], win[(u - 1 + BW) % BW], (acc[0] + acc[1]) + (acc[2] + acc[3]));
             asm volatile("" : "+v"(x) : : "memory");    // no band row read before the step ends
             win[u] = x;
 #pragma unroll
@@ -1393,6 +1390,76 @@ int32_t tri_lower_window_batched(const TriJob *d_jobs, int nbatch, int maxn, int
     HKG_HIP(hipGetLastError());
     return HKG_OK;
 }
+
+// L^{-T} applied to a few right-hand sides in place (the coarse basis: L^T X = X with L the unit
+// lower factor of a packed L D L^T, half-bandwidth band <= BW), backward, one thread per right-hand
+// side: x[k] = x[k] - sum_i L[k + 1 + i][k] x[k + 1 + i].  Column k of L below the diagonal is row k
+// of the staged band; thread c keeps the last BW entries solved in registers as above and reads and
+// writes its own column of X a block at a time.
+template <int BW>
+__global__ __launch_bounds__(64) void k_tri_ltrans_window(const TriJob *__restrict__ jobs, const double *__restrict__ Tb,
+                                                          double *__restrict__ Xb, int band) {
+    extern __shared__ double shl[];
+    const TriJob J = jobs[blockIdx.y];
+    const int n = J.n;
+    if ((int)blockIdx.x * 64 >= J.ncol || n == 0) return;
+    const int tid = threadIdx.x, c = blockIdx.x * 64 + tid;
+    double *Lt = shl;                            // n x BW: Lt[k][i] = L[k + 1 + i][k]
+    const double *Tm = Tb + J.offT;
+    staged_copy<8>(
+        n * BW, tid, 64, [&](int e) { const int k = e / BW, i = e % BW; return Tm[min(k + 1 + i, n - 1) + (int64_t)k * J.ldT]; },
+        [&](int e, double v) {
+            const int k = e / BW, i = e % BW;
+            Lt[e] = (i < band && k + 1 + i < n) ? v : 0.0;
+        });
+    __syncthreads();
+    if (c >= J.ncol) return;
+    double *x = Xb + J.offX + (int64_t)c * J.ldX;
+    double win[BW], Lc[BW], b[BW];
+#pragma unroll
+    for (int u = 0; u < BW; ++u) {
+        win[u] = 0.0;
+        Lc[u] = Lt[(int64_t)(n - 1) * BW + u];
+    }
+    for (int k0 = n - 1; k0 >= 0; k0 -= BW) {
+        // step u of the block solves row k0 - u
+#pragma unroll
+        for (int u = 0; u < BW; ++u) b[u] = x[max(k0 - u, 0)];
+#pragma unroll
+        for (int u = 0; u < BW; ++u) {
+            const double *Ln = Lt + (int64_t)max(k0 - u - 1, 0) * BW;
+            double Lx[BW];
+#pragma unroll
+            for (int i = 0; i < BW; ++i) Lx[i] = Ln[i];
+            double acc[4] = {b[u], 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int i = BW - 1; i >= 1; --i) acc[i & 3] = fma(-Lc[i], win[(u - 1 - i + 2 * BW) % BW], acc[i & 3]);
+            double xk = fma(-Lc[0], win[(u - 1 + BW) % BW], (acc[0] + acc[1]) + (acc[2] + acc[3]));
+            asm volatile("" : "+v"(xk) : : "memory");   // no band row read before the step ends
+            win[u] = xk;
+#pragma unroll
+            for (int i = 0; i < BW; ++i) Lc[i] = Lx[i];
+        }
+#pragma unroll
+        for (int u = 0; u < BW; ++u)
+            if (k0 - u >= 0) x[k0 - u] = win[u];
+    }
+}
+
+int32_t tri_ltrans_window_batched(const TriJob *d_jobs, int nbatch, int maxn, int maxcol, const double *Tm, double *X,
+                                  int band, hipStream_t s) {
+    if (nbatch == 0 || maxn == 0 || maxcol == 0) return HKG_OK;
+    if (!tri_lower_window_fits(maxn, band)) return HKG_EINVAL;
+    const int bw = tlw_width(band);
+    const size_t shm = (size_t)maxn * bw * sizeof(double);
+    const dim3 g((maxcol + 63) / 64, nbatch);
+    if (bw == 16) hipLaunchKernelGGL(k_tri_ltrans_window<16>, g, dim3(64), shm, s, d_jobs, Tm, X, band);
+    else if (bw == 24) hipLaunchKernelGGL(k_tri_ltrans_window<24>, g, dim3(64), shm, s, d_jobs, Tm, X, band);
+    else hipLaunchKernelGGL(k_tri_ltrans_window<32>, g, dim3(64), shm, s, d_jobs, Tm, X, band);
+    HKG_HIP(hipGetLastError());
+    return HKG_OK;
+}
+
 
 // ------------------------------------------------------------------------------------------------
 // Inverse of one packed LU (P A = L U) by recursive block triangular inversion: the LU_NB diagonal

@@ -584,8 +584,12 @@ int32_t coarse_space(hkgeneo_ctx *c, hipStream_t s, const std::function<int32_t(
         }
         HKG_TRY(upload_staged(c, &c->wJobsZ, hj.data(), ns * sizeof(TriJob), s));
         HKG_TRY(upload_staged(c, &c->wGjobsY, hg.data(), ns * sizeof(GemmJob), s));
-        HKG_TRY(tri_solve_batched<double>(dp<TriJob>(c->wJobsZ), ns, c->max_nI, c->max_m, dp<double>(c->wCII),
-                                          dp<double>(c->Z), TRI_LOWER_UNIT_TRANS, s, c->band_I));
+        if (tri_lower_window_fits(c->max_nI, c->band_I))
+            HKG_TRY(tri_ltrans_window_batched(dp<TriJob>(c->wJobsZ), ns, c->max_nI, c->max_m, dp<double>(c->wCII),
+                                              dp<double>(c->Z), c->band_I, s));
+        else
+            HKG_TRY(tri_solve_batched<double>(dp<TriJob>(c->wJobsZ), ns, c->max_nI, c->max_m, dp<double>(c->wCII),
+                                              dp<double>(c->Z), TRI_LOWER_UNIT_TRANS, s, c->band_I));
         HKG_TRY(finish_basis(dsub, ns, dp<int32_t>(c->I_idx), dp<double>(c->winv), dp<double>(c->Z), s));
         if (c->Zr.bytes != (size_t)offZ * sizeof(double)) HKG_TRY(dalloc(c, &c->Zr, offZ * sizeof(double)));
         HKG_TRY(transpose_basis(dsub, ns, dp<double>(c->Z), dp<double>(c->Zr), s));

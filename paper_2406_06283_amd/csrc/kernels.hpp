@@ -32,6 +32,10 @@ bool tri_lower_window_fits(int maxn, int band);
 int32_t tri_lower_window_batched(const TriJob *d_jobs, int nbatch, int maxn, int maxcol, const double *Tm,
                                  const double *Xin, bool in_cols, double *Xout, bool scale, int band,
                                  hipStream_t s);
+// X = L^{-T} X in place for a few right-hand sides (the jobs' X at (offX, ldX)), L as above; fits as
+// tri_lower_window_fits
+int32_t tri_ltrans_window_batched(const TriJob *d_jobs, int nbatch, int maxn, int maxcol, const double *Tm, double *X,
+                                  int band, hipStream_t s);
 constexpr int LU_BLOCK = 32;    // block size of the dense LU, triangular solves and inversions
 
 // diagonal LU_BLOCK blocks of L^{-1} (unit lower) and U^{-1} of one packed LU, into Linv / Uinv

@@ -128,7 +128,9 @@ void ws_sizes(const hkgeneo_ctx *c, int R, int m, size_t out[NWS]) {
                            (size_t)R,                      // rnorm
                            (size_t)(R + 1) / 2,            // iters (int32)
                            (size_t)R};                     // jcur (2 int32 per rhs)
-    std::memcpy(out, v, sizeof(v));
+    // each region a whole number of 16-byte units, so that every region (and the coarse vector c of
+    // each right-hand side when m_0 is even) starts 16-byte aligned for the paired loads
+    for (int k = 0; k < NWS; ++k) out[k] = (v[k] + 1) & ~(size_t)1;
 }
 
 int64_t ws_bytes(const hkgeneo_ctx *c, int R, int m) {

@@ -203,38 +203,78 @@ __global__ __launch_bounds__(LS_ROWS *WAVES) void k_b_local(const ProbDev *__res
     else local_body<double, WAVES>(P, sd, r, rhs, sh);
 }
 
-// Coarse solve y = B_0^{-1} c: one wave per coarse row r.  B_0 is symmetric (B_0 = Z^T B Z), so row r
-// of its inverse is read as column r of the stored column-major inverse: contiguous, coalesced.  Lane
-// l sums the columns congruent to l modulo 64 in increasing order (eight loads in flight; sixteen
-// measured slower), then a fixed-order wave reduction: the final y (no split partial sums), whatever
-// the batch composition.  y is stored in the ypart region.
-constexpr int CG_RPB = 4;        // rows (waves) per block
+// Coarse solve y = B_0^{-1} c: CG_WPR waves per coarse row r, one block per row.  B_0 is symmetric
+// (B_0 = Z^T B Z), so row r of its inverse is read as column r of the stored column-major inverse:
+// contiguous, coalesced.  Wave w takes the w-th of CG_WPR contiguous column ranges (a multiple of 64
+// loads each); with m_0 even (the column then starts 16-byte aligned) a lane reads column pairs
+// (16-byte loads: 8-byte ones reach about 3.5 TB/s on this row length, 16-byte ones 4.8) and sums the
+// pairs l, l + 64, ... of its wave's range in increasing order, both entries of a pair in turn; with
+// m_0 odd it reads single entries in the same pattern.  Each wave's sum is reduced in fixed order and
+// the CG_WPR wave sums are added in wave order: the final y (no split partial sums), whatever the
+// batch composition.  y is stored in the ypart region.
+constexpr int CG_RPB = 4;        // rows per work item (the host lists items of four rows)
+constexpr int CG_WPR = 4;        // waves per row
+constexpr int CG_U = 5;          // loads in flight per lane
 
-__global__ __launch_bounds__(64 * CG_RPB) void k_b_coarse_gemv(const ProbDev *__restrict__ probs,
+__global__ __launch_bounds__(64 * CG_WPR) void k_b_coarse_gemv(const ProbDev *__restrict__ probs,
                                                                const WorkItem *__restrict__ cblk, int mode) {
-    const WorkItem it = cblk[blockIdx.x];
+    __shared__ double wsum[CG_WPR];
+    const WorkItem it = cblk[blockIdx.x / CG_RPB];
     const ProbDev &P = probs[it.p];
     const int rhs = blockIdx.z;
     if (inactive(P, rhs, mode) || !P.two_level) return;
-    const int m0 = P.m0, lane = threadIdx.x & 63;
-    const int r = it.s * CG_RPB + (threadIdx.x >> 6);
+    const int m0 = P.m0, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int r = it.s * CG_RPB + (int)(blockIdx.x % CG_RPB);
     if (r >= m0) return;
     const double *col = P.B0inv + (int64_t)r * m0;
     const double *c = P.c + (int64_t)rhs * m0;
+    const bool pairs = (m0 & 1) == 0 && (((uintptr_t)P.B0inv | (uintptr_t)P.c) & 15) == 0;
     double acc = 0.0;
-    for (int k0 = lane; k0 < m0; k0 += 64 * 8) {
-        double b[8], x[8];
+    if (pairs) {
+        const int np = m0 / 2;
+        const int span = ((np + CG_WPR - 1) / CG_WPR + 63) / 64 * 64;
+        const int k1 = min(wv * span, np), k2 = min(k1 + span, np);
+        const double2 *b2 = reinterpret_cast<const double2 *>(col);
+        const double2 *c2 = reinterpret_cast<const double2 *>(c);
+        for (int k0 = k1 + lane; k0 < k2; k0 += 64 * CG_U) {
+            double2 b[CG_U], x[CG_U];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int q = min(k0 + 64 * k, m0 - 1);
-            b[k] = col[q];
-            x[k] = c[q];
+            for (int k = 0; k < CG_U; ++k) {
+                const int q = min(k0 + 64 * k, k2 - 1);
+                b[k] = b2[q];
+                x[k] = c2[q];
+            }
+#pragma unroll
+            for (int k = 0; k < CG_U; ++k) {
+                const bool in = k0 + 64 * k < k2;
+                acc = fma(b[k].x, in ? x[k].x : 0.0, acc);
+                acc = fma(b[k].y, in ? x[k].y : 0.0, acc);
+            }
         }
+    } else {
+        const int span = ((m0 + CG_WPR - 1) / CG_WPR + 63) / 64 * 64;
+        const int k1 = min(wv * span, m0), k2 = min(k1 + span, m0);
+        for (int k0 = k1 + lane; k0 < k2; k0 += 64 * 2 * CG_U) {
+            double b[2 * CG_U], x[2 * CG_U];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) acc = fma(b[k], k0 + 64 * k < m0 ? x[k] : 0.0, acc);
+            for (int k = 0; k < 2 * CG_U; ++k) {
+                const int q = min(k0 + 64 * k, k2 - 1);
+                b[k] = col[q];
+                x[k] = c[q];
+            }
+#pragma unroll
+            for (int k = 0; k < 2 * CG_U; ++k) acc = fma(b[k], k0 + 64 * k < k2 ? x[k] : 0.0, acc);
+        }
     }
     acc = bwsum(acc);
-    if (lane == 0) P.ypart[(int64_t)rhs * m0 + r] = acc;
+    if (lane == 0) wsum[wv] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double y = wsum[0];
+#pragma unroll
+        for (int w = 1; w < CG_WPR; ++w) y += wsum[w];
+        P.ypart[(int64_t)rhs * m0 + r] = y;
+    }
 }
 
 // z_l = sum over the positions t of dof l in the local vectors (transpose map, fixed order) of
@@ -302,7 +342,8 @@ int32_t batch_apply(const BatchGeom &g, const ProbDev *probs, const WorkItem *it
     HKG_HIP(hipGetLastError());
     if (ev1) HKG_HIP(hipEventRecord(ev1, s));
     if (g.any_coarse)
-        hipLaunchKernelGGL(k_b_coarse_gemv, dim3(g.ncblk, 1, g.max_nrhs), dim3(64 * CG_RPB), 0, s, probs, cblk, mode);
+        hipLaunchKernelGGL(k_b_coarse_gemv, dim3(g.ncblk * CG_RPB, 1, g.max_nrhs), dim3(64 * CG_WPR), 0, s, probs,
+                           cblk, mode);
     hipLaunchKernelGGL(k_b_prolong, dim3(g.nrblk, 1, g.max_nrhs), dim3(4 * BROWS), 0, s, probs, rblk, mode, par);
     HKG_HIP(hipGetLastError());
     return HKG_OK;

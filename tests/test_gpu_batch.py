@@ -213,6 +213,8 @@ def test_batch_of_24_uneven_problems_matches_oracle():
                 torch.cuda.synchronize()
             assert np.array_equal(ua.cpu().numpy(), um[q]), mix[q].name
             assert [i["iters"] for i in ia] == [i["iters"] for i in im[q]], mix[q].name
+        # the coarse product reads paired entries for even m_0 and single ones for odd m_0: both occur
+        assert {S.stats()["m0"] % 2 for S in solvers} == {0, 1}
         worst = 0.0
         for q, (m, p, S) in enumerate(zip(mix, probs, solvers)):
             M = schwarz.TwoLevelSchwarz(p, schwarz.Options(eig_mode=local.EIG_THRESHOLD, tau=m.tau))

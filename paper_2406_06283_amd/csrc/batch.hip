@@ -357,6 +357,7 @@ int32_t batch_apply(const BatchGeom &g, const ProbDev *probs, const WorkItem *it
 // sums, so that a CU keeps many independent loads of V in flight.
 constexpr int CG_T = 4 * BROWS;
 constexpr int CG_W = CG_T / 64;          // waves per block
+constexpr int RED_U = 4;                 // row-block partials a lane loads at once when reducing them
 
 // Partial sums of one row block (BROWS rows r0 .. r0 + BROWS): slot i <= j of x_i . w, slot j + 1 of
 // w . w, written column by column (out[i * nb], the row blocks of one slot contiguous).  Wave wv takes
@@ -445,12 +446,18 @@ __global__ __launch_bounds__(CG_T) void k_b_update(const ProbDev *__restrict__ p
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int i0 = wv; i0 <= j + 1; i0 += 4 * CG_W) {
         double a[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int b = lane; b < nb; b += 64) {
-            double v[4];
+        for (int b0 = lane; b0 < nb; b0 += 64 * RED_U) {
+            double v[RED_U][4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) v[k] = pin[(int64_t)min(i0 + CG_W * k, j + 1) * nb + b];
+            for (int u = 0; u < RED_U; ++u)
 #pragma unroll
-            for (int k = 0; k < 4; ++k) a[k] += v[k];
+                for (int k = 0; k < 4; ++k)
+                    v[u][k] = pin[(int64_t)min(i0 + CG_W * k, j + 1) * nb + min(b0 + 64 * u, nb - 1)];
+#pragma unroll
+            for (int u = 0; u < RED_U; ++u)
+                if (b0 + 64 * u < nb)
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) a[k] += v[u][k];
         }
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -512,7 +519,14 @@ __global__ __launch_bounds__(BROWS) void k_b_finish(const ProbDev *__restrict__ 
     const int n = P.n, m = P.restart, S = m + 2, nb = P.nblk, j = jget(P, rhs, par);
     const double *pin = part_half(P, rhs, 0);
     double nrm2 = 0.0;
-    for (int b = (threadIdx.x & 63); b < nb; b += 64) nrm2 += pin[b];
+    for (int b0 = (threadIdx.x & 63); b0 < nb; b0 += 64 * RED_U) {
+        double v[RED_U];
+#pragma unroll
+        for (int u = 0; u < RED_U; ++u) v[u] = pin[min(b0 + 64 * u, nb - 1)];
+#pragma unroll
+        for (int u = 0; u < RED_U; ++u)
+            if (b0 + 64 * u < nb) nrm2 += v[u];
+    }
     nrm2 = bwsum(nrm2);
     const double hn = sqrt(nrm2);
     double *w = vcol_w(P, rhs, j + 1);

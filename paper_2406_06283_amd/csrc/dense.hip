@@ -922,7 +922,7 @@ __global__ __launch_bounds__(256) void k_tri_band(const TriJob *__restrict__ job
         const int ka = fwd ? max(0, i0 - band) : i0;
         const int kb = fwd ? i0 + nb : min(n, i0 + nb + band);
         const int w = kb - ka;
-        __syncthreads();      // previous block done with Ls and with its rows of ys
+        sync_lds();           // previous block done with Ls and with its rows of ys
         if (MODE == TRI_LOWER_UNIT_TRANS) {
             // op(T)[i][k] = T[k][i]: consecutive k are contiguous
             staged_copy<8>(
@@ -971,7 +971,7 @@ __global__ __launch_bounds__(256) void k_tri_band(const TriJob *__restrict__ job
             }
         }
     }
-    __syncthreads();
+    sync_lds();
     // (TIN: scaled by D^{-1/2} on both sides, D the diagonal of T, into (offO, ldO))
     T *Xo = TIN ? Xb + J.offO : X;
     const int ldo = TIN ? J.ldO : J.ldX;
@@ -1063,7 +1063,7 @@ __global__ __launch_bounds__(256) void k_tri_bandw(const TriJob *__restrict__ jo
         const int kb = fwd ? i0 + nb : min(n, i0 + nb + band);
         const int w = kb - ka;
         const int s0 = i0 % WIN;                   // slot of row i0 (the block's rows are s0, s0+1, .. mod WIN)
-        __syncthreads();      // the previous block is solved; Ls is free
+        sync_lds();           // the previous block is solved; Ls is free
         if (pnb > 0) write_out(pi0, pnb);
         if (MODE == TRI_LOWER_UNIT_TRANS) {
             staged_copy<8>(
@@ -1174,7 +1174,7 @@ __global__ __launch_bounds__(256) void k_tri_bandw(const TriJob *__restrict__ jo
         pi0 = i0;
         pnb = nb;
     }
-    __syncthreads();
+    sync_lds();
     write_out(pi0, pnb);
 }
 

@@ -16,6 +16,15 @@ constexpr int DPP_QUAD_XOR2 = 0x4E;       // quad_perm [2, 3, 0, 1]
 constexpr int DPP_ROW_MIRROR = 0x140;     // lane i <- lane 15 - i within the row
 constexpr int DPP_ROW_HALF_MIRROR = 0x141; // lane i <- lane 7 - i within each half row
 
+// A workgroup barrier that first waits for this wave's LDS operations to complete
+// (s_waitcnt lgkmcnt(0), the other counters left as they are).  The compiler does not always emit
+// that wait before the barrier of __syncthreads() when the LDS stores come from a loop's previous
+// iteration; another wave can then read a slot after the barrier before the store has landed.
+__device__ __forceinline__ void sync_lds() {
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    __syncthreads();
+}
+
 template <int CTRL>
 __device__ __forceinline__ int dpp_i32(int v) {
     return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xf, 0xf, false);

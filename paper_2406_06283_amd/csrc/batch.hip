@@ -298,6 +298,7 @@ __global__ __launch_bounds__(4 * BROWS) void k_b_prolong(const ProbDev *__restri
     const int t1 = P.tp_ptr[l + 1];
     double v = 0.0;
     for (int t = P.tp_ptr[l] + q; t < t1; t += 4) {
+        const double ut = uu[P.tp_pos[t]];     // issued before the coarse row's loads
         double c = 0.0;
         if (P.two_level) {
             const TpCoarse d = P.tpc[t];
@@ -313,7 +314,7 @@ __global__ __launch_bounds__(4 * BROWS) void k_b_prolong(const ProbDev *__restri
                 for (int k = 0; k < 8; ++k) c = fma(zv[k], b0 + k < d.m ? yv[k] : 0.0, c);
             }
         }
-        v += uu[P.tp_pos[t]] + c;
+        v += ut + c;
     }
     const double s = ((dpp_f64<0x00>(v) + dpp_f64<0x55>(v)) + dpp_f64<0xAA>(v)) + dpp_f64<0xFF>(v);
     if (q == 0) {

@@ -546,8 +546,25 @@ __global__ __launch_bounds__(BROWS) void k_b_finish(const ProbDev *__restrict__ 
     }
     __syncthreads();
     if (threadIdx.x == 0) {
+        // the earlier rotations, four at a time with their operands read ahead of the chain (the
+        // same operations in the same order as one at a time)
         double cur = hs[0];
-        for (int i = 0; i < j; ++i) {
+        int i = 0;
+        for (; i + 4 <= j; i += 4) {
+            double nx[4], cc[4], ss[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                nx[u] = hs[i + 1 + u];
+                cc[u] = css[i + u];
+                ss[u] = sns[i + u];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                hs[i + u] = cc[u] * cur + ss[u] * nx[u];
+                cur = -ss[u] * cur + cc[u] * nx[u];
+            }
+        }
+        for (; i < j; ++i) {
             const double nx = hs[i + 1];
             hs[i] = css[i] * cur + sns[i] * nx;
             cur = -sns[i] * cur + css[i] * nx;
